@@ -1,0 +1,362 @@
+"""ProbGraph reference oracle (FP64 / exact integers, CPU).
+
+TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package. The GPU library
+never calls it; it shares no code, header, table or constant generator with it.
+
+Integer quantities (exact intersections, sketches, bit and match counts) come
+from ``pg_oracle.c``; the estimator formulas are written out below in FP64
+numpy, each next to the passage of the paper it follows.
+
+Functions whose result has no external pin are marked "parity unpinned".
+Every other function is pinned by ``tests/test_oracle_*.py`` against closed
+forms, brute force, published test vectors or the statistics the paper states.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pg_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libpgoracle.so")
+_lib = None
+
+BOTTOM = 0xFFFFFFFF
+KIND_BF, KIND_KH, KIND_1H = 1, 2, 3
+
+BF_ESTIMATORS = ("and", "l", "or", "pap")
+MH_ESTIMATORS = {"kh": KIND_KH, "1h": KIND_1H, "1h_lit": KIND_1H}
+
+
+def build() -> str:
+    """Compile the oracle's C half (gcc, OpenMP)."""
+    tmp = _LIB_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-lm", "-o", tmp])
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    u64, i32, i64, u32 = ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "or_splitmix64": (u64, [u64, u64]),
+        "or_hash_consts": (None, [ctypes.c_int, u64, ctypes.c_int, u64p, u64p]),
+        "or_bf_index": (u32, [u64, u64, u32, u32]),
+        "or_mh_key": (u64, [u64, u64, u32]),
+        "or_upper_edges": (i64, [i32, i32p, i32p, i32p, i32p]),
+        "or_exact_pairs": (None, [i32, i32p, i32p, i64, i32p, i32p, u32p]),
+        "or_exact_tc_listing": (u64, [i32, i32p, i32p]),
+        "or_bf_build": (None, [i32, i32p, i32p, u32, u32, u64, u64p, u32p]),
+        "or_bf_of_set": (None, [i32, i32p, u32, u32, u64, u64p]),
+        "or_bf_counts": (None, [u32, u64p, i64, i32p, i32p, u32p, u32p]),
+        "or_kh_build": (None, [i32, i32p, i32p, u32, u64, u32p]),
+        "or_kh_counts": (None, [u32, u32p, i64, i32p, i32p, u32p]),
+        "or_1h_build": (None, [i32, i32p, i32p, u32, u64, u32p]),
+        "or_1h_counts": (None, [u32, u64, u32p, i64, i32p, i32p, u32p, u32p, u32p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a, ct):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+# ---------------------------------------------------------------- hashing
+
+def splitmix64(key: int, i: int) -> int:
+    return int(_load().or_splitmix64(key & (2**64 - 1), i))
+
+
+def hash_consts(kind: int, seed: int, count: int):
+    a = np.zeros(count, dtype=np.uint64)
+    c = np.zeros(count, dtype=np.uint64)
+    _load().or_hash_consts(kind, seed & (2**64 - 1), count, _ptr(a, ctypes.c_uint64), _ptr(c, ctypes.c_uint64))
+    return a, c
+
+
+def bf_index(a: int, c: int, x: int, B: int) -> int:
+    return int(_load().or_bf_index(a, c, x, B))
+
+
+def mh_key(a: int, c: int, x: int) -> int:
+    return int(_load().or_mh_key(a, c, x))
+
+
+# ---------------------------------------------------------------- exact
+
+def upper_edges(g):
+    """The m undirected edges (v, u), v < u, in CSR order (Section 2.1, |E| = m)."""
+    lib = _load()
+    off, adj = _i32(g.offsets), _i32(g.adj)
+    m = lib.or_upper_edges(g.n, _ptr(off, ctypes.c_int32), _ptr(adj, ctypes.c_int32), None, None)
+    eu = np.empty(m, dtype=np.int32)
+    ev = np.empty(m, dtype=np.int32)
+    lib.or_upper_edges(g.n, _ptr(off, ctypes.c_int32), _ptr(adj, ctypes.c_int32),
+                       _ptr(eu, ctypes.c_int32), _ptr(ev, ctypes.c_int32))
+    return eu, ev
+
+
+def arcs(g):
+    """All 2m arcs (v, u), u in N_v, in CSR order."""
+    deg = np.diff(g.offsets)
+    return np.repeat(np.arange(g.n, dtype=np.int32), deg), _i32(g.adj)
+
+
+def exact_pairs(g, u, v) -> np.ndarray:
+    """|N_u intersect N_v| by sorted merge, per pair."""
+    u, v = _i32(u), _i32(v)
+    out = np.empty(u.shape[0], dtype=np.uint32)
+    off, adj = _i32(g.offsets), _i32(g.adj)
+    _load().or_exact_pairs(g.n, _ptr(off, ctypes.c_int32), _ptr(adj, ctypes.c_int32), u.shape[0],
+                           _ptr(u, ctypes.c_int32), _ptr(v, ctypes.c_int32), _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def exact_tc(g) -> int:
+    """TC = (1/3) * sum over the m edges of |N_u intersect N_v| (Section 7)."""
+    eu, ev = upper_edges(g)
+    s = int(exact_pairs(g, eu, ev).astype(np.uint64).sum())
+    assert s % 3 == 0
+    return s // 3
+
+
+def exact_tc_listing(g) -> int:
+    """TC by the degree-ordered node iterator of Listing "lst:tc"."""
+    off, adj = _i32(g.offsets), _i32(g.adj)
+    return int(_load().or_exact_tc_listing(g.n, _ptr(off, ctypes.c_int32), _ptr(adj, ctypes.c_int32)))
+
+
+def local_cc_from_arc_values(g, arc_values: np.ndarray) -> np.ndarray:
+    """cc_v = sum_{u in N_v} I(u, v) / (d_v (d_v - 1)); 0 when d_v < 2.
+
+    Local clustering coefficient (Watts and Strogatz 1998); sum_{u in N_v}
+    |N_u cap N_v| is twice the number of triangles at v. ``arc_values`` holds
+    I(v, u) for the arcs in CSR order."""
+    deg = np.diff(g.offsets).astype(np.float64)
+    sums = np.zeros(g.n, dtype=np.float64)
+    src = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    np.add.at(sums, src, arc_values.astype(np.float64))
+    denom = deg * (deg - 1.0)
+    out = np.zeros(g.n, dtype=np.float64)
+    ok = deg >= 2
+    out[ok] = sums[ok] / denom[ok]
+    return out
+
+
+def exact_cc(g) -> np.ndarray:
+    au, av = arcs(g)
+    return local_cc_from_arc_values(g, exact_pairs(g, au, av))
+
+
+def jaccard_from_intersection(du, dv, inter) -> np.ndarray:
+    """J = |A cap B| / (|A| + |B| - |A cap B|) (Listing "lst:sim"); 0 when the union is empty.
+    The intersection estimate is clamped to [0, min(d_u, d_v)] first (an estimate
+    outside that range has no consistent Jaccard value)."""
+    du = np.asarray(du, dtype=np.float64)
+    dv = np.asarray(dv, dtype=np.float64)
+    ic = np.clip(np.asarray(inter, dtype=np.float64), 0.0, np.minimum(du, dv))
+    den = du + dv - ic
+    out = np.zeros_like(den)
+    ok = den > 0
+    out[ok] = ic[ok] / den[ok]
+    return out
+
+
+def exact_jaccard(g, u, v) -> np.ndarray:
+    deg = g.degrees()
+    return jaccard_from_intersection(deg[u], deg[v], exact_pairs(g, u, v))
+
+
+# ---------------------------------------------------------------- estimators
+
+def est_bf_and(c, B: int, b: int) -> np.ndarray:
+    """AND estimator, Eq. "bf_int": -(B/b) ln(1 - c~/B), c the ones of B_u AND B_v,
+    with c~ = c - [c == B] so the logarithm stays finite (Appendix C)."""
+    c = np.asarray(c, dtype=np.float64)
+    ct = c - (c == B)
+    return -(B / b) * np.log(1.0 - ct / B)
+
+
+def est_bf_limit(c, B: int, b: int) -> np.ndarray:
+    """Limit estimator, Eq. "limit_xs": c / b."""
+    return np.asarray(c, dtype=np.float64) / b
+
+
+def est_bf_papapetrou(c, B: int, b: int) -> np.ndarray:
+    """Existing BF cardinality estimator (Section 8.1) applied to the AND:
+    ln(1 - c~/B) / (b ln(1 - 1/B)). The paper prints a leading minus, which
+    would make every estimate negative (both logarithms are negative); the
+    estimator is the ratio of the two logarithms."""
+    c = np.asarray(c, dtype=np.float64)
+    ct = c - (c == B)
+    return np.log(1.0 - ct / B) / (b * np.log(1.0 - 1.0 / B))
+
+
+def est_bf_or(c_or, du, dv, B: int, b: int) -> np.ndarray:
+    """OR estimator, Eq. "bf_int_union": |X| + |Y| + (B/b) ln(1 - c~_or/B)."""
+    c_or = np.asarray(c_or, dtype=np.float64)
+    ct = c_or - (c_or == B)
+    return (np.asarray(du, np.float64) + np.asarray(dv, np.float64)) + (B / b) * np.log(1.0 - ct / B)
+
+
+def est_minhash(s, kk, du, dv) -> np.ndarray:
+    """MinHash intersection estimators, Eq. "est_int_mh" and Section 4.4:
+    J^ = s / k, I^ = J^ / (1 + J^) * (|X| + |Y|). J^ = 0 when k = 0."""
+    s = np.asarray(s, dtype=np.float64)
+    kk = np.asarray(kk, dtype=np.float64) * np.ones_like(s)
+    jh = np.zeros_like(s)
+    ok = kk > 0
+    jh[ok] = s[ok] / kk[ok]
+    return jh / (1.0 + jh) * (np.asarray(du, np.float64) + np.asarray(dv, np.float64))
+
+
+# ---------------------------------------------------------------- sketches
+
+@dataclass
+class Sketches:
+    """Per-vertex sketches of one graph plus what the estimators need."""
+
+    g: object
+    kind: int
+    size: int          # B (bits) for Bloom filters, k for MinHash
+    b: int             # hash functions per Bloom filter (1 for MinHash)
+    seed: int
+    words: np.ndarray | None = None   # uint64 [n, B/64]
+    pc: np.ndarray | None = None      # uint32 [n]
+    sig: np.ndarray | None = None     # uint32 [n, k]
+    deg: np.ndarray = field(default=None)
+
+    def counts(self, u, v):
+        """Integer counts per pair: BF -> (c_and, c_or); k-hash -> s;
+        1-hash -> (s_union, kprime, s_literal)."""
+        lib = _load()
+        u, v = _i32(u), _i32(v)
+        npairs = u.shape[0]
+        pu, pv = _ptr(u, ctypes.c_int32), _ptr(v, ctypes.c_int32)
+        if self.kind == KIND_BF:
+            ca = np.empty(npairs, np.uint32)
+            co = np.empty(npairs, np.uint32)
+            lib.or_bf_counts(self.size // 64, _ptr(self.words, ctypes.c_uint64), npairs, pu, pv,
+                             _ptr(ca, ctypes.c_uint32), _ptr(co, ctypes.c_uint32))
+            return ca, co
+        if self.kind == KIND_KH:
+            s = np.empty(npairs, np.uint32)
+            lib.or_kh_counts(self.size, _ptr(self.sig, ctypes.c_uint32), npairs, pu, pv, _ptr(s, ctypes.c_uint32))
+            return s
+        su = np.empty(npairs, np.uint32)
+        kp = np.empty(npairs, np.uint32)
+        sl = np.empty(npairs, np.uint32)
+        lib.or_1h_counts(self.size, self.seed & (2**64 - 1), _ptr(self.sig, ctypes.c_uint32), npairs, pu, pv,
+                         _ptr(su, ctypes.c_uint32), _ptr(kp, ctypes.c_uint32), _ptr(sl, ctypes.c_uint32))
+        return su, kp, sl
+
+    def estimate(self, u, v, est: str) -> np.ndarray:
+        """FP64 estimate of |N_u cap N_v| per pair."""
+        u, v = _i32(u), _i32(v)
+        du, dv = self.deg[u], self.deg[v]
+        if self.kind == KIND_BF:
+            ca, co = self.counts(u, v)
+            B, b = self.size, self.b
+            if est == "and":
+                return est_bf_and(ca, B, b)
+            if est == "l":
+                return est_bf_limit(ca, B, b)
+            if est == "pap":
+                return est_bf_papapetrou(ca, B, b)
+            if est == "or":
+                return est_bf_or(co, du, dv, B, b)
+            raise ValueError(f"estimator {est} does not apply to Bloom filters")
+        if self.kind == KIND_KH:
+            if est != "kh":
+                raise ValueError(f"estimator {est} does not apply to k-hash sketches")
+            return est_minhash(self.counts(u, v), self.size, du, dv)
+        if est == "1h":
+            su, kp, _ = self.counts(u, v)
+            return est_minhash(su, kp, du, dv)
+        if est == "1h_lit":
+            _, _, sl = self.counts(u, v)
+            return est_minhash(sl, self.size, du, dv)
+        raise ValueError(f"estimator {est} does not apply to 1-hash sketches")
+
+
+def build_sketches(g, kind: int, size: int, b: int = 1, seed: int = 1) -> Sketches:
+    lib = _load()
+    off, adj = _i32(g.offsets), _i32(g.adj)
+    po, pa = _ptr(off, ctypes.c_int32), _ptr(adj, ctypes.c_int32)
+    sk = Sketches(g, kind, size, b if kind == KIND_BF else 1, seed, deg=g.degrees())
+    s64 = seed & (2**64 - 1)
+    if kind == KIND_BF:
+        if size % 64 or size <= 0:
+            raise ValueError("Bloom-filter size must be a positive multiple of 64 bits")
+        sk.words = np.zeros((g.n, size // 64), dtype=np.uint64)
+        sk.pc = np.zeros(g.n, dtype=np.uint32)
+        lib.or_bf_build(g.n, po, pa, size, b, s64, _ptr(sk.words, ctypes.c_uint64), _ptr(sk.pc, ctypes.c_uint32))
+    elif kind == KIND_KH:
+        sk.sig = np.zeros((g.n, size), dtype=np.uint32)
+        lib.or_kh_build(g.n, po, pa, size, s64, _ptr(sk.sig, ctypes.c_uint32))
+    elif kind == KIND_1H:
+        sk.sig = np.zeros((g.n, size), dtype=np.uint32)
+        lib.or_1h_build(g.n, po, pa, size, s64, _ptr(sk.sig, ctypes.c_uint32))
+    else:
+        raise ValueError("unknown sketch kind")
+    return sk
+
+
+def bf_of_set(xs, B: int, b: int, seed: int) -> np.ndarray:
+    xs = _i32(xs)
+    w = np.zeros(B // 64, dtype=np.uint64)
+    _load().or_bf_of_set(xs.shape[0], _ptr(xs, ctypes.c_int32), B, b, seed & (2**64 - 1), _ptr(w, ctypes.c_uint64))
+    return w
+
+
+# ---------------------------------------------------------------- algorithms
+
+def tc(sk: Sketches, est: str) -> float:
+    """TC^ = (1/3) * sum over the m edges of the estimate (Section 7)."""
+    eu, ev = upper_edges(sk.g)
+    return float(np.sum(sk.estimate(eu, ev, est)) / 3.0)
+
+
+def cc(sk: Sketches, est: str) -> np.ndarray:
+    """Estimated local clustering coefficient: the exact formula with the
+    estimate in place of |N_u cap N_v| for every arc."""
+    au, av = arcs(sk.g)
+    return local_cc_from_arc_values(sk.g, sk.estimate(au, av, est))
+
+
+def jaccard(sk: Sketches, est: str, u, v) -> np.ndarray:
+    """Estimated Jaccard similarity (Listing "lst:sim") per pair."""
+    u, v = _i32(u), _i32(v)
+    return jaccard_from_intersection(sk.deg[u], sk.deg[v], sk.estimate(u, v, est))
+
+
+def bits_for_budget(g, s: float) -> int:
+    """Bloom-filter size for storage budget s (Section 5.1): the largest
+    multiple of 64 bits with n * B <= s * 8 * CSR bytes, at least 64."""
+    csr_bytes = 4 * (g.n + 1) + 4 * g.nnz
+    return max(64, 64 * int(s * 8 * csr_bytes // (64 * g.n)))
