@@ -1,0 +1,180 @@
+/*
+ * probgraph.h -- C ABI of the ProbGraph GPU library (MI355X / gfx950).
+ *
+ * ProbGraph (Besta et al., SC22) replaces the exact neighbourhood
+ * intersections |N_u cap N_v| of graph-mining kernels by estimates computed
+ * from fixed-size per-vertex sketches (Section 5, usage example Listing
+ * "lst:example"): the caller (1) builds probabilistic representations of all
+ * neighbourhoods -- Bloom filters, k-hash or 1-hash MinHash -- and (2) asks
+ * for intersection estimates, from which triangle count, clustering
+ * coefficients and Jaccard similarities follow.
+ *
+ * Conventions for every call below:
+ *   - Pure C99 interface: only <stdint.h>/<stddef.h> types and opaque handles.
+ *   - Return value: PG_OK (0) or a negative PG_E_* code; no call throws or
+ *     aborts. pg_last_error() returns a thread-local description of the last
+ *     failure on the calling thread.
+ *   - Pointers to arrays are DEVICE pointers (memory of the context's GPU)
+ *     unless the description says "host". Output buffers are owned and
+ *     allocated by the caller; handles are owned by the library and freed by
+ *     their *_destroy call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *     stream). Calls enqueue their work on it and return without waiting,
+ *     except calls that return a scalar through a host pointer, which wait for
+ *     the stream before returning.
+ *   - A pg_ctx and the handles made from it may be used by one host thread at
+ *     a time; separate contexts are independent.
+ *   - Vertex IDs are int32 in [0, n). Graphs are undirected CSR: offsets[n+1]
+ *     and adj[nnz], each N_v = adj[offsets[v] .. offsets[v+1]) sorted
+ *     ascending, symmetric, with no duplicates and no self-loops (Section 2.1).
+ */
+#ifndef PROBGRAPH_H
+#define PROBGRAPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes -------------------------------------------------------- */
+#define PG_OK 0
+#define PG_E_INVALID (-1)     /* bad argument: NULL, range, size, kind/estimator mismatch */
+#define PG_E_GRAPH (-2)       /* CSR rejected by PG_VALIDATE (unsorted, duplicate, self-loop, asymmetric, out of range) */
+#define PG_E_NOMEM (-3)       /* device or host allocation failed */
+#define PG_E_DEVICE (-4)      /* a HIP runtime call failed */
+#define PG_E_UNSUPPORTED (-5) /* valid request this build does not implement */
+#define PG_E_BUSY (-6)        /* serving: request not admitted yet (no slot or memory) */
+
+/* ---- sketch kinds (Section 2.4) ----------------------------------------- */
+#define PG_BF 1        /* Bloom filter of B bits with b hash functions */
+#define PG_MH_KHASH 2  /* k-hash MinHash: k minima of k hash functions */
+#define PG_MH_1HASH 3  /* 1-hash MinHash: k smallest elements under one hash */
+
+/* ---- estimators of |X cap Y| --------------------------------------------- */
+#define PG_EST_BF_AND 1           /* -(B/b) ln(1 - c~/B), c = ones(B_X AND B_Y): Eq. "bf_int", divergence fix of Appendix C */
+#define PG_EST_BF_L 2             /* c / b: Eq. "limit_xs" */
+#define PG_EST_BF_OR 3            /* |X| + |Y| + (B/b) ln(1 - c~_or/B), c_or = ones(B_X OR B_Y): Eq. "bf_int_union" */
+#define PG_EST_BF_PAPAPETROU 4    /* ln(1 - c~/B) / (b ln(1 - 1/B)) on the AND (Section 8.1) */
+#define PG_EST_MH_KHASH 5         /* s = #positions i with M_X[i] = M_Y[i]; J = s/k; I = J/(1+J)(|X|+|Y|): Eq. "est_int_mh" */
+#define PG_EST_MH_1HASH 6         /* s = |U cap M_X cap M_Y|, U = bottom-k' of M_X u M_Y, k' = min(k, |M_X u M_Y|); J = s/k' (Section 4.4) */
+#define PG_EST_MH_1HASH_LITERAL 7 /* s = |M_X cap M_Y|, J = s/k (Section 4.4, as printed) */
+
+/* ---- graph flags -------------------------------------------------------- */
+#define PG_MEM_HOST 0u   /* offsets/adj are host pointers (copied to the device) */
+#define PG_MEM_DEVICE 1u /* offsets/adj are device pointers */
+#define PG_BORROW 2u     /* with PG_MEM_DEVICE: use the caller's arrays in place; they must outlive the graph */
+#define PG_VALIDATE 4u   /* check the CSR invariants on the device; PG_E_GRAPH if violated */
+
+/* ---- exact baselines ---------------------------------------------------- */
+#define PG_EXACT_MERGE 1  /* sorted-list intersection: binary search of the shorter list in the longer (Fig. 1, Table "tab:queries-int") */
+#define PG_EXACT_BITMAP 2 /* per-vertex bitmap of N_v in on-chip memory, probed by the other list */
+
+typedef struct pg_ctx pg_ctx;
+typedef struct pg_graph pg_graph;
+typedef struct pg_sketches pg_sketches;
+
+typedef struct pg_graph_info {
+  int32_t n;          /* vertices */
+  int32_t max_degree; /* d */
+  int64_t nnz;        /* arcs = 2m */
+  int64_t m;          /* undirected edges */
+} pg_graph_info;
+
+typedef struct pg_sketch_info {
+  int32_t kind;          /* PG_BF, PG_MH_KHASH, PG_MH_1HASH */
+  uint32_t size;         /* B (bits) for PG_BF, k for MinHash */
+  uint32_t b;            /* hash functions per Bloom filter (1 for MinHash) */
+  uint32_t row_bytes;    /* bytes per vertex row: B/8, or 4k */
+  uint64_t seed;         /* seed the hash constants were drawn from */
+  uint64_t total_bytes;  /* device bytes held (rows + per-vertex popcounts) */
+} pg_sketch_info;
+
+/* Thread-local text of the last error ("" if none). Never NULL. */
+const char* pg_last_error(void);
+
+/* Library version string. */
+const char* pg_version(void);
+
+/* Context on GPU `device`. *out receives the handle. */
+int pg_ctx_create(int device, pg_ctx** out);
+int pg_ctx_destroy(pg_ctx* ctx);
+
+/* Device-resident CSR graph (Section 2.1) plus the derived arrays every later
+ * call uses: degrees and the m undirected edges (v, u), v < u, in CSR order
+ * ("upper edges"). With PG_MEM_HOST the arrays are copied; with PG_MEM_DEVICE
+ * they are copied unless PG_BORROW. Waits for `stream`. Destroying a graph
+ * while sketches built on it are alive fails with PG_E_INVALID. */
+int pg_graph_create(pg_ctx* ctx, int32_t n, int64_t nnz, const int32_t* offsets, const int32_t* adj,
+                    uint32_t flags, void* stream, pg_graph** out);
+int pg_graph_destroy(pg_graph* g);
+int pg_graph_get_info(const pg_graph* g, pg_graph_info* out /* host */);
+/* Copy the upper edges into eu[m], ev[m] (device). */
+int pg_graph_upper_edges(const pg_graph* g, int32_t* eu, int32_t* ev, void* stream);
+
+/* Bloom-filter size for storage budget s in (0, 1] (Section 5.1): the largest
+ * multiple of 64 bits B with n*B <= s * 8 * CSR bytes, CSR bytes =
+ * 4(n+1) + 4 nnz; at least 64. *bits is a host pointer. */
+int pg_sketch_bits_for_budget(const pg_graph* g, double s, uint32_t* bits);
+
+/* Build one sketch per vertex (Section 2.4, construction costs Table
+ * "tab:constr").
+ *   kind PG_BF:       size = B bits, a multiple of 64 in [64, 4096]; b in [1, 16].
+ *   kind PG_MH_KHASH: size = k in [1, 1024]; b ignored.
+ *   kind PG_MH_1HASH: size = k in [1, 1024]; b ignored.
+ * Hash constants are drawn from `seed` with SplitMix64 (see the design notes
+ * shipped with the library); equal (graph, kind, size, b, seed) give
+ * bit-identical sketches. Device layout: BF rows of B/64 uint64 words, bit i
+ * of the filter = bit (i & 63) of word (i >> 6); MinHash rows of k uint32
+ * vertex IDs (0xFFFFFFFF = empty slot), 1-hash rows in ascending hash order. */
+int pg_build_sketches(pg_ctx* ctx, const pg_graph* g, int kind, uint32_t size, uint32_t b, uint64_t seed,
+                      void* stream, pg_sketches** out);
+int pg_sketches_destroy(pg_sketches* sk);
+int pg_sketches_get_info(const pg_sketches* sk, pg_sketch_info* out /* host */);
+/* Copy the rows (n * row_bytes bytes) and, for PG_BF, the per-vertex
+ * popcounts (pc[n]) into caller device buffers; either may be NULL. */
+int pg_sketches_export(const pg_sketches* sk, void* rows, uint32_t* pc, void* stream);
+
+/* Estimate |N_u cap N_v| for npairs pairs (u[i], v[i]); u = v = NULL means the
+ * graph's m upper edges in CSR order (npairs ignored). est (FP64) and raw
+ * (the integer count the estimator consumes: c, c_or or s) may each be NULL.
+ * The estimator must match the sketch kind. */
+int pg_intersect_edges(pg_ctx* ctx, const pg_sketches* sk, int estimator, const int32_t* u, const int32_t* v,
+                       int64_t npairs, double* est, uint32_t* raw, void* stream);
+
+/* Estimated triangle count TC^ = (1/3) sum over the m edges of the estimate
+ * (Section 7). *tc is a host pointer; waits for `stream`. */
+int pg_tc(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* tc, void* stream);
+
+/* Estimated local clustering coefficient cc[n] (device, FP32 rounded once
+ * from FP64): cc_v = sum_{u in N_v} I^(u,v) / (d_v (d_v - 1)), 0 if d_v < 2.
+ * If transitivity (host) is not NULL it receives 3 TC^ / sum_v C(d_v, 2) and
+ * the call waits for `stream`. */
+int pg_cc(pg_ctx* ctx, const pg_sketches* sk, int estimator, float* cc, double* transitivity, void* stream);
+
+/* Estimated Jaccard similarity per pair (Listing "lst:sim"):
+ * J = I_c / (d_u + d_v - I_c), I_c = the estimate clamped to [0, min(d_u, d_v)];
+ * 0 when d_u + d_v = 0. u = v = NULL means the m upper edges. out: FP32. */
+int pg_jaccard(pg_ctx* ctx, const pg_sketches* sk, int estimator, const int32_t* u, const int32_t* v,
+               int64_t npairs, float* out, void* stream);
+
+/* ---- exact baselines on the same graph ---------------------------------- */
+/* Exact |N_u cap N_v| per pair (u = v = NULL: the m upper edges). */
+int pg_exact_intersect_edges(pg_ctx* ctx, const pg_graph* g, int algo, const int32_t* u, const int32_t* v,
+                             int64_t npairs, uint32_t* out, void* stream);
+/* Exact triangle count by the degree-ordered node iterator (Listing
+ * "lst:tc"): orient every edge towards the endpoint of larger (degree, ID)
+ * and sum |N+_v cap N+_u| over the oriented edges. *tc host; waits. */
+int pg_exact_tc(pg_ctx* ctx, const pg_graph* g, int algo, uint64_t* tc, void* stream);
+/* Exact local clustering coefficient (FP32) and, optionally, transitivity (host; waits). */
+int pg_exact_cc(pg_ctx* ctx, const pg_graph* g, float* cc, double* transitivity, void* stream);
+/* Exact Jaccard similarity per pair (FP32); u = v = NULL: the m upper edges. */
+int pg_exact_jaccard(pg_ctx* ctx, const pg_graph* g, const int32_t* u, const int32_t* v, int64_t npairs,
+                     float* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROBGRAPH_H */

@@ -360,3 +360,19 @@ def bits_for_budget(g, s: float) -> int:
     multiple of 64 bits with n * B <= s * 8 * CSR bytes, at least 64."""
     csr_bytes = 4 * (g.n + 1) + 4 * g.nnz
     return max(64, 64 * int(s * 8 * csr_bytes // (64 * g.n)))
+
+
+def sketch_rows(g, verts, kind: int, size: int, b: int = 1, seed: int = 1) -> Sketches:
+    """Sketches of the listed vertices only: row i is the sketch of N_{verts[i]},
+    by the same definition as ``build_sketches`` (used to check samples of a
+    large graph). ``deg`` holds the degrees of the listed vertices."""
+    import types
+    verts = np.asarray(verts, dtype=np.int64)
+    lens = g.degrees()[verts]
+    off = np.zeros(len(verts) + 1, dtype=np.int32)
+    off[1:] = np.cumsum(lens)
+    parts = [g.adj[g.offsets[v]:g.offsets[v + 1]] for v in verts]
+    adj = np.concatenate(parts).astype(np.int32) if parts else np.zeros(0, np.int32)
+    sub = types.SimpleNamespace(n=len(verts), offsets=off, adj=adj, nnz=int(adj.shape[0]),
+                                degrees=lambda: lens.astype(np.int64))
+    return build_sketches(sub, kind, size, b, seed)

@@ -1,0 +1,442 @@
+"""ProbGraph on MI355X: a thin ctypes binding over ``libprobgraph.so``.
+
+The functions named ``pg_*`` mirror the C ABI in ``include/probgraph.h`` one to
+one (argument marshalling only: every step runs in the library's HIP kernels).
+``Context``, ``Graph`` and ``Sketches`` wrap the handles for convenience.
+Device buffers are torch tensors on the context's GPU; streams default to
+torch's current stream. There is no CPU fallback: if the library is not built
+or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libprobgraph.so")
+
+# return codes
+PG_OK = 0
+PG_E_INVALID = -1
+PG_E_GRAPH = -2
+PG_E_NOMEM = -3
+PG_E_DEVICE = -4
+PG_E_UNSUPPORTED = -5
+PG_E_BUSY = -6
+# sketch kinds
+PG_BF = 1
+PG_MH_KHASH = 2
+PG_MH_1HASH = 3
+# estimators
+PG_EST_BF_AND = 1
+PG_EST_BF_L = 2
+PG_EST_BF_OR = 3
+PG_EST_BF_PAPAPETROU = 4
+PG_EST_MH_KHASH = 5
+PG_EST_MH_1HASH = 6
+PG_EST_MH_1HASH_LITERAL = 7
+# graph flags
+PG_MEM_HOST = 0
+PG_MEM_DEVICE = 1
+PG_BORROW = 2
+PG_VALIDATE = 4
+# exact algorithms
+PG_EXACT_MERGE = 1
+PG_EXACT_BITMAP = 2
+
+ESTIMATORS = {
+    "and": PG_EST_BF_AND, "l": PG_EST_BF_L, "or": PG_EST_BF_OR, "pap": PG_EST_BF_PAPAPETROU,
+    "kh": PG_EST_MH_KHASH, "1h": PG_EST_MH_1HASH, "1h_lit": PG_EST_MH_1HASH_LITERAL,
+}
+KINDS = {"bf": PG_BF, "kh": PG_MH_KHASH, "1h": PG_MH_1HASH}
+
+
+class PGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"probgraph error {code}: {msg}")
+        self.code = code
+
+
+class _GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("max_degree", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("m", ctypes.c_int64)]
+
+
+class _SketchInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("size", ctypes.c_uint32), ("b", ctypes.c_uint32),
+                ("row_bytes", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def _declare(lib):
+    P = ctypes.POINTER
+    i32, i64, u32, u64, i = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    sigs = {
+        "pg_last_error": (ctypes.c_char_p, []),
+        "pg_version": (ctypes.c_char_p, []),
+        "pg_ctx_create": (i, [i, P(_vp)]),
+        "pg_ctx_destroy": (i, [_vp]),
+        "pg_graph_create": (i, [_vp, i32, i64, _vp, _vp, u32, _vp, P(_vp)]),
+        "pg_graph_destroy": (i, [_vp]),
+        "pg_graph_get_info": (i, [_vp, P(_GraphInfo)]),
+        "pg_graph_upper_edges": (i, [_vp, _vp, _vp, _vp]),
+        "pg_sketch_bits_for_budget": (i, [_vp, ctypes.c_double, P(u32)]),
+        "pg_build_sketches": (i, [_vp, _vp, i, u32, u32, u64, _vp, P(_vp)]),
+        "pg_sketches_destroy": (i, [_vp]),
+        "pg_sketches_get_info": (i, [_vp, P(_SketchInfo)]),
+        "pg_sketches_export": (i, [_vp, _vp, _vp, _vp]),
+        "pg_intersect_edges": (i, [_vp, _vp, i, _vp, _vp, i64, _vp, _vp, _vp]),
+        "pg_tc": (i, [_vp, _vp, i, P(ctypes.c_double), _vp]),
+        "pg_cc": (i, [_vp, _vp, i, _vp, P(ctypes.c_double), _vp]),
+        "pg_jaccard": (i, [_vp, _vp, i, _vp, _vp, i64, _vp, _vp]),
+        "pg_exact_intersect_edges": (i, [_vp, _vp, i, _vp, _vp, i64, _vp, _vp]),
+        "pg_exact_tc": (i, [_vp, _vp, i, P(u64), _vp]),
+        "pg_exact_cc": (i, [_vp, _vp, _vp, P(ctypes.c_double), _vp]),
+        "pg_exact_jaccard": (i, [_vp, _vp, _vp, _vp, i64, _vp, _vp]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return list(sigs)
+
+
+EXPORTED = None
+
+
+def load():
+    """Load the built library (raises if it was not built)."""
+    global _lib, EXPORTED
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2208_11469_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    EXPORTED = _declare(lib)
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != PG_OK:
+        raise PGError(rc, load().pg_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dptr(t, dtype=None):
+    """Device pointer of a contiguous CUDA tensor (or None)."""
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device (cuda) tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+# ---- the C ABI, one wrapper per call ------------------------------------------------
+
+def pg_version() -> str:
+    return load().pg_version().decode()
+
+
+def pg_last_error() -> str:
+    return load().pg_last_error().decode()
+
+
+def pg_ctx_create(device: int = 0):
+    h = _vp()
+    _check(load().pg_ctx_create(device, ctypes.byref(h)))
+    return h
+
+
+def pg_ctx_destroy(ctx):
+    _check(load().pg_ctx_destroy(ctx))
+
+
+def pg_graph_create(ctx, n, nnz, offsets_ptr, adj_ptr, flags, stream=None):
+    h = _vp()
+    _check(load().pg_graph_create(ctx, n, nnz, offsets_ptr, adj_ptr, flags, _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def pg_graph_destroy(g):
+    _check(load().pg_graph_destroy(g))
+
+
+def pg_graph_get_info(g) -> _GraphInfo:
+    info = _GraphInfo()
+    _check(load().pg_graph_get_info(g, ctypes.byref(info)))
+    return info
+
+
+def pg_graph_upper_edges(g, eu, ev, stream=None):
+    torch = _torch()
+    _check(load().pg_graph_upper_edges(g, _dptr(eu, torch.int32), _dptr(ev, torch.int32), _stream(stream)))
+
+
+def pg_sketch_bits_for_budget(g, s: float) -> int:
+    bits = ctypes.c_uint32()
+    _check(load().pg_sketch_bits_for_budget(g, s, ctypes.byref(bits)))
+    return int(bits.value)
+
+
+def pg_build_sketches(ctx, g, kind, size, b, seed, stream=None):
+    h = _vp()
+    _check(load().pg_build_sketches(ctx, g, kind, size, b, seed & (2**64 - 1), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def pg_sketches_destroy(sk):
+    _check(load().pg_sketches_destroy(sk))
+
+
+def pg_sketches_get_info(sk) -> _SketchInfo:
+    info = _SketchInfo()
+    _check(load().pg_sketches_get_info(sk, ctypes.byref(info)))
+    return info
+
+
+def pg_sketches_export(sk, rows, pc, stream=None):
+    _check(load().pg_sketches_export(sk, _dptr(rows), _dptr(pc), _stream(stream)))
+
+
+def pg_intersect_edges(ctx, sk, estimator, u, v, npairs, est, raw, stream=None):
+    _check(load().pg_intersect_edges(ctx, sk, estimator, _dptr(u), _dptr(v), npairs, _dptr(est), _dptr(raw),
+                                     _stream(stream)))
+
+
+def pg_tc(ctx, sk, estimator, stream=None) -> float:
+    out = ctypes.c_double()
+    _check(load().pg_tc(ctx, sk, estimator, ctypes.byref(out), _stream(stream)))
+    return float(out.value)
+
+
+def pg_cc(ctx, sk, estimator, cc, want_transitivity=False, stream=None):
+    t = ctypes.c_double()
+    _check(load().pg_cc(ctx, sk, estimator, _dptr(cc), ctypes.byref(t) if want_transitivity else None,
+                        _stream(stream)))
+    return float(t.value) if want_transitivity else None
+
+
+def pg_jaccard(ctx, sk, estimator, u, v, npairs, out, stream=None):
+    _check(load().pg_jaccard(ctx, sk, estimator, _dptr(u), _dptr(v), npairs, _dptr(out), _stream(stream)))
+
+
+def pg_exact_intersect_edges(ctx, g, algo, u, v, npairs, out, stream=None):
+    _check(load().pg_exact_intersect_edges(ctx, g, algo, _dptr(u), _dptr(v), npairs, _dptr(out), _stream(stream)))
+
+
+def pg_exact_tc(ctx, g, algo, stream=None) -> int:
+    out = ctypes.c_uint64()
+    _check(load().pg_exact_tc(ctx, g, algo, ctypes.byref(out), _stream(stream)))
+    return int(out.value)
+
+
+def pg_exact_cc(ctx, g, cc, want_transitivity=False, stream=None):
+    t = ctypes.c_double()
+    _check(load().pg_exact_cc(ctx, g, _dptr(cc), ctypes.byref(t) if want_transitivity else None, _stream(stream)))
+    return float(t.value) if want_transitivity else None
+
+
+def pg_exact_jaccard(ctx, g, u, v, npairs, out, stream=None):
+    _check(load().pg_exact_jaccard(ctx, g, _dptr(u), _dptr(v), npairs, _dptr(out), _stream(stream)))
+
+
+# ---- handle classes ---------------------------------------------------------------
+
+def _pairs(u, v):
+    """Explicit pair lists as contiguous int32 tensors. (None, None) selects the
+    graph's upper edges. An empty explicit list is returned as-is: callers must
+    not pass it to the C ABI, where a NULL pointer (an empty tensor's data
+    pointer) means "all upper edges"."""
+    torch = _torch()
+    if u is None and v is None:
+        return None, None, 0
+    if u is None or v is None:
+        raise ValueError("give both u and v, or neither")
+    if u.shape != v.shape:
+        raise ValueError("u and v differ in length")
+    return u.to(torch.int32).contiguous(), v.to(torch.int32).contiguous(), int(u.shape[0])
+
+
+def _is_empty_explicit(u):
+    return u is not None and u.shape[0] == 0
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.h = pg_ctx_create(device)
+
+    def close(self):
+        if self.h:
+            pg_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A device-resident CSR graph. ``offsets``/``adj`` may be numpy arrays
+    (copied from the host) or int32 device tensors (copied, or borrowed)."""
+
+    def __init__(self, ctx: Context, offsets, adj, validate: bool = False, borrow: bool = False, stream=None):
+        torch = _torch()
+        self.ctx = ctx
+        flags = PG_VALIDATE if validate else 0
+        if isinstance(offsets, np.ndarray):
+            off = np.ascontiguousarray(offsets, dtype=np.int32)
+            ad = np.ascontiguousarray(adj, dtype=np.int32)
+            n, nnz = off.shape[0] - 1, ad.shape[0]
+            self._keep = (off, ad)
+            po = off.ctypes.data
+            pa = ad.ctypes.data if nnz else None
+        else:
+            off = offsets.to(torch.int32).contiguous()
+            ad = adj.to(torch.int32).contiguous()
+            n, nnz = off.shape[0] - 1, ad.shape[0]
+            flags |= PG_MEM_DEVICE | (PG_BORROW if borrow else 0)
+            self._keep = (off, ad)
+            po, pa = off.data_ptr(), (ad.data_ptr() if nnz else None)
+        self.h = pg_graph_create(ctx.h, n, nnz, po, pa, flags, stream)
+        info = pg_graph_get_info(self.h)
+        self.n, self.nnz, self.m, self.max_degree = info.n, info.nnz, info.m, info.max_degree
+
+    def close(self):
+        if self.h:
+            pg_graph_destroy(self.h)
+            self.h = None
+
+    def upper_edges(self, stream=None):
+        torch = _torch()
+        dev = torch.device("cuda", self.ctx.device)
+        eu = torch.empty(max(self.m, 1), dtype=torch.int32, device=dev)[: self.m]
+        ev = torch.empty(max(self.m, 1), dtype=torch.int32, device=dev)[: self.m]
+        if self.m:
+            pg_graph_upper_edges(self.h, eu, ev, stream)
+        return eu, ev
+
+    def bits_for_budget(self, s: float) -> int:
+        return pg_sketch_bits_for_budget(self.h, s)
+
+    def build_sketches(self, kind, size: int, b: int = 1, seed: int = 1, stream=None) -> "Sketches":
+        kind = KINDS.get(kind, kind)
+        return Sketches(self, pg_build_sketches(self.ctx.h, self.h, kind, size, b, seed, stream))
+
+    def _dev(self):
+        return _torch().device("cuda", self.ctx.device)
+
+    def exact_intersect(self, u=None, v=None, algo=PG_EXACT_MERGE, stream=None):
+        torch = _torch()
+        u, v, npairs = _pairs(u, v)
+        count = self.m if u is None else npairs
+        out = torch.empty(max(count, 1), dtype=torch.int32, device=self._dev())[:count]
+        if _is_empty_explicit(u):
+            return out
+        pg_exact_intersect_edges(self.ctx.h, self.h, algo, u, v, npairs, out if count else None, stream)
+        return out
+
+    def exact_tc(self, algo=PG_EXACT_MERGE, stream=None) -> int:
+        return pg_exact_tc(self.ctx.h, self.h, algo, stream)
+
+    def exact_cc(self, transitivity=False, stream=None):
+        torch = _torch()
+        cc = torch.empty(max(self.n, 1), dtype=torch.float32, device=self._dev())[: self.n]
+        t = pg_exact_cc(self.ctx.h, self.h, cc, transitivity, stream)
+        return (cc, t) if transitivity else cc
+
+    def exact_jaccard(self, u=None, v=None, stream=None):
+        torch = _torch()
+        u, v, npairs = _pairs(u, v)
+        count = self.m if u is None else npairs
+        out = torch.empty(max(count, 1), dtype=torch.float32, device=self._dev())[:count]
+        if _is_empty_explicit(u):
+            return out
+        pg_exact_jaccard(self.ctx.h, self.h, u, v, npairs, out, stream)
+        return out
+
+
+class Sketches:
+    def __init__(self, graph: Graph, h):
+        self.graph = graph
+        self.h = h
+        info = pg_sketches_get_info(h)
+        self.kind, self.size, self.b, self.row_bytes = info.kind, info.size, info.b, info.row_bytes
+        self.seed, self.total_bytes = info.seed, info.total_bytes
+
+    def close(self):
+        if self.h:
+            pg_sketches_destroy(self.h)
+            self.h = None
+
+    def export(self, stream=None):
+        """(rows, pc): rows as uint8 [n, row_bytes] device tensor; pc int32 [n] or None."""
+        torch = _torch()
+        n = self.graph.n
+        dev = self.graph._dev()
+        rows = torch.empty((max(n, 1), self.row_bytes), dtype=torch.uint8, device=dev)[:n]
+        pc = torch.empty(max(n, 1), dtype=torch.int32, device=dev)[:n] if self.kind == PG_BF else None
+        if n:
+            pg_sketches_export(self.h, rows, pc, stream)
+        return rows, pc
+
+    def intersect(self, estimator, u=None, v=None, want_est=True, want_raw=True, stream=None):
+        torch = _torch()
+        est_id = ESTIMATORS.get(estimator, estimator)
+        u, v, npairs = _pairs(u, v)
+        count = self.graph.m if u is None else npairs
+        dev = self.graph._dev()
+        est = torch.empty(max(count, 1), dtype=torch.float64, device=dev)[:count] if want_est else None
+        raw = torch.empty(max(count, 1), dtype=torch.int32, device=dev)[:count] if want_raw else None
+        if _is_empty_explicit(u):
+            return est, raw
+        pg_intersect_edges(self.graph.ctx.h, self.h, est_id, u, v, npairs, est if count else None,
+                           raw if count else None, stream)
+        return est, raw
+
+    def tc(self, estimator, stream=None) -> float:
+        return pg_tc(self.graph.ctx.h, self.h, ESTIMATORS.get(estimator, estimator), stream)
+
+    def cc(self, estimator, transitivity=False, stream=None):
+        torch = _torch()
+        n = self.graph.n
+        cc = torch.empty(max(n, 1), dtype=torch.float32, device=self.graph._dev())[:n]
+        t = pg_cc(self.graph.ctx.h, self.h, ESTIMATORS.get(estimator, estimator), cc, transitivity, stream)
+        return (cc, t) if transitivity else cc
+
+    def jaccard(self, estimator, u=None, v=None, stream=None):
+        torch = _torch()
+        u, v, npairs = _pairs(u, v)
+        count = self.graph.m if u is None else npairs
+        out = torch.empty(max(count, 1), dtype=torch.float32, device=self.graph._dev())[:count]
+        if _is_empty_explicit(u):
+            return out
+        pg_jaccard(self.graph.ctx.h, self.h, ESTIMATORS.get(estimator, estimator), u, v, npairs,
+                   out if count else None, stream)
+        return out

@@ -1,0 +1,405 @@
+// Sketch construction (Section 2.4; work and depth in Table "tab:constr").
+//
+// Bloom filter: every element x of N_v sets bit idx_i(x) for each of b hash
+// functions. k-hash: for each hash function i, the element of N_v with the
+// smallest key_i. 1-hash: the min(k, d_v) elements of N_v with the smallest
+// key, in ascending key order.
+//
+// Vertices are processed in degree bins (a group of G lanes per vertex, G
+// growing with the degree). Inside a group every lane builds a private
+// partial sketch over a strided slice of N_v in registers; the partials are
+// combined by a fixed butterfly (OR for filters, lexicographic (key, ID)
+// minimum for k-hash). No global or LDS atomics are involved, so the result
+// is independent of scheduling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "pg_device.h"
+#include "pg_internal.h"
+
+namespace pg {
+namespace {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------- Bloom filter
+
+template <int WMAX, int G>
+__global__ __launch_bounds__(kBlock) void k_bf_build(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
+                                                     const int32_t* __restrict__ verts, int64_t nverts, uint32_t B,
+                                                     uint32_t W, uint32_t b, const uint64_t* __restrict__ ha,
+                                                     const uint64_t* __restrict__ hc, uint64_t* __restrict__ words,
+                                                     uint32_t* __restrict__ pc) {
+  __shared__ uint64_t lds[(G > kWave) ? (kBlock / kWave) * WMAX : 1];
+  const int64_t grp = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  const bool active = grp < nverts;
+  const int32_t v = active ? verts[grp] : 0;
+  const int64_t beg = active ? off[v] : 0;
+  const int64_t end = active ? off[v + 1] : 0;
+  uint64_t bm[WMAX];
+#pragma unroll
+  for (int j = 0; j < WMAX; ++j) bm[j] = 0;
+  for (int64_t p = beg + lane; p < end; p += G) {
+    const uint32_t x = (uint32_t)adj[p];
+    for (uint32_t i = 0; i < b; ++i) {
+      const uint32_t idx = bf_index(ha[i], hc[i], x, B);
+      const uint32_t w = idx >> 6;
+      const uint64_t bit = 1ull << (idx & 63u);
+#pragma unroll
+      for (int j = 0; j < WMAX; ++j) bm[j] |= ((uint32_t)j == w) ? bit : 0ull;
+    }
+  }
+  if constexpr (G <= kWave) {
+#pragma unroll
+    for (int j = 0; j < WMAX; ++j) bm[j] = group_or<G>(bm[j]);
+  } else {
+    // one vertex per block: OR inside each wave, then the four waves in order
+#pragma unroll
+    for (int j = 0; j < WMAX; ++j) bm[j] = group_or<kWave>(bm[j]);
+    const int wv = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+#pragma unroll
+      for (int j = 0; j < WMAX; ++j) lds[wv * WMAX + j] = bm[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < WMAX; ++j) bm[j] = lds[j] | lds[WMAX + j] | lds[2 * WMAX + j] | lds[3 * WMAX + j];
+  }
+  if (!active) return;
+  uint64_t* row = words + (size_t)v * W;
+#pragma unroll
+  for (int j = 0; j < WMAX; ++j)
+    if ((uint32_t)j < W && (j % G) == lane) row[j] = bm[j];
+  if (lane == 0) {
+    uint32_t ones = 0;
+#pragma unroll
+    for (int j = 0; j < WMAX; ++j) ones += (uint32_t)__popcll(bm[j]);
+    pc[v] = ones;
+  }
+}
+
+// Filters wider than 16 words: one wave per vertex, lane w owns word w
+// (W <= 64); every lane evaluates all hashes and keeps the bits of its word.
+__global__ __launch_bounds__(kBlock) void k_bf_build_wide(const int32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ adj, int32_t n, uint32_t B,
+                                                          uint32_t W, uint32_t b, const uint64_t* __restrict__ ha,
+                                                          const uint64_t* __restrict__ hc, uint64_t* __restrict__ words,
+                                                          uint32_t* __restrict__ pc) {
+  const int64_t v = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+  const int lane = lane_id();
+  if (v >= n) return;
+  uint64_t mine = 0;
+  for (int64_t p = off[v]; p < off[v + 1]; ++p) {
+    const uint32_t x = (uint32_t)adj[p];
+    for (uint32_t i = 0; i < b; ++i) {
+      const uint32_t idx = bf_index(ha[i], hc[i], x, B);
+      if ((idx >> 6) == (uint32_t)lane) mine |= 1ull << (idx & 63u);
+    }
+  }
+  if ((uint32_t)lane < W) words[(size_t)v * W + lane] = mine;
+  const uint32_t ones = group_sum_u32<kWave>((uint32_t)__popcll(mine));
+  if (lane == 0) pc[v] = ones;
+}
+
+// ---------------------------------------------------------------- k-hash
+
+constexpr int kKhBatch = 16;  // hash functions kept in registers at a time
+
+template <int G>
+__device__ __forceinline__ void min_pair_group(uint64_t& key, uint32_t& id) {
+#pragma unroll
+  for (int s = G / 2; s >= 1; s >>= 1) {
+    const uint64_t ok = __shfl_xor(key, s, G);
+    const uint32_t oi = __shfl_xor(id, s, G);
+    if (ok < key || (ok == key && oi < id)) {
+      key = ok;
+      id = oi;
+    }
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_kh_build(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
+                                                     const int32_t* __restrict__ verts, int64_t nverts, uint32_t k,
+                                                     const uint64_t* __restrict__ ha, const uint64_t* __restrict__ hc,
+                                                     uint32_t* __restrict__ sig) {
+  __shared__ uint64_t lkey[(G > kWave) ? (kBlock / kWave) * kKhBatch : 1];
+  __shared__ uint32_t lid[(G > kWave) ? (kBlock / kWave) * kKhBatch : 1];
+  const int64_t grp = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  const bool active = grp < nverts;
+  const int32_t v = active ? verts[grp] : 0;
+  const int64_t beg = active ? off[v] : 0;
+  const int64_t end = active ? off[v + 1] : 0;
+  for (uint32_t i0 = 0; i0 < k; i0 += kKhBatch) {
+    uint64_t best[kKhBatch];
+    uint32_t bid[kKhBatch];
+#pragma unroll
+    for (int j = 0; j < kKhBatch; ++j) {
+      best[j] = ~0ull;
+      bid[j] = kBottom;
+    }
+    for (int64_t p = beg + lane; p < end; p += G) {
+      const uint32_t x = (uint32_t)adj[p];
+#pragma unroll
+      for (int j = 0; j < kKhBatch; ++j) {
+        if (i0 + j < k) {
+          const uint64_t key = mh_key(ha[i0 + j], hc[i0 + j], x);
+          if (key < best[j] || (key == best[j] && x < bid[j])) {
+            best[j] = key;
+            bid[j] = x;
+          }
+        }
+      }
+    }
+    if constexpr (G <= kWave) {
+#pragma unroll
+      for (int j = 0; j < kKhBatch; ++j) min_pair_group<G>(best[j], bid[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kKhBatch; ++j) min_pair_group<kWave>(best[j], bid[j]);
+      const int wv = threadIdx.x / kWave;
+      if (lane_id() == 0) {
+#pragma unroll
+        for (int j = 0; j < kKhBatch; ++j) {
+          lkey[wv * kKhBatch + j] = best[j];
+          lid[wv * kKhBatch + j] = bid[j];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kKhBatch; ++j) {
+        uint64_t bk = lkey[j];
+        uint32_t bi = lid[j];
+        for (int w = 1; w < kBlock / kWave; ++w) {
+          const uint64_t ok = lkey[w * kKhBatch + j];
+          const uint32_t oi = lid[w * kKhBatch + j];
+          if (ok < bk || (ok == bk && oi < bi)) {
+            bk = ok;
+            bi = oi;
+          }
+        }
+        best[j] = bk;
+        bid[j] = bi;
+      }
+      __syncthreads();
+    }
+    if (active) {
+      uint32_t* row = sig + (size_t)v * k;
+#pragma unroll
+      for (int j = 0; j < kKhBatch; ++j)
+        if (i0 + j < k && (j % G) == lane) row[i0 + j] = bid[j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- 1-hash
+
+constexpr int kOhWaves = kBlock / kWave;
+
+// Shared bytes per wave: k keys (8 B) + k IDs (4 B) + 256 histogram bins,
+// rounded to 16 bytes so every wave's key array stays 8-byte aligned.
+__host__ __device__ constexpr size_t oh_wave_bytes(uint32_t k) { return (((size_t)k * 12 + 256 * 4) + 15) & ~(size_t)15; }
+
+// One wave per vertex. Shared memory per wave: keys and IDs of up to k
+// elements, plus a 256-bin digit histogram.
+__global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
+                                                     const int32_t* __restrict__ verts, int64_t nverts, uint32_t k,
+                                                     uint64_t a, uint64_t c, uint32_t* __restrict__ sig) {
+  extern __shared__ unsigned char smem[];
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  const size_t per_wave = oh_wave_bytes(k);
+  uint64_t* skey = (uint64_t*)(smem + wv * per_wave);
+  uint32_t* sid = (uint32_t*)(smem + wv * per_wave + (size_t)k * 8);
+  uint32_t* hist = (uint32_t*)(smem + wv * per_wave + (size_t)k * 12);
+  const int64_t grp = blockIdx.x * (int64_t)kOhWaves + wv;
+  if (grp >= nverts) return;
+  const int32_t v = verts[grp];
+  const int64_t beg = off[v], end = off[v + 1];
+  const int64_t d = end - beg;
+  uint32_t* row = sig + (size_t)v * k;
+  int64_t taken = 0;  // elements staged in skey/sid
+  if (d <= (int64_t)k) {
+    for (int64_t t = lane; t < d; t += kWave) {
+      const uint32_t x = (uint32_t)adj[beg + t];
+      skey[t] = mh_key(a, c, x);
+      sid[t] = x;
+    }
+    taken = d;
+  } else {
+    // radix select of the k-th smallest key, 8 bits at a time from the top
+    uint64_t prefix = 0, pmask = 0;
+    uint32_t want = k;  // rank (1-based) still wanted among keys matching the prefix
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      for (int i = lane; i < 256; i += kWave) hist[i] = 0;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      for (int64_t t = beg + lane; t < end; t += kWave) {
+        const uint64_t key = mh_key(a, c, (uint32_t)adj[t]);
+        if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // find the digit holding rank `want`: lane l scans bins 4l..4l+3
+      uint32_t local[4];
+      uint32_t lsum = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        local[q] = hist[lane * 4 + q];
+        lsum += local[q];
+      }
+      uint32_t incl = lsum;
+#pragma unroll
+      for (int dd = 1; dd < kWave; dd <<= 1) {
+        const uint32_t y = __shfl_up(incl, dd);
+        if (lane >= dd) incl += y;
+      }
+      const uint32_t excl = incl - lsum;
+      int digit = -1;
+      uint32_t below = 0;
+      if (excl < want && want <= incl) {
+        uint32_t run = excl;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (digit < 0 && want <= run + local[q]) {
+            digit = lane * 4 + q;
+            below = run;
+          }
+          run += local[q];
+        }
+      }
+      const unsigned long long owner = __ballot(digit >= 0);
+      const int src = __ffsll((long long)owner) - 1;
+      digit = __shfl(digit, src);
+      below = __shfl(below, src);
+      prefix |= (uint64_t)digit << shift;
+      pmask |= 255ull << shift;
+      want -= below;
+    }
+    // prefix is now the k-th smallest key: stage the k keys <= prefix
+    int64_t base = 0;
+    for (int64_t t0 = beg; t0 < end; t0 += kWave) {
+      const int64_t t = t0 + lane;
+      uint64_t key = 0;
+      uint32_t x = 0;
+      bool keep = false;
+      if (t < end) {
+        x = (uint32_t)adj[t];
+        key = mh_key(a, c, x);
+        keep = key <= prefix;
+      }
+      const unsigned long long bal = __ballot(keep);
+      if (keep) {
+        const int64_t pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+        if (pos < (int64_t)k) {  // exactly k keys qualify when the IDs of N_v are distinct
+          skey[pos] = key;
+          sid[pos] = x;
+        }
+      }
+      base += __popcll(bal);
+    }
+    taken = base < (int64_t)k ? base : (int64_t)k;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  // rank sort of the staged elements (keys distinct)
+  for (int64_t t = lane; t < taken; t += kWave) {
+    const uint64_t key = skey[t];
+    uint32_t r = 0;
+    for (int64_t q = 0; q < taken; ++q) r += skey[q] < key ? 1u : 0u;
+    row[r] = sid[t];
+  }
+  for (int64_t t = taken + lane; t < (int64_t)k; t += kWave) row[t] = kBottom;
+}
+
+}  // namespace
+
+int build_bf(pg_sketches* sk, hipStream_t s) {
+  const pg_graph* g = sk->g;
+  const uint32_t W = sk->W;
+  if (W > 16) {
+    if (g->n > 0) {
+      hipLaunchKernelGGL(k_bf_build_wide, dim3(grid_for((int64_t)g->n * kWave, kBlock, 1ll << 31)), dim3(kBlock), 0,
+                         s, g->off, g->adj, g->n, sk->size, W, sk->b, sk->ha, sk->hc, sk->words, sk->pc);
+      PG_LAUNCH_CHECK();
+    }
+    return PG_OK;
+  }
+  for (int bin = 0; bin < kNumBins; ++bin) {
+    const int64_t cnt = g->bin_start[bin + 1] - g->bin_start[bin];
+    if (cnt <= 0) continue;
+    const int32_t* verts = g->bin_verts + g->bin_start[bin];
+    const int G = kBinGroup[bin];
+    const unsigned grid = (unsigned)((cnt * G + kBlock - 1) / kBlock);
+#define PG_BF_LAUNCH(WM, GG)                                                                                   \
+  hipLaunchKernelGGL((k_bf_build<WM, GG>), dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, verts, cnt, sk->size, \
+                     W, sk->b, sk->ha, sk->hc, sk->words, sk->pc)
+#define PG_BF_BY_G(WM)          \
+  do {                          \
+    if (G == 4)                 \
+      PG_BF_LAUNCH(WM, 4);      \
+    else if (G == 16)           \
+      PG_BF_LAUNCH(WM, 16);     \
+    else if (G == 64)           \
+      PG_BF_LAUNCH(WM, 64);     \
+    else                        \
+      PG_BF_LAUNCH(WM, 256);    \
+  } while (0)
+    if (W <= 2)
+      PG_BF_BY_G(2);
+    else if (W <= 4)
+      PG_BF_BY_G(4);
+    else if (W <= 8)
+      PG_BF_BY_G(8);
+    else
+      PG_BF_BY_G(16);
+#undef PG_BF_BY_G
+#undef PG_BF_LAUNCH
+    PG_LAUNCH_CHECK();
+  }
+  return PG_OK;
+}
+
+int build_khash(pg_sketches* sk, hipStream_t s) {
+  const pg_graph* g = sk->g;
+  for (int bin = 0; bin < kNumBins; ++bin) {
+    const int64_t cnt = g->bin_start[bin + 1] - g->bin_start[bin];
+    if (cnt <= 0) continue;
+    const int32_t* verts = g->bin_verts + g->bin_start[bin];
+    const int G = kBinGroup[bin];
+    const unsigned grid = (unsigned)((cnt * G + kBlock - 1) / kBlock);
+    if (G == 4)
+      hipLaunchKernelGGL(k_kh_build<4>, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, verts, cnt, sk->size, sk->ha,
+                         sk->hc, sk->sig);
+    else if (G == 16)
+      hipLaunchKernelGGL(k_kh_build<16>, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, verts, cnt, sk->size, sk->ha,
+                         sk->hc, sk->sig);
+    else if (G == 64)
+      hipLaunchKernelGGL(k_kh_build<64>, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, verts, cnt, sk->size, sk->ha,
+                         sk->hc, sk->sig);
+    else
+      hipLaunchKernelGGL(k_kh_build<256>, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, verts, cnt, sk->size,
+                         sk->ha, sk->hc, sk->sig);
+    PG_LAUNCH_CHECK();
+  }
+  return PG_OK;
+}
+
+int build_onehash(pg_sketches* sk, hipStream_t s) {
+  const pg_graph* g = sk->g;
+  const int64_t nv = g->n;
+  if (nv <= 0) return PG_OK;
+  const size_t shmem = (size_t)kOhWaves * oh_wave_bytes(sk->size);
+  uint64_t a = 0, c = 0;
+  hash_constants(PG_MH_1HASH, sk->seed, 1, &a, &c);
+  // all vertices, in bin order (degree-sorted blocks balance better)
+  hipLaunchKernelGGL(k_oh_build, dim3((unsigned)((nv + kOhWaves - 1) / kOhWaves)), dim3(kBlock), shmem, s, g->off,
+                     g->adj, g->bin_verts, nv, sk->size, a, c, sk->sig);
+  PG_LAUNCH_CHECK();
+  return PG_OK;
+}
+
+}  // namespace pg

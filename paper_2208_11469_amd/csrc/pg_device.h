@@ -1,0 +1,81 @@
+// Device-side helpers shared by the library's kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pg {
+
+constexpr uint32_t kBottom = 0xFFFFFFFFu;  // empty MinHash slot
+constexpr int kWave = 64;
+
+// SplitMix64's output mix (Steele, Lea, Flood 2014): a bijection of 64-bit words.
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Bloom-filter bit of element x under hash (a, c): the top 32 bits of the
+// multiply-add a*x + c (mod 2^64), scaled to [0, B) by a multiply-high.
+__device__ __forceinline__ uint32_t bf_index(uint64_t a, uint64_t c, uint32_t x, uint32_t B) {
+  const uint64_t g = a * (uint64_t)x + c;
+  return __umulhi((uint32_t)(g >> 32), B);
+}
+
+// MinHash key of element x under hash (a, c): mix64(a*x + c). Odd a makes the
+// map injective on 64-bit words, so different vertices never tie.
+__device__ __forceinline__ uint64_t mh_key(uint64_t a, uint64_t c, uint32_t x) {
+  return mix64(a * (uint64_t)x + c);
+}
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Fixed-order butterfly sum over groups of G lanes (G a power of two <= 64);
+// every lane of the group ends with the same bits.
+template <int G>
+__device__ __forceinline__ double group_sum(double x) {
+#pragma unroll
+  for (int s = G / 2; s >= 1; s >>= 1) x += __shfl_xor(x, s, G);
+  return x;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_or(uint64_t x) {
+#pragma unroll
+  for (int s = G / 2; s >= 1; s >>= 1) x |= __shfl_xor(x, s, G);
+  return x;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_min(uint64_t x) {
+#pragma unroll
+  for (int s = G / 2; s >= 1; s >>= 1) {
+    const uint64_t y = __shfl_xor(x, s, G);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t group_sum_u32(uint32_t x) {
+#pragma unroll
+  for (int s = G / 2; s >= 1; s >>= 1) x += __shfl_xor(x, s, G);
+  return x;
+}
+
+// Block-wide deterministic FP64 sum for blockDim.x == 256 (4 waves); result
+// valid in thread 0.
+__device__ __forceinline__ double block_sum_256(double x, double* lds4) {
+  x = group_sum<64>(x);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds4[w] = x;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = ((lds4[0] + lds4[1]) + (lds4[2] + lds4[3]));
+  __syncthreads();
+  return r;
+}
+
+}  // namespace pg

@@ -1,0 +1,393 @@
+// Intersection estimates over vertex pairs (Sections 4.2-4.4) and the
+// quantities built from them: the triangle-count sum (Section 7), local
+// clustering coefficients and Jaccard similarities (Listing "lst:sim").
+//
+// Every pair is independent: one lane per pair gathers the two sketch rows,
+// reduces them to an integer count (ones of the AND or OR of two filters,
+// positional matches of two k-hash rows, or the bottom-k union walk of two
+// 1-hash rows) and maps the count to an FP64 estimate. Sums use a fixed
+// chunking of the pair list and a fixed reduction tree, so they are
+// bit-reproducible and independent of the launch configuration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "pg_device.h"
+#include "pg_internal.h"
+
+namespace pg {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kChunkItems = 8;
+constexpr int64_t kChunk = (int64_t)kBlock * kChunkItems;  // pairs per chunk partial
+
+struct SkView {
+  int kind;
+  int est;
+  uint32_t size;  // B or k
+  uint32_t b;
+  uint32_t W;
+  int32_t n;
+  const uint64_t* words;
+  const uint32_t* pc;
+  const uint32_t* sig;
+  const double* table;
+  const int32_t* deg;
+  uint64_t a1, c1;  // 1-hash constants
+};
+
+// ---- integer counts ----------------------------------------------------------
+
+template <int WT>
+__device__ __forceinline__ uint32_t bf_and_count(const uint64_t* __restrict__ ru, const uint64_t* __restrict__ rv,
+                                                 uint32_t W) {
+  uint32_t c = 0;
+  if constexpr (WT > 0 && (WT % 2) == 0) {
+    // rows of an even word count start on 16-byte boundaries
+    const ulonglong2* u2 = reinterpret_cast<const ulonglong2*>(ru);
+    const ulonglong2* v2 = reinterpret_cast<const ulonglong2*>(rv);
+#pragma unroll
+    for (int j = 0; j < WT / 2; ++j) {
+      const ulonglong2 x = u2[j], y = v2[j];
+      c += (uint32_t)__popcll(x.x & y.x) + (uint32_t)__popcll(x.y & y.y);
+    }
+  } else if constexpr (WT > 0) {
+#pragma unroll
+    for (int j = 0; j < WT; ++j) c += (uint32_t)__popcll(ru[j] & rv[j]);
+  } else {
+    for (uint32_t j = 0; j < W; ++j) c += (uint32_t)__popcll(ru[j] & rv[j]);
+  }
+  return c;
+}
+
+__device__ __forceinline__ uint32_t kh_matches(const uint32_t* __restrict__ mu, const uint32_t* __restrict__ mv,
+                                               uint32_t k) {
+  uint32_t s = 0;
+  if ((k & 3u) == 0) {
+    const uint4* u4 = reinterpret_cast<const uint4*>(mu);
+    const uint4* v4 = reinterpret_cast<const uint4*>(mv);
+    for (uint32_t j = 0; j < k / 4; ++j) {
+      const uint4 x = u4[j], y = v4[j];
+      s += (x.x == y.x && x.x != kBottom) + (x.y == y.y && x.y != kBottom) + (x.z == y.z && x.z != kBottom) +
+           (x.w == y.w && x.w != kBottom);
+    }
+  } else {
+    for (uint32_t j = 0; j < k; ++j) s += (mu[j] == mv[j] && mu[j] != kBottom);
+  }
+  return s;
+}
+
+// Walk of two 1-hash rows (each ascending in key) in key order.
+//   common      = |M_u cap M_v|
+//   kprime      = min(k, |M_u cup M_v|)
+//   s_union     = commons among the kprime smallest of the union
+__device__ __forceinline__ void oh_counts(const uint32_t* __restrict__ mu, const uint32_t* __restrict__ mv, uint32_t k,
+                                          uint32_t nu, uint32_t nv, uint64_t a, uint64_t c, uint32_t& s_union,
+                                          uint32_t& kprime, uint32_t& common) {
+  uint32_t i = 0, j = 0, rank = 0, com = 0, com_k = 0;
+  uint64_t ku = nu ? mh_key(a, c, mu[0]) : ~0ull;
+  uint64_t kv = nv ? mh_key(a, c, mv[0]) : ~0ull;
+  while (i < nu || j < nv) {
+    if (i < nu && j < nv && mu[i] == mv[j]) {
+      com_k += rank < k ? 1u : 0u;
+      ++com;
+      ++i;
+      ++j;
+      ku = i < nu ? mh_key(a, c, mu[i]) : ~0ull;
+      kv = j < nv ? mh_key(a, c, mv[j]) : ~0ull;
+    } else if (j >= nv || (i < nu && ku < kv)) {
+      ++i;
+      ku = i < nu ? mh_key(a, c, mu[i]) : ~0ull;
+    } else {
+      ++j;
+      kv = j < nv ? mh_key(a, c, mv[j]) : ~0ull;
+    }
+    ++rank;
+  }
+  const uint32_t uni = nu + nv - com;
+  kprime = uni < k ? uni : k;
+  s_union = uni >= k ? com_k : com;
+  common = com;
+}
+
+// J^ = s / kk, I^ = J^ / (1 + J^) (|X| + |Y|)  (Eq. "est_int_mh", Section 4.4)
+__device__ __forceinline__ double minhash_estimate(uint32_t s, uint32_t kk, int32_t du, int32_t dv) {
+  const double j = kk > 0 ? (double)s / (double)kk : 0.0;
+  return j / (1.0 + j) * ((double)du + (double)dv);
+}
+
+template <int KIND, int WT>
+__device__ __forceinline__ double eval_pair(const SkView& s, int32_t u, int32_t v, uint32_t& raw) {
+  if ((uint32_t)u >= (uint32_t)s.n || (uint32_t)v >= (uint32_t)s.n) {
+    raw = 0xFFFFFFFFu;
+    return __longlong_as_double(0x7FF8000000000000ll);  // NaN for an out-of-range pair
+  }
+  if constexpr (KIND == PG_BF) {
+    const uint32_t c = bf_and_count<WT>(s.words + (size_t)u * s.W, s.words + (size_t)v * s.W, s.W);
+    if (s.est == PG_EST_BF_OR) {
+      const uint32_t cor = s.pc[u] + s.pc[v] - c;  // ones of the OR
+      raw = cor;
+      return ((double)s.deg[u] + (double)s.deg[v]) + s.table[cor];
+    }
+    raw = c;
+    return s.table[c];
+  } else if constexpr (KIND == PG_MH_KHASH) {
+    const uint32_t m = kh_matches(s.sig + (size_t)u * s.size, s.sig + (size_t)v * s.size, s.size);
+    raw = m;
+    return minhash_estimate(m, s.size, s.deg[u], s.deg[v]);
+  } else {
+    const int32_t du = s.deg[u], dv = s.deg[v];
+    const uint32_t nu = (uint32_t)du < s.size ? (uint32_t)du : s.size;
+    const uint32_t nv = (uint32_t)dv < s.size ? (uint32_t)dv : s.size;
+    uint32_t su, kp, com;
+    oh_counts(s.sig + (size_t)u * s.size, s.sig + (size_t)v * s.size, s.size, nu, nv, s.a1, s.c1, su, kp, com);
+    if (s.est == PG_EST_MH_1HASH_LITERAL) {
+      raw = com;
+      return minhash_estimate(com, s.size, du, dv);
+    }
+    raw = su;
+    return minhash_estimate(su, kp, du, dv);
+  }
+}
+
+// J = I_c / (d_u + d_v - I_c), I_c = clamp(I^, 0, min(d_u, d_v)); 0 on an empty union.
+__device__ __forceinline__ double jaccard_of(double est, int32_t du, int32_t dv) {
+  const double lo = 0.0, hi = (double)(du < dv ? du : dv);
+  const double ic = est < lo ? lo : (est > hi ? hi : est);
+  const double den = ((double)du + (double)dv) - ic;
+  return den > 0.0 ? ic / den : 0.0;
+}
+
+// ---- kernels -------------------------------------------------------------------
+
+template <int KIND, int WT>
+__global__ __launch_bounds__(kBlock) void k_pairs(SkView s, const int32_t* __restrict__ pu,
+                                                  const int32_t* __restrict__ pv, int64_t npairs,
+                                                  double* __restrict__ est_out, uint32_t* __restrict__ raw_out,
+                                                  float* __restrict__ jac_out) {
+  for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < npairs; e += (int64_t)gridDim.x * kBlock) {
+    const int32_t u = pu[e], v = pv[e];
+    uint32_t raw;
+    const double est = eval_pair<KIND, WT>(s, u, v, raw);
+    if (est_out) est_out[e] = est;
+    if (raw_out) raw_out[e] = raw;
+    if (jac_out) {
+      const bool ok = (uint32_t)u < (uint32_t)s.n && (uint32_t)v < (uint32_t)s.n;
+      jac_out[e] = ok ? (float)jaccard_of(est, s.deg[u], s.deg[v]) : __int_as_float(0x7FC00000);
+    }
+  }
+}
+
+// Partial sums over fixed chunks of kChunk pairs: thread t of the chunk adds
+// pairs chunk*kChunk + j*kBlock + t, j = 0..7, then a fixed tree.
+template <int KIND, int WT>
+__global__ __launch_bounds__(kBlock) void k_pairs_sum(SkView s, const int32_t* __restrict__ pu,
+                                                      const int32_t* __restrict__ pv, int64_t npairs,
+                                                      double* __restrict__ chunks) {
+  __shared__ double lds[kBlock / kWave];
+  const int64_t nchunks = (npairs + kChunk - 1) / kChunk;
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < kChunkItems; ++j) {
+      const int64_t e = ch * kChunk + (int64_t)j * kBlock + threadIdx.x;
+      if (e < npairs) {
+        uint32_t raw;
+        acc += eval_pair<KIND, WT>(s, pu[e], pv[e], raw);
+      }
+    }
+    const double r = block_sum_256(acc, lds);
+    if (threadIdx.x == 0) chunks[ch] = r;
+  }
+}
+
+// cc_v = sum_{u in N_v} I^(u, v) / (d_v (d_v - 1)); G lanes per vertex, fixed order.
+template <int KIND, int WT, int G>
+__global__ __launch_bounds__(kBlock) void k_cc(SkView s, const int32_t* __restrict__ off,
+                                               const int32_t* __restrict__ adj, const int32_t* __restrict__ verts,
+                                               int64_t nverts, float* __restrict__ cc, double* __restrict__ vsum) {
+  __shared__ double lds[kBlock / kWave];
+  const int64_t grp = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  const bool active = grp < nverts;
+  const int32_t v = active ? verts[grp] : 0;
+  double acc = 0.0;
+  if (active) {
+    for (int64_t p = off[v] + lane; p < off[v + 1]; p += G) {
+      uint32_t raw;
+      acc += eval_pair<KIND, WT>(s, v, adj[p], raw);
+    }
+  }
+  double tot;
+  if constexpr (G <= kWave) {
+    tot = group_sum<G>(acc);
+  } else {
+    tot = block_sum_256(acc, lds);
+  }
+  if (active && lane == 0) {
+    const int32_t d = s.deg[v];
+    const double val = d >= 2 ? tot / ((double)d * ((double)d - 1.0)) : 0.0;
+    cc[v] = (float)val;
+    if (vsum) vsum[v] = tot;
+  }
+}
+
+__global__ void k_make_table(double* __restrict__ t, uint32_t B, uint32_t b, int est) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > B) return;
+  const double Bd = (double)B, bd = (double)b;
+  const double ct = (double)(c == B ? c - 1 : c);  // Appendix C: B~_1 = B_1 - [B_1 = B]
+  double r;
+  switch (est) {
+    case PG_EST_BF_AND:
+      r = -(Bd / bd) * log(1.0 - ct / Bd);
+      break;
+    case PG_EST_BF_L:
+      r = (double)c / bd;
+      break;
+    case PG_EST_BF_PAPAPETROU:
+      r = log(1.0 - ct / Bd) / (bd * log(1.0 - 1.0 / Bd));
+      break;
+    default:  // PG_EST_BF_OR: the logarithmic term, added to |X| + |Y|
+      r = (Bd / bd) * log(1.0 - ct / Bd);
+      break;
+  }
+  t[c] = r;
+}
+
+SkView make_view(const pg_sketches* sk, int est) {
+  SkView v{};
+  v.kind = sk->kind;
+  v.est = est;
+  v.size = sk->size;
+  v.b = sk->b;
+  v.W = sk->W;
+  v.n = sk->g->n;
+  v.words = sk->words;
+  v.pc = sk->pc;
+  v.sig = sk->sig;
+  v.table = sk->table;
+  v.deg = sk->g->deg;
+  if (sk->kind == PG_MH_1HASH) hash_constants(PG_MH_1HASH, sk->seed, 1, &v.a1, &v.c1);
+  return v;
+}
+
+int check_estimator(const pg_sketches* sk, int est) {
+  const bool bf = est == PG_EST_BF_AND || est == PG_EST_BF_L || est == PG_EST_BF_OR || est == PG_EST_BF_PAPAPETROU;
+  if (sk->kind == PG_BF && bf) return PG_OK;
+  if (sk->kind == PG_MH_KHASH && est == PG_EST_MH_KHASH) return PG_OK;
+  if (sk->kind == PG_MH_1HASH && (est == PG_EST_MH_1HASH || est == PG_EST_MH_1HASH_LITERAL)) return PG_OK;
+  return fail(PG_E_INVALID, "estimator does not match the sketch kind");
+}
+
+// Dispatch on (kind, W): Bloom filters get an instantiation per word count up
+// to 16 words; wider filters and MinHash use the general path.
+#define PG_DISPATCH(sk, LAUNCH)                    \
+  do {                                             \
+    if ((sk)->kind == PG_BF) {                     \
+      switch ((sk)->W) {                           \
+        case 1: LAUNCH(PG_BF, 1); break;           \
+        case 2: LAUNCH(PG_BF, 2); break;           \
+        case 3: LAUNCH(PG_BF, 3); break;           \
+        case 4: LAUNCH(PG_BF, 4); break;           \
+        case 5: LAUNCH(PG_BF, 5); break;           \
+        case 6: LAUNCH(PG_BF, 6); break;           \
+        case 7: LAUNCH(PG_BF, 7); break;           \
+        case 8: LAUNCH(PG_BF, 8); break;           \
+        case 9: LAUNCH(PG_BF, 9); break;           \
+        case 10: LAUNCH(PG_BF, 10); break;         \
+        case 11: LAUNCH(PG_BF, 11); break;         \
+        case 12: LAUNCH(PG_BF, 12); break;         \
+        case 13: LAUNCH(PG_BF, 13); break;         \
+        case 14: LAUNCH(PG_BF, 14); break;         \
+        case 15: LAUNCH(PG_BF, 15); break;         \
+        case 16: LAUNCH(PG_BF, 16); break;         \
+        default: LAUNCH(PG_BF, 0); break;          \
+      }                                            \
+    } else if ((sk)->kind == PG_MH_KHASH) {        \
+      LAUNCH(PG_MH_KHASH, 0);                      \
+    } else {                                       \
+      LAUNCH(PG_MH_1HASH, 0);                      \
+    }                                              \
+  } while (0)
+
+}  // namespace
+
+int64_t chunk_count(int64_t npairs) { return (npairs + kChunk - 1) / kChunk; }
+
+int ensure_table(pg_sketches* sk, int est, hipStream_t s) {
+  if (sk->kind != PG_BF) return PG_OK;
+  if (sk->table_est == est) return PG_OK;
+  const uint32_t entries = sk->size + 1;
+  hipLaunchKernelGGL(k_make_table, dim3((entries + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sk->table, sk->size,
+                     sk->b, est);
+  PG_LAUNCH_CHECK();
+  sk->table_est = est;
+  return PG_OK;
+}
+
+int estimate_pairs(const pg_sketches* sk, int est, const int32_t* u, const int32_t* v, int64_t npairs,
+                   double* est_out, uint32_t* raw_out, float* jac_out, hipStream_t s) {
+  PG_TRY(check_estimator(sk, est));
+  PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
+  if (npairs <= 0) return PG_OK;
+  const SkView view = make_view(sk, est);
+  const unsigned grid = grid_for(npairs, kBlock, 65536);
+#define PG_LAUNCH_PAIRS(KIND, WT) \
+  hipLaunchKernelGGL((k_pairs<KIND, WT>), dim3(grid), dim3(kBlock), 0, s, view, u, v, npairs, est_out, raw_out, jac_out)
+  PG_DISPATCH(sk, PG_LAUNCH_PAIRS);
+#undef PG_LAUNCH_PAIRS
+  PG_LAUNCH_CHECK();
+  return PG_OK;
+}
+
+int estimate_sum(const pg_sketches* sk, int est, const int32_t* u, const int32_t* v, int64_t npairs, double* chunks,
+                 hipStream_t s) {
+  PG_TRY(check_estimator(sk, est));
+  PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
+  const int64_t nchunks = chunk_count(npairs);
+  if (nchunks <= 0) return PG_OK;
+  const SkView view = make_view(sk, est);
+  const unsigned grid = (unsigned)std::min<int64_t>(nchunks, 65536);
+#define PG_LAUNCH_SUM(KIND, WT) \
+  hipLaunchKernelGGL((k_pairs_sum<KIND, WT>), dim3(grid), dim3(kBlock), 0, s, view, u, v, npairs, chunks)
+  PG_DISPATCH(sk, PG_LAUNCH_SUM);
+#undef PG_LAUNCH_SUM
+  PG_LAUNCH_CHECK();
+  return PG_OK;
+}
+
+int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStream_t s) {
+  PG_TRY(check_estimator(sk, est));
+  PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
+  const pg_graph* g = sk->g;
+  const SkView view = make_view(sk, est);
+  for (int bin = 0; bin < kNumBins; ++bin) {
+    const int64_t cnt = g->bin_start[bin + 1] - g->bin_start[bin];
+    if (cnt <= 0) continue;
+    const int32_t* verts = g->bin_verts + g->bin_start[bin];
+    const int G = kBinGroup[bin];
+    const unsigned grid = (unsigned)((cnt * G + kBlock - 1) / kBlock);
+#define PG_LAUNCH_CC_G(KIND, WT, GG) \
+  hipLaunchKernelGGL((k_cc<KIND, WT, GG>), dim3(grid), dim3(kBlock), 0, s, view, g->off, g->adj, verts, cnt, cc, vsum)
+#define PG_LAUNCH_CC(KIND, WT)        \
+  do {                                \
+    if (G == 4)                       \
+      PG_LAUNCH_CC_G(KIND, WT, 4);    \
+    else if (G == 16)                 \
+      PG_LAUNCH_CC_G(KIND, WT, 16);   \
+    else if (G == 64)                 \
+      PG_LAUNCH_CC_G(KIND, WT, 64);   \
+    else                              \
+      PG_LAUNCH_CC_G(KIND, WT, 256);  \
+  } while (0)
+    PG_DISPATCH(sk, PG_LAUNCH_CC);
+#undef PG_LAUNCH_CC
+#undef PG_LAUNCH_CC_G
+    PG_LAUNCH_CHECK();
+  }
+  return PG_OK;
+}
+
+}  // namespace pg

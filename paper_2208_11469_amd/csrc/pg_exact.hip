@@ -1,0 +1,235 @@
+// Exact intersection baselines on the same graphs: |N_u cap N_v| from the
+// sorted neighbour lists (Fig. 1; the exact rows of Table "tab:queries-int"),
+// the node-iterator triangle count over the degree orientation (Listing
+// "lst:tc"), exact local clustering coefficients and Jaccard similarities.
+//
+// Intersection kernel: a wave takes 64 pairs. The elements of the shorter list
+// of every pair become the wave's work items; they are spread evenly over the
+// 64 lanes regardless of which pair they belong to, and each item is
+// binary-searched in the longer list. This balances skewed degree mixes inside
+// a wave, and the cost per pair is min(d_u, d_v) * log max(d_u, d_v).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "pg_device.h"
+#include "pg_internal.h"
+
+namespace pg {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+__device__ __forceinline__ bool contains(const int32_t* __restrict__ a, int64_t lo, int64_t hi, int32_t key) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int32_t x = a[mid];
+    if (x == key) return true;
+    if (x < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return false;
+}
+
+struct WaveShared {
+  int64_t excl[kWave];
+  int64_t abeg[kWave];
+  int64_t bbeg[kWave];
+  int64_t blen[kWave];
+  uint32_t cnt[kWave];
+};
+
+// Intersect the lane's pair of lists (a = shorter, b = longer, both in `lists`)
+// cooperatively with the other lanes of the wave; returns the lane's count.
+__device__ uint32_t wave_intersect(const int32_t* __restrict__ lists, int64_t abeg, int64_t alen, int64_t bbeg,
+                                   int64_t blen, WaveShared& sh) {
+  const int lane = lane_id();
+  const int64_t work = (blen > 0) ? alen : 0;
+  int64_t incl = work;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t y = __shfl_up(incl, d);
+    if (lane >= d) incl += y;
+  }
+  const int64_t total = __shfl(incl, kWave - 1);
+  sh.excl[lane] = incl - work;
+  sh.abeg[lane] = abeg;
+  sh.bbeg[lane] = bbeg;
+  sh.blen[lane] = blen;
+  sh.cnt[lane] = 0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int64_t t = lane; t < total; t += kWave) {
+    // owner: the last lane q with excl[q] <= t
+    int lo = 0, hi = kWave;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (sh.excl[mid] <= t)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int q = lo;
+    const int32_t x = lists[sh.abeg[q] + (t - sh.excl[q])];
+    if (contains(lists, sh.bbeg[q], sh.bbeg[q] + sh.blen[q], x)) atomicAdd(&sh.cnt[q], 1u);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint32_t r = sh.cnt[lane];
+  __builtin_amdgcn_wave_barrier();
+  return r;
+}
+
+// out[e] = |N_u cap N_v|; optional integer scatter of the count to both
+// endpoints' sums (order-independent, so deterministic).
+__global__ __launch_bounds__(kBlock) void k_exact_pairs(const int32_t* __restrict__ off,
+                                                        const int32_t* __restrict__ adj, int32_t n,
+                                                        const int32_t* __restrict__ pu, const int32_t* __restrict__ pv,
+                                                        int64_t npairs, uint32_t* __restrict__ out,
+                                                        unsigned long long* __restrict__ vsum) {
+  __shared__ WaveShared shw[kWavesPerBlock];
+  WaveShared& sh = shw[threadIdx.x / kWave];
+  const int64_t nwaves_total = (int64_t)gridDim.x * kWavesPerBlock;
+  for (int64_t wbase = (blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave) * kWave; wbase < npairs;
+       wbase += nwaves_total * kWave) {
+    const int64_t e = wbase + lane_id();
+    int64_t abeg = 0, alen = 0, bbeg = 0, blen = 0;
+    int32_t u = -1, v = -1;
+    bool ok = false;
+    if (e < npairs) {
+      u = pu[e];
+      v = pv[e];
+      ok = (uint32_t)u < (uint32_t)n && (uint32_t)v < (uint32_t)n;
+      if (ok) {
+        const int64_t ub = off[u], ul = off[u + 1] - ub;
+        const int64_t vb = off[v], vl = off[v + 1] - vb;
+        if (ul <= vl) {
+          abeg = ub; alen = ul; bbeg = vb; blen = vl;
+        } else {
+          abeg = vb; alen = vl; bbeg = ub; blen = ul;
+        }
+      }
+    }
+    const uint32_t c = wave_intersect(adj, abeg, alen, bbeg, blen, sh);
+    if (e < npairs) {
+      if (out) out[e] = ok ? c : 0xFFFFFFFFu;
+      if (vsum && ok && c) {
+        atomicAdd(&vsum[u], (unsigned long long)c);
+        atomicAdd(&vsum[v], (unsigned long long)c);
+      }
+    }
+  }
+}
+
+// Node iterator over the orientation: sum over oriented edges (v, u) of
+// |N+_v cap N+_u|; one integer atomic per wave.
+__global__ __launch_bounds__(kBlock) void k_exact_tc(const int32_t* __restrict__ poff, const int32_t* __restrict__ padj,
+                                                     const int32_t* __restrict__ psrc, int64_t m,
+                                                     unsigned long long* __restrict__ tc) {
+  __shared__ WaveShared shw[kWavesPerBlock];
+  WaveShared& sh = shw[threadIdx.x / kWave];
+  const int64_t nwaves_total = (int64_t)gridDim.x * kWavesPerBlock;
+  unsigned long long acc = 0;
+  for (int64_t wbase = (blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave) * kWave; wbase < m;
+       wbase += nwaves_total * kWave) {
+    const int64_t p = wbase + lane_id();
+    int64_t abeg = 0, alen = 0, bbeg = 0, blen = 0;
+    if (p < m) {
+      const int32_t v = psrc[p], u = padj[p];
+      const int64_t vb = poff[v], vl = poff[v + 1] - vb;
+      const int64_t ub = poff[u], ul = poff[u + 1] - ub;
+      if (vl <= ul) {
+        abeg = vb; alen = vl; bbeg = ub; blen = ul;
+      } else {
+        abeg = ub; alen = ul; bbeg = vb; blen = vl;
+      }
+    }
+    acc += wave_intersect(padj, abeg, alen, bbeg, blen, sh);
+  }
+#pragma unroll
+  for (int s = kWave / 2; s >= 1; s >>= 1) acc += __shfl_xor(acc, s);
+  if (lane_id() == 0 && acc) atomicAdd(tc, acc);
+}
+
+__global__ void k_exact_cc_finish(const unsigned long long* __restrict__ vsum, const int32_t* __restrict__ deg,
+                                  int32_t n, float* __restrict__ cc) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t d = deg[v];
+  cc[v] = d >= 2 ? (float)((double)vsum[v] / ((double)d * ((double)d - 1.0))) : 0.0f;
+}
+
+__global__ void k_exact_jaccard(const uint32_t* __restrict__ inter, const int32_t* __restrict__ deg, int32_t n,
+                                const int32_t* __restrict__ pu, const int32_t* __restrict__ pv, int64_t npairs,
+                                float* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < npairs; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = pu[e], v = pv[e];
+    if ((uint32_t)u >= (uint32_t)n || (uint32_t)v >= (uint32_t)n) {
+      out[e] = __int_as_float(0x7FC00000);
+      continue;
+    }
+    const double i = (double)inter[e];
+    const double den = ((double)deg[u] + (double)deg[v]) - i;
+    out[e] = den > 0.0 ? (float)(i / den) : 0.0f;
+  }
+}
+
+}  // namespace
+
+int exact_pairs(const pg_graph* g, int algo, const int32_t* u, const int32_t* v, int64_t npairs, uint32_t* out,
+                hipStream_t s) {
+  if (algo != PG_EXACT_MERGE) return fail(PG_E_UNSUPPORTED, "only PG_EXACT_MERGE is implemented for pair lists");
+  if (npairs <= 0) return PG_OK;
+  const unsigned grid = grid_for((npairs + kWave - 1) / kWave * kWave, kBlock, 65536);
+  hipLaunchKernelGGL(k_exact_pairs, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, g->n, u, v, npairs, out,
+                     (unsigned long long*)nullptr);
+  PG_LAUNCH_CHECK();
+  return PG_OK;
+}
+
+int exact_tc(pg_graph* g, int algo, uint64_t* d_tc, hipStream_t s) {
+  if (algo != PG_EXACT_MERGE) return fail(PG_E_UNSUPPORTED, "only PG_EXACT_MERGE is implemented for triangle counting");
+  PG_TRY(graph_orient(g, s));
+  PG_TRY(fill_u64(d_tc, 0, 1, s));
+  if (g->m <= 0) return PG_OK;
+  const unsigned grid = grid_for((g->m + kWave - 1) / kWave * kWave, kBlock, 65536);
+  hipLaunchKernelGGL(k_exact_tc, dim3(grid), dim3(kBlock), 0, s, g->poff, g->padj, g->parc_src, g->m,
+                     (unsigned long long*)d_tc);
+  PG_LAUNCH_CHECK();
+  return PG_OK;
+}
+
+int exact_cc(pg_graph* g, float* cc, hipStream_t s) {
+  if (g->n <= 0) return PG_OK;
+  uint64_t* vsum = nullptr;
+  PG_TRY(dmalloc((void**)&vsum, sizeof(uint64_t) * (size_t)g->n, s));
+  PG_TRY(fill_u64(vsum, 0, g->n, s));
+  if (g->m > 0) {
+    const unsigned grid = grid_for((g->m + kWave - 1) / kWave * kWave, kBlock, 65536);
+    hipLaunchKernelGGL(k_exact_pairs, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, g->n, g->eu, g->ev, g->m,
+                       (uint32_t*)nullptr, (unsigned long long*)vsum);
+    PG_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_exact_cc_finish, dim3(grid_for(g->n, kBlock)), dim3(kBlock), 0, s,
+                     (const unsigned long long*)vsum, g->deg, g->n, cc);
+  PG_LAUNCH_CHECK();
+  return dfree(vsum, s);
+}
+
+int exact_jaccard(const pg_graph* g, const int32_t* u, const int32_t* v, int64_t npairs, float* out, hipStream_t s) {
+  if (npairs <= 0) return PG_OK;
+  uint32_t* inter = nullptr;
+  PG_TRY(dmalloc((void**)&inter, sizeof(uint32_t) * (size_t)npairs, s));
+  PG_TRY(exact_pairs(g, PG_EXACT_MERGE, u, v, npairs, inter, s));
+  hipLaunchKernelGGL(k_exact_jaccard, dim3(grid_for(npairs, kBlock, 65536)), dim3(kBlock), 0, s, inter, g->deg, g->n,
+                     u, v, npairs, out);
+  PG_LAUNCH_CHECK();
+  return dfree(inter, s);
+}
+
+}  // namespace pg

@@ -1,0 +1,554 @@
+// Graph ingest on the device: CSR checks, degrees, the degree-bin partition of
+// the vertices, the m undirected edges (v, u), v < u, in CSR order, arc
+// sources, and the degree orientation used by the exact node iterator
+// (Listing "lst:tc"). Also the scan / fill / fixed-order sum utilities.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
+#include "pg_device.h"
+#include "pg_internal.h"
+
+namespace pg {
+namespace {
+
+constexpr int kBlock = 256;
+
+// Error bits raised by the checks.
+constexpr int kBadOffsets = 1, kBadRange = 2, kSelfLoop = 4, kUnsorted = 8, kAsymmetric = 16;
+
+__global__ void k_check_offsets(const int32_t* __restrict__ off, int32_t n, int64_t nnz, int* flags) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v > n) return;
+  bool bad = false;
+  if (v == 0 && off[0] != 0) bad = true;
+  if (v == n && (int64_t)off[n] != nnz) bad = true;
+  if (v < n && off[v + 1] < off[v]) bad = true;
+  if (v <= n && (off[v] < 0 || (int64_t)off[v] > nnz)) bad = true;
+  if (bad) atomicOr(flags, kBadOffsets);
+}
+
+__global__ void k_check_range(const int32_t* __restrict__ adj, int64_t nnz, int32_t n, int* flags) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = adj[p];
+    if (x < 0 || x >= n) atomicOr(flags, kBadRange);
+  }
+}
+
+// Lower bound of key in a[lo, hi) (a sorted ascending).
+__device__ __forceinline__ int64_t lower_bound_i32(const int32_t* __restrict__ a, int64_t lo, int64_t hi, int32_t key) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Source vertex of arc p: the last v with off[v] <= p (offsets validated).
+__device__ __forceinline__ int32_t arc_source(const int32_t* __restrict__ off, int32_t n, int64_t p) {
+  int32_t lo = 0, hi = n;  // answer in [0, n)
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if ((int64_t)off[mid] <= p)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Sortedness, duplicates, self-loops and symmetry (u in N_v => v in N_u).
+__global__ void k_check_structure(const int32_t* __restrict__ off, const int32_t* __restrict__ adj, int32_t n,
+                                  int64_t nnz, int* flags) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = arc_source(off, n, p);
+    const int32_t u = adj[p];
+    int f = 0;
+    if (u == v) f |= kSelfLoop;
+    if (p > off[v] && adj[p - 1] >= u) f |= kUnsorted;
+    const int64_t q = lower_bound_i32(adj, off[u], off[u + 1], v);
+    if (q >= off[u + 1] || adj[q] != v) f |= kAsymmetric;
+    if (f) atomicOr(flags, f);
+  }
+}
+
+__global__ void k_degrees(const int32_t* __restrict__ off, int32_t n, int32_t* __restrict__ deg, int* max_deg,
+                          unsigned long long* wedges) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int32_t d = 0;
+  if (v < n) {
+    d = off[v + 1] - off[v];
+    deg[v] = d;
+  }
+  // wave-level combine, one atomic per wave (integer: order-independent)
+  unsigned long long w = (unsigned long long)d * (unsigned long long)(d > 0 ? d - 1 : 0) / 2ull;
+  int mx = d;
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+    w += __shfl_xor(w, s);
+    const int o = __shfl_xor(mx, s);
+    mx = o > mx ? o : mx;
+  }
+  if (lane_id() == 0) {
+    atomicMax(max_deg, mx);
+    atomicAdd(wedges, w);
+  }
+}
+
+__device__ __forceinline__ int degree_bin(int32_t d) {
+  return d <= kBinMaxDeg[0] ? 0 : d <= kBinMaxDeg[1] ? 1 : d <= kBinMaxDeg[2] ? 2 : 3;
+}
+
+// Stable partition of the vertices by degree bin: per-block counts (bin-major).
+__global__ void k_bin_count(const int32_t* __restrict__ deg, int32_t n, int64_t* __restrict__ counts, int64_t nblk) {
+  __shared__ int wc[kBlock / kWave][kNumBins];
+  const int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  const int key = v < n ? degree_bin(deg[v]) : -1;
+  const int w = threadIdx.x / kWave;
+#pragma unroll
+  for (int j = 0; j < kNumBins; ++j) {
+    const unsigned long long bal = __ballot(key == j);
+    if (lane_id() == 0) wc[w][j] = __popcll(bal);
+  }
+  __syncthreads();
+  if (threadIdx.x < kNumBins) {
+    int64_t t = 0;
+    for (int i = 0; i < kBlock / kWave; ++i) t += wc[i][threadIdx.x];
+    counts[threadIdx.x * nblk + blockIdx.x] = t;
+  }
+}
+
+__global__ void k_bin_scatter(const int32_t* __restrict__ deg, int32_t n, const int64_t* __restrict__ base,
+                              int64_t nblk, int32_t* __restrict__ out) {
+  __shared__ int wc[kBlock / kWave][kNumBins];
+  const int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  const int key = v < n ? degree_bin(deg[v]) : -1;
+  const int w = threadIdx.x / kWave;
+  unsigned long long mine = 0;
+#pragma unroll
+  for (int j = 0; j < kNumBins; ++j) {
+    const unsigned long long bal = __ballot(key == j);
+    if (lane_id() == 0) wc[w][j] = __popcll(bal);
+    if (key == j) mine = bal;
+  }
+  __syncthreads();
+  if (key >= 0) {
+    int64_t rank = __popcll(mine & ((1ull << lane_id()) - 1ull));
+    for (int i = 0; i < w; ++i) rank += wc[i][key];
+    out[base[key * nblk + blockIdx.x] + rank] = (int32_t)v;
+  }
+}
+
+// ---- per-vertex group kernels: G lanes per vertex, G <= 256 divides 256 -----
+
+// Number of neighbours above v (the suffix of the sorted N_v).
+template <int G>
+__global__ void k_upper_count(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
+                              const int32_t* __restrict__ verts, int64_t nverts, int64_t* __restrict__ cnt) {
+  const int64_t grp = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  if (grp >= nverts || lane != 0) return;
+  const int32_t v = verts[grp];
+  const int64_t fg = lower_bound_i32(adj, off[v], off[v + 1], v + 1);
+  cnt[v] = off[v + 1] - fg;
+}
+
+template <int G>
+__global__ void k_upper_fill(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
+                             const int32_t* __restrict__ verts, int64_t nverts, const int64_t* __restrict__ up_off,
+                             int32_t* __restrict__ eu, int32_t* __restrict__ ev) {
+  const int64_t grp = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  if (grp >= nverts) return;
+  const int32_t v = verts[grp];
+  const int64_t end = off[v + 1];
+  const int64_t cnt = up_off[v + 1] - up_off[v];
+  const int64_t fg = end - cnt;
+  const int64_t e0 = up_off[v];
+  for (int64_t j = fg + lane; j < end; j += G) {
+    eu[e0 + (j - fg)] = v;
+    ev[e0 + (j - fg)] = adj[j];
+  }
+}
+
+template <int G>
+__global__ void k_arc_src(const int32_t* __restrict__ off, const int32_t* __restrict__ verts, int64_t nverts,
+                          int32_t* __restrict__ src) {
+  const int64_t grp = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  if (grp >= nverts) return;
+  const int32_t v = verts[grp];
+  for (int64_t p = off[v] + lane; p < off[v + 1]; p += G) src[p] = v;
+}
+
+// Degree order R: R(v) < R(u) iff (d_v, v) < (d_u, u) (Listing "lst:tc").
+__device__ __forceinline__ bool rank_less(const int32_t* __restrict__ deg, int32_t v, int32_t u) {
+  const int32_t dv = deg[v], du = deg[u];
+  return dv < du || (dv == du && v < u);
+}
+
+template <int G>
+__global__ void k_orient_count(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
+                               const int32_t* __restrict__ deg, const int32_t* __restrict__ verts, int64_t nverts,
+                               int64_t* __restrict__ cnt) {
+  __shared__ int64_t part[kBlock];
+  const int64_t grp = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  int64_t c = 0;
+  int32_t v = -1;
+  if (grp < nverts) {
+    v = verts[grp];
+    for (int64_t p = off[v] + lane; p < off[v + 1]; p += G) c += rank_less(deg, v, adj[p]) ? 1 : 0;
+  }
+  part[threadIdx.x] = c;
+  __syncthreads();
+  if (grp < nverts && lane == 0) {
+    int64_t t = 0;
+    for (int i = 0; i < G; ++i) t += part[threadIdx.x + i];
+    cnt[v] = t;
+  }
+}
+
+// Keeps the order of N_v, so every N+_v stays sorted by ID. G <= 64 lanes per
+// vertex, so a group never straddles a wave; output positions come from a
+// ballot prefix inside the group.
+template <int G>
+__global__ void k_orient_fill(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
+                              const int32_t* __restrict__ deg, const int32_t* __restrict__ verts, int64_t nverts,
+                              const int64_t* __restrict__ poff, int32_t* __restrict__ padj, int32_t* __restrict__ psrc) {
+  static_assert(G <= kWave, "group must fit in a wave");
+  const int64_t grp = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  if (grp >= nverts) return;
+  const int32_t v = verts[grp];
+  const int64_t end = off[v + 1];
+  int64_t q = poff[v];
+  const int shift = lane_id() - lane;  // first lane of this group inside the wave
+  const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+  for (int64_t p0 = off[v]; p0 < end; p0 += G) {
+    const int64_t p = p0 + lane;
+    const bool keep = (p < end) && rank_less(deg, v, adj[p]);
+    const unsigned long long bits = (__ballot(keep) >> shift) & gmask;
+    if (keep) {
+      const int before = __popcll(bits & ((1ull << lane) - 1ull));
+      padj[q + before] = adj[p];
+      psrc[q + before] = v;
+    }
+    q += __popcll(bits);
+  }
+}
+
+// ---- scan ------------------------------------------------------------------
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t x) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t y = __shfl_up(x, d);
+    if (lane_id() >= d) x += y;
+  }
+  return x;
+}
+
+__global__ void k_scan_tile(const int64_t* __restrict__ in, int64_t* __restrict__ out, int64_t count,
+                            int64_t* __restrict__ tile_sums) {
+  __shared__ int64_t wsum[kBlock / kWave];
+  const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * (int64_t)kScanItems;
+  int64_t v[kScanItems];
+  int64_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i;
+    v[i] = idx < count ? in[idx] : 0;
+    sum += v[i];
+  }
+  const int64_t incl = wave_incl_scan(sum);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) wsum[w] = incl;
+  __syncthreads();
+  int64_t wbase = 0, total = 0;
+#pragma unroll
+  for (int i = 0; i < kBlock / kWave; ++i) {
+    wbase += (i < w) ? wsum[i] : 0;
+    total += wsum[i];
+  }
+  int64_t run = wbase + incl - sum;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i;
+    if (idx < count) out[idx] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == 0 && tile_sums) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ out, int64_t count, const int64_t* __restrict__ tile_off) {
+  const int64_t base = blockIdx.x * (int64_t)kScanTile;
+  const int64_t add = tile_off[blockIdx.x];
+  for (int i = threadIdx.x; i < kScanTile; i += kBlock) {
+    const int64_t idx = base + i;
+    if (idx < count) out[idx] += add;
+  }
+}
+
+__global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t value, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// Single block: thread t adds entries t, t + 256, ... in order; fixed tree.
+__global__ void k_sum_chunks(const double* __restrict__ chunks, int64_t nchunks, double divisor, double* out) {
+  __shared__ double lds[kBlock / kWave];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < nchunks; i += kBlock) acc += chunks[i];
+  const double r = block_sum_256(acc, lds);
+  if (threadIdx.x == 0) out[0] = r / divisor;
+}
+
+// Partials of a plain array over fixed chunks of 2048 entries.
+__global__ void k_array_chunks(const double* __restrict__ x, int64_t count, double* __restrict__ chunks) {
+  __shared__ double lds[kBlock / kWave];
+  const int64_t nchunks = (count + kScanTile - 1) / kScanTile;
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < kScanItems; ++j) {
+      const int64_t i = ch * kScanTile + (int64_t)j * kBlock + threadIdx.x;
+      if (i < count) acc += x[i];
+    }
+    const double r = block_sum_256(acc, lds);
+    if (threadIdx.x == 0) chunks[ch] = r;
+  }
+}
+
+__global__ void k_i64_to_i32(const int64_t* __restrict__ in, int32_t* __restrict__ out, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (int32_t)in[i];
+}
+
+}  // namespace
+
+// ---- host side ---------------------------------------------------------------
+
+int exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t count, hipStream_t s) {
+  if (count <= 0) return PG_OK;
+  const int64_t ntiles = (count + kScanTile - 1) / kScanTile;
+  if (ntiles == 1) {
+    hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(kBlock), 0, s, in, out, count, (int64_t*)nullptr);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+  }
+  int64_t* sums = nullptr;
+  PG_TRY(dmalloc((void**)&sums, sizeof(int64_t) * 2 * ntiles, s));
+  int64_t* offs = sums + ntiles;
+  hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)ntiles), dim3(kBlock), 0, s, in, out, count, sums);
+  PG_LAUNCH_CHECK();
+  PG_TRY(exclusive_scan_i64(sums, offs, ntiles, s));
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)ntiles), dim3(kBlock), 0, s, out, count, offs);
+  PG_LAUNCH_CHECK();
+  return dfree(sums, s);
+}
+
+int fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s) {
+  if (count <= 0) return PG_OK;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, kBlock, 4096)), dim3(kBlock), 0, s, p, value, count);
+  PG_LAUNCH_CHECK();
+  return PG_OK;
+}
+
+int sum_chunks(const double* chunks, int64_t nchunks, double divisor, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(kBlock), 0, s, chunks, nchunks, divisor, out);
+  PG_LAUNCH_CHECK();
+  return PG_OK;
+}
+
+int sum_array(const double* x, int64_t count, double divisor, double* out, hipStream_t s) {
+  const int64_t nchunks = std::max<int64_t>(1, (count + kScanTile - 1) / kScanTile);
+  double* chunks = nullptr;
+  PG_TRY(dmalloc((void**)&chunks, sizeof(double) * nchunks, s));
+  PG_HIP(hipMemsetAsync(chunks, 0, sizeof(double) * nchunks, s));
+  if (count > 0) {
+    hipLaunchKernelGGL(k_array_chunks, dim3((unsigned)std::min<int64_t>(nchunks, 65536)), dim3(kBlock), 0, s, x, count,
+                       chunks);
+    PG_LAUNCH_CHECK();
+  }
+  PG_TRY(sum_chunks(chunks, nchunks, divisor, out, s));
+  return dfree(chunks, s);
+}
+
+namespace {
+
+// Launch a group-per-vertex kernel over every degree bin.
+#define PG_FOR_BINS(KERNEL, g, s, ...)                                                               \
+  do {                                                                                               \
+    for (int bin_ = 0; bin_ < kNumBins; ++bin_) {                                                    \
+      const int64_t cnt_ = (g)->bin_start[bin_ + 1] - (g)->bin_start[bin_];                          \
+      if (cnt_ <= 0) continue;                                                                       \
+      const int32_t* verts_ = (g)->bin_verts + (g)->bin_start[bin_];                                 \
+      const int G_ = kBinGroup[bin_];                                                                \
+      const unsigned grid_ = (unsigned)((cnt_ * G_ + kBlock - 1) / kBlock);                          \
+      if (G_ == 4)                                                                                   \
+        hipLaunchKernelGGL(KERNEL<4>, dim3(grid_), dim3(kBlock), 0, s, __VA_ARGS__);                 \
+      else if (G_ == 16)                                                                             \
+        hipLaunchKernelGGL(KERNEL<16>, dim3(grid_), dim3(kBlock), 0, s, __VA_ARGS__);                \
+      else if (G_ == 64)                                                                             \
+        hipLaunchKernelGGL(KERNEL<64>, dim3(grid_), dim3(kBlock), 0, s, __VA_ARGS__);                \
+      else                                                                                           \
+        hipLaunchKernelGGL(KERNEL<256>, dim3(grid_), dim3(kBlock), 0, s, __VA_ARGS__);               \
+      PG_LAUNCH_CHECK();                                                                             \
+    }                                                                                                \
+  } while (0)
+
+}  // namespace
+
+int graph_prepare(pg_graph* g, bool validate, hipStream_t s) {
+  const int32_t n = g->n;
+  int* d_flags = nullptr;
+  int* d_maxdeg = nullptr;
+  unsigned long long* d_wedges = nullptr;
+  PG_TRY(dmalloc((void**)&d_flags, 64, s));
+  d_maxdeg = d_flags + 1;
+  d_wedges = (unsigned long long*)(d_flags + 2);
+  PG_HIP(hipMemsetAsync(d_flags, 0, 64, s));
+
+  // 1. bounds: offsets monotone in [0, nnz], IDs in [0, n). After this every
+  //    later kernel's indexing stays inside the arrays.
+  hipLaunchKernelGGL(k_check_offsets, dim3(grid_for((int64_t)n + 1, kBlock)), dim3(kBlock), 0, s, g->off, n, g->nnz,
+                     d_flags);
+  PG_LAUNCH_CHECK();
+  int h_flags = 0;
+  PG_HIP(hipMemcpyAsync(&h_flags, d_flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  if (h_flags) {
+    dfree(d_flags, s);
+    return fail(PG_E_GRAPH, "CSR offsets are not a monotone sequence from 0 to nnz");
+  }
+  if (g->nnz > 0) {
+    hipLaunchKernelGGL(k_check_range, dim3(grid_for(g->nnz, kBlock, 8192)), dim3(kBlock), 0, s, g->adj, g->nnz, n,
+                       d_flags);
+    PG_LAUNCH_CHECK();
+  }
+  if (validate && g->nnz > 0) {
+    PG_HIP(hipMemcpyAsync(&h_flags, d_flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (h_flags == 0) {
+      hipLaunchKernelGGL(k_check_structure, dim3(grid_for(g->nnz, kBlock, 8192)), dim3(kBlock), 0, s, g->off, g->adj,
+                         n, g->nnz, d_flags);
+      PG_LAUNCH_CHECK();
+    }
+  }
+  PG_HIP(hipMemcpyAsync(&h_flags, d_flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  if (h_flags) {
+    dfree(d_flags, s);
+    std::string why;
+    if (h_flags & kBadRange) why += " neighbour ID out of range;";
+    if (h_flags & kSelfLoop) why += " self-loop;";
+    if (h_flags & kUnsorted) why += " neighbourhood not strictly ascending (unsorted or duplicate);";
+    if (h_flags & kAsymmetric) why += " not symmetric;";
+    return fail(PG_E_GRAPH, "CSR rejected:" + why);
+  }
+
+  // 2. degrees, max degree, wedge count
+  PG_TRY(palloc((void**)&g->deg, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
+  if (n > 0) {
+    hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, g->off, n, g->deg, d_maxdeg,
+                       d_wedges);
+    PG_LAUNCH_CHECK();
+  }
+
+  // 3. degree bins (stable)
+  PG_TRY(palloc((void**)&g->bin_verts, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
+  const int64_t nblk = std::max<int64_t>(1, ((int64_t)n + kBlock - 1) / kBlock);
+  int64_t* counts = nullptr;
+  PG_TRY(dmalloc((void**)&counts, sizeof(int64_t) * 2 * kNumBins * nblk, s));
+  int64_t* base = counts + kNumBins * nblk;
+  std::vector<int64_t> hbase(kNumBins, 0);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)nblk), dim3(kBlock), 0, s, g->deg, n, counts, nblk);
+    PG_LAUNCH_CHECK();
+    PG_TRY(exclusive_scan_i64(counts, base, kNumBins * nblk, s));
+    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, s, g->deg, n, base, nblk, g->bin_verts);
+    PG_LAUNCH_CHECK();
+    for (int j = 0; j < kNumBins; ++j)
+      PG_HIP(hipMemcpyAsync(&hbase[j], base + j * nblk, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  }
+  int h_max = 0;
+  unsigned long long h_wedges = 0;
+  PG_HIP(hipMemcpyAsync(&h_max, d_maxdeg, sizeof(int), hipMemcpyDeviceToHost, s));
+  PG_HIP(hipMemcpyAsync(&h_wedges, d_wedges, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < kNumBins; ++j) g->bin_start[j] = hbase[j];
+  g->bin_start[kNumBins] = n;
+  g->max_degree = h_max;
+  g->wedges = h_wedges;
+
+  // 4. upper edges
+  int64_t* up = nullptr;
+  PG_TRY(dmalloc((void**)&up, sizeof(int64_t) * 2 * ((size_t)n + 1), s));
+  int64_t* up_off = up + (n + 1);
+  PG_HIP(hipMemsetAsync(up, 0, sizeof(int64_t) * ((size_t)n + 1), s));
+  PG_FOR_BINS(k_upper_count, g, s, g->off, g->adj, verts_, cnt_, up);
+  PG_TRY(exclusive_scan_i64(up, up_off, (int64_t)n + 1, s));
+  int64_t m = 0;
+  PG_HIP(hipMemcpyAsync(&m, up_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  g->m = m;
+  PG_TRY(palloc((void**)&g->eu, sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1)));
+  PG_TRY(palloc((void**)&g->ev, sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1)));
+  PG_FOR_BINS(k_upper_fill, g, s, g->off, g->adj, verts_, cnt_, up_off, g->eu, g->ev);
+  PG_TRY(dfree(up, s));
+  PG_TRY(dfree(counts, s));
+  PG_TRY(dfree(d_flags, s));
+  return PG_OK;
+}
+
+int graph_arc_sources(pg_graph* g, hipStream_t s) {
+  if (g->arc_src) return PG_OK;
+  PG_TRY(palloc((void**)&g->arc_src, sizeof(int32_t) * (size_t)std::max<int64_t>(g->nnz, 1)));
+  PG_FOR_BINS(k_arc_src, g, s, g->off, verts_, cnt_, g->arc_src);
+  return PG_OK;
+}
+
+int graph_orient(pg_graph* g, hipStream_t s) {
+  if (g->poff) return PG_OK;
+  const int32_t n = g->n;
+  int64_t* cnt = nullptr;
+  PG_TRY(dmalloc((void**)&cnt, sizeof(int64_t) * 2 * ((size_t)n + 1), s));
+  int64_t* poff64 = cnt + (n + 1);
+  PG_HIP(hipMemsetAsync(cnt, 0, sizeof(int64_t) * ((size_t)n + 1), s));
+  PG_FOR_BINS(k_orient_count, g, s, g->off, g->adj, g->deg, verts_, cnt_, cnt);
+  PG_TRY(exclusive_scan_i64(cnt, poff64, (int64_t)n + 1, s));
+  PG_TRY(palloc((void**)&g->padj, sizeof(int32_t) * (size_t)std::max<int64_t>(g->m, 1)));
+  PG_TRY(palloc((void**)&g->parc_src, sizeof(int32_t) * (size_t)std::max<int64_t>(g->m, 1)));
+  for (int bin = 0; bin < kNumBins; ++bin) {
+    const int64_t cnt_v = g->bin_start[bin + 1] - g->bin_start[bin];
+    if (cnt_v <= 0) continue;
+    const int32_t* verts = g->bin_verts + g->bin_start[bin];
+    const int G = std::min(kBinGroup[bin], kWave);
+    const unsigned grid = (unsigned)((cnt_v * G + kBlock - 1) / kBlock);
+    if (G == 4)
+      hipLaunchKernelGGL(k_orient_fill<4>, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, g->deg, verts, cnt_v,
+                         poff64, g->padj, g->parc_src);
+    else if (G == 16)
+      hipLaunchKernelGGL(k_orient_fill<16>, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, g->deg, verts, cnt_v,
+                         poff64, g->padj, g->parc_src);
+    else
+      hipLaunchKernelGGL(k_orient_fill<64>, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, g->deg, verts, cnt_v,
+                         poff64, g->padj, g->parc_src);
+    PG_LAUNCH_CHECK();
+  }
+  PG_TRY(palloc((void**)&g->poff, sizeof(int32_t) * ((size_t)n + 1)));
+  hipLaunchKernelGGL(k_i64_to_i32, dim3(grid_for((int64_t)n + 1, kBlock, 4096)), dim3(kBlock), 0, s, poff64, g->poff,
+                     (int64_t)n + 1);
+  PG_LAUNCH_CHECK();
+  return dfree(cnt, s);
+}
+
+}  // namespace pg

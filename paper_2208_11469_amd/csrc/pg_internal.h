@@ -1,0 +1,141 @@
+// Internal declarations of the ProbGraph GPU library: handle layouts, error
+// plumbing and the host-side launchers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "probgraph.h"
+
+namespace pg {
+
+// ---- errors ----------------------------------------------------------------
+void set_error(const std::string& msg);
+void clear_error();
+int fail(int code, const std::string& msg);
+
+#define PG_HIP(call)                                                                              \
+  do {                                                                                            \
+    hipError_t pg_e_ = (call);                                                                    \
+    if (pg_e_ != hipSuccess)                                                                      \
+      return ::pg::fail(PG_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(pg_e_));      \
+  } while (0)
+
+#define PG_TRY(call)                   \
+  do {                                 \
+    int pg_rc_ = (call);               \
+    if (pg_rc_ != PG_OK) return pg_rc_; \
+  } while (0)
+
+// Launch-error check right after a kernel launch.
+#define PG_LAUNCH_CHECK() PG_HIP(hipGetLastError())
+
+int dmalloc(void** p, size_t bytes, hipStream_t s);  // stream-ordered temporary device allocation
+int dfree(void* p, hipStream_t s);
+int palloc(void** p, size_t bytes);                 // long-lived device allocation
+int pfree(void* p);
+
+// ---- degree bins -----------------------------------------------------------
+// Vertices are partitioned once per graph by degree; per-vertex kernels map a
+// group of G lanes to one vertex, G growing with the bin.
+constexpr int kNumBins = 4;
+constexpr int32_t kBinMaxDeg[kNumBins - 1] = {16, 256, 4096};  // bin 3: d > 4096
+constexpr int kBinGroup[kNumBins] = {4, 16, 64, 256};
+
+}  // namespace pg
+
+struct pg_ctx {
+  int device = 0;
+  int num_cus = 0;
+  double* h_scalar = nullptr;  // pinned host slot for scalar results
+};
+
+struct pg_graph {
+  pg_ctx* ctx = nullptr;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int64_t m = 0;
+  int32_t max_degree = 0;
+  uint64_t wedges = 0;         // sum_v C(d_v, 2)
+  bool owns_csr = true;
+  int32_t* off = nullptr;      // [n+1]
+  int32_t* adj = nullptr;      // [nnz]
+  int32_t* deg = nullptr;      // [n]
+  int32_t* eu = nullptr;       // [m] smaller endpoint of each undirected edge
+  int32_t* ev = nullptr;       // [m] larger endpoint
+  int32_t* arc_src = nullptr;  // [nnz] source vertex of each arc
+  int32_t* bin_verts = nullptr;              // [n] vertices grouped by degree bin, ascending inside a bin
+  int64_t bin_start[pg::kNumBins + 1] = {};  // bin j = bin_verts[bin_start[j] .. bin_start[j+1])
+  // degree-oriented CSR for the exact node iterator (built on first use)
+  int32_t* poff = nullptr;     // [n+1]
+  int32_t* padj = nullptr;     // [m]
+  int32_t* parc_src = nullptr; // [m]
+  int live_sketches = 0;
+};
+
+struct pg_sketches {
+  pg_graph* g = nullptr;
+  int kind = 0;
+  uint32_t size = 0;   // B or k
+  uint32_t b = 1;
+  uint32_t W = 0;      // 64-bit words per Bloom-filter row
+  uint64_t seed = 0;
+  uint64_t* words = nullptr;  // [n*W]  Bloom filters
+  uint32_t* pc = nullptr;     // [n]    ones per filter
+  uint32_t* sig = nullptr;    // [n*k]  MinHash rows
+  uint64_t* ha = nullptr;     // device hash multipliers
+  uint64_t* hc = nullptr;     // device hash increments
+  double* table = nullptr;    // [B+1]  estimator table (Bloom filters)
+  int table_est = 0;          // estimator the table holds
+};
+
+namespace pg {
+
+// ---- launchers (pg_graph.hip) ------------------------------------------------
+int graph_prepare(pg_graph* g, bool validate, hipStream_t s);
+int graph_arc_sources(pg_graph* g, hipStream_t s);
+int graph_orient(pg_graph* g, hipStream_t s);
+int exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t count, hipStream_t s);
+int fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s);
+int sum_chunks(const double* chunks, int64_t nchunks, double divisor, double* out, hipStream_t s);
+int sum_array(const double* x, int64_t count, double divisor, double* out, hipStream_t s);
+
+// ---- launchers (pg_build.hip) ------------------------------------------------
+int build_bf(pg_sketches* sk, hipStream_t s);
+int build_khash(pg_sketches* sk, hipStream_t s);
+int build_onehash(pg_sketches* sk, hipStream_t s);
+
+// ---- launchers (pg_estimate.hip) ---------------------------------------------
+int ensure_table(pg_sketches* sk, int est, hipStream_t s);
+// Per pair: est / raw / Jaccard outputs (each nullable).
+int estimate_pairs(const pg_sketches* sk, int est, const int32_t* u, const int32_t* v, int64_t npairs,
+                   double* est_out, uint32_t* raw_out, float* jac_out, hipStream_t s);
+// Deterministic sum of the estimate over pairs into chunk partials; nchunks_out
+// receives the number of partials written to `chunks` (sized by chunk_count()).
+int64_t chunk_count(int64_t npairs);
+int estimate_sum(const pg_sketches* sk, int est, const int32_t* u, const int32_t* v, int64_t npairs,
+                 double* chunks, hipStream_t s);
+int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStream_t s);
+
+// ---- launchers (pg_exact.hip) ------------------------------------------------
+int exact_pairs(const pg_graph* g, int algo, const int32_t* u, const int32_t* v, int64_t npairs,
+                uint32_t* out, hipStream_t s);
+int exact_tc(pg_graph* g, int algo, uint64_t* d_tc, hipStream_t s);
+int exact_cc(pg_graph* g, float* cc, hipStream_t s);
+int exact_jaccard(const pg_graph* g, const int32_t* u, const int32_t* v, int64_t npairs, float* out,
+                  hipStream_t s);
+
+// ---- host utilities (pg_api.hip) ---------------------------------------------
+uint64_t splitmix64(uint64_t key, uint64_t i);
+void hash_constants(int kind, uint64_t seed, uint32_t count, uint64_t* a, uint64_t* c);
+
+inline unsigned grid_for(int64_t threads, int block, int64_t cap = 1 << 20) {
+  int64_t g = (threads + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace pg
