@@ -123,11 +123,20 @@ int pg_sketch_bits_for_budget(const pg_graph* g, double s, uint32_t* bits);
  *   kind PG_BF:       size = B bits, a multiple of 64 in [64, 4096]; b in [1, 16].
  *   kind PG_MH_KHASH: size = k in [1, 1024]; b ignored.
  *   kind PG_MH_1HASH: size = k in [1, 1024]; b ignored.
- * Hash constants are drawn from `seed` with SplitMix64 (see the design notes
- * shipped with the library); equal (graph, kind, size, b, seed) give
- * bit-identical sketches. Device layout: BF rows of B/64 uint64 words, bit i
- * of the filter = bit (i & 63) of word (i >> 6); MinHash rows of k uint32
- * vertex IDs (0xFFFFFFFF = empty slot), 1-hash rows in ascending hash order. */
+ * Hashing (the paper's MurmurHash3 with a time seed is replaced by a seeded,
+ * reproducible family):
+ *   mix(z)        = SplitMix64's output mix (Steele, Lea, Flood 2014)
+ *   sm(key, i)    = mix(key + (i+1) * 0x9E3779B97F4A7C15)
+ *   key           = seed XOR tag, tag = 0x42462D48 (PG_BF), 0x4B482D48
+ *                   (PG_MH_KHASH), 0x31482D48 (PG_MH_1HASH)
+ *   a_i = sm(key, 2i) | 1,  c_i = sm(key, 2i+1),  g_i(x) = a_i*x + c_i mod 2^64
+ *   Bloom-filter bit of x: ((g_i(x) >> 32) * B) >> 32, for i < b
+ *   MinHash key of x:      mix(g_i(x)) (injective on 64-bit words: no ties)
+ * Equal (graph, kind, size, b, seed) give bit-identical sketches. Device
+ * layout: BF rows of B/64 uint64 words, bit t of the filter = bit (t & 63) of
+ * word (t >> 6); MinHash rows of k uint32 vertex IDs (0xFFFFFFFF = empty
+ * slot); k-hash slot i holds the argmin of key_i; 1-hash rows hold the
+ * min(k, d_v) smallest keys' elements in ascending key order. */
 int pg_build_sketches(pg_ctx* ctx, const pg_graph* g, int kind, uint32_t size, uint32_t b, uint64_t seed,
                       void* stream, pg_sketches** out);
 int pg_sketches_destroy(pg_sketches* sk);
@@ -146,6 +155,10 @@ int pg_intersect_edges(pg_ctx* ctx, const pg_sketches* sk, int estimator, const 
 /* Estimated triangle count TC^ = (1/3) sum over the m edges of the estimate
  * (Section 7). *tc is a host pointer; waits for `stream`. */
 int pg_tc(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* tc, void* stream);
+
+/* Same estimate written to d_tc[0] (device FP64); enqueued on `stream`
+ * without waiting, so successive calls pipeline. */
+int pg_tc_async(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* d_tc, void* stream);
 
 /* Estimated local clustering coefficient cc[n] (device, FP32 rounded once
  * from FP64): cc_v = sum_{u in N_v} I^(u,v) / (d_v (d_v - 1)), 0 if d_v < 2.
@@ -172,6 +185,31 @@ int pg_exact_cc(pg_ctx* ctx, const pg_graph* g, float* cc, double* transitivity,
 /* Exact Jaccard similarity per pair (FP32); u = v = NULL: the m upper edges. */
 int pg_exact_jaccard(pg_ctx* ctx, const pg_graph* g, const int32_t* u, const int32_t* v, int64_t npairs,
                      float* out, void* stream);
+
+/* Recompute the rows of existing sketches in place (same kind, size and b;
+ * new hash constants from `seed`), e.g. after the graph's arrays changed or to
+ * draw a fresh sketch set. Allocates nothing. */
+int pg_sketches_rebuild(pg_ctx* ctx, pg_sketches* sk, uint64_t seed, void* stream);
+
+/* ---- measurement ----------------------------------------------------------- */
+typedef struct pg_kernel_time {
+  char name[48];     /* launch site, e.g. "bf_build", "pairs_sum" */
+  int64_t launches;  /* launches recorded since the last reset */
+  double total_ms;   /* summed device time between HIP events recorded on the launch stream */
+} pg_kernel_time;
+
+/* Per-kernel device timing: while enabled, every kernel launch of the library
+ * is bracketed by two HIP events on its stream. Process-wide. */
+int pg_profile_enable(pg_ctx* ctx, int enable);
+/* Wait for the recorded events and return up to `capacity` entries (host
+ * array); *count receives the number of distinct launch sites. */
+int pg_profile_read(pg_ctx* ctx, pg_kernel_time* out, int capacity, int* count);
+int pg_profile_reset(pg_ctx* ctx);
+
+/* Reference copy kernel: dst[i] = src[i] for `bytes` bytes (16-byte aligned
+ * device buffers, bytes a multiple of 16). Used to calibrate HBM byte
+ * counters and to measure the achievable copy bandwidth. */
+int pg_copy(pg_ctx* ctx, void* dst, const void* src, size_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -53,6 +53,7 @@ def _load():
     u64p = ctypes.POINTER(ctypes.c_uint64)
     u64, i32, i64, u32 = ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     sig = {
+        "or_threads": (ctypes.c_int, []),
         "or_splitmix64": (u64, [u64, u64]),
         "or_hash_consts": (None, [ctypes.c_int, u64, ctypes.c_int, u64p, u64p]),
         "or_bf_index": (u32, [u64, u64, u32, u32]),
@@ -84,6 +85,11 @@ def _ptr(a, ct):
 
 def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().or_threads())
 
 
 # ---------------------------------------------------------------- hashing

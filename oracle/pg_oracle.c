@@ -27,6 +27,7 @@
  *                        so two different vertices never tie.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -37,6 +38,9 @@
 #define OR_TAG_BF 0x42462D48ull  /* "BF-H" */
 #define OR_TAG_KH 0x4B482D48ull  /* "KH-H" */
 #define OR_TAG_1H 0x31482D48ull  /* "1H-H" */
+
+/* Threads an OpenMP loop of this library uses (reported with CPU timings). */
+int or_threads(void) { return omp_get_max_threads(); }
 
 /* ---------------------------------------------------------------- hashing */
 

@@ -64,6 +64,10 @@ class _GraphInfo(ctypes.Structure):
                 ("m", ctypes.c_int64)]
 
 
+class _KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
 class _SketchInfo(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("size", ctypes.c_uint32), ("b", ctypes.c_uint32),
                 ("row_bytes", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64)]
@@ -92,12 +96,18 @@ def _declare(lib):
         "pg_sketches_export": (i, [_vp, _vp, _vp, _vp]),
         "pg_intersect_edges": (i, [_vp, _vp, i, _vp, _vp, i64, _vp, _vp, _vp]),
         "pg_tc": (i, [_vp, _vp, i, P(ctypes.c_double), _vp]),
+        "pg_tc_async": (i, [_vp, _vp, i, _vp, _vp]),
         "pg_cc": (i, [_vp, _vp, i, _vp, P(ctypes.c_double), _vp]),
         "pg_jaccard": (i, [_vp, _vp, i, _vp, _vp, i64, _vp, _vp]),
         "pg_exact_intersect_edges": (i, [_vp, _vp, i, _vp, _vp, i64, _vp, _vp]),
         "pg_exact_tc": (i, [_vp, _vp, i, P(u64), _vp]),
         "pg_exact_cc": (i, [_vp, _vp, _vp, P(ctypes.c_double), _vp]),
         "pg_exact_jaccard": (i, [_vp, _vp, _vp, _vp, i64, _vp, _vp]),
+        "pg_sketches_rebuild": (i, [_vp, _vp, u64, _vp]),
+        "pg_profile_enable": (i, [_vp, i]),
+        "pg_profile_read": (i, [_vp, P(_KernelTime), i, P(i)]),
+        "pg_profile_reset": (i, [_vp]),
+        "pg_copy": (i, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -233,6 +243,11 @@ def pg_tc(ctx, sk, estimator, stream=None) -> float:
     return float(out.value)
 
 
+def pg_tc_async(ctx, sk, estimator, d_tc, stream=None):
+    torch = _torch()
+    _check(load().pg_tc_async(ctx, sk, estimator, _dptr(d_tc, torch.float64), _stream(stream)))
+
+
 def pg_cc(ctx, sk, estimator, cc, want_transitivity=False, stream=None):
     t = ctypes.c_double()
     _check(load().pg_cc(ctx, sk, estimator, _dptr(cc), ctypes.byref(t) if want_transitivity else None,
@@ -262,6 +277,31 @@ def pg_exact_cc(ctx, g, cc, want_transitivity=False, stream=None):
 
 def pg_exact_jaccard(ctx, g, u, v, npairs, out, stream=None):
     _check(load().pg_exact_jaccard(ctx, g, _dptr(u), _dptr(v), npairs, _dptr(out), _stream(stream)))
+
+
+def pg_sketches_rebuild(ctx, sk, seed, stream=None):
+    _check(load().pg_sketches_rebuild(ctx, sk, seed & (2**64 - 1), _stream(stream)))
+
+
+def pg_profile_enable(ctx, enable: bool):
+    _check(load().pg_profile_enable(ctx, 1 if enable else 0))
+
+
+def pg_profile_read(ctx) -> dict:
+    """{launch site: (launches, total_ms)} since the last reset (waits for the events)."""
+    cap = 64
+    arr = (_KernelTime * cap)()
+    cnt = ctypes.c_int()
+    _check(load().pg_profile_read(ctx, arr, cap, ctypes.byref(cnt)))
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(cnt.value, cap))}
+
+
+def pg_profile_reset(ctx):
+    _check(load().pg_profile_reset(ctx))
+
+
+def pg_copy(ctx, dst, src, nbytes, stream=None):
+    _check(load().pg_copy(ctx, _dptr(dst), _dptr(src), nbytes, _stream(stream)))
 
 
 # ---- handle classes ---------------------------------------------------------------
@@ -395,6 +435,12 @@ class Sketches:
             pg_sketches_destroy(self.h)
             self.h = None
 
+    def rebuild(self, seed=None, stream=None):
+        """Recompute the rows in place (optionally from a new seed); allocates nothing."""
+        seed = self.seed if seed is None else seed
+        pg_sketches_rebuild(self.graph.ctx.h, self.h, seed, stream)
+        self.seed = seed
+
     def export(self, stream=None):
         """(rows, pc): rows as uint8 [n, row_bytes] device tensor; pc int32 [n] or None."""
         torch = _torch()
@@ -422,6 +468,11 @@ class Sketches:
 
     def tc(self, estimator, stream=None) -> float:
         return pg_tc(self.graph.ctx.h, self.h, ESTIMATORS.get(estimator, estimator), stream)
+
+    def tc_async(self, estimator, out, stream=None):
+        """Enqueue the estimate into out[0] (float64 device tensor) without waiting."""
+        pg_tc_async(self.graph.ctx.h, self.h, ESTIMATORS.get(estimator, estimator), out, stream)
+        return out
 
     def cc(self, estimator, transitivity=False, stream=None):
         torch = _torch()

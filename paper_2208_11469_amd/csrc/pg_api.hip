@@ -98,6 +98,10 @@ void free_graph(pg_graph* g) {
   pfree(g->poff);
   pfree(g->padj);
   pfree(g->parc_src);
+  pfree(g->ustart);
+  pfree(g->upoff);
+  free_plan(&g->plan_all);
+  free_plan(&g->plan_up);
   delete g;
 }
 
@@ -109,6 +113,7 @@ void free_sketches(pg_sketches* sk) {
   pfree(sk->ha);
   pfree(sk->hc);
   pfree(sk->table);
+  pfree(sk->scratch);
   delete sk;
 }
 
@@ -306,6 +311,9 @@ int pg_build_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, 
     if (rc == PG_OK) rc = palloc((void**)&sk->words, sizeof(uint64_t) * sk->W * n);
     if (rc == PG_OK) rc = palloc((void**)&sk->pc, sizeof(uint32_t) * n);
     if (rc == PG_OK) rc = palloc((void**)&sk->table, sizeof(double) * (size + 1));
+    if (rc == PG_OK)
+      rc = palloc((void**)&sk->scratch, sizeof(uint64_t) * sk->W * (size_t)std::max<int64_t>(g->plan_all.n_chunks, 1));
+
     if (rc == PG_OK && g->n > 0) rc = build_bf(sk, s);
   } else {
     if (rc == PG_OK) rc = palloc((void**)&sk->sig, sizeof(uint32_t) * size * n);
@@ -319,6 +327,26 @@ int pg_build_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, 
   g->live_sketches++;
   *out = sk;
   return PG_OK;
+}
+
+int pg_sketches_rebuild(pg_ctx* ctx, pg_sketches* sk, uint64_t seed, void* stream) {
+  clear_error();
+  if (!ctx || !sk) return fail(PG_E_INVALID, "NULL argument");
+  PG_TRY(use_device(ctx));
+  hipStream_t s = (hipStream_t)stream;
+  if (seed != sk->seed) {
+    const uint32_t nh = sk->kind == PG_BF ? sk->b : (sk->kind == PG_MH_KHASH ? sk->size : 1);
+    uint64_t ha[1024], hc[1024];
+    hash_constants(sk->kind, seed, nh, ha, hc);
+    PG_HIP(hipMemcpyAsync(sk->ha, ha, sizeof(uint64_t) * nh, hipMemcpyHostToDevice, s));
+    PG_HIP(hipMemcpyAsync(sk->hc, hc, sizeof(uint64_t) * nh, hipMemcpyHostToDevice, s));
+    PG_HIP(hipStreamSynchronize(s));  // the host arrays are on this stack frame
+    sk->seed = seed;
+  }
+  if (sk->g->n == 0) return PG_OK;
+  if (sk->kind == PG_BF) return build_bf(sk, s);
+  if (sk->kind == PG_MH_KHASH) return build_khash(sk, s);
+  return build_onehash(sk, s);
 }
 
 int pg_sketches_destroy(pg_sketches* sk) {
@@ -376,20 +404,19 @@ int pg_tc(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* tc, void* s
   if (!ctx || !sk || !tc) return fail(PG_E_INVALID, "NULL argument");
   PG_TRY(use_device(ctx));
   hipStream_t s = (hipStream_t)stream;
-  const pg_graph* g = sk->g;
-  const int64_t nchunks = chunk_count(g->m);
-  double* buf = nullptr;
-  PG_TRY(dmalloc((void**)&buf, sizeof(double) * (size_t)(nchunks + 1), s));
-  int rc = PG_OK;
-  if (nchunks == 0) {
-    PG_HIP(hipMemsetAsync(buf, 0, sizeof(double), s));
-  } else {
-    rc = estimate_sum(sk, estimator, g->eu, g->ev, g->m, buf, s);
-    if (rc == PG_OK) rc = sum_chunks(buf, nchunks, 3.0, buf + nchunks, s);
-  }
-  if (rc == PG_OK) rc = scalar_to_host(ctx, buf + nchunks, tc, s);
-  dfree(buf, s);
+  double* d = nullptr;
+  PG_TRY(dmalloc((void**)&d, sizeof(double), s));
+  int rc = estimate_tc(sk, estimator, d, s);
+  if (rc == PG_OK) rc = scalar_to_host(ctx, d, tc, s);
+  dfree(d, s);
   return rc;
+}
+
+int pg_tc_async(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* d_tc, void* stream) {
+  clear_error();
+  if (!ctx || !sk || !d_tc) return fail(PG_E_INVALID, "NULL argument");
+  PG_TRY(use_device(ctx));
+  return estimate_tc(sk, estimator, d_tc, (hipStream_t)stream);
 }
 
 int pg_cc(pg_ctx* ctx, const pg_sketches* sk, int estimator, float* cc, double* transitivity, void* stream) {

@@ -80,6 +80,145 @@ __global__ __launch_bounds__(kBlock) void k_bf_build(const int32_t* __restrict__
   }
 }
 
+// ---- Bloom filter over a vertex work plan (W <= 16 words) -------------------
+//
+// One launch, three tiers (heavy chunks first): heavy vertices are split into
+// chunks of kHeavyChunk arcs, one block each; medium vertices get a wave;
+// light vertices (at most kLightMax neighbours) get kLightGroup lanes.
+//
+// Bit scatter: every lane owns a private W-word bitmap in LDS and sets the bit
+// of each hashed neighbour with a plain read-OR-write (no atomics, no lane
+// ever touches another lane's words). The lanes serving one vertex are then
+// combined by OR-ing their bitmaps word by word. Each lane issues U neighbour
+// loads before hashing any of them.
+
+constexpr int kLdsStride = kBlock + 1;  // words of one bitmap slot across the block; odd stride spreads banks
+
+template <int W, int U, int G>
+__device__ __forceinline__ void bf_scatter(const int32_t* __restrict__ adj, int64_t beg, int64_t end, int lane,
+                                           uint32_t B, uint32_t b, const uint64_t* __restrict__ ha,
+                                           const uint64_t* __restrict__ hc, uint64_t* __restrict__ mine) {
+  for (int64_t p0 = beg + lane; p0 < end; p0 += (int64_t)G * U) {
+    uint32_t x[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int64_t p = p0 + (int64_t)j * G;
+      x[j] = p < end ? (uint32_t)adj[p] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (p0 + (int64_t)j * G < end) {
+        for (uint32_t i = 0; i < b; ++i) {
+          const uint32_t idx = bf_index(ha[i], hc[i], x[j], B);
+          mine[(idx >> 6) * kLdsStride] |= 1ull << (idx & 63u);
+        }
+      }
+    }
+  }
+}
+
+// OR of the G lane bitmaps starting at thread `first`, for word k.
+template <int G>
+__device__ __forceinline__ uint64_t bf_gather_word(const uint64_t* __restrict__ lds, int first, int k) {
+  uint64_t acc = 0;
+  const uint64_t* p = lds + k * kLdsStride + first;
+#pragma unroll 8
+  for (int i = 0; i < G; ++i) acc |= p[i];
+  return acc;
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_bf_build_plan(PlanView P, const int32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ adj, uint32_t B, uint32_t b,
+                                                          const uint64_t* __restrict__ ha,
+                                                          const uint64_t* __restrict__ hc, uint64_t* __restrict__ words,
+                                                          uint32_t* __restrict__ pc, uint64_t* __restrict__ part) {
+  __shared__ uint64_t lds[W * kLdsStride];
+  __shared__ uint32_t ones_lds[kBlock / kWave][W];
+  const int64_t blk = blockIdx.x;
+  const int tid = threadIdx.x;
+  uint64_t* mine = lds + tid;
+#pragma unroll
+  for (int k = 0; k < W; ++k) mine[k * kLdsStride] = 0;
+
+  if (blk < P.n_chunks) {  // ---- heavy chunk: the whole block; partial row to `part`
+    bf_scatter<W, 8, kBlock>(adj, P.chunk_begin[blk], P.chunk_end[blk], tid, B, b, ha, hc, mine);
+    __syncthreads();
+    if (tid < W) part[blk * W + tid] = bf_gather_word<kBlock>(lds, 0, tid);
+    return;
+  }
+  const int64_t mb = blk - P.n_chunks;
+  if (mb < P.n_medium_blocks) {  // ---- medium: one wave per vertex
+    const int wv = tid / kWave;
+    const int64_t idx = mb * (kBlock / kWave) + wv;
+    const bool active = idx < P.n_medium;
+    const int32_t v = active ? P.medium[idx] : 0;
+    if (active) bf_scatter<W, 8, kWave>(adj, off[v], off[v + 1], lane_id(), B, b, ha, hc, mine);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int lane = lane_id();
+    if (active && lane < W) {
+      const uint64_t w = bf_gather_word<kWave>(lds, wv * kWave, lane);
+      words[(size_t)v * W + lane] = w;
+      ones_lds[wv][lane] = (uint32_t)__popcll(w);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (active && lane == 0) {
+      uint32_t ones = 0;
+#pragma unroll
+      for (int k = 0; k < W; ++k) ones += ones_lds[wv][k];
+      pc[v] = ones;
+    }
+    return;
+  }
+  // ---- light: kLightGroup lanes per vertex of the light list
+  const int64_t idx = ((mb - P.n_medium_blocks) * kBlock + tid) / kLightGroup;
+  const int lane = tid % kLightGroup;
+  bool active = idx < P.n_light;
+  const int32_t v = active ? (P.light ? P.light[idx] : (int32_t)idx) : 0;
+  int64_t beg = 0, end = 0;
+  if (active) {
+    beg = off[v];
+    end = off[v + 1];
+    active = P.light || end - beg <= kLightMax;
+  }
+  if (active) bf_scatter<W, 4, kLightGroup>(adj, beg, end, lane, B, b, ha, hc, mine);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint32_t ones = 0;
+  if (active) {
+    uint64_t* row = words + (size_t)v * W;
+    for (int k = lane; k < W; k += kLightGroup) {
+      const uint64_t w = bf_gather_word<kLightGroup>(lds, tid - lane, k);
+      row[k] = w;
+      ones += (uint32_t)__popcll(w);
+    }
+  }
+  ones = group_sum_u32<kLightGroup>(ones);
+  if (active && lane == 0) pc[v] = ones;
+}
+
+// Heavy vertices: OR of the chunk partials in chunk order; one wave per vertex.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_bf_combine(PlanView P, const uint64_t* __restrict__ part, int64_t n_heavy,
+                                                       uint64_t* __restrict__ words, uint32_t* __restrict__ pc) {
+  const int64_t h = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+  if (h >= n_heavy) return;
+  const int lane = lane_id();
+  const int32_t c0 = P.heavy_first[h], c1 = P.heavy_first[h + 1];
+  const int32_t v = P.chunk_vertex[c0];
+  uint64_t acc = 0;
+  if (lane < W)
+    for (int32_t c = c0; c < c1; ++c) acc |= part[(int64_t)c * W + lane];
+  if (lane < W) words[(size_t)v * W + lane] = acc;
+  const uint32_t ones = group_sum_u32<kWave>((uint32_t)__popcll(acc));
+  if (lane == 0) pc[v] = ones;
+}
+
 // Filters wider than 16 words: one wave per vertex, lane w owns word w
 // (W <= 64); every lane evaluates all hashes and keeps the bits of its word.
 __global__ __launch_bounds__(kBlock) void k_bf_build_wide(const int32_t* __restrict__ off,
@@ -319,7 +458,43 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
 
 int build_bf(pg_sketches* sk, hipStream_t s) {
   const pg_graph* g = sk->g;
+  ProfScope ps(s, "bf_build");
   const uint32_t W = sk->W;
+  if (W <= 16 && g->n > 0) {
+    const VertexPlan& P = g->plan_all;
+    const PlanView pv = plan_view(P);
+    const unsigned grid = (unsigned)plan_blocks(P);
+    const unsigned cgrid = (unsigned)((P.n_heavy * kWave + kBlock - 1) / kBlock);
+#define PG_BFP(WW)                                                                                                 \
+  do {                                                                                                             \
+    hipLaunchKernelGGL((k_bf_build_plan<WW>), dim3(grid), dim3(kBlock), 0, s, pv, g->off, g->adj, sk->size, sk->b, \
+                       sk->ha, sk->hc, sk->words, sk->pc, sk->scratch);                                            \
+    if (P.n_heavy > 0)                                                                                             \
+      hipLaunchKernelGGL((k_bf_combine<WW>), dim3(cgrid), dim3(kBlock), 0, s, pv, (const uint64_t*)sk->scratch,    \
+                         P.n_heavy, sk->words, sk->pc);                                                            \
+  } while (0)
+    switch (W) {
+      case 1: PG_BFP(1); break;
+      case 2: PG_BFP(2); break;
+      case 3: PG_BFP(3); break;
+      case 4: PG_BFP(4); break;
+      case 5: PG_BFP(5); break;
+      case 6: PG_BFP(6); break;
+      case 7: PG_BFP(7); break;
+      case 8: PG_BFP(8); break;
+      case 9: PG_BFP(9); break;
+      case 10: PG_BFP(10); break;
+      case 11: PG_BFP(11); break;
+      case 12: PG_BFP(12); break;
+      case 13: PG_BFP(13); break;
+      case 14: PG_BFP(14); break;
+      case 15: PG_BFP(15); break;
+      default: PG_BFP(16); break;
+    }
+#undef PG_BFP
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+  }
   if (W > 16) {
     if (g->n > 0) {
       hipLaunchKernelGGL(k_bf_build_wide, dim3(grid_for((int64_t)g->n * kWave, kBlock, 1ll << 31)), dim3(kBlock), 0,
@@ -365,6 +540,7 @@ int build_bf(pg_sketches* sk, hipStream_t s) {
 
 int build_khash(pg_sketches* sk, hipStream_t s) {
   const pg_graph* g = sk->g;
+  ProfScope ps(s, "kh_build");
   for (int bin = 0; bin < kNumBins; ++bin) {
     const int64_t cnt = g->bin_start[bin + 1] - g->bin_start[bin];
     if (cnt <= 0) continue;
@@ -395,6 +571,7 @@ int build_onehash(pg_sketches* sk, hipStream_t s) {
   const size_t shmem = (size_t)kOhWaves * oh_wave_bytes(sk->size);
   uint64_t a = 0, c = 0;
   hash_constants(PG_MH_1HASH, sk->seed, 1, &a, &c);
+  ProfScope ps(s, "oh_build");
   // all vertices, in bin order (degree-sorted blocks balance better)
   hipLaunchKernelGGL(k_oh_build, dim3((unsigned)((nv + kOhWaves - 1) / kOhWaves)), dim3(kBlock), shmem, s, g->off,
                      g->adj, g->bin_verts, nv, sk->size, a, c, sk->sig);

@@ -233,6 +233,108 @@ __global__ __launch_bounds__(kBlock) void k_cc(SkView s, const int32_t* __restri
   }
 }
 
+// ---- triangle count over the upper-neighbour plan (Bloom filters, W <= 16) ----
+//
+// Vertex-centric: the group owning v keeps B_v in registers and walks the
+// neighbours above v straight from the CSR, gathering U rows per lane before
+// reducing any of them. The estimator table sits in LDS. Every block writes
+// one partial sum; the final fixed-order sum makes the result independent of
+// scheduling.
+
+template <int W>
+struct RowUnroll {
+  static constexpr int value = W <= 4 ? 8 : (W <= 8 ? 4 : 2);
+};
+
+template <int W, int U, int G, bool OR>
+__device__ __forceinline__ double bf_row_sum(const SkView& s, const uint64_t (&ru)[W], int32_t du, uint32_t pcu,
+                                             const int32_t* __restrict__ adj, int64_t beg, int64_t end, int lane,
+                                             const double* __restrict__ tab) {
+  double acc = 0.0;
+  for (int64_t p0 = beg + lane; p0 < end; p0 += (int64_t)G * U) {
+    int32_t x[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int64_t p = p0 + (int64_t)j * G;
+      x[j] = p < end ? adj[p] : -1;
+    }
+    uint64_t rv[U][W];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (x[j] >= 0) {
+        const uint64_t* r = s.words + (size_t)x[j] * W;
+#pragma unroll
+        for (int k = 0; k < W; ++k) rv[j][k] = r[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k) rv[j][k] = 0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (x[j] >= 0) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) c += (uint32_t)__popcll(ru[k] & rv[j][k]);
+        if constexpr (OR)
+          acc += ((double)du + (double)s.deg[x[j]]) + tab[pcu + s.pc[x[j]] - c];
+        else
+          acc += tab[c];
+      }
+    }
+  }
+  return acc;
+}
+
+template <int W>
+__device__ __forceinline__ void load_row(const uint64_t* __restrict__ words, int32_t v, uint64_t (&r)[W]) {
+  const uint64_t* p = words + (size_t)v * W;
+#pragma unroll
+  for (int k = 0; k < W; ++k) r[k] = p[k];
+}
+
+template <int W, bool OR>
+__global__ __launch_bounds__(kBlock) void k_bf_tc_plan(PlanView P, SkView s, const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ ustart,
+                                                       const int32_t* __restrict__ adj, double* __restrict__ partials) {
+  extern __shared__ double tab[];
+  __shared__ double red[kBlock / kWave];
+  for (uint32_t i = threadIdx.x; i <= s.size; i += kBlock) tab[i] = s.table[i];
+  __syncthreads();
+  constexpr int U = RowUnroll<W>::value;
+  const int64_t blk = blockIdx.x;
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  uint64_t ru[W];
+  if (blk < P.n_chunks) {  // heavy chunk: the whole block
+    const int32_t v = P.chunk_vertex[blk];
+    load_row<W>(s.words, v, ru);
+    acc = bf_row_sum<W, U, kBlock, OR>(s, ru, OR ? s.deg[v] : 0, OR ? s.pc[v] : 0u, adj, P.chunk_begin[blk],
+                                       P.chunk_end[blk], tid, tab);
+  } else {
+    const int64_t mb = blk - P.n_chunks;
+    if (mb < P.n_medium_blocks) {  // medium: one wave per vertex
+      const int64_t idx = mb * (kBlock / kWave) + tid / kWave;
+      if (idx < P.n_medium) {
+        const int32_t v = P.medium[idx];
+        load_row<W>(s.words, v, ru);
+        acc = bf_row_sum<W, U, kWave, OR>(s, ru, OR ? s.deg[v] : 0, OR ? s.pc[v] : 0u, adj, ustart[v], off[v + 1],
+                                          lane_id(), tab);
+      }
+    } else {  // light: kLightGroup lanes per vertex of the light list
+      const int64_t idx = ((mb - P.n_medium_blocks) * kBlock + tid) / kLightGroup;
+      if (idx < P.n_light) {  // the upper plan always lists its light vertices
+        const int32_t v = P.light[idx];
+        load_row<W>(s.words, v, ru);
+        acc = bf_row_sum<W, U, kLightGroup, OR>(s, ru, OR ? s.deg[v] : 0, OR ? s.pc[v] : 0u, adj, ustart[v],
+                                                off[v + 1], tid % kLightGroup, tab);
+      }
+    }
+  }
+  const double r = block_sum_256(acc, red);
+  if (tid == 0) partials[blk] = r;
+}
+
 __global__ void k_make_table(double* __restrict__ t, uint32_t B, uint32_t b, int est) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c > B) return;
@@ -320,6 +422,7 @@ int ensure_table(pg_sketches* sk, int est, hipStream_t s) {
   if (sk->kind != PG_BF) return PG_OK;
   if (sk->table_est == est) return PG_OK;
   const uint32_t entries = sk->size + 1;
+  ProfScope ps(s, "table");
   hipLaunchKernelGGL(k_make_table, dim3((entries + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sk->table, sk->size,
                      sk->b, est);
   PG_LAUNCH_CHECK();
@@ -334,6 +437,7 @@ int estimate_pairs(const pg_sketches* sk, int est, const int32_t* u, const int32
   if (npairs <= 0) return PG_OK;
   const SkView view = make_view(sk, est);
   const unsigned grid = grid_for(npairs, kBlock, 65536);
+  ProfScope ps(s, "pairs");
 #define PG_LAUNCH_PAIRS(KIND, WT) \
   hipLaunchKernelGGL((k_pairs<KIND, WT>), dim3(grid), dim3(kBlock), 0, s, view, u, v, npairs, est_out, raw_out, jac_out)
   PG_DISPATCH(sk, PG_LAUNCH_PAIRS);
@@ -350,6 +454,7 @@ int estimate_sum(const pg_sketches* sk, int est, const int32_t* u, const int32_t
   if (nchunks <= 0) return PG_OK;
   const SkView view = make_view(sk, est);
   const unsigned grid = (unsigned)std::min<int64_t>(nchunks, 65536);
+  ProfScope ps(s, "pairs_sum");
 #define PG_LAUNCH_SUM(KIND, WT) \
   hipLaunchKernelGGL((k_pairs_sum<KIND, WT>), dim3(grid), dim3(kBlock), 0, s, view, u, v, npairs, chunks)
   PG_DISPATCH(sk, PG_LAUNCH_SUM);
@@ -358,11 +463,69 @@ int estimate_sum(const pg_sketches* sk, int est, const int32_t* u, const int32_t
   return PG_OK;
 }
 
+int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
+  PG_TRY(check_estimator(sk, est));
+  PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
+  const pg_graph* g = sk->g;
+  if (sk->kind == PG_BF && sk->W <= 16 && g->n > 0) {
+    const VertexPlan& P = g->plan_up;
+    const int64_t nblk = std::max<int64_t>(plan_blocks(P), 1);
+    double* partials = nullptr;
+    PG_TRY(dmalloc((void**)&partials, sizeof(double) * (size_t)nblk, s));
+    const SkView view = make_view(sk, est);
+    const PlanView pv = plan_view(P);
+    const size_t shmem = sizeof(double) * ((size_t)sk->size + 1);
+    {
+      ProfScope ps(s, "bf_tc");
+#define PG_TCP(WW)                                                                                                    \
+  do {                                                                                                                \
+    if (est == PG_EST_BF_OR)                                                                                          \
+      hipLaunchKernelGGL((k_bf_tc_plan<WW, true>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, pv, view, g->off,    \
+                         g->ustart, g->adj, partials);                                                                \
+    else                                                                                                              \
+      hipLaunchKernelGGL((k_bf_tc_plan<WW, false>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, pv, view, g->off,   \
+                         g->ustart, g->adj, partials);                                                                \
+  } while (0)
+      switch (sk->W) {
+        case 1: PG_TCP(1); break;
+        case 2: PG_TCP(2); break;
+        case 3: PG_TCP(3); break;
+        case 4: PG_TCP(4); break;
+        case 5: PG_TCP(5); break;
+        case 6: PG_TCP(6); break;
+        case 7: PG_TCP(7); break;
+        case 8: PG_TCP(8); break;
+        case 9: PG_TCP(9); break;
+        case 10: PG_TCP(10); break;
+        case 11: PG_TCP(11); break;
+        case 12: PG_TCP(12); break;
+        case 13: PG_TCP(13); break;
+        case 14: PG_TCP(14); break;
+        case 15: PG_TCP(15); break;
+        default: PG_TCP(16); break;
+      }
+#undef PG_TCP
+      PG_LAUNCH_CHECK();
+    }
+    PG_TRY(sum_chunks(partials, nblk, 3.0, d_out, s));
+    return dfree(partials, s);
+  }
+  // general path: one lane per upper edge, fixed chunks
+  const int64_t nchunks = std::max<int64_t>(chunk_count(g->m), 1);
+  double* chunks = nullptr;
+  PG_TRY(dmalloc((void**)&chunks, sizeof(double) * (size_t)nchunks, s));
+  PG_TRY(fill_u64((uint64_t*)chunks, 0, nchunks, s));
+  if (g->m > 0) PG_TRY(estimate_sum(sk, est, g->eu, g->ev, g->m, chunks, s));
+  PG_TRY(sum_chunks(chunks, nchunks, 3.0, d_out, s));
+  return dfree(chunks, s);
+}
+
 int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStream_t s) {
   PG_TRY(check_estimator(sk, est));
   PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
   const pg_graph* g = sk->g;
   const SkView view = make_view(sk, est);
+  ProfScope ps(s, "cc");
   for (int bin = 0; bin < kNumBins; ++bin) {
     const int64_t cnt = g->bin_start[bin + 1] - g->bin_start[bin];
     if (cnt <= 0) continue;

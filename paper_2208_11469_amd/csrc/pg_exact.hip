@@ -186,6 +186,7 @@ int exact_pairs(const pg_graph* g, int algo, const int32_t* u, const int32_t* v,
   if (algo != PG_EXACT_MERGE) return fail(PG_E_UNSUPPORTED, "only PG_EXACT_MERGE is implemented for pair lists");
   if (npairs <= 0) return PG_OK;
   const unsigned grid = grid_for((npairs + kWave - 1) / kWave * kWave, kBlock, 65536);
+  ProfScope ps(s, "exact_pairs");
   hipLaunchKernelGGL(k_exact_pairs, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, g->n, u, v, npairs, out,
                      (unsigned long long*)nullptr);
   PG_LAUNCH_CHECK();
@@ -198,6 +199,7 @@ int exact_tc(pg_graph* g, int algo, uint64_t* d_tc, hipStream_t s) {
   PG_TRY(fill_u64(d_tc, 0, 1, s));
   if (g->m <= 0) return PG_OK;
   const unsigned grid = grid_for((g->m + kWave - 1) / kWave * kWave, kBlock, 65536);
+  ProfScope ps(s, "exact_tc");
   hipLaunchKernelGGL(k_exact_tc, dim3(grid), dim3(kBlock), 0, s, g->poff, g->padj, g->parc_src, g->m,
                      (unsigned long long*)d_tc);
   PG_LAUNCH_CHECK();
@@ -209,6 +211,7 @@ int exact_cc(pg_graph* g, float* cc, hipStream_t s) {
   uint64_t* vsum = nullptr;
   PG_TRY(dmalloc((void**)&vsum, sizeof(uint64_t) * (size_t)g->n, s));
   PG_TRY(fill_u64(vsum, 0, g->n, s));
+  ProfScope ps(s, "exact_cc");
   if (g->m > 0) {
     const unsigned grid = grid_for((g->m + kWave - 1) / kWave * kWave, kBlock, 65536);
     hipLaunchKernelGGL(k_exact_pairs, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, g->n, g->eu, g->ev, g->m,

@@ -104,11 +104,27 @@ __device__ __forceinline__ int degree_bin(int32_t d) {
   return d <= kBinMaxDeg[0] ? 0 : d <= kBinMaxDeg[1] ? 1 : d <= kBinMaxDeg[2] ? 2 : 3;
 }
 
-// Stable partition of the vertices by degree bin: per-block counts (bin-major).
-__global__ void k_bin_count(const int32_t* __restrict__ deg, int32_t n, int64_t* __restrict__ counts, int64_t nblk) {
+__global__ void k_degree_bin_keys(const int32_t* __restrict__ deg, int32_t n, uint8_t* __restrict__ key) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v < n) key[v] = (uint8_t)degree_bin(deg[v]);
+}
+
+// Plan tier of a vertex by the arcs it owns: 0 dropped (no upper arcs),
+// 1 light, 2 medium, 3 heavy.
+__global__ void k_plan_keys(const int32_t* __restrict__ off, const int32_t* __restrict__ ustart, int32_t n,
+                            uint8_t* __restrict__ key) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t d = off[v + 1] - (ustart ? ustart[v] : off[v]);
+  key[v] = (ustart && d == 0) ? 0 : (d <= kLightMax ? 1 : (d <= kMediumMax ? 2 : 3));
+}
+
+// Stable partition of the vertices by a small key (< kNumBins): per-block
+// counts, key-major.
+__global__ void k_part_count(const uint8_t* __restrict__ keys, int32_t n, int64_t* __restrict__ counts, int64_t nblk) {
   __shared__ int wc[kBlock / kWave][kNumBins];
   const int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  const int key = v < n ? degree_bin(deg[v]) : -1;
+  const int key = v < n ? (int)keys[v] : -1;
   const int w = threadIdx.x / kWave;
 #pragma unroll
   for (int j = 0; j < kNumBins; ++j) {
@@ -123,11 +139,11 @@ __global__ void k_bin_count(const int32_t* __restrict__ deg, int32_t n, int64_t*
   }
 }
 
-__global__ void k_bin_scatter(const int32_t* __restrict__ deg, int32_t n, const int64_t* __restrict__ base,
-                              int64_t nblk, int32_t* __restrict__ out) {
+__global__ void k_part_scatter(const uint8_t* __restrict__ keys, int32_t n, const int64_t* __restrict__ base,
+                               int64_t nblk, int32_t* __restrict__ out) {
   __shared__ int wc[kBlock / kWave][kNumBins];
   const int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  const int key = v < n ? degree_bin(deg[v]) : -1;
+  const int key = v < n ? (int)keys[v] : -1;
   const int w = threadIdx.x / kWave;
   unsigned long long mine = 0;
 #pragma unroll
@@ -144,18 +160,29 @@ __global__ void k_bin_scatter(const int32_t* __restrict__ deg, int32_t n, const 
   }
 }
 
+__global__ void k_heavy_ranges(const int32_t* __restrict__ verts, int64_t count, const int32_t* __restrict__ off,
+                               const int32_t* __restrict__ ustart, int64_t* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int32_t v = verts[i];
+  out[2 * i] = ustart ? ustart[v] : off[v];
+  out[2 * i + 1] = off[v + 1];
+}
+
 // ---- per-vertex group kernels: G lanes per vertex, G <= 256 divides 256 -----
 
 // Number of neighbours above v (the suffix of the sorted N_v).
 template <int G>
 __global__ void k_upper_count(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
-                              const int32_t* __restrict__ verts, int64_t nverts, int64_t* __restrict__ cnt) {
+                              const int32_t* __restrict__ verts, int64_t nverts, int64_t* __restrict__ cnt,
+                              int32_t* __restrict__ ustart) {
   const int64_t grp = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / G;
   const int lane = threadIdx.x % G;
   if (grp >= nverts || lane != 0) return;
   const int32_t v = verts[grp];
   const int64_t fg = lower_bound_i32(adj, off[v], off[v + 1], v + 1);
   cnt[v] = off[v + 1] - fg;
+  ustart[v] = (int32_t)fg;
 }
 
 template <int G>
@@ -363,6 +390,19 @@ int fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s) {
 }
 
 int sum_chunks(const double* chunks, int64_t nchunks, double divisor, double* out, hipStream_t s) {
+  ProfScope ps(s, "sum_chunks");
+  if (nchunks > 4 * kScanTile) {
+    // two levels: fixed tiles of kScanTile partials, then the tile sums
+    const int64_t nt = (nchunks + kScanTile - 1) / kScanTile;
+    double* tiles = nullptr;
+    PG_TRY(dmalloc((void**)&tiles, sizeof(double) * nt, s));
+    hipLaunchKernelGGL(k_array_chunks, dim3((unsigned)std::min<int64_t>(nt, 65536)), dim3(kBlock), 0, s, chunks,
+                       nchunks, tiles);
+    PG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(kBlock), 0, s, (const double*)tiles, nt, divisor, out);
+    PG_LAUNCH_CHECK();
+    return dfree(tiles, s);
+  }
   hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(kBlock), 0, s, chunks, nchunks, divisor, out);
   PG_LAUNCH_CHECK();
   return PG_OK;
@@ -406,6 +446,114 @@ namespace {
   } while (0)
 
 }  // namespace
+
+namespace {
+
+// Stable partition of all vertices into `out` by degree bin (plan_upper < 0)
+// or by plan tier over N_v (0) / over the upper neighbours (1). starts[j] is
+// the first position of key j, starts[kNumBins] = n.
+int partition(pg_graph* g, int plan_upper, int32_t* out, int64_t* starts, hipStream_t s) {
+  const int32_t n = g->n;
+  for (int j = 0; j <= kNumBins; ++j) starts[j] = n;
+  if (n <= 0) {
+    for (int j = 0; j <= kNumBins; ++j) starts[j] = 0;
+    return PG_OK;
+  }
+  const int64_t nblk = ((int64_t)n + kBlock - 1) / kBlock;
+  uint8_t* keys = nullptr;
+  int64_t* counts = nullptr;
+  PG_TRY(dmalloc((void**)&keys, (size_t)n, s));
+  PG_TRY(dmalloc((void**)&counts, sizeof(int64_t) * 2 * kNumBins * nblk, s));
+  int64_t* base = counts + kNumBins * nblk;
+  if (plan_upper < 0)
+    hipLaunchKernelGGL(k_degree_bin_keys, dim3((unsigned)nblk), dim3(kBlock), 0, s, g->deg, n, keys);
+  else
+    hipLaunchKernelGGL(k_plan_keys, dim3((unsigned)nblk), dim3(kBlock), 0, s, g->off,
+                       plan_upper ? (const int32_t*)g->ustart : nullptr, n, keys);
+  PG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_part_count, dim3((unsigned)nblk), dim3(kBlock), 0, s, keys, n, counts, nblk);
+  PG_LAUNCH_CHECK();
+  PG_TRY(exclusive_scan_i64(counts, base, kNumBins * nblk, s));
+  hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, s, keys, n, base, nblk, out);
+  PG_LAUNCH_CHECK();
+  for (int j = 0; j < kNumBins; ++j)
+    PG_HIP(hipMemcpyAsync(&starts[j], base + j * nblk, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  starts[kNumBins] = n;
+  PG_TRY(dfree(counts, s));
+  return dfree(keys, s);
+}
+
+}  // namespace
+
+void free_plan(VertexPlan* p) {
+  pfree(p->sorted);
+  pfree(p->chunk_vertex);
+  pfree(p->chunk_begin);
+  pfree(p->chunk_end);
+  pfree(p->chunk_slot);
+  pfree(p->heavy_first);
+  *p = VertexPlan();
+}
+
+int build_plan(pg_graph* g, VertexPlan* P, bool upper, hipStream_t s) {
+  free_plan(P);
+  P->upper = upper;
+  const int32_t n = g->n;
+  PG_TRY(palloc((void**)&P->sorted, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
+  int64_t starts[kNumBins + 1];
+  PG_TRY(partition(g, upper ? 1 : 0, P->sorted, starts, s));
+  if (upper) {
+    P->light = P->sorted + starts[1];
+    P->n_light = starts[2] - starts[1];
+  } else {  // nearly every vertex is light over N_v: natural order saves the list lookup
+    P->light = nullptr;
+    P->n_light = n;
+  }
+  P->medium = P->sorted + starts[2];
+  P->n_medium = starts[3] - starts[2];
+  P->n_heavy = starts[4] - starts[3];
+  const int64_t nh = P->n_heavy;
+  std::vector<int64_t> ranges(2 * (size_t)nh);
+  if (nh > 0) {
+    int64_t* d_ranges = nullptr;
+    PG_TRY(dmalloc((void**)&d_ranges, sizeof(int64_t) * 2 * nh, s));
+    hipLaunchKernelGGL(k_heavy_ranges, dim3((unsigned)((nh + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       P->sorted + starts[3], nh, g->off, upper ? (const int32_t*)g->ustart : nullptr, d_ranges);
+    PG_LAUNCH_CHECK();
+    PG_HIP(hipMemcpyAsync(ranges.data(), d_ranges, sizeof(int64_t) * 2 * nh, hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> hv((size_t)nh);
+    PG_HIP(hipMemcpyAsync(hv.data(), P->sorted + starts[3], sizeof(int32_t) * nh, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    PG_TRY(dfree(d_ranges, s));
+    std::vector<int32_t> cv, cslot, first((size_t)nh + 1, 0);
+    std::vector<int64_t> cb, ce;
+    for (int64_t h = 0; h < nh; ++h) {
+      first[h] = (int32_t)cv.size();
+      for (int64_t b = ranges[2 * h]; b < ranges[2 * h + 1]; b += kHeavyChunk) {
+        cv.push_back(hv[h]);
+        cb.push_back(b);
+        ce.push_back(std::min<int64_t>(b + kHeavyChunk, ranges[2 * h + 1]));
+        cslot.push_back((int32_t)h);
+      }
+    }
+    first[nh] = (int32_t)cv.size();
+    P->n_chunks = (int64_t)cv.size();
+    const size_t nc = cv.size();
+    PG_TRY(palloc((void**)&P->chunk_vertex, sizeof(int32_t) * nc));
+    PG_TRY(palloc((void**)&P->chunk_begin, sizeof(int64_t) * nc));
+    PG_TRY(palloc((void**)&P->chunk_end, sizeof(int64_t) * nc));
+    PG_TRY(palloc((void**)&P->chunk_slot, sizeof(int32_t) * nc));
+    PG_TRY(palloc((void**)&P->heavy_first, sizeof(int32_t) * (nh + 1)));
+    PG_HIP(hipMemcpyAsync(P->chunk_vertex, cv.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
+    PG_HIP(hipMemcpyAsync(P->chunk_begin, cb.data(), sizeof(int64_t) * nc, hipMemcpyHostToDevice, s));
+    PG_HIP(hipMemcpyAsync(P->chunk_end, ce.data(), sizeof(int64_t) * nc, hipMemcpyHostToDevice, s));
+    PG_HIP(hipMemcpyAsync(P->chunk_slot, cslot.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
+    PG_HIP(hipMemcpyAsync(P->heavy_first, first.data(), sizeof(int32_t) * (nh + 1), hipMemcpyHostToDevice, s));
+    PG_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+  }
+  return PG_OK;
+}
 
 int graph_prepare(pg_graph* g, bool validate, hipStream_t s) {
   const int32_t n = g->n;
@@ -465,47 +613,38 @@ int graph_prepare(pg_graph* g, bool validate, hipStream_t s) {
 
   // 3. degree bins (stable)
   PG_TRY(palloc((void**)&g->bin_verts, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
-  const int64_t nblk = std::max<int64_t>(1, ((int64_t)n + kBlock - 1) / kBlock);
-  int64_t* counts = nullptr;
-  PG_TRY(dmalloc((void**)&counts, sizeof(int64_t) * 2 * kNumBins * nblk, s));
-  int64_t* base = counts + kNumBins * nblk;
-  std::vector<int64_t> hbase(kNumBins, 0);
-  if (n > 0) {
-    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)nblk), dim3(kBlock), 0, s, g->deg, n, counts, nblk);
-    PG_LAUNCH_CHECK();
-    PG_TRY(exclusive_scan_i64(counts, base, kNumBins * nblk, s));
-    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, s, g->deg, n, base, nblk, g->bin_verts);
-    PG_LAUNCH_CHECK();
-    for (int j = 0; j < kNumBins; ++j)
-      PG_HIP(hipMemcpyAsync(&hbase[j], base + j * nblk, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  }
+  int64_t hbase[kNumBins + 1] = {};
+  PG_TRY(partition(g, /*plan_upper=*/-1, g->bin_verts, hbase, s));
   int h_max = 0;
   unsigned long long h_wedges = 0;
   PG_HIP(hipMemcpyAsync(&h_max, d_maxdeg, sizeof(int), hipMemcpyDeviceToHost, s));
   PG_HIP(hipMemcpyAsync(&h_wedges, d_wedges, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   PG_HIP(hipStreamSynchronize(s));
-  for (int j = 0; j < kNumBins; ++j) g->bin_start[j] = hbase[j];
-  g->bin_start[kNumBins] = n;
+  for (int j = 0; j <= kNumBins; ++j) g->bin_start[j] = hbase[j];
   g->max_degree = h_max;
   g->wedges = h_wedges;
 
-  // 4. upper edges
+  // 4. upper edges: ustart, upper-edge offsets, (eu, ev) in CSR order
   int64_t* up = nullptr;
-  PG_TRY(dmalloc((void**)&up, sizeof(int64_t) * 2 * ((size_t)n + 1), s));
-  int64_t* up_off = up + (n + 1);
+  PG_TRY(dmalloc((void**)&up, sizeof(int64_t) * ((size_t)n + 1), s));
+  PG_TRY(palloc((void**)&g->ustart, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
+  PG_TRY(palloc((void**)&g->upoff, sizeof(int64_t) * ((size_t)n + 1)));
   PG_HIP(hipMemsetAsync(up, 0, sizeof(int64_t) * ((size_t)n + 1), s));
-  PG_FOR_BINS(k_upper_count, g, s, g->off, g->adj, verts_, cnt_, up);
-  PG_TRY(exclusive_scan_i64(up, up_off, (int64_t)n + 1, s));
+  PG_FOR_BINS(k_upper_count, g, s, g->off, g->adj, verts_, cnt_, up, g->ustart);
+  PG_TRY(exclusive_scan_i64(up, g->upoff, (int64_t)n + 1, s));
   int64_t m = 0;
-  PG_HIP(hipMemcpyAsync(&m, up_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PG_HIP(hipMemcpyAsync(&m, g->upoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   PG_HIP(hipStreamSynchronize(s));
   g->m = m;
   PG_TRY(palloc((void**)&g->eu, sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1)));
   PG_TRY(palloc((void**)&g->ev, sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1)));
-  PG_FOR_BINS(k_upper_fill, g, s, g->off, g->adj, verts_, cnt_, up_off, g->eu, g->ev);
+  PG_FOR_BINS(k_upper_fill, g, s, g->off, g->adj, verts_, cnt_, g->upoff, g->eu, g->ev);
   PG_TRY(dfree(up, s));
-  PG_TRY(dfree(counts, s));
   PG_TRY(dfree(d_flags, s));
+
+  // 5. work plans over N_v and over the upper neighbours
+  PG_TRY(build_plan(g, &g->plan_all, false, s));
+  PG_TRY(build_plan(g, &g->plan_up, true, s));
   return PG_OK;
 }
 
@@ -518,6 +657,7 @@ int graph_arc_sources(pg_graph* g, hipStream_t s) {
 
 int graph_orient(pg_graph* g, hipStream_t s) {
   if (g->poff) return PG_OK;
+  ProfScope ps(s, "orient");
   const int32_t n = g->n;
   int64_t* cnt = nullptr;
   PG_TRY(dmalloc((void**)&cnt, sizeof(int64_t) * 2 * ((size_t)n + 1), s));

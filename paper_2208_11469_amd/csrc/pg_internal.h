@@ -37,12 +37,92 @@ int dfree(void* p, hipStream_t s);
 int palloc(void** p, size_t bytes);                 // long-lived device allocation
 int pfree(void* p);
 
+// ---- per-kernel device timing ---------------------------------------------------
+// While profiling is enabled, a ProfScope records a HIP event on its stream at
+// construction and another at destruction; pg_profile_read sums the elapsed
+// times per name.
+bool prof_enabled();
+struct ProfScope {
+  ProfScope(hipStream_t s, const char* name);
+  ~ProfScope();
+  hipStream_t s_;
+  const char* name_;
+  hipEvent_t start_ = nullptr;
+};
+
 // ---- degree bins -----------------------------------------------------------
 // Vertices are partitioned once per graph by degree; per-vertex kernels map a
 // group of G lanes to one vertex, G growing with the bin.
 constexpr int kNumBins = 4;
 constexpr int32_t kBinMaxDeg[kNumBins - 1] = {16, 256, 4096};  // bin 3: d > 4096
 constexpr int kBinGroup[kNumBins] = {4, 16, 64, 256};
+
+// ---- vertex work plans -----------------------------------------------------
+// A plan splits per-vertex work (over N_v, or over the upper part of N_v) into
+// three tiers launched together, heaviest first:
+//   heavy  (key >  kMediumMax): chunks of kHeavyChunk arcs, one block each
+//   medium (kLightMax < key <= kMediumMax): one wave per vertex
+//   light  (key <= kLightMax): kLightGroup lanes per vertex
+// where key is the number of arcs the vertex owns in the plan. Vertices with
+// no arcs are dropped from the upper plan; the full plan keeps them in the
+// light tier (their sketch rows still have to be written).
+constexpr int32_t kLightMax = 64;
+constexpr int32_t kMediumMax = 2048;
+constexpr int64_t kHeavyChunk = 2048;
+constexpr int kLightGroup = 8;
+
+struct VertexPlan {
+  bool upper = false;             // arcs of v: [ustart[v], off[v+1]) if upper, else [off[v], off[v+1])
+  int64_t n_light = 0;
+  int32_t* light = nullptr;       // [n_light] light vertices, ascending; nullptr: every vertex in natural
+                                  // order, the kernel skipping those above kLightMax (n_light = n)
+  int64_t n_medium = 0;
+  int32_t* medium = nullptr;      // [n_medium] medium vertices, ascending
+  int64_t n_chunks = 0;
+  int32_t* chunk_vertex = nullptr;  // [n_chunks]
+  int64_t* chunk_begin = nullptr;   // [n_chunks] arc range of the chunk
+  int64_t* chunk_end = nullptr;     // [n_chunks]
+  int32_t* chunk_slot = nullptr;    // [n_chunks] index of the chunk's heavy vertex
+  int64_t n_heavy = 0;
+  int32_t* heavy_first = nullptr;   // [n_heavy + 1] chunks of heavy vertex h: [heavy_first[h], heavy_first[h+1])
+  int32_t* sorted = nullptr;        // [n] vertices by tier (backing store of `light` and `medium`)
+};
+
+// Plan view passed to kernels by value.
+struct PlanView {
+  int64_t n_chunks;
+  int64_t n_medium;
+  int64_t n_medium_blocks;
+  int64_t n_light;
+  const int32_t* light;
+  const int32_t* medium;
+  const int32_t* chunk_vertex;
+  const int64_t* chunk_begin;
+  const int64_t* chunk_end;
+  const int32_t* chunk_slot;
+  const int32_t* heavy_first;
+};
+
+inline PlanView plan_view(const VertexPlan& p) {
+  PlanView v;
+  v.n_chunks = p.n_chunks;
+  v.n_medium = p.n_medium;
+  v.n_medium_blocks = (p.n_medium + 3) / 4;
+  v.n_light = p.n_light;
+  v.light = p.light;
+  v.medium = p.medium;
+  v.chunk_vertex = p.chunk_vertex;
+  v.chunk_begin = p.chunk_begin;
+  v.chunk_end = p.chunk_end;
+  v.chunk_slot = p.chunk_slot;
+  v.heavy_first = p.heavy_first;
+  return v;
+}
+
+// Blocks of 256 threads a plan launch needs.
+inline int64_t plan_blocks(const VertexPlan& p) {
+  return p.n_chunks + (p.n_medium + 3) / 4 + (p.n_light * kLightGroup + 255) / 256;
+}
 
 }  // namespace pg
 
@@ -63,6 +143,10 @@ struct pg_graph {
   int32_t* off = nullptr;      // [n+1]
   int32_t* adj = nullptr;      // [nnz]
   int32_t* deg = nullptr;      // [n]
+  int32_t* ustart = nullptr;   // [n] position in adj of the first neighbour above v
+  int64_t* upoff = nullptr;    // [n+1] first upper-edge index of v (edges in CSR order)
+  pg::VertexPlan plan_all;     // work over N_v (sketch builds, clustering coefficient)
+  pg::VertexPlan plan_up;      // work over the neighbours above v (triangle count)
   int32_t* eu = nullptr;       // [m] smaller endpoint of each undirected edge
   int32_t* ev = nullptr;       // [m] larger endpoint
   int32_t* arc_src = nullptr;  // [nnz] source vertex of each arc
@@ -88,6 +172,7 @@ struct pg_sketches {
   uint64_t* ha = nullptr;     // device hash multipliers
   uint64_t* hc = nullptr;     // device hash increments
   double* table = nullptr;    // [B+1]  estimator table (Bloom filters)
+  uint64_t* scratch = nullptr;    // partial rows of heavy chunks (plan_all.n_chunks * W words)
   int table_est = 0;          // estimator the table holds
 };
 
@@ -97,6 +182,8 @@ namespace pg {
 int graph_prepare(pg_graph* g, bool validate, hipStream_t s);
 int graph_arc_sources(pg_graph* g, hipStream_t s);
 int graph_orient(pg_graph* g, hipStream_t s);
+int build_plan(pg_graph* g, pg::VertexPlan* plan, bool upper, hipStream_t s);
+void free_plan(pg::VertexPlan* plan);
 int exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t count, hipStream_t s);
 int fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s);
 int sum_chunks(const double* chunks, int64_t nchunks, double divisor, double* out, hipStream_t s);
@@ -118,6 +205,8 @@ int64_t chunk_count(int64_t npairs);
 int estimate_sum(const pg_sketches* sk, int est, const int32_t* u, const int32_t* v, int64_t npairs,
                  double* chunks, hipStream_t s);
 int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStream_t s);
+// TC^ = (1/3) sum over the m edges of the estimate, into d_out[0] (device).
+int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s);
 
 // ---- launchers (pg_exact.hip) ------------------------------------------------
 int exact_pairs(const pg_graph* g, int algo, const int32_t* u, const int32_t* v, int64_t npairs,

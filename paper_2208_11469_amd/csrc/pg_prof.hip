@@ -1,0 +1,146 @@
+// Measurement support: per-launch-site device timing with HIP events, and a
+// plain copy kernel used as the reference for HBM bandwidth and byte counters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pg_device.h"
+#include "pg_internal.h"
+
+namespace pg {
+namespace {
+
+struct Pending {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+std::mutex g_mu;
+bool g_enabled = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;
+std::map<std::string, std::pair<int64_t, double>> g_totals;
+
+hipEvent_t take_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Wait for every pending pair, add it to the totals, recycle the events.
+int drain_locked() {
+  for (const Pending& p : g_pending) {
+    float ms = 0.0f;
+    PG_HIP(hipEventSynchronize(p.b));
+    PG_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    auto& t = g_totals[p.name];
+    t.first += 1;
+    t.second += (double)ms;
+    g_pool.push_back(p.a);
+    g_pool.push_back(p.b);
+  }
+  g_pending.clear();
+  return PG_OK;
+}
+
+// 16 bytes per lane per step, grid-stride.
+__global__ __launch_bounds__(256) void k_copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, int64_t n16) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+}  // namespace
+
+bool prof_enabled() { return g_enabled; }
+
+ProfScope::ProfScope(hipStream_t s, const char* name) : s_(s), name_(name) {
+  if (!g_enabled) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  start_ = take_event();
+  if (start_ && hipEventRecord(start_, s_) != hipSuccess) {
+    g_pool.push_back(start_);
+    start_ = nullptr;
+  }
+}
+
+ProfScope::~ProfScope() {
+  if (!start_) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipEvent_t stop = take_event();
+  if (stop && hipEventRecord(stop, s_) == hipSuccess) {
+    g_pending.push_back({name_, start_, stop});
+  } else {
+    g_pool.push_back(start_);
+    if (stop) g_pool.push_back(stop);
+  }
+}
+
+}  // namespace pg
+
+using namespace pg;
+
+extern "C" {
+
+int pg_profile_enable(pg_ctx* ctx, int enable) {
+  clear_error();
+  if (!ctx) return fail(PG_E_INVALID, "ctx is NULL");
+  g_enabled = enable != 0;
+  return PG_OK;
+}
+
+int pg_profile_read(pg_ctx* ctx, pg_kernel_time* out, int capacity, int* count) {
+  clear_error();
+  if (!ctx || !count || (capacity > 0 && !out)) return fail(PG_E_INVALID, "NULL argument");
+  PG_HIP(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> lk(g_mu);
+  PG_TRY(drain_locked());
+  int i = 0;
+  for (const auto& kv : g_totals) {
+    if (i < capacity) {
+      std::memset(out[i].name, 0, sizeof(out[i].name));
+      std::strncpy(out[i].name, kv.first.c_str(), sizeof(out[i].name) - 1);
+      out[i].launches = kv.second.first;
+      out[i].total_ms = kv.second.second;
+    }
+    ++i;
+  }
+  *count = i;
+  return PG_OK;
+}
+
+int pg_profile_reset(pg_ctx* ctx) {
+  clear_error();
+  if (!ctx) return fail(PG_E_INVALID, "ctx is NULL");
+  PG_HIP(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> lk(g_mu);
+  PG_TRY(drain_locked());
+  g_totals.clear();
+  return PG_OK;
+}
+
+int pg_copy(pg_ctx* ctx, void* dst, const void* src, size_t bytes, void* stream) {
+  clear_error();
+  if (!ctx || !dst || !src) return fail(PG_E_INVALID, "NULL argument");
+  if (bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16) return fail(PG_E_INVALID, "copy needs 16-byte alignment");
+  PG_HIP(hipSetDevice(ctx->device));
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return PG_OK;
+  hipStream_t s = (hipStream_t)stream;
+  ProfScope ps(s, "copy");
+  const unsigned grid = (unsigned)std::min<int64_t>((n16 + 255) / 256, (int64_t)std::max(1, ctx->num_cus) * 32);
+  hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (uint4*)dst, (const uint4*)src, n16);
+  PG_LAUNCH_CHECK();
+  return PG_OK;
+}
+
+}  // extern "C"
