@@ -79,6 +79,53 @@ def timed(fn, reps, sync):
     return statistics.median(out)
 
 
+def measure_serving(args, pg, pggen, np, log):
+    """Query serving on a resident R-MAT graph: closed-loop saturation, then
+    open-loop Poisson arrivals at 50/80/95% of it; latency from arrival to
+    result on the host."""
+    t = time.perf_counter()
+    g = pggen.rmat(args.serving_scale, 16, seed=args.seed)
+    ctx = pg.Context(0)
+    dg = pg.Graph(ctx, g.offsets, g.adj)
+    sks = [dg.build_sketches("bf", 512, 1, seed=args.seed), dg.build_sketches("kh", 32, seed=args.seed)]
+    log(f"serving: R-MAT s{args.serving_scale} n={g.n} nnz={g.nnz} resident with BF-512 and k-hash-32 "
+        f"({time.perf_counter() - t:.1f}s)")
+    trace = pggen.query_trace(g.n, args.serving_requests, rate_hz=1.0, seed=args.seed)
+    srv = pg.Server(dg, sks, max_batches_in_flight=3)
+    reqs = []
+    for r in trace:
+        op = pg.PG_OP_CN if r.op == "cn" else pg.PG_OP_JACCARD
+        sk, est = (0, "and") if r.kind == "bf" else (1, "kh")
+        reqs.append(srv.make_request(op, sk, est, r.u, r.v))
+    pairs = sum(int(r.u.shape[0]) for r in trace)
+    mean_pairs = pairs / len(trace)
+    srv.replay(reqs[: min(200, len(reqs))], max_outstanding=32)  # warm-up
+    lat, el = srv.replay(reqs, max_outstanding=64)
+    sat_pairs = pairs / el
+    sat_rate = len(reqs) / el
+    log(f"serving saturation: {sat_pairs:.3e} pairs/s, {sat_rate:.0f} requests/s, p50 {np.percentile(lat, 50):.3f} ms")
+    unit_gaps = np.diff(np.concatenate([[0.0], [r.arrival_s for r in trace]]))  # Poisson gaps at 1 request/s
+    loads = []
+    for frac in (0.5, 0.8, 0.95):
+        rate = frac * sat_rate
+        arrivals = np.cumsum(unit_gaps / rate)
+        lat, el = srv.replay(reqs, arrival_s=arrivals)
+        loads.append({"load": frac, "rate_requests_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+                      "p99_ms": float(np.percentile(lat, 99)), "pairs_per_s": pairs / el})
+        log(f"serving at {frac:.0%}: p50 {loads[-1]['p50_ms']:.3f} ms p99 {loads[-1]['p99_ms']:.3f} ms")
+    st = srv.stats()
+    srv.close()
+    for sk in sks:
+        sk.close()
+    dg.close()
+    ctx.close()
+    return {"workload": f"R-MAT s{args.serving_scale} ef16 resident, BF 512 bits b=1 + k-hash k=32; "
+                        f"{len(reqs)} Poisson requests, 1..65536 pairs (log-uniform), CN/Jaccard x BF/MH",
+            "mean_pairs_per_request": mean_pairs, "saturation_pairs_per_s": sat_pairs,
+            "saturation_requests_per_s": sat_rate, "loads": loads, "batches": st["batches"],
+            "requests": st["completed"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +138,9 @@ def main():
     ap.add_argument("--b", type=int, default=1)
     ap.add_argument("--skip-cpu", action="store_true", help="leave out the CPU oracle baseline")
     ap.add_argument("--skip-rows", action="store_true", help="leave out the extra rows")
+    ap.add_argument("--skip-serving", action="store_true", help="leave out the serving measurement")
+    ap.add_argument("--serving-scale", type=int, default=22)
+    ap.add_argument("--serving-requests", type=int, default=10000)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -241,6 +291,10 @@ def main():
                "seconds": round(cpu_s, 4), "tc_matches_gpu_rel": abs(tc_cpu - tc_bf) / abs(tc_cpu)}
         log(f"cpu oracle: {cpu_s:.3f} s -> {m / cpu_s:.4e} {UNIT} on {oracle.threads()} threads")
 
+    serving = None
+    if not args.skip_serving:
+        serving = measure_serving(args, pg, pggen, np, log)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -272,6 +326,7 @@ def main():
         "copy_kernel_gbs": round(copy_gbs, 1),
         "phases": phases,
         "rows": rows,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     sk.close()

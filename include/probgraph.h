@@ -191,6 +191,73 @@ int pg_exact_jaccard(pg_ctx* ctx, const pg_graph* g, const int32_t* u, const int
  * draw a fresh sketch set. Allocates nothing. */
 int pg_sketches_rebuild(pg_ctx* ctx, pg_sketches* sk, uint64_t seed, void* stream);
 
+/* ---- serving: resident sketches, continuous batching ---------------------- */
+/* A server keeps a graph and its sketch sets resident and answers vertex-pair
+ * queries (common-neighbour estimates or Jaccard similarities, Listing
+ * "lst:sim") as they arrive. Admitted requests are packed into batches; up to
+ * max_batches_in_flight batches run concurrently on separate streams, and
+ * requests submitted while batches run join the next batch as soon as a batch
+ * slot frees. A request is admitted only if its bytes (16 per pair: pair IDs
+ * and result) fit in memory_budget_bytes together with all requests already
+ * admitted and not yet collected; otherwise submit returns PG_E_BUSY.
+ * Per-pair results do not depend on batching: a request's result is
+ * bit-identical alone and in any mix. The graph and sketch sets must outlive
+ * the server. One thread may submit while another waits. */
+#define PG_OP_CN 1      /* estimate of |N_u cap N_v| (common neighbours), FP64 */
+#define PG_OP_JACCARD 2 /* estimated Jaccard similarity, FP32 (rounded once from FP64) */
+
+typedef struct pg_server pg_server;
+
+typedef struct pg_server_params {
+  int32_t max_batches_in_flight; /* concurrent batches (streams); 0 = 3 */
+  int32_t max_pairs_per_request; /* 0 = 65536 */
+  int64_t max_batch_pairs;       /* pairs packed into one launch; 0 = 1 << 20 */
+  uint64_t memory_budget_bytes;  /* admission budget; 0 = 256 MiB */
+} pg_server_params;
+
+typedef struct pg_request {
+  int32_t op;        /* PG_OP_CN or PG_OP_JACCARD */
+  int32_t sketch;    /* index into the server's sketch sets */
+  int32_t estimator; /* must match that set's kind */
+  int32_t reserved;  /* 0 */
+  int64_t npairs;    /* 1 .. max_pairs_per_request */
+  const int32_t* u;  /* host [npairs]; copied during submit */
+  const int32_t* v;  /* host [npairs]; copied during submit */
+  void* out;         /* host: double[npairs] (CN) or float[npairs] (Jaccard); written by the server */
+} pg_request;
+
+typedef struct pg_server_stats {
+  uint64_t submitted;        /* admitted requests */
+  uint64_t rejected_busy;    /* PG_E_BUSY answers */
+  uint64_t rejected_invalid; /* malformed requests refused before enqueue */
+  uint64_t completed;        /* requests whose results were delivered */
+  uint64_t batches;          /* launches */
+  uint64_t pairs;            /* pairs answered */
+} pg_server_stats;
+
+/* sketches: host array of nsketches handles built on `g`. params may be NULL. */
+int pg_server_create(pg_ctx* ctx, const pg_graph* g, pg_sketches* const* sketches, int32_t nsketches,
+                     const pg_server_params* params, pg_server** out);
+/* Validates and admits a request (*ticket receives its id, host pointer).
+ * PG_E_INVALID: malformed (op, sketch index, estimator/kind mismatch, npairs
+ * out of range, a vertex ID outside [0, n)); PG_E_BUSY: not admitted now. */
+int pg_server_submit(pg_server* srv, const pg_request* req, uint64_t* ticket);
+/* *done = 1 once the request's results are in its out buffer. */
+int pg_server_poll(pg_server* srv, uint64_t ticket, int32_t* done);
+/* Blocks until the request is answered, then releases the ticket; latency_ms
+ * (host, nullable) receives the time from submit to result delivery. */
+int pg_server_wait(pg_server* srv, uint64_t ticket, double* latency_ms);
+int pg_server_get_stats(pg_server* srv, pg_server_stats* out);
+/* Load replay: submits reqs[0..nreq) in order -- at t0 + arrival_s[i] (open
+ * loop) or, with arrival_s NULL, keeping max_outstanding requests unanswered
+ * (closed loop) -- retrying while the server answers PG_E_BUSY, and writes each
+ * request's latency from its arrival to its result (host array latency_ms).
+ * *elapsed_s (nullable) receives the wall time of the whole replay. */
+int pg_server_replay(pg_server* srv, int64_t nreq, const pg_request* reqs, const double* arrival_s,
+                     int32_t max_outstanding, double* latency_ms, double* elapsed_s);
+/* Waits for every admitted request, stops the engine and frees the server. */
+int pg_server_destroy(pg_server* srv);
+
 /* ---- measurement ----------------------------------------------------------- */
 typedef struct pg_kernel_time {
   char name[48];     /* launch site, e.g. "bf_build", "pairs_sum" */

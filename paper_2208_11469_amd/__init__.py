@@ -73,6 +73,26 @@ class _SketchInfo(ctypes.Structure):
                 ("row_bytes", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64)]
 
 
+class _ServerParams(ctypes.Structure):
+    _fields_ = [("max_batches_in_flight", ctypes.c_int32), ("max_pairs_per_request", ctypes.c_int32),
+                ("max_batch_pairs", ctypes.c_int64), ("memory_budget_bytes", ctypes.c_uint64)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("sketch", ctypes.c_int32), ("estimator", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("npairs", ctypes.c_int64), ("u", ctypes.c_void_p),
+                ("v", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("rejected_busy", ctypes.c_uint64),
+                ("rejected_invalid", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("pairs", ctypes.c_uint64)]
+
+
+PG_OP_CN = 1
+PG_OP_JACCARD = 2
+
 _lib = None
 _vp = ctypes.c_void_p
 
@@ -108,6 +128,14 @@ def _declare(lib):
         "pg_profile_read": (i, [_vp, P(_KernelTime), i, P(i)]),
         "pg_profile_reset": (i, [_vp]),
         "pg_copy": (i, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
+        "pg_server_create": (i, [_vp, _vp, P(_vp), i32, P(_ServerParams), P(_vp)]),
+        "pg_server_submit": (i, [_vp, P(_Request), P(u64)]),
+        "pg_server_poll": (i, [_vp, u64, P(i32)]),
+        "pg_server_wait": (i, [_vp, u64, P(ctypes.c_double)]),
+        "pg_server_get_stats": (i, [_vp, P(_ServerStats)]),
+        "pg_server_replay": (i, [_vp, i64, P(_Request), P(ctypes.c_double), i32, P(ctypes.c_double),
+                                 P(ctypes.c_double)]),
+        "pg_server_destroy": (i, [_vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -304,6 +332,43 @@ def pg_copy(ctx, dst, src, nbytes, stream=None):
     _check(load().pg_copy(ctx, _dptr(dst), _dptr(src), nbytes, _stream(stream)))
 
 
+def pg_server_create(ctx, g, sketch_handles, params=None):
+    arr = (_vp * len(sketch_handles))(*[h.value if isinstance(h, _vp) else h for h in sketch_handles])
+    h = _vp()
+    _check(load().pg_server_create(ctx, g, arr, len(sketch_handles), ctypes.byref(params) if params else None,
+                                   ctypes.byref(h)))
+    return h
+
+
+def pg_server_submit(srv, req) -> int:
+    """Returns the ticket; raises PGError (code PG_E_BUSY when not admitted)."""
+    t = ctypes.c_uint64()
+    _check(load().pg_server_submit(srv, ctypes.byref(req), ctypes.byref(t)))
+    return int(t.value)
+
+
+def pg_server_poll(srv, ticket) -> bool:
+    d = ctypes.c_int32()
+    _check(load().pg_server_poll(srv, ticket, ctypes.byref(d)))
+    return bool(d.value)
+
+
+def pg_server_wait(srv, ticket) -> float:
+    lat = ctypes.c_double()
+    _check(load().pg_server_wait(srv, ticket, ctypes.byref(lat)))
+    return float(lat.value)
+
+
+def pg_server_get_stats(srv) -> dict:
+    st = _ServerStats()
+    _check(load().pg_server_get_stats(srv, ctypes.byref(st)))
+    return {f: int(getattr(st, f)) for f, _ in _ServerStats._fields_}
+
+
+def pg_server_destroy(srv):
+    _check(load().pg_server_destroy(srv))
+
+
 # ---- handle classes ---------------------------------------------------------------
 
 def _pairs(u, v):
@@ -491,3 +556,65 @@ class Sketches:
         pg_jaccard(self.graph.ctx.h, self.h, ESTIMATORS.get(estimator, estimator), u, v, npairs,
                    out if count else None, stream)
         return out
+
+
+class Server:
+    """Serving engine over resident sketch sets (see pg_server_* in probgraph.h).
+
+    Requests are (op, sketch index, estimator, u, v) with host numpy int32
+    arrays; results land in host numpy arrays (float64 for common neighbours,
+    float32 for Jaccard)."""
+
+    def __init__(self, graph: Graph, sketches, max_batches_in_flight=0, max_pairs_per_request=0,
+                 max_batch_pairs=0, memory_budget_bytes=0):
+        self.graph = graph
+        self.sketches = list(sketches)
+        p = _ServerParams(max_batches_in_flight, max_pairs_per_request, max_batch_pairs, memory_budget_bytes)
+        self.h = pg_server_create(graph.ctx.h, graph.h, [sk.h for sk in self.sketches], p)
+        self._keep = {}
+
+    def make_request(self, op, sketch, estimator, u, v):
+        u = np.ascontiguousarray(u, dtype=np.int32)
+        v = np.ascontiguousarray(v, dtype=np.int32)
+        out = np.empty(u.shape[0], dtype=np.float64 if op == PG_OP_CN else np.float32)
+        req = _Request(op, sketch, ESTIMATORS.get(estimator, estimator), 0, u.shape[0], u.ctypes.data,
+                       v.ctypes.data, out.ctypes.data)
+        return req, (u, v, out)
+
+    def submit(self, op, sketch, estimator, u, v):
+        """Returns (ticket, out array); raises PGError(PG_E_BUSY) when not admitted."""
+        req, keep = self.make_request(op, sketch, estimator, u, v)
+        t = pg_server_submit(self.h, req)
+        self._keep[t] = keep
+        return t, keep[2]
+
+    def poll(self, ticket) -> bool:
+        return pg_server_poll(self.h, ticket)
+
+    def wait(self, ticket) -> float:
+        lat = pg_server_wait(self.h, ticket)
+        self._keep.pop(ticket, None)
+        return lat
+
+    def stats(self) -> dict:
+        return pg_server_get_stats(self.h)
+
+    def replay(self, requests, arrival_s=None, max_outstanding=0):
+        """requests: list of (req struct, keep) from make_request. Returns
+        (latency_ms array from arrival to result, elapsed seconds)."""
+        n = len(requests)
+        arr = (_Request * n)(*[r for r, _ in requests])
+        lat = np.zeros(n, dtype=np.float64)
+        el = ctypes.c_double()
+        arrp = None
+        if arrival_s is not None:
+            arrival_s = np.ascontiguousarray(arrival_s, dtype=np.float64)
+            arrp = arrival_s.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        _check(load().pg_server_replay(self.h, n, arr, arrp, max_outstanding,
+                                       lat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(el)))
+        return lat, float(el.value)
+
+    def close(self):
+        if self.h:
+            pg_server_destroy(self.h)
+            self.h = None

@@ -28,7 +28,8 @@ COMMON_FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
 
-SOURCES = ["pg_api.hip", "pg_graph.hip", "pg_build.hip", "pg_estimate.hip", "pg_exact.hip", "pg_prof.hip"]
+SOURCES = ["pg_api.hip", "pg_graph.hip", "pg_build.hip", "pg_estimate.hip", "pg_exact.hip", "pg_prof.hip",
+           "pg_server.hip"]
 
 
 def _compile(src: str) -> str:

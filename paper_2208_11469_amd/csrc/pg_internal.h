@@ -196,6 +196,8 @@ int build_onehash(pg_sketches* sk, hipStream_t s);
 
 // ---- launchers (pg_estimate.hip) ---------------------------------------------
 int ensure_table(pg_sketches* sk, int est, hipStream_t s);
+// Estimator table of a Bloom-filter size into a caller-owned [B+1] array.
+int fill_table(double* table, uint32_t B, uint32_t b, int est, hipStream_t s);
 // Per pair: est / raw / Jaccard outputs (each nullable).
 int estimate_pairs(const pg_sketches* sk, int est, const int32_t* u, const int32_t* v, int64_t npairs,
                    double* est_out, uint32_t* raw_out, float* jac_out, hipStream_t s);

@@ -1,0 +1,166 @@
+// Per-pair intersection estimates (Sections 4.2-4.4), shared by the batch
+// kernels of the estimate path and of the serving engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pg_device.h"
+#include "probgraph.h"
+
+struct pg_sketches;
+
+namespace pg {
+
+struct SkView {
+  int kind;
+  int est;
+  uint32_t size;  // B or k
+  uint32_t b;
+  uint32_t W;
+  int32_t n;
+  const uint64_t* words;
+  const uint32_t* pc;
+  const uint32_t* sig;
+  const double* table;
+  const int32_t* deg;
+  uint64_t a1, c1;  // 1-hash constants
+};
+
+// ---- integer counts ----------------------------------------------------------
+
+template <int WT>
+__device__ __forceinline__ uint32_t bf_and_count(const uint64_t* __restrict__ ru, const uint64_t* __restrict__ rv,
+                                                 uint32_t W) {
+  uint32_t c = 0;
+  if constexpr (WT > 0 && (WT % 2) == 0) {
+    // rows of an even word count start on 16-byte boundaries
+    const ulonglong2* u2 = reinterpret_cast<const ulonglong2*>(ru);
+    const ulonglong2* v2 = reinterpret_cast<const ulonglong2*>(rv);
+#pragma unroll
+    for (int j = 0; j < WT / 2; ++j) {
+      const ulonglong2 x = u2[j], y = v2[j];
+      c += (uint32_t)__popcll(x.x & y.x) + (uint32_t)__popcll(x.y & y.y);
+    }
+  } else if constexpr (WT > 0) {
+#pragma unroll
+    for (int j = 0; j < WT; ++j) c += (uint32_t)__popcll(ru[j] & rv[j]);
+  } else {
+    for (uint32_t j = 0; j < W; ++j) c += (uint32_t)__popcll(ru[j] & rv[j]);
+  }
+  return c;
+}
+
+__device__ __forceinline__ uint32_t kh_matches(const uint32_t* __restrict__ mu, const uint32_t* __restrict__ mv,
+                                               uint32_t k) {
+  uint32_t s = 0;
+  if ((k & 3u) == 0) {
+    const uint4* u4 = reinterpret_cast<const uint4*>(mu);
+    const uint4* v4 = reinterpret_cast<const uint4*>(mv);
+    for (uint32_t j = 0; j < k / 4; ++j) {
+      const uint4 x = u4[j], y = v4[j];
+      s += (x.x == y.x && x.x != kBottom) + (x.y == y.y && x.y != kBottom) + (x.z == y.z && x.z != kBottom) +
+           (x.w == y.w && x.w != kBottom);
+    }
+  } else {
+    for (uint32_t j = 0; j < k; ++j) s += (mu[j] == mv[j] && mu[j] != kBottom);
+  }
+  return s;
+}
+
+// Walk of two 1-hash rows (each ascending in key) in key order.
+//   common      = |M_u cap M_v|
+//   kprime      = min(k, |M_u cup M_v|)
+//   s_union     = commons among the kprime smallest of the union
+__device__ __forceinline__ void oh_counts(const uint32_t* __restrict__ mu, const uint32_t* __restrict__ mv, uint32_t k,
+                                          uint32_t nu, uint32_t nv, uint64_t a, uint64_t c, uint32_t& s_union,
+                                          uint32_t& kprime, uint32_t& common) {
+  uint32_t i = 0, j = 0, rank = 0, com = 0, com_k = 0;
+  uint64_t ku = nu ? mh_key(a, c, mu[0]) : ~0ull;
+  uint64_t kv = nv ? mh_key(a, c, mv[0]) : ~0ull;
+  while (i < nu || j < nv) {
+    if (i < nu && j < nv && mu[i] == mv[j]) {
+      com_k += rank < k ? 1u : 0u;
+      ++com;
+      ++i;
+      ++j;
+      ku = i < nu ? mh_key(a, c, mu[i]) : ~0ull;
+      kv = j < nv ? mh_key(a, c, mv[j]) : ~0ull;
+    } else if (j >= nv || (i < nu && ku < kv)) {
+      ++i;
+      ku = i < nu ? mh_key(a, c, mu[i]) : ~0ull;
+    } else {
+      ++j;
+      kv = j < nv ? mh_key(a, c, mv[j]) : ~0ull;
+    }
+    ++rank;
+  }
+  const uint32_t uni = nu + nv - com;
+  kprime = uni < k ? uni : k;
+  s_union = uni >= k ? com_k : com;
+  common = com;
+}
+
+// J^ = s / kk, I^ = J^ / (1 + J^) (|X| + |Y|)  (Eq. "est_int_mh", Section 4.4)
+__device__ __forceinline__ double minhash_estimate(uint32_t s, uint32_t kk, int32_t du, int32_t dv) {
+  const double j = kk > 0 ? (double)s / (double)kk : 0.0;
+  return j / (1.0 + j) * ((double)du + (double)dv);
+}
+
+template <int KIND, int WT>
+__device__ __forceinline__ double eval_pair(const SkView& s, int32_t u, int32_t v, uint32_t& raw) {
+  if ((uint32_t)u >= (uint32_t)s.n || (uint32_t)v >= (uint32_t)s.n) {
+    raw = 0xFFFFFFFFu;
+    return __longlong_as_double(0x7FF8000000000000ll);  // NaN for an out-of-range pair
+  }
+  if constexpr (KIND == PG_BF) {
+    const uint32_t c = bf_and_count<WT>(s.words + (size_t)u * s.W, s.words + (size_t)v * s.W, s.W);
+    if (s.est == PG_EST_BF_OR) {
+      const uint32_t cor = s.pc[u] + s.pc[v] - c;  // ones of the OR
+      raw = cor;
+      return ((double)s.deg[u] + (double)s.deg[v]) + s.table[cor];
+    }
+    raw = c;
+    return s.table[c];
+  } else if constexpr (KIND == PG_MH_KHASH) {
+    const uint32_t m = kh_matches(s.sig + (size_t)u * s.size, s.sig + (size_t)v * s.size, s.size);
+    raw = m;
+    return minhash_estimate(m, s.size, s.deg[u], s.deg[v]);
+  } else {
+    const int32_t du = s.deg[u], dv = s.deg[v];
+    const uint32_t nu = (uint32_t)du < s.size ? (uint32_t)du : s.size;
+    const uint32_t nv = (uint32_t)dv < s.size ? (uint32_t)dv : s.size;
+    uint32_t su, kp, com;
+    oh_counts(s.sig + (size_t)u * s.size, s.sig + (size_t)v * s.size, s.size, nu, nv, s.a1, s.c1, su, kp, com);
+    if (s.est == PG_EST_MH_1HASH_LITERAL) {
+      raw = com;
+      return minhash_estimate(com, s.size, du, dv);
+    }
+    raw = su;
+    return minhash_estimate(su, kp, du, dv);
+  }
+}
+
+// J = I_c / (d_u + d_v - I_c), I_c = clamp(I^, 0, min(d_u, d_v)); 0 on an empty union.
+__device__ __forceinline__ double jaccard_of(double est, int32_t du, int32_t dv) {
+  const double lo = 0.0, hi = (double)(du < dv ? du : dv);
+  const double ic = est < lo ? lo : (est > hi ? hi : est);
+  const double den = ((double)du + (double)dv) - ic;
+  return den > 0.0 ? ic / den : 0.0;
+}
+
+
+// Kind chosen at run time (mixed batches); Bloom filters use the general word loop.
+__device__ __forceinline__ double eval_pair_any(const SkView& s, int32_t u, int32_t v, uint32_t& raw) {
+  if (s.kind == PG_BF) return eval_pair<PG_BF, 0>(s, u, v, raw);
+  if (s.kind == PG_MH_KHASH) return eval_pair<PG_MH_KHASH, 0>(s, u, v, raw);
+  return eval_pair<PG_MH_1HASH, 0>(s, u, v, raw);
+}
+
+// Host side (pg_estimate.hip): the view of a sketch set for an estimator, and
+// the check that the estimator applies to the sketch kind.
+SkView make_view(const pg_sketches* sk, int est);
+int check_estimator(const pg_sketches* sk, int est);
+
+}  // namespace pg

@@ -1,0 +1,138 @@
+"""Serving engine on the GPU: continuous batching keeps per-pair results
+bit-identical alone and in a mix; admission and validation behave."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import pggen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2208_11469_amd as pg  # noqa: E402
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("serving env: rmat12, BF 512 b=1, k-hash 32, 1-hash 16")
+    g = pggen.rmat(12, 16, seed=7)
+    ctx = pg.Context(0)
+    dg = pg.Graph(ctx, g.offsets, g.adj, validate=True)
+    sks = [dg.build_sketches("bf", 512, 1, seed=3), dg.build_sketches("kh", 32, seed=3),
+           dg.build_sketches("1h", 16, seed=3)]
+    yield g, ctx, dg, sks
+    for s in sks:
+        s.close()
+    dg.close()
+    ctx.close()
+
+
+KINDS = [(0, "and"), (0, "or"), (0, "l"), (0, "pap"), (1, "kh"), (2, "1h"), (2, "1h_lit")]
+
+
+def _requests(g, count, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        L = int(2 ** rng.uniform(0, 12))
+        u = rng.integers(0, g.n, L).astype(np.int32)
+        v = rng.integers(0, g.n, L).astype(np.int32)
+        sk, est = KINDS[i % len(KINDS)]
+        op = pg.PG_OP_CN if rng.integers(0, 2) == 0 else pg.PG_OP_JACCARD
+        reqs.append((op, sk, est, u, v))
+    return reqs
+
+
+def test_alone_equals_mixed_and_matches_direct_calls(env):
+    g, ctx, dg, sks = env
+    reqs = _requests(g, 40, seed=1)
+    srv = pg.Server(dg, sks, max_batches_in_flight=3)
+    alone = []
+    for op, sk, est, u, v in reqs:
+        t, out = srv.submit(op, sk, est, u, v)
+        srv.wait(t)
+        alone.append(out.copy())
+    srv.close()
+    say("replaying the mix back to back on one batch slot")
+    srv = pg.Server(dg, sks, max_batches_in_flight=1)
+    mix = [srv.make_request(op, sk, est, u, v) for op, sk, est, u, v in reqs]
+    srv.replay(mix, max_outstanding=len(mix))
+    st = srv.stats()
+    assert st["completed"] == 40 and st["rejected_invalid"] == 0
+    assert st["batches"] < 40, st  # requests that queued behind a running batch were merged
+    tickets = [(None, keep[2]) for _, keep in mix]
+    dev = torch.device("cuda", 0)
+    refs = {0: oracle.build_sketches(g, oracle.KIND_BF, 512, 1, seed=3),
+            1: oracle.build_sketches(g, oracle.KIND_KH, 32, seed=3),
+            2: oracle.build_sketches(g, oracle.KIND_1H, 16, seed=3)}
+    for (op, sk, est, u, v), a, (_, m) in zip(reqs, alone, tickets):
+        assert a.tobytes() == m.tobytes()  # bitwise: alone == in the mix
+        tu, tv = torch.from_numpy(u).to(dev), torch.from_numpy(v).to(dev)
+        if op == pg.PG_OP_CN:
+            direct, _ = sks[sk].intersect(est, tu, tv)
+            want = refs[sk].estimate(u, v, est)
+        else:
+            direct = sks[sk].jaccard(est, tu, tv)
+            want = oracle.jaccard(refs[sk], est, u, v)
+        torch.cuda.synchronize()
+        assert direct.cpu().numpy().tobytes() == a.tobytes()
+        assert np.allclose(a, want, rtol=1e-6 + (2.0**-23 if op == pg.PG_OP_JACCARD else 0), atol=1e-12)
+    srv.close()
+
+
+def test_admission_by_memory_budget(env):
+    g, ctx, dg, sks = env
+    srv = pg.Server(dg, sks, memory_budget_bytes=16 * 1000)
+    u = np.arange(1000, dtype=np.int32) % g.n
+    t1, _ = srv.submit(pg.PG_OP_CN, 0, "and", u, u[::-1].copy())
+    with pytest.raises(pg.PGError) as ei:
+        srv.submit(pg.PG_OP_CN, 0, "and", u[:10], u[:10])
+    assert ei.value.code == pg.PG_E_BUSY
+    srv.wait(t1)  # collecting releases the budget
+    t2, _ = srv.submit(pg.PG_OP_CN, 0, "and", u[:10], u[:10])
+    srv.wait(t2)
+    assert srv.stats()["rejected_busy"] == 1
+    srv.close()
+
+
+def test_malformed_requests_rejected_before_enqueue(env):
+    g, ctx, dg, sks = env
+    srv = pg.Server(dg, sks, max_pairs_per_request=100)
+    ok = np.zeros(4, np.int32)
+    bad = np.array([0, 1, g.n, 2], np.int32)
+    cases = [(pg.PG_OP_CN, 0, "and", bad, ok), (pg.PG_OP_CN, 0, "kh", ok, ok), (pg.PG_OP_CN, 5, "and", ok, ok),
+             (7, 0, "and", ok, ok), (pg.PG_OP_CN, 1, "kh", np.zeros(101, np.int32), np.zeros(101, np.int32)),
+             (pg.PG_OP_CN, 0, "and", np.zeros(0, np.int32), np.zeros(0, np.int32))]
+    for op, sk, est, u, v in cases:
+        with pytest.raises(pg.PGError) as ei:
+            srv.submit(op, sk, est, u, v)
+        assert ei.value.code == pg.PG_E_INVALID
+    assert srv.stats()["rejected_invalid"] == len(cases) and srv.stats()["submitted"] == 0
+    srv.close()
+
+
+def test_replay_open_and_closed_loop(env):
+    g, ctx, dg, sks = env
+    srv = pg.Server(dg, sks)
+    reqs = [srv.make_request(op, sk, est, u, v) for op, sk, est, u, v in _requests(g, 60, seed=2)]
+    lat, el = srv.replay(reqs, max_outstanding=8)
+    assert np.all(lat > 0) and el > 0
+    arrivals = np.cumsum(np.full(60, 1e-4))
+    lat2, el2 = srv.replay(reqs, arrival_s=arrivals)
+    assert np.all(lat2 > 0) and el2 >= arrivals[-1]
+    assert srv.stats()["completed"] == 120
+    # replayed results are the same as a direct call
+    op, sk, est, u, v = _requests(g, 60, seed=2)[3]
+    t, out = srv.submit(op, sk, est, u, v)
+    srv.wait(t)
+    assert out.tobytes() == reqs[3][1][2].tobytes()
+    srv.close()
