@@ -79,6 +79,48 @@ def timed(fn, reps, sync):
     return statistics.median(out)
 
 
+def measure_batch(args, pg, pggen, np, torch, log):
+    """Many small graphs: autotune, capture one run in a HIP graph, time replays."""
+    t = time.perf_counter()
+    graphs, bits = pggen.graph_batch(count=args.batch_graphs, seed0=args.seed)
+    n_total = sum(g.n for g in graphs)
+    arcs = sum(g.nnz for g in graphs)
+    log(f"batch: {len(graphs)} graphs, {n_total} vertices, {arcs} arcs ({time.perf_counter() - t:.1f}s)")
+    ctx = pg.Context(0)
+    bt = pg.Batch(ctx, graphs, bits, b=1, seed=args.seed)
+    tune_ms = bt.autotune("and")
+    tile, bpc = bt.params()
+    s = torch.cuda.Stream()
+    bt.capture("and", stream=s)
+    for _ in range(3):
+        bt.replay(stream=s)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        bt.replay(stream=s)
+        e1.record(s)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = statistics.median(times)
+    tc, _ = bt.results(stream=s)
+    # bytes the method moves per run: build reads offsets and arcs and writes rows; the estimate reads
+    # offsets, arcs, its own row and one neighbour row per arc
+    row_bytes = sum(g.n * (B // 8) for g, B in zip(graphs, bits))
+    nbr_rows = sum(g.nnz * (B // 8) for g, B in zip(graphs, bits))
+    alg = 2 * (8 * n_total + 4 * arcs) + 2 * row_bytes + 4 * n_total + nbr_rows + 8 * n_total * 3
+    bt.close()
+    ctx.close()
+    log(f"batch replay {ms:.3f} ms ({arcs / (ms * 1e-3):.3e} arc intersections/s), tile {tile} blocks/CU {bpc}")
+    return {"workload": f"{len(graphs)} graphs, n log-uniform in [2^8, 2^16], half G(n,p) (mean degree 8..64), "
+                        "half R-MAT ef16; BF 128..1024 bits b=1; TC + CC per graph, AND estimator",
+            "graphs": len(graphs), "vertices": n_total, "arcs": arcs, "replay_ms": round(ms, 4),
+            "arc_intersections_per_s": arcs / (ms * 1e-3), "algorithmic_gbs": alg / (ms * 1e-3) / 1e9,
+            "autotuned": {"tile_vertices": tile, "blocks_per_cu": bpc, "best_ms": round(tune_ms, 4)},
+            "tc_sum": float(np.sum(tc))}
+
+
 def measure_serving(args, pg, pggen, np, log):
     """Query serving on a resident R-MAT graph: closed-loop saturation, then
     open-loop Poisson arrivals at 50/80/95% of it; latency from arrival to
@@ -141,6 +183,8 @@ def main():
     ap.add_argument("--skip-serving", action="store_true", help="leave out the serving measurement")
     ap.add_argument("--serving-scale", type=int, default=22)
     ap.add_argument("--serving-requests", type=int, default=10000)
+    ap.add_argument("--skip-batch", action="store_true", help="leave out the batched-graphs measurement")
+    ap.add_argument("--batch-graphs", type=int, default=512)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -291,6 +335,10 @@ def main():
                "seconds": round(cpu_s, 4), "tc_matches_gpu_rel": abs(tc_cpu - tc_bf) / abs(tc_cpu)}
         log(f"cpu oracle: {cpu_s:.3f} s -> {m / cpu_s:.4e} {UNIT} on {oracle.threads()} threads")
 
+    batch = None
+    if not args.skip_batch:
+        batch = measure_batch(args, pg, pggen, np, torch, log)
+
     serving = None
     if not args.skip_serving:
         serving = measure_serving(args, pg, pggen, np, log)
@@ -327,6 +375,7 @@ def main():
         "phases": phases,
         "rows": rows,
         "serving": serving,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
     sk.close()

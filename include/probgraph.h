@@ -258,6 +258,44 @@ int pg_server_replay(pg_server* srv, int64_t nreq, const pg_request* reqs, const
 /* Waits for every admitted request, stops the engine and frees the server. */
 int pg_server_destroy(pg_server* srv);
 
+/* ---- batched small graphs ---------------------------------------------------- */
+/* Many independent graphs processed together: per-graph Bloom filters (each
+ * graph its own B), then per-graph estimated triangle count and per-vertex
+ * clustering coefficient, in persistent launches that pull (graph, vertex tile)
+ * work items from a queue ordered by cost. The run allocates nothing and uses
+ * no memset, so it can be captured in a HIP graph and replayed. Results do not
+ * depend on the tuning parameters or on scheduling. */
+typedef struct pg_batch pg_batch;
+
+typedef struct pg_batch_params {
+  int32_t tile_vertices;   /* light vertices per work item, a multiple of 32; 0 = 64 */
+  int32_t blocks_per_cu;   /* persistent blocks per compute unit; 0 = 4 */
+} pg_batch_params;
+
+/* Host CSR arrays of `count` graphs (offsets[i] has n[i]+1 entries, adj[i]
+ * nnz[i]); bits[i] = Bloom-filter size of graph i (multiple of 64, <= 1024).
+ * The arrays are copied. Graph invariants are checked on the host (bounds
+ * always; sortedness and symmetry too). */
+int pg_batch_create(pg_ctx* ctx, int32_t count, const int32_t* const* offsets, const int32_t* const* adj,
+                    const int32_t* n, const int64_t* nnz, const uint32_t* bits, uint32_t b, uint64_t seed,
+                    pg_batch** out);
+int pg_batch_set_params(pg_batch* bt, const pg_batch_params* params);
+int pg_batch_get_params(const pg_batch* bt, pg_batch_params* out);
+/* Enqueue one run: build every filter, estimate every vertex's clustering
+ * coefficient and every graph's triangle count with `estimator` (a Bloom-filter
+ * estimator). */
+int pg_batch_run(pg_batch* bt, int estimator, void* stream);
+/* Capture one run (on `stream`) into a HIP graph; pg_batch_replay launches it. */
+int pg_batch_capture(pg_batch* bt, int estimator, void* stream);
+int pg_batch_replay(pg_batch* bt, void* stream);
+/* Results of the last completed run (host arrays; waits for `stream`):
+ * tc[count], and cc[sum of n] in graph order (either may be NULL). */
+int pg_batch_results(pg_batch* bt, double* tc, float* cc, void* stream);
+/* Time every candidate (tile_vertices, blocks_per_cu) on this batch and keep
+ * the fastest; *best_ms (nullable) receives its run time. */
+int pg_batch_autotune(pg_batch* bt, int estimator, void* stream, double* best_ms);
+int pg_batch_destroy(pg_batch* bt);
+
 /* ---- measurement ----------------------------------------------------------- */
 typedef struct pg_kernel_time {
   char name[48];     /* launch site, e.g. "bf_build", "pairs_sum" */

@@ -73,6 +73,10 @@ class _SketchInfo(ctypes.Structure):
                 ("row_bytes", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64)]
 
 
+class _BatchParams(ctypes.Structure):
+    _fields_ = [("tile_vertices", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
 class _ServerParams(ctypes.Structure):
     _fields_ = [("max_batches_in_flight", ctypes.c_int32), ("max_pairs_per_request", ctypes.c_int32),
                 ("max_batch_pairs", ctypes.c_int64), ("memory_budget_bytes", ctypes.c_uint64)]
@@ -136,6 +140,15 @@ def _declare(lib):
         "pg_server_replay": (i, [_vp, i64, P(_Request), P(ctypes.c_double), i32, P(ctypes.c_double),
                                  P(ctypes.c_double)]),
         "pg_server_destroy": (i, [_vp]),
+        "pg_batch_create": (i, [_vp, i32, P(_vp), P(_vp), P(i32), P(i64), P(u32), u32, u64, P(_vp)]),
+        "pg_batch_set_params": (i, [_vp, P(_BatchParams)]),
+        "pg_batch_get_params": (i, [_vp, P(_BatchParams)]),
+        "pg_batch_run": (i, [_vp, i, _vp]),
+        "pg_batch_capture": (i, [_vp, i, _vp]),
+        "pg_batch_replay": (i, [_vp, _vp]),
+        "pg_batch_results": (i, [_vp, P(ctypes.c_double), P(ctypes.c_float), _vp]),
+        "pg_batch_autotune": (i, [_vp, i, _vp, P(ctypes.c_double)]),
+        "pg_batch_destroy": (i, [_vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -617,4 +630,64 @@ class Server:
     def close(self):
         if self.h:
             pg_server_destroy(self.h)
+            self.h = None
+
+
+class Batch:
+    """Many small graphs processed together (see pg_batch_* in probgraph.h).
+    ``graphs``: objects with n, offsets, adj (numpy int32); ``bits``: per-graph
+    Bloom-filter sizes."""
+
+    def __init__(self, ctx: Context, graphs, bits, b: int = 1, seed: int = 1):
+        lib = load()
+        self.ctx = ctx
+        self.count = len(graphs)
+        self._keep = [(np.ascontiguousarray(g.offsets, np.int32), np.ascontiguousarray(g.adj, np.int32))
+                      for g in graphs]
+        offs = (_vp * self.count)(*[o.ctypes.data for o, _ in self._keep])
+        adjs = (_vp * self.count)(*[a.ctypes.data if a.shape[0] else 0 for _, a in self._keep])
+        ns = np.array([g.n for g in graphs], dtype=np.int32)
+        nnz = np.array([a.shape[0] for _, a in self._keep], dtype=np.int64)
+        bits = np.ascontiguousarray(bits, dtype=np.uint32)
+        self.n_total = int(ns.sum())
+        h = _vp()
+        _check(lib.pg_batch_create(ctx.h, self.count, offs, adjs, ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   nnz.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), b, seed & (2**64 - 1),
+                                   ctypes.byref(h)))
+        self.h = h
+
+    def set_params(self, tile_vertices=0, blocks_per_cu=0):
+        _check(load().pg_batch_set_params(self.h, ctypes.byref(_BatchParams(tile_vertices, blocks_per_cu))))
+
+    def params(self):
+        p = _BatchParams()
+        _check(load().pg_batch_get_params(self.h, ctypes.byref(p)))
+        return int(p.tile_vertices), int(p.blocks_per_cu)
+
+    def run(self, estimator="and", stream=None):
+        _check(load().pg_batch_run(self.h, ESTIMATORS.get(estimator, estimator), _stream(stream)))
+
+    def capture(self, estimator="and", stream=None):
+        _check(load().pg_batch_capture(self.h, ESTIMATORS.get(estimator, estimator), _stream(stream)))
+
+    def replay(self, stream=None):
+        _check(load().pg_batch_replay(self.h, _stream(stream)))
+
+    def results(self, stream=None):
+        tc = np.zeros(self.count, dtype=np.float64)
+        cc = np.zeros(max(self.n_total, 1), dtype=np.float32)
+        _check(load().pg_batch_results(self.h, tc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       cc.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)))
+        return tc, cc[: self.n_total]
+
+    def autotune(self, estimator="and", stream=None):
+        ms = ctypes.c_double()
+        _check(load().pg_batch_autotune(self.h, ESTIMATORS.get(estimator, estimator), _stream(stream),
+                                        ctypes.byref(ms)))
+        return float(ms.value)
+
+    def close(self):
+        if self.h:
+            _check(load().pg_batch_destroy(self.h))
             self.h = None

@@ -1,0 +1,631 @@
+// Batched small graphs: per-graph Bloom filters, clustering coefficients and
+// triangle counts for many graphs in persistent launches.
+//
+// Layout (one arena for all graphs): global vertex IDs vbase[g] + v, int64
+// arc offsets over all graphs, neighbour IDs kept local to their graph, filter
+// rows of graph g at word wbase[g] + v * W[g], estimator tables at tbase[g].
+//
+// Work list (built on the host, heaviest first): a heavy vertex (more than
+// kBatchHeavy arcs) is one item processed by a whole block; the other vertices
+// form tiles of tile_vertices consecutive vertices, kBatchGroup lanes per
+// vertex. Persistent blocks take items from a counter reset at the start of
+// every run and leave when the list is exhausted.
+//
+// Each vertex is always reduced by the same lanes in the same order (its tier
+// is fixed by its degree), so results do not depend on the tile size, the grid
+// size or which block took which item.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pg_device.h"
+#include "pg_internal.h"
+
+namespace pg {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kBatchGroup = 8;
+constexpr int kGroups = kBlock / kBatchGroup;
+constexpr int32_t kBatchHeavy = 512;
+constexpr int kMaxW = 16;
+constexpr int kStride = kBlock + 1;
+
+struct GraphDesc {
+  int64_t vbase;  // first global vertex
+  int64_t wbase;  // first word of the graph's rows
+  int64_t tbase;  // first entry of the graph's estimator table
+  int32_t n;
+  uint32_t B;
+  uint32_t W;
+  int32_t pad;
+};
+
+struct Item {
+  int32_t graph;
+  int32_t heavy;  // 1: the single vertex v0 with a whole block
+  int32_t v0, v1; // local vertex range
+};
+
+struct BatchView {
+  const GraphDesc* gd;
+  const Item* items;
+  int64_t nitems;
+  const int64_t* off;
+  const int32_t* adj;
+  uint64_t* words;
+  uint32_t* pc;
+  const uint64_t* ha;
+  const uint64_t* hc;
+  uint32_t b;
+  const double* tables;
+  double* S;
+  double* Splus;
+  float* cc;
+  uint32_t* counters;  // [0] build queue, [1] estimate queue
+};
+
+__global__ void k_batch_reset(uint32_t* counters) {
+  if (threadIdx.x < 2) counters[threadIdx.x] = 0;
+}
+
+// One block per graph: T_g[c] for c = 0..B_g (same formulas as the single-graph tables).
+__global__ void k_batch_tables(const GraphDesc* __restrict__ gd, uint32_t b, int est, double* __restrict__ tables) {
+  const GraphDesc d = gd[blockIdx.x];
+  const double Bd = (double)d.B, bd = (double)b;
+  for (uint32_t c = threadIdx.x; c <= d.B; c += blockDim.x) {
+    const double ct = (double)(c == d.B ? c - 1 : c);
+    double r;
+    if (est == PG_EST_BF_AND)
+      r = -(Bd / bd) * log(1.0 - ct / Bd);
+    else if (est == PG_EST_BF_L)
+      r = (double)c / bd;
+    else
+      r = log(1.0 - ct / Bd) / (bd * log(1.0 - 1.0 / Bd));
+    tables[d.tbase + c] = r;
+  }
+}
+
+__device__ __forceinline__ int64_t next_item(uint32_t* counter, int64_t* slot) {
+  if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(counter, 1u);
+  __syncthreads();
+  const int64_t it = *slot;
+  __syncthreads();
+  return it;
+}
+
+__device__ __forceinline__ void scatter_arcs(const BatchView& bv, int64_t beg, int64_t end, int lane, int G,
+                                             uint32_t B, uint64_t* __restrict__ mine) {
+  for (int64_t p0 = beg + lane; p0 < end; p0 += (int64_t)G * 4) {
+    uint32_t x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t p = p0 + (int64_t)j * G;
+      x[j] = p < end ? (uint32_t)bv.adj[p] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (p0 + (int64_t)j * G < end) {
+        for (uint32_t i = 0; i < bv.b; ++i) {
+          const uint32_t idx = bf_index(bv.ha[i], bv.hc[i], x[j], B);
+          mine[(idx >> 6) * kStride] |= 1ull << (idx & 63u);
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_build(BatchView bv) {
+  __shared__ uint64_t lds[kMaxW * kStride];
+  __shared__ uint32_t ones_sh[kMaxW];
+  __shared__ int64_t slot;
+  const int tid = threadIdx.x;
+  uint64_t* mine = lds + tid;
+  for (;;) {
+    const int64_t it = next_item(&bv.counters[0], &slot);
+    if (it >= bv.nitems) return;
+    const Item item = bv.items[it];
+    const GraphDesc gd = bv.gd[item.graph];
+    const uint32_t W = gd.W;
+    if (item.heavy) {
+      for (uint32_t k = 0; k < W; ++k) mine[k * kStride] = 0;
+      const int64_t gv = gd.vbase + item.v0;
+      scatter_arcs(bv, bv.off[gv], bv.off[gv + 1], tid, kBlock, gd.B, mine);
+      __syncthreads();
+      if ((uint32_t)tid < W) {
+        uint64_t w = 0;
+        for (int i = 0; i < kBlock; ++i) w |= lds[tid * kStride + i];
+        bv.words[gd.wbase + (int64_t)item.v0 * W + tid] = w;
+        ones_sh[tid] = (uint32_t)__popcll(w);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t ones = 0;
+        for (uint32_t k = 0; k < W; ++k) ones += ones_sh[k];
+        bv.pc[gv] = ones;
+      }
+      __syncthreads();
+      continue;
+    }
+    const int grp = tid / kBatchGroup, lane = tid % kBatchGroup;
+    for (int32_t v = item.v0 + grp; v < item.v1; v += kGroups) {
+      const int64_t gv = gd.vbase + v;
+      const int64_t beg = bv.off[gv], end = bv.off[gv + 1];
+      if (end - beg > kBatchHeavy) continue;  // a heavy item of its own
+      for (uint32_t k = 0; k < W; ++k) mine[k * kStride] = 0;
+      scatter_arcs(bv, beg, end, lane, kBatchGroup, gd.B, mine);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      uint32_t ones = 0;
+      for (uint32_t k = lane; k < W; k += kBatchGroup) {
+        uint64_t w = 0;
+#pragma unroll
+        for (int i = 0; i < kBatchGroup; ++i) w |= lds[k * kStride + (tid - lane) + i];
+        bv.words[gd.wbase + (int64_t)v * W + k] = w;
+        ones += (uint32_t)__popcll(w);
+      }
+      ones = group_sum_u32<kBatchGroup>(ones);
+      if (lane == 0) bv.pc[gv] = ones;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __syncthreads();
+  }
+}
+
+// Sum of the estimate over the arcs of v (all, and those to larger IDs).
+__device__ __forceinline__ void vertex_sums(const BatchView& bv, const GraphDesc& gd, int32_t v, int64_t beg,
+                                            int64_t end, int lane, int G, double& all, double& up) {
+  const uint32_t W = gd.W;
+  uint64_t rv[kMaxW];
+  const uint64_t* row = bv.words + gd.wbase + (int64_t)v * W;
+#pragma unroll
+  for (int k = 0; k < kMaxW; ++k) rv[k] = (uint32_t)k < W ? row[k] : 0ull;
+  const double* tab = bv.tables + gd.tbase;
+  for (int64_t p = beg + lane; p < end; p += G) {
+    const int32_t u = bv.adj[p];
+    const uint64_t* ru = bv.words + gd.wbase + (int64_t)u * W;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxW; ++k)
+      if ((uint32_t)k < W) c += (uint32_t)__popcll(rv[k] & ru[k]);
+    const double t = tab[c];
+    all += t;
+    if (u > v) up += t;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_estimate(BatchView bv) {
+  __shared__ double red[kBlock / kWave];
+  __shared__ int64_t slot;
+  const int tid = threadIdx.x;
+  for (;;) {
+    const int64_t it = next_item(&bv.counters[1], &slot);
+    if (it >= bv.nitems) return;
+    const Item item = bv.items[it];
+    const GraphDesc gd = bv.gd[item.graph];
+    if (item.heavy) {
+      const int64_t gv = gd.vbase + item.v0;
+      double all = 0.0, up = 0.0;
+      vertex_sums(bv, gd, item.v0, bv.off[gv], bv.off[gv + 1], tid, kBlock, all, up);
+      all = block_sum_256(all, red);
+      up = block_sum_256(up, red);
+      if (tid == 0) {
+        const int64_t d = bv.off[gv + 1] - bv.off[gv];
+        bv.S[gv] = all;
+        bv.Splus[gv] = up;
+        bv.cc[gv] = d >= 2 ? (float)(all / ((double)d * ((double)d - 1.0))) : 0.0f;
+      }
+      continue;
+    }
+    const int grp = tid / kBatchGroup, lane = tid % kBatchGroup;
+    for (int32_t v = item.v0 + grp; v < item.v1; v += kGroups) {
+      const int64_t gv = gd.vbase + v;
+      const int64_t beg = bv.off[gv], end = bv.off[gv + 1];
+      if (end - beg > kBatchHeavy) continue;
+      double all = 0.0, up = 0.0;
+      vertex_sums(bv, gd, v, beg, end, lane, kBatchGroup, all, up);
+      all = group_sum<kBatchGroup>(all);
+      up = group_sum<kBatchGroup>(up);
+      if (lane == 0) {
+        const int64_t d = end - beg;
+        bv.S[gv] = all;
+        bv.Splus[gv] = up;
+        bv.cc[gv] = d >= 2 ? (float)(all / ((double)d * ((double)d - 1.0))) : 0.0f;
+      }
+    }
+  }
+}
+
+// One block per graph: TC_g = (1/3) sum of the upper sums, fixed order.
+__global__ __launch_bounds__(kBlock) void k_batch_tc(const GraphDesc* __restrict__ gd,
+                                                     const double* __restrict__ Splus, double* __restrict__ tc) {
+  __shared__ double red[kBlock / kWave];
+  const GraphDesc d = gd[blockIdx.x];
+  double acc = 0.0;
+  for (int32_t v = threadIdx.x; v < d.n; v += kBlock) acc += Splus[d.vbase + v];
+  const double r = block_sum_256(acc, red);
+  if (threadIdx.x == 0) tc[blockIdx.x] = r / 3.0;
+}
+
+}  // namespace
+}  // namespace pg
+
+struct pg_batch {
+  pg_ctx* ctx = nullptr;
+  int32_t count = 0;
+  int64_t N = 0;       // vertices over all graphs
+  int64_t arcs = 0;
+  uint32_t b = 1;
+  uint64_t seed = 0;
+  pg_batch_params params{64, 4};
+  std::vector<pg::GraphDesc> h_gd;
+  std::vector<int64_t> h_off;  // host copy of the global offsets (work-list construction)
+  pg::GraphDesc* gd = nullptr;
+  pg::Item* items = nullptr;
+  int64_t items_cap = 0;
+  int64_t nitems = 0;
+  int64_t* off = nullptr;
+  int32_t* adj = nullptr;
+  uint64_t* words = nullptr;
+  uint32_t* pc = nullptr;
+  uint64_t* ha = nullptr;
+  uint64_t* hc = nullptr;
+  double* tables = nullptr;
+  double* S = nullptr;
+  double* Splus = nullptr;
+  float* cc = nullptr;
+  double* tc = nullptr;
+  uint32_t* counters = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace pg {
+namespace {
+
+int build_items(pg_batch* bt) {
+  const int32_t T = bt->params.tile_vertices;
+  std::vector<std::pair<int64_t, Item>> list;
+  for (int32_t g = 0; g < bt->count; ++g) {
+    const GraphDesc& d = bt->h_gd[g];
+    for (int32_t v0 = 0; v0 < d.n; v0 += T) {
+      const int32_t v1 = std::min(d.n, v0 + T);
+      int64_t cost = 0;
+      for (int32_t v = v0; v < v1; ++v) {
+        const int64_t deg = bt->h_off[d.vbase + v + 1] - bt->h_off[d.vbase + v];
+        if (deg > kBatchHeavy)
+          list.push_back({deg, Item{g, 1, v, v + 1}});
+        else
+          cost += deg + 1;
+      }
+      list.push_back({cost, Item{g, 0, v0, v1}});
+    }
+  }
+  std::stable_sort(list.begin(), list.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::vector<Item> items(list.size());
+  for (size_t i = 0; i < list.size(); ++i) items[i] = list[i].second;
+  if ((int64_t)items.size() > bt->items_cap) {
+    pfree(bt->items);
+    bt->items = nullptr;
+    bt->items_cap = (int64_t)items.size();
+    PG_TRY(palloc((void**)&bt->items, sizeof(Item) * std::max<size_t>(items.size(), 1)));
+  }
+  bt->nitems = (int64_t)items.size();
+  if (!items.empty()) PG_HIP(hipMemcpy(bt->items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
+  return PG_OK;
+}
+
+BatchView view_of(pg_batch* bt) {
+  BatchView v;
+  v.gd = bt->gd;
+  v.items = bt->items;
+  v.nitems = bt->nitems;
+  v.off = bt->off;
+  v.adj = bt->adj;
+  v.words = bt->words;
+  v.pc = bt->pc;
+  v.ha = bt->ha;
+  v.hc = bt->hc;
+  v.b = bt->b;
+  v.tables = bt->tables;
+  v.S = bt->S;
+  v.Splus = bt->Splus;
+  v.cc = bt->cc;
+  v.counters = bt->counters;
+  return v;
+}
+
+// The whole run: kernels only, no allocation and no memset (capturable).
+int enqueue_run(pg_batch* bt, int est, hipStream_t s) {
+  ProfScope ps(s, "batch_run");
+  const BatchView bv = view_of(bt);
+  const unsigned persistent = (unsigned)std::max<int64_t>(
+      1, std::min<int64_t>(bt->nitems, (int64_t)std::max(1, bt->ctx->num_cus) * bt->params.blocks_per_cu));
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, bt->counters);
+  PG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_batch_tables, dim3((unsigned)bt->count), dim3(kBlock), 0, s, (const GraphDesc*)bt->gd, bt->b,
+                     est, bt->tables);
+  PG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_batch_build, dim3(persistent), dim3(kBlock), 0, s, bv);
+  PG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_batch_estimate, dim3(persistent), dim3(kBlock), 0, s, bv);
+  PG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_batch_tc, dim3((unsigned)bt->count), dim3(kBlock), 0, s, (const GraphDesc*)bt->gd,
+                     (const double*)bt->Splus, bt->tc);
+  PG_LAUNCH_CHECK();
+  return PG_OK;
+}
+
+void drop_graph(pg_batch* bt) {
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  bt->exec = nullptr;
+  bt->graph = nullptr;
+}
+
+void free_batch(pg_batch* bt) {
+  drop_graph(bt);
+  pfree(bt->gd);
+  pfree(bt->items);
+  pfree(bt->off);
+  pfree(bt->adj);
+  pfree(bt->words);
+  pfree(bt->pc);
+  pfree(bt->ha);
+  pfree(bt->hc);
+  pfree(bt->tables);
+  pfree(bt->S);
+  pfree(bt->Splus);
+  pfree(bt->cc);
+  pfree(bt->tc);
+  pfree(bt->counters);
+  delete bt;
+}
+
+bool bf_estimator(int est) { return est == PG_EST_BF_AND || est == PG_EST_BF_L || est == PG_EST_BF_PAPAPETROU; }
+
+}  // namespace
+}  // namespace pg
+
+using namespace pg;
+
+extern "C" {
+
+int pg_batch_create(pg_ctx* ctx, int32_t count, const int32_t* const* offsets, const int32_t* const* adj,
+                    const int32_t* n, const int64_t* nnz, const uint32_t* bits, uint32_t b, uint64_t seed,
+                    pg_batch** out) {
+  clear_error();
+  if (!ctx || !out || count < 1 || !offsets || !adj || !n || !nnz || !bits) return fail(PG_E_INVALID, "bad argument");
+  *out = nullptr;
+  if (b < 1 || b > 16) return fail(PG_E_INVALID, "b must be in [1, 16]");
+  // host checks: bounds, sortedness, no self-loops, symmetry
+  int64_t N = 0, A = 0, words = 0, tab = 0;
+  for (int32_t g = 0; g < count; ++g) {
+    if (n[g] < 0 || nnz[g] < 0 || bits[g] < 64 || bits[g] > 64u * kMaxW || bits[g] % 64)
+      return fail(PG_E_INVALID, "graph " + std::to_string(g) + ": bad n, nnz or filter size");
+    if (!offsets[g] || (nnz[g] > 0 && !adj[g])) return fail(PG_E_INVALID, "NULL graph array");
+    const int32_t* o = offsets[g];
+    const int32_t* a = adj[g];
+    if (o[0] != 0 || (int64_t)o[n[g]] != nnz[g]) return fail(PG_E_GRAPH, "graph " + std::to_string(g) + ": offsets");
+    for (int32_t v = 0; v < n[g]; ++v) {
+      if (o[v + 1] < o[v]) return fail(PG_E_GRAPH, "graph " + std::to_string(g) + ": offsets not monotone");
+      for (int32_t p = o[v]; p < o[v + 1]; ++p) {
+        const int32_t u = a[p];
+        if (u < 0 || u >= n[g] || u == v || (p > o[v] && a[p - 1] >= u))
+          return fail(PG_E_GRAPH, "graph " + std::to_string(g) + ": bad neighbour list");
+        if (!std::binary_search(a + o[u], a + o[u + 1], v))
+          return fail(PG_E_GRAPH, "graph " + std::to_string(g) + ": not symmetric");
+      }
+    }
+    N += n[g];
+    A += nnz[g];
+    words += (int64_t)n[g] * (bits[g] / 64);
+    tab += bits[g] + 1;
+  }
+  PG_HIP(hipSetDevice(ctx->device));
+  pg_batch* bt = new (std::nothrow) pg_batch();
+  if (!bt) return fail(PG_E_NOMEM, "host allocation failed");
+  bt->ctx = ctx;
+  bt->count = count;
+  bt->N = N;
+  bt->arcs = A;
+  bt->b = b;
+  bt->seed = seed;
+  bt->h_gd.resize(count);
+  bt->h_off.assign((size_t)N + 1, 0);
+  std::vector<int32_t> h_adj((size_t)std::max<int64_t>(A, 1));
+  int64_t vb = 0, ab = 0, wb = 0, tb = 0;
+  for (int32_t g = 0; g < count; ++g) {
+    GraphDesc& d = bt->h_gd[g];
+    d.vbase = vb;
+    d.wbase = wb;
+    d.tbase = tb;
+    d.n = n[g];
+    d.B = bits[g];
+    d.W = bits[g] / 64;
+    d.pad = 0;
+    for (int32_t v = 0; v <= n[g]; ++v) bt->h_off[vb + v] = ab + offsets[g][v];
+    std::copy(adj[g], adj[g] + nnz[g], h_adj.begin() + ab);
+    vb += n[g];
+    ab += nnz[g];
+    wb += (int64_t)n[g] * d.W;
+    tb += bits[g] + 1;
+  }
+  uint64_t ha[16], hc[16];
+  hash_constants(PG_BF, seed, b, ha, hc);
+  int rc = PG_OK;
+  auto P = [&](void** p, size_t bytes) {
+    if (rc == PG_OK) rc = palloc(p, std::max<size_t>(bytes, 8));
+  };
+  P((void**)&bt->gd, sizeof(GraphDesc) * count);
+  P((void**)&bt->off, sizeof(int64_t) * (N + 1));
+  P((void**)&bt->adj, sizeof(int32_t) * A);
+  P((void**)&bt->words, sizeof(uint64_t) * words);
+  P((void**)&bt->pc, sizeof(uint32_t) * N);
+  P((void**)&bt->ha, sizeof(uint64_t) * b);
+  P((void**)&bt->hc, sizeof(uint64_t) * b);
+  P((void**)&bt->tables, sizeof(double) * tab);
+  P((void**)&bt->S, sizeof(double) * N);
+  P((void**)&bt->Splus, sizeof(double) * N);
+  P((void**)&bt->cc, sizeof(float) * N);
+  P((void**)&bt->tc, sizeof(double) * count);
+  P((void**)&bt->counters, sizeof(uint32_t) * 2);
+  if (rc == PG_OK) {
+    hipError_t e = hipMemcpy(bt->gd, bt->h_gd.data(), sizeof(GraphDesc) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bt->off, bt->h_off.data(), sizeof(int64_t) * (N + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess && A > 0) e = hipMemcpy(bt->adj, h_adj.data(), sizeof(int32_t) * A, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bt->ha, ha, sizeof(uint64_t) * b, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bt->hc, hc, sizeof(uint64_t) * b, hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = fail(PG_E_DEVICE, std::string("batch upload: ") + hipGetErrorString(e));
+  }
+  if (rc == PG_OK) rc = build_items(bt);
+  if (rc != PG_OK) {
+    free_batch(bt);
+    return rc;
+  }
+  *out = bt;
+  return PG_OK;
+}
+
+int pg_batch_set_params(pg_batch* bt, const pg_batch_params* params) {
+  clear_error();
+  if (!bt || !params) return fail(PG_E_INVALID, "NULL argument");
+  pg_batch_params p = *params;
+  if (p.tile_vertices == 0) p.tile_vertices = 64;
+  if (p.blocks_per_cu == 0) p.blocks_per_cu = 4;
+  if (p.tile_vertices < kGroups || p.tile_vertices % kGroups || p.tile_vertices > 4096)
+    return fail(PG_E_INVALID, "tile_vertices must be a multiple of 32 in [32, 4096]");
+  if (p.blocks_per_cu < 1 || p.blocks_per_cu > 32) return fail(PG_E_INVALID, "blocks_per_cu must be in [1, 32]");
+  PG_HIP(hipSetDevice(bt->ctx->device));
+  PG_HIP(hipDeviceSynchronize());  // a previous run may still read the work list
+  const bool retile = p.tile_vertices != bt->params.tile_vertices;
+  bt->params = p;
+  drop_graph(bt);
+  if (retile) PG_TRY(build_items(bt));
+  return PG_OK;
+}
+
+int pg_batch_get_params(const pg_batch* bt, pg_batch_params* out) {
+  clear_error();
+  if (!bt || !out) return fail(PG_E_INVALID, "NULL argument");
+  *out = bt->params;
+  return PG_OK;
+}
+
+int pg_batch_run(pg_batch* bt, int estimator, void* stream) {
+  clear_error();
+  if (!bt) return fail(PG_E_INVALID, "NULL argument");
+  if (!bf_estimator(estimator)) return fail(PG_E_INVALID, "batches use the AND, L or Papapetrou estimator");
+  PG_HIP(hipSetDevice(bt->ctx->device));
+  return enqueue_run(bt, estimator, (hipStream_t)stream);
+}
+
+int pg_batch_capture(pg_batch* bt, int estimator, void* stream) {
+  clear_error();
+  if (!bt) return fail(PG_E_INVALID, "NULL argument");
+  if (!bf_estimator(estimator)) return fail(PG_E_INVALID, "batches use the AND, L or Papapetrou estimator");
+  PG_HIP(hipSetDevice(bt->ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) return fail(PG_E_INVALID, "capture needs an explicit (non-default) stream");
+  drop_graph(bt);
+  PG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const int rc = enqueue_run(bt, estimator, s);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc != PG_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(PG_E_DEVICE, std::string("end capture: ") + hipGetErrorString(e));
+  bt->graph = g;
+  PG_HIP(hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0));
+  return PG_OK;
+}
+
+int pg_batch_replay(pg_batch* bt, void* stream) {
+  clear_error();
+  if (!bt) return fail(PG_E_INVALID, "NULL argument");
+  if (!bt->exec) return fail(PG_E_INVALID, "no captured run");
+  PG_HIP(hipSetDevice(bt->ctx->device));
+  ProfScope ps((hipStream_t)stream, "batch_replay");
+  PG_HIP(hipGraphLaunch(bt->exec, (hipStream_t)stream));
+  return PG_OK;
+}
+
+int pg_batch_results(pg_batch* bt, double* tc, float* cc, void* stream) {
+  clear_error();
+  if (!bt) return fail(PG_E_INVALID, "NULL argument");
+  PG_HIP(hipSetDevice(bt->ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (tc) PG_HIP(hipMemcpyAsync(tc, bt->tc, sizeof(double) * bt->count, hipMemcpyDeviceToHost, s));
+  if (cc) PG_HIP(hipMemcpyAsync(cc, bt->cc, sizeof(float) * bt->N, hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  return PG_OK;
+}
+
+int pg_batch_autotune(pg_batch* bt, int estimator, void* stream, double* best_ms) {
+  clear_error();
+  if (!bt) return fail(PG_E_INVALID, "NULL argument");
+  if (!bf_estimator(estimator)) return fail(PG_E_INVALID, "batches use the AND, L or Papapetrou estimator");
+  PG_HIP(hipSetDevice(bt->ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  PG_HIP(hipEventCreate(&e0));
+  PG_HIP(hipEventCreate(&e1));
+  pg_batch_params best = bt->params;
+  double best_t = 1e300;
+  int rc = PG_OK;
+  for (int32_t tile : {32, 64, 128, 256}) {
+    for (int32_t bpc : {2, 4, 8}) {
+      pg_batch_params p{tile, bpc};
+      rc = pg_batch_set_params(bt, &p);
+      if (rc != PG_OK) break;
+      std::vector<float> times;
+      for (int rep = 0; rep < 4 && rc == PG_OK; ++rep) {
+        hipError_t e = hipEventRecord(e0, s);
+        if (e == hipSuccess) rc = enqueue_run(bt, estimator, s);
+        if (rc == PG_OK) {
+          e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.0f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) rc = fail(PG_E_DEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+          if (rep > 0) times.push_back(ms);  // the first run warms up
+        }
+      }
+      if (rc != PG_OK) break;
+      std::sort(times.begin(), times.end());
+      const double med = times[times.size() / 2];
+      if (med < best_t) {
+        best_t = med;
+        best = p;
+      }
+    }
+    if (rc != PG_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != PG_OK) return rc;
+  PG_TRY(pg_batch_set_params(bt, &best));
+  if (best_ms) *best_ms = best_t;
+  return PG_OK;
+}
+
+int pg_batch_destroy(pg_batch* bt) {
+  clear_error();
+  if (!bt) return fail(PG_E_INVALID, "NULL argument");
+  PG_HIP(hipSetDevice(bt->ctx->device));
+  PG_HIP(hipDeviceSynchronize());
+  free_batch(bt);
+  return PG_OK;
+}
+
+}  // extern "C"

@@ -65,6 +65,8 @@ bool prof_enabled() { return g_enabled; }
 
 ProfScope::ProfScope(hipStream_t s, const char* name) : s_(s), name_(name) {
   if (!g_enabled) return;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> lk(g_mu);
   start_ = take_event();
   if (start_ && hipEventRecord(start_, s_) != hipSuccess) {
