@@ -132,11 +132,13 @@ int pg_sketch_bits_for_budget(const pg_graph* g, double s, uint32_t* bits);
  *   a_i = sm(key, 2i) | 1,  c_i = sm(key, 2i+1),  g_i(x) = a_i*x + c_i mod 2^64
  *   Bloom-filter bit of x: ((g_i(x) >> 32) * B) >> 32, for i < b
  *   MinHash key of x:      mix(g_i(x)) (injective on 64-bit words: no ties)
- * Equal (graph, kind, size, b, seed) give bit-identical sketches. Device
- * layout: BF rows of B/64 uint64 words, bit t of the filter = bit (t & 63) of
- * word (t >> 6); MinHash rows of k uint32 vertex IDs (0xFFFFFFFF = empty
- * slot); k-hash slot i holds the argmin of key_i; 1-hash rows hold the
- * min(k, d_v) smallest keys' elements in ascending key order. */
+ * Equal (graph, kind, size, b, seed) give bit-identical sketches. Rows as
+ * exported (pg_sketches_export): BF rows of B/64 uint64 words, bit t of the
+ * filter = bit (t & 63) of word (t >> 6); MinHash rows of k uint32 vertex IDs
+ * (0xFFFFFFFF = empty slot); k-hash slot i holds the argmin of key_i; 1-hash
+ * rows hold the min(k, d_v) smallest keys' elements in ascending key order.
+ * (Inside the library BF rows are packed so that none crosses a 128-byte
+ * line; export returns them dense.) */
 int pg_build_sketches(pg_ctx* ctx, const pg_graph* g, int kind, uint32_t size, uint32_t b, uint64_t seed,
                       void* stream, pg_sketches** out);
 int pg_sketches_destroy(pg_sketches* sk);

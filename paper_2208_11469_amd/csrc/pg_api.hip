@@ -308,7 +308,7 @@ int pg_build_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, 
   }
   if (kind == PG_BF) {
     sk->W = size / 64;
-    if (rc == PG_OK) rc = palloc((void**)&sk->words, sizeof(uint64_t) * sk->W * n);
+    if (rc == PG_OK) rc = palloc((void**)&sk->words, sizeof(uint64_t) * bf_total_words((int64_t)n, sk->W));
     if (rc == PG_OK) rc = palloc((void**)&sk->pc, sizeof(uint32_t) * n);
     if (rc == PG_OK) rc = palloc((void**)&sk->table, sizeof(double) * (size + 1));
     if (rc == PG_OK)
@@ -379,9 +379,10 @@ int pg_sketches_export(const pg_sketches* sk, void* rows, uint32_t* pc, void* st
   const size_t n = (size_t)sk->g->n;
   if (n == 0) return PG_OK;
   if (rows) {
-    const size_t bytes = sk->kind == PG_BF ? n * sk->W * 8 : n * sk->size * 4;
-    PG_HIP(hipMemcpyAsync(rows, sk->kind == PG_BF ? (const void*)sk->words : (const void*)sk->sig, bytes,
-                          hipMemcpyDeviceToDevice, s));
+    if (sk->kind == PG_BF)
+      PG_TRY(bf_unpack(sk, rows, s));
+    else
+      PG_HIP(hipMemcpyAsync(rows, sk->sig, n * sk->size * 4, hipMemcpyDeviceToDevice, s));
   }
   if (pc) {
     if (sk->kind != PG_BF) return fail(PG_E_INVALID, "popcounts exist only for Bloom filters");

@@ -25,61 +25,6 @@ constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------- Bloom filter
 
-template <int WMAX, int G>
-__global__ __launch_bounds__(kBlock) void k_bf_build(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
-                                                     const int32_t* __restrict__ verts, int64_t nverts, uint32_t B,
-                                                     uint32_t W, uint32_t b, const uint64_t* __restrict__ ha,
-                                                     const uint64_t* __restrict__ hc, uint64_t* __restrict__ words,
-                                                     uint32_t* __restrict__ pc) {
-  __shared__ uint64_t lds[(G > kWave) ? (kBlock / kWave) * WMAX : 1];
-  const int64_t grp = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / G;
-  const int lane = threadIdx.x % G;
-  const bool active = grp < nverts;
-  const int32_t v = active ? verts[grp] : 0;
-  const int64_t beg = active ? off[v] : 0;
-  const int64_t end = active ? off[v + 1] : 0;
-  uint64_t bm[WMAX];
-#pragma unroll
-  for (int j = 0; j < WMAX; ++j) bm[j] = 0;
-  for (int64_t p = beg + lane; p < end; p += G) {
-    const uint32_t x = (uint32_t)adj[p];
-    for (uint32_t i = 0; i < b; ++i) {
-      const uint32_t idx = bf_index(ha[i], hc[i], x, B);
-      const uint32_t w = idx >> 6;
-      const uint64_t bit = 1ull << (idx & 63u);
-#pragma unroll
-      for (int j = 0; j < WMAX; ++j) bm[j] |= ((uint32_t)j == w) ? bit : 0ull;
-    }
-  }
-  if constexpr (G <= kWave) {
-#pragma unroll
-    for (int j = 0; j < WMAX; ++j) bm[j] = group_or<G>(bm[j]);
-  } else {
-    // one vertex per block: OR inside each wave, then the four waves in order
-#pragma unroll
-    for (int j = 0; j < WMAX; ++j) bm[j] = group_or<kWave>(bm[j]);
-    const int wv = threadIdx.x / kWave;
-    if (lane_id() == 0) {
-#pragma unroll
-      for (int j = 0; j < WMAX; ++j) lds[wv * WMAX + j] = bm[j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < WMAX; ++j) bm[j] = lds[j] | lds[WMAX + j] | lds[2 * WMAX + j] | lds[3 * WMAX + j];
-  }
-  if (!active) return;
-  uint64_t* row = words + (size_t)v * W;
-#pragma unroll
-  for (int j = 0; j < WMAX; ++j)
-    if ((uint32_t)j < W && (j % G) == lane) row[j] = bm[j];
-  if (lane == 0) {
-    uint32_t ones = 0;
-#pragma unroll
-    for (int j = 0; j < WMAX; ++j) ones += (uint32_t)__popcll(bm[j]);
-    pc[v] = ones;
-  }
-}
-
 // ---- Bloom filter over a vertex work plan (W <= 16 words) -------------------
 //
 // One launch, three tiers (heavy chunks first): heavy vertices are split into
@@ -160,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_bf_build_plan(PlanView P, const int3
     const int lane = lane_id();
     if (active && lane < W) {
       const uint64_t w = bf_gather_word<kWave>(lds, wv * kWave, lane);
-      words[(size_t)v * W + lane] = w;
+      words[bf_row_offset(v, W) + lane] = w;
       ones_lds[wv][lane] = (uint32_t)__popcll(w);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -191,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_bf_build_plan(PlanView P, const int3
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   uint32_t ones = 0;
   if (active) {
-    uint64_t* row = words + (size_t)v * W;
+    uint64_t* row = words + bf_row_offset(v, W);
     for (int k = lane; k < W; k += kLightGroup) {
       const uint64_t w = bf_gather_word<kLightGroup>(lds, tid - lane, k);
       row[k] = w;
@@ -214,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_bf_combine(PlanView P, const uint64_
   uint64_t acc = 0;
   if (lane < W)
     for (int32_t c = c0; c < c1; ++c) acc |= part[(int64_t)c * W + lane];
-  if (lane < W) words[(size_t)v * W + lane] = acc;
+  if (lane < W) words[bf_row_offset(v, W) + lane] = acc;
   const uint32_t ones = group_sum_u32<kWave>((uint32_t)__popcll(acc));
   if (lane == 0) pc[v] = ones;
 }
@@ -237,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_bf_build_wide(const int32_t* __restr
       if ((idx >> 6) == (uint32_t)lane) mine |= 1ull << (idx & 63u);
     }
   }
-  if ((uint32_t)lane < W) words[(size_t)v * W + lane] = mine;
+  if ((uint32_t)lane < W) words[bf_row_offset(v, W) + lane] = mine;
   const uint32_t ones = group_sum_u32<kWave>((uint32_t)__popcll(mine));
   if (lane == 0) pc[v] = ones;
 }
@@ -454,7 +399,25 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
   for (int64_t t = taken + lane; t < (int64_t)k; t += kWave) row[t] = kBottom;
 }
 
+// Dense copy of the rows (row v at v * W words) for export.
+__global__ void k_bf_unpack(const uint64_t* __restrict__ words, int64_t n, uint32_t W, uint64_t* __restrict__ out) {
+  const int64_t total = n * (int64_t)W;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = i / W;
+    out[i] = words[bf_row_offset(v, W) + (i - v * W)];
+  }
+}
+
 }  // namespace
+
+int bf_unpack(const pg_sketches* sk, void* rows, hipStream_t s) {
+  const int64_t n = sk->g->n;
+  if (n <= 0) return PG_OK;
+  hipLaunchKernelGGL(k_bf_unpack, dim3(grid_for(n * sk->W, kBlock, 65536)), dim3(kBlock), 0, s,
+                     (const uint64_t*)sk->words, n, sk->W, (uint64_t*)rows);
+  PG_LAUNCH_CHECK();
+  return PG_OK;
+}
 
 int build_bf(pg_sketches* sk, hipStream_t s) {
   const pg_graph* g = sk->g;
@@ -495,44 +458,9 @@ int build_bf(pg_sketches* sk, hipStream_t s) {
     PG_LAUNCH_CHECK();
     return PG_OK;
   }
-  if (W > 16) {
-    if (g->n > 0) {
-      hipLaunchKernelGGL(k_bf_build_wide, dim3(grid_for((int64_t)g->n * kWave, kBlock, 1ll << 31)), dim3(kBlock), 0,
-                         s, g->off, g->adj, g->n, sk->size, W, sk->b, sk->ha, sk->hc, sk->words, sk->pc);
-      PG_LAUNCH_CHECK();
-    }
-    return PG_OK;
-  }
-  for (int bin = 0; bin < kNumBins; ++bin) {
-    const int64_t cnt = g->bin_start[bin + 1] - g->bin_start[bin];
-    if (cnt <= 0) continue;
-    const int32_t* verts = g->bin_verts + g->bin_start[bin];
-    const int G = kBinGroup[bin];
-    const unsigned grid = (unsigned)((cnt * G + kBlock - 1) / kBlock);
-#define PG_BF_LAUNCH(WM, GG)                                                                                   \
-  hipLaunchKernelGGL((k_bf_build<WM, GG>), dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, verts, cnt, sk->size, \
-                     W, sk->b, sk->ha, sk->hc, sk->words, sk->pc)
-#define PG_BF_BY_G(WM)          \
-  do {                          \
-    if (G == 4)                 \
-      PG_BF_LAUNCH(WM, 4);      \
-    else if (G == 16)           \
-      PG_BF_LAUNCH(WM, 16);     \
-    else if (G == 64)           \
-      PG_BF_LAUNCH(WM, 64);     \
-    else                        \
-      PG_BF_LAUNCH(WM, 256);    \
-  } while (0)
-    if (W <= 2)
-      PG_BF_BY_G(2);
-    else if (W <= 4)
-      PG_BF_BY_G(4);
-    else if (W <= 8)
-      PG_BF_BY_G(8);
-    else
-      PG_BF_BY_G(16);
-#undef PG_BF_BY_G
-#undef PG_BF_LAUNCH
+  if (g->n > 0) {  // filters wider than 16 words
+    hipLaunchKernelGGL(k_bf_build_wide, dim3(grid_for((int64_t)g->n * kWave, kBlock, 1ll << 31)), dim3(kBlock), 0, s,
+                       g->off, g->adj, g->n, sk->size, W, sk->b, sk->ha, sk->hc, sk->words, sk->pc);
     PG_LAUNCH_CHECK();
   }
   return PG_OK;

@@ -30,6 +30,24 @@ __device__ __forceinline__ uint64_t mh_key(uint64_t a, uint64_t c, uint32_t x) {
   return mix64(a * (uint64_t)x + c);
 }
 
+// Bloom-filter row layout ("line-packed"): rows of W 64-bit words are packed
+// r = bf_rows_per_group(W) to a group of bf_group_words(W) words. For the
+// widths where a 128-byte group wastes at most a quarter of its bytes, groups
+// are exactly 128 bytes, so no row crosses a 128-byte cache line and a row
+// gather touches one line; other widths stay dense (r = 1, group = W).
+__host__ __device__ constexpr uint32_t bf_rows_per_group(uint32_t W) {
+  return (W <= 16 && 16 % W <= 4) ? 16 / W : 1;
+}
+__host__ __device__ constexpr uint32_t bf_group_words(uint32_t W) { return (W <= 16 && 16 % W <= 4) ? 16 : W; }
+__host__ __device__ __forceinline__ size_t bf_row_offset(int64_t v, uint32_t W) {
+  const uint32_t r = bf_rows_per_group(W);
+  return (size_t)(v / r) * bf_group_words(W) + (size_t)(v % r) * W;
+}
+// Words of a sketch set of n rows.
+__host__ __device__ constexpr size_t bf_total_words(int64_t n, uint32_t W) {
+  return (size_t)((n + bf_rows_per_group(W) - 1) / bf_rows_per_group(W)) * bf_group_words(W);
+}
+
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 // Fixed-order butterfly sum over groups of G lanes (G a power of two <= 64);

@@ -126,7 +126,7 @@ __device__ __forceinline__ double bf_row_sum(const SkView& s, const uint64_t (&r
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       if (x[j] >= 0) {
-        const uint64_t* r = s.words + (size_t)x[j] * W;
+        const uint64_t* r = s.words + bf_row_offset(x[j], W);
 #pragma unroll
         for (int k = 0; k < W; ++k) rv[j][k] = r[k];
       } else {
@@ -152,7 +152,7 @@ __device__ __forceinline__ double bf_row_sum(const SkView& s, const uint64_t (&r
 
 template <int W>
 __device__ __forceinline__ void load_row(const uint64_t* __restrict__ words, int32_t v, uint64_t (&r)[W]) {
-  const uint64_t* p = words + (size_t)v * W;
+  const uint64_t* p = words + bf_row_offset(v, W);
 #pragma unroll
   for (int k = 0; k < W; ++k) r[k] = p[k];
 }

@@ -166,7 +166,7 @@ struct pg_sketches {
   uint32_t b = 1;
   uint32_t W = 0;      // 64-bit words per Bloom-filter row
   uint64_t seed = 0;
-  uint64_t* words = nullptr;  // [n*W]  Bloom filters
+  uint64_t* words = nullptr;  // Bloom-filter rows, line-packed (bf_row_offset)
   uint32_t* pc = nullptr;     // [n]    ones per filter
   uint32_t* sig = nullptr;    // [n*k]  MinHash rows
   uint64_t* ha = nullptr;     // device hash multipliers
@@ -193,6 +193,8 @@ int sum_array(const double* x, int64_t count, double divisor, double* out, hipSt
 int build_bf(pg_sketches* sk, hipStream_t s);
 int build_khash(pg_sketches* sk, hipStream_t s);
 int build_onehash(pg_sketches* sk, hipStream_t s);
+// Dense row-major copy (n * W words) of line-packed Bloom-filter rows.
+int bf_unpack(const pg_sketches* sk, void* rows, hipStream_t s);
 
 // ---- launchers (pg_estimate.hip) ---------------------------------------------
 int ensure_table(pg_sketches* sk, int est, hipStream_t s);

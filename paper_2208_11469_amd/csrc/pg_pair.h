@@ -115,7 +115,8 @@ __device__ __forceinline__ double eval_pair(const SkView& s, int32_t u, int32_t 
     return __longlong_as_double(0x7FF8000000000000ll);  // NaN for an out-of-range pair
   }
   if constexpr (KIND == PG_BF) {
-    const uint32_t c = bf_and_count<WT>(s.words + (size_t)u * s.W, s.words + (size_t)v * s.W, s.W);
+    const uint32_t W = WT > 0 ? (uint32_t)WT : s.W;
+    const uint32_t c = bf_and_count<WT>(s.words + bf_row_offset(u, W), s.words + bf_row_offset(v, W), W);
     if (s.est == PG_EST_BF_OR) {
       const uint32_t cor = s.pc[u] + s.pc[v] - c;  // ones of the OR
       raw = cor;
