@@ -42,9 +42,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def _src_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+# sources the triangle-count kernel and its work plan are built from
+TC_SOURCES = ("pg_estimate.hip", "pg_graph.hip", "pg_internal.h", "pg_device.h", "pg_pair.h")
+
+
+def _src_hash(paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def tc_source_hash():
+    return _src_hash([os.path.join(ROOT, "paper_2208_11469_amd", "csrc", f) for f in TC_SOURCES])
 
 
 def _read_traffic(B: int):
@@ -58,8 +69,7 @@ def _read_traffic(B: int):
             if ":" in line and not line.lstrip().startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2208_11469_amd", "csrc", "pg_estimate.hip")
-    if kv.get("kernel_source_sha256_16") != _src_hash(src) or int(kv.get("bf_bits", -1)) != B:
+    if kv.get("kernel_source_sha256_16") != tc_source_hash() or int(kv.get("bf_bits", -1)) != B:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -263,7 +273,7 @@ def main():
     traffic = _read_traffic(B)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_bf_tc_plan (AND count + estimate over every upper edge, vertex-centric)",
+                "kernel": "k_bf_tc_slab (AND count + estimate over every upper edge, XCD-sliced vertex plan)",
                 "kernel_ms": round(k_ms, 5), "algorithmic_bytes": alg_bytes,
                 "bytes_rule": "m*(S+4) + n_active*(S+12), S = B/8"}
     build_ms = avg("bf_build")

@@ -101,7 +101,7 @@ void free_graph(pg_graph* g) {
   pfree(g->ustart);
   pfree(g->upoff);
   free_plan(&g->plan_all);
-  free_plan(&g->plan_up);
+  free_slabs(&g->slabs);
   delete g;
 }
 
@@ -308,7 +308,7 @@ int pg_build_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, 
   }
   if (kind == PG_BF) {
     sk->W = size / 64;
-    if (rc == PG_OK) rc = palloc((void**)&sk->words, sizeof(uint64_t) * bf_total_words((int64_t)n, sk->W));
+    if (rc == PG_OK) rc = palloc((void**)&sk->words, sizeof(uint64_t) * (bf_total_words((int64_t)n, sk->W) + kBfSlackWords));
     if (rc == PG_OK) rc = palloc((void**)&sk->pc, sizeof(uint32_t) * n);
     if (rc == PG_OK) rc = palloc((void**)&sk->table, sizeof(double) * (size + 1));
     if (rc == PG_OK)

@@ -47,6 +47,9 @@ __host__ __device__ __forceinline__ size_t bf_row_offset(int64_t v, uint32_t W) 
 __host__ __device__ constexpr size_t bf_total_words(int64_t n, uint32_t W) {
   return (size_t)((n + bf_rows_per_group(W) - 1) / bf_rows_per_group(W)) * bf_group_words(W);
 }
+// Slack words allocated after the last group: team readers of a row may read
+// up to 15 words past its end (those words are never counted).
+constexpr size_t kBfSlackWords = 16;
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 

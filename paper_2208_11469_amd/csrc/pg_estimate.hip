@@ -100,46 +100,93 @@ __global__ __launch_bounds__(kBlock) void k_cc(SkView s, const int32_t* __restri
 // ---- triangle count over the upper-neighbour plan (Bloom filters, W <= 16) ----
 //
 // Vertex-centric: the group owning v keeps B_v in registers and walks the
-// neighbours above v straight from the CSR, gathering U rows per lane before
-// reducing any of them. The estimator table sits in LDS. Every block writes
-// one partial sum; the final fixed-order sum makes the result independent of
-// scheduling.
+// neighbours above v straight from the CSR, gathering U rows ahead before
+// reducing any of them. A neighbour row is read by a team of T lanes side by
+// side, lane k holding words [kQ, kQ + Q) of B_v and loading the same words of
+// the row (Q = ceil(W / T), 16-byte loads); the team's counts meet in quad DPP
+// adds. Scattered row reads are limited by the L1 address and data path, not
+// by bytes: two lanes per row cut the cache accesses per row, while wider
+// teams cost more VALU work than they save (measured on gfx950). The last
+// lane of a team may read up to Q-1 words past the row (the next row, the
+// group padding, or the slack words after the last group); the matching words
+// of B_v are zero, so they never count. The estimator table sits in LDS.
+// Every block writes one partial sum; the final fixed-order sum makes the
+// result independent of scheduling.
 
 template <int W>
 struct RowUnroll {
   static constexpr int value = W <= 4 ? 8 : (W <= 8 ? 4 : 2);
 };
 
+constexpr int kTcTeamMax = 2;  // lanes per row at most (within a quad, so DPP can reduce)
+
+// Lanes per row for a group of G lanes: enough 16-byte loads to cover W
+// words, at most kTcTeamMax and at most G.
+template <int W, int G>
+struct TcTeam {
+  static constexpr int want = W <= 2 ? 1 : (W <= 4 ? 2 : 4);
+  static constexpr int capped = want < kTcTeamMax ? want : kTcTeamMax;
+  static constexpr int value = capped < G ? capped : G;
+  static constexpr int words = (W + value - 1) / value;  // Q
+};
+
+// Sum over the T lanes of a team (T in {1, 2, 4}, teams aligned to quads).
+template <int T>
+__device__ __forceinline__ uint32_t team_sum(uint32_t c) {
+  if constexpr (T >= 2) c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0xB1, 0xF, 0xF, false);  // lane ^ 1
+  if constexpr (T >= 4) c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0x4E, 0xF, 0xF, false);  // lane ^ 2
+  return c;
+}
+
+// Words [kQ, kQ + Q) of row v for team member k, zero past the row's end.
+template <int W, int G>
+__device__ __forceinline__ void load_team_row(const uint64_t* __restrict__ words, int32_t v, int k,
+                                              uint64_t (&r)[TcTeam<W, G>::words]) {
+  constexpr int Q = TcTeam<W, G>::words;
+  const uint64_t* p = words + bf_row_offset(v, W) + k * Q;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) r[i] = (k * Q + i < W) ? p[i] : 0;
+}
+
 template <int W, int U, int G, bool OR>
-__device__ __forceinline__ double bf_row_sum(const SkView& s, const uint64_t (&ru)[W], int32_t du, uint32_t pcu,
-                                             const int32_t* __restrict__ adj, int64_t beg, int64_t end, int lane,
-                                             const double* __restrict__ tab) {
+__device__ __forceinline__ double bf_row_sum(const SkView& s, const uint64_t (&ru)[TcTeam<W, G>::words], int32_t du,
+                                             uint32_t pcu, const int32_t* __restrict__ adj, int64_t beg, int64_t end,
+                                             int lane, const double* __restrict__ tab) {
+  constexpr int T = TcTeam<W, G>::value;
+  constexpr int Q = TcTeam<W, G>::words;
+  constexpr int NT = G / T;  // teams in the group
+  static_assert(G % T == 0, "a group holds whole teams");
+  const int k = lane % T;
+  const bool reads = k * Q < W;  // members past the row's end load nothing
   double acc = 0.0;
-  for (int64_t p0 = beg + lane; p0 < end; p0 += (int64_t)G * U) {
+  // every member of a team takes the same trip count, so the DPP adds only
+  // read lanes that are active
+  for (int64_t p0 = beg + lane / T; p0 < end; p0 += (int64_t)NT * U) {
     int32_t x[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      const int64_t p = p0 + (int64_t)j * G;
+      const int64_t p = p0 + (int64_t)j * NT;
       x[j] = p < end ? adj[p] : -1;
     }
-    uint64_t rv[U][W];
+    uint64_t rv[U][Q];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      if (x[j] >= 0) {
-        const uint64_t* r = s.words + bf_row_offset(x[j], W);
+      if (x[j] >= 0 && reads) {
+        const uint64_t* r = s.words + bf_row_offset(x[j], W) + k * Q;
 #pragma unroll
-        for (int k = 0; k < W; ++k) rv[j][k] = r[k];
+        for (int i = 0; i < Q; ++i) rv[j][i] = r[i];
       } else {
 #pragma unroll
-        for (int k = 0; k < W; ++k) rv[j][k] = 0;
+        for (int i = 0; i < Q; ++i) rv[j][i] = 0;
       }
     }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      if (x[j] >= 0) {
-        uint32_t c = 0;
+      uint32_t c = 0;
 #pragma unroll
-        for (int k = 0; k < W; ++k) c += (uint32_t)__popcll(ru[k] & rv[j][k]);
+      for (int i = 0; i < Q; ++i) c += (uint32_t)__popcll(ru[i] & rv[j][i]);
+      c = team_sum<T>(c);
+      if (k == 0 && x[j] >= 0) {
         if constexpr (OR)
           acc += ((double)du + (double)s.deg[x[j]]) + tab[pcu + s.pc[x[j]] - c];
         else
@@ -150,53 +197,66 @@ __device__ __forceinline__ double bf_row_sum(const SkView& s, const uint64_t (&r
   return acc;
 }
 
-template <int W>
-__device__ __forceinline__ void load_row(const uint64_t* __restrict__ words, int32_t v, uint64_t (&r)[W]) {
-  const uint64_t* p = words + bf_row_offset(v, W);
-#pragma unroll
-  for (int k = 0; k < W; ++k) r[k] = p[k];
+// Block i < slab_grid serves slab x = i mod kSlabs (the XCD it runs on) and
+// works on the (i / kSlabs)-th block of that slab's plan; the slab part is
+// sized for the busiest slab and surplus blocks of the other slabs write a
+// zero partial. Blocks from slab_grid on take the whole vertices.
+// Work of one group of G lanes on the upper neighbours adj[beg, end) of v.
+template <int W, int U, int G, bool OR>
+__device__ __forceinline__ double bf_item(const SkView& s, int32_t v, const int32_t* __restrict__ adj, int64_t beg,
+                                          int64_t end, int lane, const double* __restrict__ tab) {
+  uint64_t ru[TcTeam<W, G>::words];
+  load_team_row<W, G>(s.words, v, lane % TcTeam<W, G>::value, ru);
+  return bf_row_sum<W, U, G, OR>(s, ru, OR ? s.deg[v] : 0, OR ? s.pc[v] : 0u, adj, beg, end, lane, tab);
 }
 
 template <int W, bool OR>
-__global__ __launch_bounds__(kBlock) void k_bf_tc_plan(PlanView P, SkView s, const int32_t* __restrict__ off,
+__global__ __launch_bounds__(kBlock) void k_bf_tc_slab(SlabPlan P, SkView s, const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ ustart,
                                                        const int32_t* __restrict__ adj, double* __restrict__ partials) {
+  const bool whole = (int64_t)blockIdx.x >= P.slab_grid;
+  const int x = (int)(blockIdx.x % kSlabs);
+  const int64_t blk = whole ? (int64_t)blockIdx.x - P.slab_grid : (int64_t)(blockIdx.x / kSlabs);
+  const int64_t n_chunks = whole ? 0 : P.n_chunks[x];
+  const int64_t n_medium_blocks = whole ? 0 : (P.n_medium[x] + 3) / 4;
+  if (!whole && blk >= slab_blocks(P, x)) {
+    if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+    return;
+  }
   extern __shared__ double tab[];
   __shared__ double red[kBlock / kWave];
   for (uint32_t i = threadIdx.x; i <= s.size; i += kBlock) tab[i] = s.table[i];
   __syncthreads();
   constexpr int U = RowUnroll<W>::value;
-  const int64_t blk = blockIdx.x;
+  const size_t n = (size_t)s.n;
   const int tid = threadIdx.x;
   double acc = 0.0;
-  uint64_t ru[W];
-  if (blk < P.n_chunks) {  // heavy chunk: the whole block
-    const int32_t v = P.chunk_vertex[blk];
-    load_row<W>(s.words, v, ru);
-    acc = bf_row_sum<W, U, kBlock, OR>(s, ru, OR ? s.deg[v] : 0, OR ? s.pc[v] : 0u, adj, P.chunk_begin[blk],
-                                       P.chunk_end[blk], tid, tab);
-  } else {
-    const int64_t mb = blk - P.n_chunks;
-    if (mb < P.n_medium_blocks) {  // medium: one wave per vertex
-      const int64_t idx = mb * (kBlock / kWave) + tid / kWave;
-      if (idx < P.n_medium) {
-        const int32_t v = P.medium[idx];
-        load_row<W>(s.words, v, ru);
-        acc = bf_row_sum<W, U, kWave, OR>(s, ru, OR ? s.deg[v] : 0, OR ? s.pc[v] : 0u, adj, ustart[v], off[v + 1],
-                                          lane_id(), tab);
-      }
-    } else {  // light: kLightGroup lanes per vertex of the light list
-      const int64_t idx = ((mb - P.n_medium_blocks) * kBlock + tid) / kLightGroup;
-      if (idx < P.n_light) {  // the upper plan always lists its light vertices
-        const int32_t v = P.light[idx];
-        load_row<W>(s.words, v, ru);
-        acc = bf_row_sum<W, U, kLightGroup, OR>(s, ru, OR ? s.deg[v] : 0, OR ? s.pc[v] : 0u, adj, ustart[v],
-                                                off[v + 1], tid % kLightGroup, tab);
-      }
+  if (whole) {  // kWholeGroup lanes per whole vertex, all its upper neighbours
+    const int64_t idx = (blk * kBlock + tid) / kWholeGroup;
+    if (idx < P.n_whole) {
+      const int32_t v = P.verts[P.whole_at + idx];
+      acc = bf_item<W, U, kWholeGroup, OR>(s, v, adj, ustart[v], off[v + 1], tid % kWholeGroup, tab);
+    }
+  } else if (blk < n_chunks) {  // heavy chunk: the whole block
+    const int64_t c = P.chunk_at[x] + blk;
+    acc = bf_item<W, U, kBlock, OR>(s, P.chunk_vertex[c], adj, P.chunk_begin[c], P.chunk_end[c], tid, tab);
+  } else if (blk - n_chunks < n_medium_blocks) {  // medium: one wave per item
+    const int64_t idx = (blk - n_chunks) * (kBlock / kWave) + tid / kWave;
+    if (idx < P.n_medium[x]) {
+      const int32_t v = P.verts[P.medium_at[x] + idx];
+      acc = bf_item<W, U, kWave, OR>(s, v, adj, slab_begin(ustart, P.split, n, x, v), slab_end(off, P.split, n, x, v),
+                                     lane_id(), tab);
+    }
+  } else {  // light: kSlabLightGroup lanes per item
+    const int64_t idx = ((blk - n_chunks - n_medium_blocks) * kBlock + tid) / kSlabLightGroup;
+    if (idx < P.n_light[x]) {
+      const int32_t v = P.verts[P.light_at[x] + idx];
+      acc = bf_item<W, U, kSlabLightGroup, OR>(s, v, adj, slab_begin(ustart, P.split, n, x, v),
+                                                slab_end(off, P.split, n, x, v), tid % kSlabLightGroup, tab);
     }
   }
   const double r = block_sum_256(acc, red);
-  if (tid == 0) partials[blk] = r;
+  if (tid == 0) partials[blockIdx.x] = r;
 }
 
 __global__ void k_make_table(double* __restrict__ t, uint32_t B, uint32_t b, int est) {
@@ -336,22 +396,23 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
   PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
   const pg_graph* g = sk->g;
   if (sk->kind == PG_BF && sk->W <= 16 && g->n > 0) {
-    const VertexPlan& P = g->plan_up;
-    const int64_t nblk = std::max<int64_t>(plan_blocks(P), 1);
+    PG_TRY(graph_slabs(const_cast<pg_graph*>(g), s));
+    const SlabPlan& P = g->slabs;
+    const int64_t nblk = std::max<int64_t>(slab_plan_blocks(P), 1);
+    if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one triangle-count launch");
     double* partials = nullptr;
     PG_TRY(dmalloc((void**)&partials, sizeof(double) * (size_t)nblk, s));
     const SkView view = make_view(sk, est);
-    const PlanView pv = plan_view(P);
     const size_t shmem = sizeof(double) * ((size_t)sk->size + 1);
     {
       ProfScope ps(s, "bf_tc");
 #define PG_TCP(WW)                                                                                                    \
   do {                                                                                                                \
     if (est == PG_EST_BF_OR)                                                                                          \
-      hipLaunchKernelGGL((k_bf_tc_plan<WW, true>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, pv, view, g->off,    \
+      hipLaunchKernelGGL((k_bf_tc_slab<WW, true>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, P, view, g->off,     \
                          g->ustart, g->adj, partials);                                                                \
     else                                                                                                              \
-      hipLaunchKernelGGL((k_bf_tc_plan<WW, false>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, pv, view, g->off,   \
+      hipLaunchKernelGGL((k_bf_tc_slab<WW, false>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, P, view, g->off,    \
                          g->ustart, g->adj, partials);                                                                \
   } while (0)
       switch (sk->W) {

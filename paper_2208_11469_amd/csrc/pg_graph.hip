@@ -109,14 +109,30 @@ __global__ void k_degree_bin_keys(const int32_t* __restrict__ deg, int32_t n, ui
   if (v < n) key[v] = (uint8_t)degree_bin(deg[v]);
 }
 
-// Plan tier of a vertex by the arcs it owns: 0 dropped (no upper arcs),
-// 1 light, 2 medium, 3 heavy.
-__global__ void k_plan_keys(const int32_t* __restrict__ off, const int32_t* __restrict__ ustart, int32_t n,
-                            uint8_t* __restrict__ key) {
+// Plan tier of a count of arcs: 1 light, 2 medium, 3 heavy.
+__device__ __forceinline__ uint8_t plan_tier(int64_t d) { return d <= kLightMax ? 1 : (d <= kMediumMax ? 2 : 3); }
+
+__global__ void k_plan_keys(const int32_t* __restrict__ off, int32_t n, uint8_t* __restrict__ key) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int32_t d = off[v + 1] - (ustart ? ustart[v] : off[v]);
-  key[v] = (ustart && d == 0) ? 0 : (d <= kLightMax ? 1 : (d <= kMediumMax ? 2 : 3));
+  if (v < n) key[v] = plan_tier(off[v + 1] - off[v]);
+}
+
+// Slab-plan keys. Items (x, v), x < kSlabs, at key[x*n + v]: the tier of v's
+// upper neighbours in slab x, 0 when there are none or v is not sliced. Whole
+// vertices at key[kSlabs*n + v]: 1 for a whole vertex, else 0.
+__global__ void k_slab_keys(const int32_t* __restrict__ off, const int32_t* __restrict__ ustart,
+                            const int32_t* __restrict__ split, int32_t n, uint8_t* __restrict__ key) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)(kSlabs + 1) * n) return;
+  const int x = (int)(i / n);
+  const int32_t v = (int32_t)(i % n);
+  const int32_t dup = off[v + 1] - ustart[v];
+  if (x == kSlabs) {
+    key[i] = (dup >= 1 && dup <= kSliceMin) ? 1 : 0;
+    return;
+  }
+  const int64_t d = slab_end(off, split, (size_t)n, x, v) - slab_begin(ustart, split, (size_t)n, x, v);
+  key[i] = (dup <= kSliceMin || d == 0) ? 0 : plan_tier(d);
 }
 
 // Stable partition of the vertices by a small key (< kNumBins): per-block
@@ -160,13 +176,15 @@ __global__ void k_part_scatter(const uint8_t* __restrict__ keys, int32_t n, cons
   }
 }
 
+// Arc ranges of listed vertices: over N_v (x < 0) or of item (x, v).
 __global__ void k_heavy_ranges(const int32_t* __restrict__ verts, int64_t count, const int32_t* __restrict__ off,
-                               const int32_t* __restrict__ ustart, int64_t* __restrict__ out) {
+                               const int32_t* __restrict__ ustart, const int32_t* __restrict__ split, int32_t n, int x,
+                               int64_t* __restrict__ out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= count) return;
   const int32_t v = verts[i];
-  out[2 * i] = ustart ? ustart[v] : off[v];
-  out[2 * i + 1] = off[v + 1];
+  out[2 * i] = x < 0 ? off[v] : slab_begin(ustart, split, (size_t)n, x, v);
+  out[2 * i + 1] = x < 0 ? off[v + 1] : slab_end(off, split, (size_t)n, x, v);
 }
 
 // ---- per-vertex group kernels: G lanes per vertex, G <= 256 divides 256 -----
@@ -325,6 +343,86 @@ __global__ void k_scan_add(int64_t* __restrict__ out, int64_t count, const int64
   }
 }
 
+// Incoming upper arcs of v from sliced vertices (neighbours u below v with
+// more than kSliceMin upper neighbours).
+__global__ void k_in_sliced(const int32_t* __restrict__ off, const int32_t* __restrict__ ustart,
+                            const int32_t* __restrict__ adj, int32_t n, int64_t* __restrict__ cnt) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    int64_t c = 0;
+    for (int64_t p = off[v]; p < ustart[v]; ++p) {
+      const int32_t u = adj[p];
+      c += (off[u + 1] - ustart[u]) > kSliceMin;
+    }
+    cnt[v] = c;
+  }
+}
+
+// Slab boundaries: lo[x] is the first vertex whose exclusive prefix of
+// incoming sliced arcs reaches x/kSlabs of the total (lo[0] = 0, lo[kSlabs] = n).
+__global__ void k_slab_bounds(const int64_t* __restrict__ pre, const int64_t* __restrict__ cnt, int32_t n,
+                              int32_t* __restrict__ lo) {
+  const int x = threadIdx.x;
+  if (x > kSlabs) return;
+  if (x == 0 || x == kSlabs) {
+    lo[x] = x == 0 ? 0 : n;
+    return;
+  }
+  const int64_t total = n > 0 ? pre[n - 1] + cnt[n - 1] : 0;
+  const int64_t target = total * x / kSlabs;
+  int64_t a = 0, b = n;  // first v in [0, n) with pre[v] >= target, n if none
+  while (a < b) {
+    const int64_t mid = (a + b) >> 1;
+    if (pre[mid] < target)
+      a = mid + 1;
+    else
+      b = mid;
+  }
+  lo[x] = (int32_t)a;
+}
+
+__global__ void k_slab_split(const int32_t* __restrict__ off, const int32_t* __restrict__ ustart,
+                             const int32_t* __restrict__ adj, int32_t n, const int32_t* __restrict__ lo,
+                             int32_t* __restrict__ split) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t beg = ustart[v], end = off[v + 1];
+    int64_t p = beg;
+    for (int x = 1; x < kSlabs; ++x) {
+      p = lower_bound_i32(adj, p, end, lo[x]);
+      split[(size_t)(x - 1) * n + v] = (int32_t)p;
+    }
+  }
+}
+
+// Arc count of listed items: of (x, v) for slab x >= 0, of v's upper
+// neighbours for x < 0 (whole vertices). Counts are at most kSliceMin.
+__global__ void k_item_keys(const int32_t* __restrict__ verts, int64_t count, int x, const int32_t* __restrict__ off,
+                            const int32_t* __restrict__ ustart, const int32_t* __restrict__ split, int32_t n,
+                            uint8_t* __restrict__ key) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int32_t v = verts[i];
+  const int64_t d = x < 0 ? off[v + 1] - ustart[v]
+                          : slab_end(off, split, (size_t)n, x, v) - slab_begin(ustart, split, (size_t)n, x, v);
+  key[i] = (uint8_t)d;
+}
+
+// Complemented 2-bit digit `pass` of a key: partitioning by it, least
+// significant digit first, sorts by descending key.
+__global__ void k_desc_digit(const uint8_t* __restrict__ key, int64_t count, int pass, uint8_t* __restrict__ digit) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) digit[i] = (uint8_t)(3 - ((key[i] >> (2 * pass)) & 3));
+}
+
+__global__ void k_permute(const int32_t* __restrict__ perm, const int32_t* __restrict__ vals,
+                          const uint8_t* __restrict__ key, int64_t count, int32_t* __restrict__ vals_out,
+                          uint8_t* __restrict__ key_out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int32_t j = perm[i];
+  vals_out[i] = vals[j];
+  key_out[i] = key[j];
+}
+
 __global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t value, int64_t count) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = value;
@@ -449,28 +547,15 @@ namespace {
 
 namespace {
 
-// Stable partition of all vertices into `out` by degree bin (plan_upper < 0)
-// or by plan tier over N_v (0) / over the upper neighbours (1). starts[j] is
-// the first position of key j, starts[kNumBins] = n.
-int partition(pg_graph* g, int plan_upper, int32_t* out, int64_t* starts, hipStream_t s) {
-  const int32_t n = g->n;
-  for (int j = 0; j <= kNumBins; ++j) starts[j] = n;
-  if (n <= 0) {
-    for (int j = 0; j <= kNumBins; ++j) starts[j] = 0;
-    return PG_OK;
-  }
+// Stable partition of the indices 0..n-1 into `out` by keys[i] < kNumBins.
+// starts[j] is the first position of key j, starts[kNumBins] = n.
+int partition_keys(const uint8_t* keys, int32_t n, int32_t* out, int64_t* starts, hipStream_t s) {
+  for (int j = 0; j <= kNumBins; ++j) starts[j] = n <= 0 ? 0 : n;
+  if (n <= 0) return PG_OK;
   const int64_t nblk = ((int64_t)n + kBlock - 1) / kBlock;
-  uint8_t* keys = nullptr;
   int64_t* counts = nullptr;
-  PG_TRY(dmalloc((void**)&keys, (size_t)n, s));
   PG_TRY(dmalloc((void**)&counts, sizeof(int64_t) * 2 * kNumBins * nblk, s));
   int64_t* base = counts + kNumBins * nblk;
-  if (plan_upper < 0)
-    hipLaunchKernelGGL(k_degree_bin_keys, dim3((unsigned)nblk), dim3(kBlock), 0, s, g->deg, n, keys);
-  else
-    hipLaunchKernelGGL(k_plan_keys, dim3((unsigned)nblk), dim3(kBlock), 0, s, g->off,
-                       plan_upper ? (const int32_t*)g->ustart : nullptr, n, keys);
-  PG_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_part_count, dim3((unsigned)nblk), dim3(kBlock), 0, s, keys, n, counts, nblk);
   PG_LAUNCH_CHECK();
   PG_TRY(exclusive_scan_i64(counts, base, kNumBins * nblk, s));
@@ -480,8 +565,106 @@ int partition(pg_graph* g, int plan_upper, int32_t* out, int64_t* starts, hipStr
     PG_HIP(hipMemcpyAsync(&starts[j], base + j * nblk, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   PG_HIP(hipStreamSynchronize(s));
   starts[kNumBins] = n;
-  PG_TRY(dfree(counts, s));
+  return dfree(counts, s);
+}
+
+// Stable partition of all vertices by degree bin (by_plan false) or by plan
+// tier over N_v (by_plan true).
+int partition(pg_graph* g, bool by_plan, int32_t* out, int64_t* starts, hipStream_t s) {
+  const int32_t n = g->n;
+  if (n <= 0) return partition_keys(nullptr, 0, out, starts, s);
+  const unsigned nblk = (unsigned)(((int64_t)n + kBlock - 1) / kBlock);
+  uint8_t* keys = nullptr;
+  PG_TRY(dmalloc((void**)&keys, (size_t)n, s));
+  if (by_plan)
+    hipLaunchKernelGGL(k_plan_keys, dim3(nblk), dim3(kBlock), 0, s, g->off, n, keys);
+  else
+    hipLaunchKernelGGL(k_degree_bin_keys, dim3(nblk), dim3(kBlock), 0, s, g->deg, n, keys);
+  PG_LAUNCH_CHECK();
+  PG_TRY(partition_keys(keys, n, out, starts, s));
   return dfree(keys, s);
+}
+
+// Stable sort of vals[0 .. count) by descending key[] (keys < 256): LSD radix
+// with the 4-way partition, 2 bits per pass. vals and key are sorted in place.
+int sort_desc_small(int32_t* vals, uint8_t* key, int64_t count, hipStream_t s) {
+  if (count <= 1) return PG_OK;
+  const unsigned grid = (unsigned)((count + kBlock - 1) / kBlock);
+  uint8_t* digit = nullptr;
+  int32_t* perm = nullptr;
+  int32_t* vals2 = nullptr;
+  uint8_t* key2 = nullptr;
+  PG_TRY(dmalloc((void**)&perm, sizeof(int32_t) * 2 * (size_t)count + 2 * (size_t)count, s));
+  vals2 = perm + count;
+  digit = (uint8_t*)(vals2 + count);
+  key2 = digit + count;
+  int32_t* a = vals;
+  uint8_t* ka = key;
+  int32_t* b = vals2;
+  uint8_t* kb = key2;
+  for (int pass = 0; pass < 4; ++pass) {  // 4 passes: the result ends in the input buffers
+    hipLaunchKernelGGL(k_desc_digit, dim3(grid), dim3(kBlock), 0, s, (const uint8_t*)ka, count, pass, digit);
+    PG_LAUNCH_CHECK();
+    int64_t starts[kNumBins + 1];
+    PG_TRY(partition_keys(digit, (int32_t)count, perm, starts, s));
+    hipLaunchKernelGGL(k_permute, dim3(grid), dim3(kBlock), 0, s, (const int32_t*)perm, (const int32_t*)a,
+                       (const uint8_t*)ka, count, b, kb);
+    PG_LAUNCH_CHECK();
+    std::swap(a, b);
+    std::swap(ka, kb);
+  }
+  return dfree(perm, s);
+}
+
+// Sorts a light list (slab x, or whole vertices for x < 0) by descending arc
+// count, so the lanes of a wave walk about equally many arcs.
+int sort_light_list(int32_t* verts, int64_t count, int x, pg_graph* g, const int32_t* split, hipStream_t s) {
+  if (count <= 1) return PG_OK;
+  uint8_t* key = nullptr;
+  PG_TRY(dmalloc((void**)&key, (size_t)count, s));
+  hipLaunchKernelGGL(k_item_keys, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     (const int32_t*)verts, count, x, g->off, g->ustart, split, g->n, key);
+  PG_LAUNCH_CHECK();
+  PG_TRY(sort_desc_small(verts, key, count, s));
+  return dfree(key, s);
+}
+
+// Heavy-tier chunks: the arc ranges of `nh` listed vertices (read back from
+// the device) cut into pieces of at most kHeavyChunk arcs, appended to the
+// host vectors. `slot` numbers the vertices from slot0.
+int heavy_chunks(const int32_t* d_verts, int64_t nh, pg_graph* g, const int32_t* split, int x, int32_t slot0,
+                 std::vector<int32_t>& cv,
+                 std::vector<int64_t>& cb, std::vector<int64_t>& ce, std::vector<int32_t>& cslot,
+                 std::vector<int32_t>& first, hipStream_t s) {
+  if (nh <= 0) return PG_OK;
+  std::vector<int64_t> ranges(2 * (size_t)nh);
+  std::vector<int32_t> hv((size_t)nh);
+  int64_t* d_ranges = nullptr;
+  PG_TRY(dmalloc((void**)&d_ranges, sizeof(int64_t) * 2 * nh, s));
+  hipLaunchKernelGGL(k_heavy_ranges, dim3((unsigned)((nh + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d_verts, nh,
+                     g->off, g->ustart, split, g->n, x, d_ranges);
+  PG_LAUNCH_CHECK();
+  PG_HIP(hipMemcpyAsync(ranges.data(), d_ranges, sizeof(int64_t) * 2 * nh, hipMemcpyDeviceToHost, s));
+  PG_HIP(hipMemcpyAsync(hv.data(), d_verts, sizeof(int32_t) * nh, hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  PG_TRY(dfree(d_ranges, s));
+  for (int64_t h = 0; h < nh; ++h) {
+    first.push_back((int32_t)cv.size());
+    for (int64_t b = ranges[2 * h]; b < ranges[2 * h + 1]; b += kHeavyChunk) {
+      cv.push_back(hv[h]);
+      cb.push_back(b);
+      ce.push_back(std::min<int64_t>(b + kHeavyChunk, ranges[2 * h + 1]));
+      cslot.push_back(slot0 + (int32_t)h);
+    }
+  }
+  return PG_OK;
+}
+
+template <typename T>
+int upload(T** dst, const std::vector<T>& src, hipStream_t s) {
+  PG_TRY(palloc((void**)dst, sizeof(T) * std::max<size_t>(src.size(), 1)));
+  if (!src.empty()) PG_HIP(hipMemcpyAsync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s));
+  return PG_OK;
 }
 
 }  // namespace
@@ -496,62 +679,29 @@ void free_plan(VertexPlan* p) {
   *p = VertexPlan();
 }
 
-int build_plan(pg_graph* g, VertexPlan* P, bool upper, hipStream_t s) {
+int build_plan(pg_graph* g, VertexPlan* P, hipStream_t s) {
   free_plan(P);
-  P->upper = upper;
   const int32_t n = g->n;
   PG_TRY(palloc((void**)&P->sorted, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
   int64_t starts[kNumBins + 1];
-  PG_TRY(partition(g, upper ? 1 : 0, P->sorted, starts, s));
-  if (upper) {
-    P->light = P->sorted + starts[1];
-    P->n_light = starts[2] - starts[1];
-  } else {  // nearly every vertex is light over N_v: natural order saves the list lookup
-    P->light = nullptr;
-    P->n_light = n;
-  }
+  PG_TRY(partition(g, true, P->sorted, starts, s));
+  // nearly every vertex is light over N_v: natural order saves the list lookup
+  P->light = nullptr;
+  P->n_light = n;
   P->medium = P->sorted + starts[2];
   P->n_medium = starts[3] - starts[2];
   P->n_heavy = starts[4] - starts[3];
-  const int64_t nh = P->n_heavy;
-  std::vector<int64_t> ranges(2 * (size_t)nh);
-  if (nh > 0) {
-    int64_t* d_ranges = nullptr;
-    PG_TRY(dmalloc((void**)&d_ranges, sizeof(int64_t) * 2 * nh, s));
-    hipLaunchKernelGGL(k_heavy_ranges, dim3((unsigned)((nh + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       P->sorted + starts[3], nh, g->off, upper ? (const int32_t*)g->ustart : nullptr, d_ranges);
-    PG_LAUNCH_CHECK();
-    PG_HIP(hipMemcpyAsync(ranges.data(), d_ranges, sizeof(int64_t) * 2 * nh, hipMemcpyDeviceToHost, s));
-    std::vector<int32_t> hv((size_t)nh);
-    PG_HIP(hipMemcpyAsync(hv.data(), P->sorted + starts[3], sizeof(int32_t) * nh, hipMemcpyDeviceToHost, s));
-    PG_HIP(hipStreamSynchronize(s));
-    PG_TRY(dfree(d_ranges, s));
-    std::vector<int32_t> cv, cslot, first((size_t)nh + 1, 0);
-    std::vector<int64_t> cb, ce;
-    for (int64_t h = 0; h < nh; ++h) {
-      first[h] = (int32_t)cv.size();
-      for (int64_t b = ranges[2 * h]; b < ranges[2 * h + 1]; b += kHeavyChunk) {
-        cv.push_back(hv[h]);
-        cb.push_back(b);
-        ce.push_back(std::min<int64_t>(b + kHeavyChunk, ranges[2 * h + 1]));
-        cslot.push_back((int32_t)h);
-      }
-    }
-    first[nh] = (int32_t)cv.size();
-    P->n_chunks = (int64_t)cv.size();
-    const size_t nc = cv.size();
-    PG_TRY(palloc((void**)&P->chunk_vertex, sizeof(int32_t) * nc));
-    PG_TRY(palloc((void**)&P->chunk_begin, sizeof(int64_t) * nc));
-    PG_TRY(palloc((void**)&P->chunk_end, sizeof(int64_t) * nc));
-    PG_TRY(palloc((void**)&P->chunk_slot, sizeof(int32_t) * nc));
-    PG_TRY(palloc((void**)&P->heavy_first, sizeof(int32_t) * (nh + 1)));
-    PG_HIP(hipMemcpyAsync(P->chunk_vertex, cv.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
-    PG_HIP(hipMemcpyAsync(P->chunk_begin, cb.data(), sizeof(int64_t) * nc, hipMemcpyHostToDevice, s));
-    PG_HIP(hipMemcpyAsync(P->chunk_end, ce.data(), sizeof(int64_t) * nc, hipMemcpyHostToDevice, s));
-    PG_HIP(hipMemcpyAsync(P->chunk_slot, cslot.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
-    PG_HIP(hipMemcpyAsync(P->heavy_first, first.data(), sizeof(int32_t) * (nh + 1), hipMemcpyHostToDevice, s));
-    PG_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
-  }
+  std::vector<int32_t> cv, cslot, first;
+  std::vector<int64_t> cb, ce;
+  PG_TRY(heavy_chunks(P->sorted + starts[3], P->n_heavy, g, nullptr, -1, 0, cv, cb, ce, cslot, first, s));
+  first.push_back((int32_t)cv.size());
+  P->n_chunks = (int64_t)cv.size();
+  PG_TRY(upload(&P->chunk_vertex, cv, s));
+  PG_TRY(upload(&P->chunk_begin, cb, s));
+  PG_TRY(upload(&P->chunk_end, ce, s));
+  PG_TRY(upload(&P->chunk_slot, cslot, s));
+  PG_TRY(upload(&P->heavy_first, first, s));
+  PG_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
   return PG_OK;
 }
 
@@ -614,7 +764,7 @@ int graph_prepare(pg_graph* g, bool validate, hipStream_t s) {
   // 3. degree bins (stable)
   PG_TRY(palloc((void**)&g->bin_verts, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
   int64_t hbase[kNumBins + 1] = {};
-  PG_TRY(partition(g, /*plan_upper=*/-1, g->bin_verts, hbase, s));
+  PG_TRY(partition(g, false, g->bin_verts, hbase, s));
   int h_max = 0;
   unsigned long long h_wedges = 0;
   PG_HIP(hipMemcpyAsync(&h_max, d_maxdeg, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -643,8 +793,7 @@ int graph_prepare(pg_graph* g, bool validate, hipStream_t s) {
   PG_TRY(dfree(d_flags, s));
 
   // 5. work plans over N_v and over the upper neighbours
-  PG_TRY(build_plan(g, &g->plan_all, false, s));
-  PG_TRY(build_plan(g, &g->plan_up, true, s));
+  PG_TRY(build_plan(g, &g->plan_all, s));
   return PG_OK;
 }
 
@@ -689,6 +838,102 @@ int graph_orient(pg_graph* g, hipStream_t s) {
                      (int64_t)n + 1);
   PG_LAUNCH_CHECK();
   return dfree(cnt, s);
+}
+
+void free_slabs(SlabPlan* p) {
+  pfree(p->split);
+  pfree(p->verts);
+  pfree(p->chunk_vertex);
+  pfree(p->chunk_begin);
+  pfree(p->chunk_end);
+  *p = SlabPlan();
+}
+
+int graph_slabs(pg_graph* g, hipStream_t s) {
+  SlabPlan& P = g->slabs;
+  if (P.split || g->n == 0) return PG_OK;
+  ProfScope ps(s, "slabs");
+  const int32_t n = g->n;
+  SlabPlan Q;  // filled here, moved into the graph once complete
+  int rc = [&]() -> int {
+    // 1. boundaries by incoming sliced arcs, 2. per-vertex split positions
+    int64_t* cnt = nullptr;
+    PG_TRY(dmalloc((void**)&cnt, sizeof(int64_t) * 2 * (size_t)n + 16 * sizeof(int32_t), s));
+    int64_t* pre = cnt + n;
+    int32_t* lo = (int32_t*)(pre + n);
+    hipLaunchKernelGGL(k_in_sliced, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, g->off, g->ustart, g->adj, n,
+                       cnt);
+    PG_LAUNCH_CHECK();
+    PG_TRY(exclusive_scan_i64(cnt, pre, n, s));
+    hipLaunchKernelGGL(k_slab_bounds, dim3(1), dim3(64), 0, s, (const int64_t*)pre, (const int64_t*)cnt, n, lo);
+    PG_LAUNCH_CHECK();
+    PG_TRY(palloc((void**)&Q.split, sizeof(int32_t) * (size_t)(kSlabs - 1) * (size_t)n));
+    hipLaunchKernelGGL(k_slab_split, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, g->off, g->ustart, g->adj,
+                       n, (const int32_t*)lo, Q.split);
+    PG_LAUNCH_CHECK();
+    PG_TRY(dfree(cnt, s));
+    // 3. item tiers slab by slab, then the whole vertices
+    const int64_t nk = (int64_t)(kSlabs + 1) * n;
+    uint8_t* keys = nullptr;
+    int32_t* sorted = nullptr;
+    PG_TRY(dmalloc((void**)&keys, (size_t)nk, s));
+    PG_TRY(dmalloc((void**)&sorted, sizeof(int32_t) * (size_t)nk, s));
+    hipLaunchKernelGGL(k_slab_keys, dim3((unsigned)((nk + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g->off,
+                       g->ustart, (const int32_t*)Q.split, n, keys);
+    PG_LAUNCH_CHECK();
+    int64_t st[kSlabs + 1][kNumBins + 1];
+    int64_t lists = 0;
+    for (int x = 0; x <= kSlabs; ++x) {
+      PG_TRY(partition_keys(keys + (size_t)x * n, n, sorted + (size_t)x * n, st[x], s));
+      lists += st[x][3] - st[x][1];
+    }
+    // 4. light and medium lists of every slab, then the whole vertices
+    PG_TRY(palloc((void**)&Q.verts, sizeof(int32_t) * (size_t)std::max<int64_t>(lists, 1)));
+    int64_t at = 0;
+    for (int x = 0; x <= kSlabs; ++x) {
+      const int64_t cnt_x = st[x][3] - st[x][1];
+      if (x < kSlabs) {
+        Q.light_at[x] = at;
+        Q.n_light[x] = st[x][2] - st[x][1];
+        Q.medium_at[x] = at + Q.n_light[x];
+        Q.n_medium[x] = st[x][3] - st[x][2];
+      } else {
+        Q.whole_at = at;
+        Q.n_whole = cnt_x;
+      }
+      if (cnt_x > 0)
+        PG_HIP(hipMemcpyAsync(Q.verts + at, sorted + (size_t)x * n + st[x][1], sizeof(int32_t) * cnt_x,
+                              hipMemcpyDeviceToDevice, s));
+      at += cnt_x;
+    }
+    for (int x = 0; x < kSlabs; ++x)
+      PG_TRY(sort_light_list(Q.verts + Q.light_at[x], Q.n_light[x], x, g, Q.split, s));
+    PG_TRY(sort_light_list(Q.verts + Q.whole_at, Q.n_whole, -1, g, Q.split, s));
+    // 5. heavy items in chunks
+    std::vector<int32_t> cv, cslot, first;
+    std::vector<int64_t> cb, ce;
+    for (int x = 0; x < kSlabs; ++x) {
+      Q.chunk_at[x] = (int64_t)cv.size();
+      PG_TRY(heavy_chunks(sorted + (size_t)x * n + st[x][3], st[x][4] - st[x][3], g, Q.split, x, 0, cv, cb, ce, cslot,
+                          first, s));
+      Q.n_chunks[x] = (int64_t)cv.size() - Q.chunk_at[x];
+    }
+    int64_t busiest = 0;
+    for (int x = 0; x < kSlabs; ++x) busiest = std::max(busiest, slab_blocks(Q, x));
+    Q.slab_grid = busiest * kSlabs;
+    PG_TRY(upload(&Q.chunk_vertex, cv, s));
+    PG_TRY(upload(&Q.chunk_begin, cb, s));
+    PG_TRY(upload(&Q.chunk_end, ce, s));
+    PG_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+    PG_TRY(dfree(sorted, s));
+    return dfree(keys, s);
+  }();
+  if (rc != PG_OK) {
+    free_slabs(&Q);
+    return rc;
+  }
+  P = Q;
+  return PG_OK;
 }
 
 }  // namespace pg

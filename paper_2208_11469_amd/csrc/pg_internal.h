@@ -58,21 +58,19 @@ constexpr int32_t kBinMaxDeg[kNumBins - 1] = {16, 256, 4096};  // bin 3: d > 409
 constexpr int kBinGroup[kNumBins] = {4, 16, 64, 256};
 
 // ---- vertex work plans -----------------------------------------------------
-// A plan splits per-vertex work (over N_v, or over the upper part of N_v) into
-// three tiers launched together, heaviest first:
-//   heavy  (key >  kMediumMax): chunks of kHeavyChunk arcs, one block each
-//   medium (kLightMax < key <= kMediumMax): one wave per vertex
-//   light  (key <= kLightMax): kLightGroup lanes per vertex
-// where key is the number of arcs the vertex owns in the plan. Vertices with
-// no arcs are dropped from the upper plan; the full plan keeps them in the
-// light tier (their sketch rows still have to be written).
+// A plan splits per-vertex work over N_v into three tiers launched together,
+// heaviest first:
+//   heavy  (d_v >  kMediumMax): chunks of kHeavyChunk arcs, one block each
+//   medium (kLightMax < d_v <= kMediumMax): one wave per vertex
+//   light  (d_v <= kLightMax): kLightGroup lanes per vertex
+// Isolated vertices stay in the light tier (their sketch rows still have to
+// be written).
 constexpr int32_t kLightMax = 64;
 constexpr int32_t kMediumMax = 2048;
 constexpr int64_t kHeavyChunk = 2048;
 constexpr int kLightGroup = 8;
 
 struct VertexPlan {
-  bool upper = false;             // arcs of v: [ustart[v], off[v+1]) if upper, else [off[v], off[v+1])
   int64_t n_light = 0;
   int32_t* light = nullptr;       // [n_light] light vertices, ascending; nullptr: every vertex in natural
                                   // order, the kernel skipping those above kLightMax (n_light = n)
@@ -124,6 +122,62 @@ inline int64_t plan_blocks(const VertexPlan& p) {
   return p.n_chunks + (p.n_medium + 3) / 4 + (p.n_light * kLightGroup + 255) / 256;
 }
 
+// ---- XCD slabs of the triangle count ----------------------------------------
+// gfx950 has 8 accelerator dies (XCDs), each with its own 4 MB L2, and hands
+// workgroup i of a launch to XCD i mod 8. The vertex IDs are cut into kSlabs
+// ranges; block i of the slab part of the triangle-count launch only gathers
+// Bloom-filter rows of slab i mod kSlabs, so each L2 caches an eighth of the
+// rows instead of all of them.
+//
+// Only vertices with more than kSliceMin upper neighbours are sliced: item
+// (x, v) is v's upper neighbours inside slab x, tiered by their number like a
+// VertexPlan (light items get kSlabLightGroup lanes, medium ones a wave, heavy
+// ones chunks of kHeavyChunk arcs). The slabs hold about equal numbers of
+// these arcs. The remaining vertices ("whole" vertices, 1..kSliceMin upper
+// neighbours) are not worth a slab each: their blocks follow the slab blocks,
+// kWholeGroup lanes per vertex over all upper neighbours. Light lists are
+// sorted by descending arc count, so the groups of a wave walk about equally
+// many arcs and few load instructions run with idle lanes.
+constexpr int kSlabs = 8;
+constexpr int32_t kSliceMin = 64;
+constexpr int kSlabLightGroup = 8;
+constexpr int kWholeGroup = 8;
+
+struct SlabPlan {
+  int32_t* split = nullptr;  // [(kSlabs-1) * n]: split[(x-1)*n + v] = first arc of v into slab x >= 1
+  int64_t n_light[kSlabs] = {};
+  int64_t n_medium[kSlabs] = {};
+  int64_t n_chunks[kSlabs] = {};
+  int64_t light_at[kSlabs] = {};   // slab x's light items: verts[light_at[x] ..], by descending arc count
+  int64_t medium_at[kSlabs] = {};  // slab x's medium items: verts[medium_at[x] ..]
+  int64_t chunk_at[kSlabs] = {};   // slab x's chunks: chunk_*[chunk_at[x] ..]
+  int64_t slab_grid = 0;           // blocks of the slab part: kSlabs * (blocks of the busiest slab)
+  int64_t n_whole = 0;             // whole vertices: verts[whole_at ..], by descending arc count
+  int64_t whole_at = 0;
+  int32_t* verts = nullptr;
+  int32_t* chunk_vertex = nullptr;
+  int64_t* chunk_begin = nullptr;
+  int64_t* chunk_end = nullptr;
+};
+
+// Blocks of slab x (block i of the slab part serves slab i mod kSlabs).
+__host__ __device__ inline int64_t slab_blocks(const SlabPlan& p, int x) {
+  return p.n_chunks[x] + (p.n_medium[x] + 3) / 4 + (p.n_light[x] * kSlabLightGroup + 255) / 256;
+}
+// Blocks of the whole launch.
+inline int64_t slab_plan_blocks(const SlabPlan& p) {
+  return p.slab_grid + (p.n_whole * kWholeGroup + 255) / 256;
+}
+
+__device__ __forceinline__ int64_t slab_begin(const int32_t* __restrict__ ustart, const int32_t* __restrict__ split,
+                                              size_t n, int x, int32_t v) {
+  return x == 0 ? ustart[v] : split[(size_t)(x - 1) * n + v];
+}
+__device__ __forceinline__ int64_t slab_end(const int32_t* __restrict__ off, const int32_t* __restrict__ split,
+                                            size_t n, int x, int32_t v) {
+  return x == kSlabs - 1 ? off[v + 1] : split[(size_t)x * n + v];
+}
+
 }  // namespace pg
 
 struct pg_ctx {
@@ -146,7 +200,7 @@ struct pg_graph {
   int32_t* ustart = nullptr;   // [n] position in adj of the first neighbour above v
   int64_t* upoff = nullptr;    // [n+1] first upper-edge index of v (edges in CSR order)
   pg::VertexPlan plan_all;     // work over N_v (sketch builds, clustering coefficient)
-  pg::VertexPlan plan_up;      // work over the neighbours above v (triangle count)
+  pg::SlabPlan slabs;          // triangle-count plan over XCD slabs (built on first use)
   int32_t* eu = nullptr;       // [m] smaller endpoint of each undirected edge
   int32_t* ev = nullptr;       // [m] larger endpoint
   int32_t* arc_src = nullptr;  // [nnz] source vertex of each arc
@@ -182,8 +236,10 @@ namespace pg {
 int graph_prepare(pg_graph* g, bool validate, hipStream_t s);
 int graph_arc_sources(pg_graph* g, hipStream_t s);
 int graph_orient(pg_graph* g, hipStream_t s);
-int build_plan(pg_graph* g, pg::VertexPlan* plan, bool upper, hipStream_t s);
+int graph_slabs(pg_graph* g, hipStream_t s);
+int build_plan(pg_graph* g, pg::VertexPlan* plan, hipStream_t s);
 void free_plan(pg::VertexPlan* plan);
+void free_slabs(pg::SlabPlan* plan);
 int exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t count, hipStream_t s);
 int fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s);
 int sum_chunks(const double* chunks, int64_t nchunks, double divisor, double* out, hipStream_t s);
