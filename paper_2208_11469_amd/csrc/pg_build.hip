@@ -5,12 +5,12 @@
 // smallest key_i. 1-hash: the min(k, d_v) elements of N_v with the smallest
 // key, in ascending key order.
 //
-// Vertices are processed in degree bins (a group of G lanes per vertex, G
-// growing with the degree). Inside a group every lane builds a private
-// partial sketch over a strided slice of N_v in registers; the partials are
-// combined by a fixed butterfly (OR for filters, lexicographic (key, ID)
-// minimum for k-hash). No global or LDS atomics are involved, so the result
-// is independent of scheduling.
+// Vertices are processed by groups of G lanes, G growing with the degree.
+// Filters: the lanes of a group set bits in one shared LDS bitmap with atomic
+// OR. k-hash: every lane keeps private minima over a strided slice of N_v in
+// registers, combined by a fixed butterfly (lexicographic (key, ID) minimum).
+// Both combinations are order-independent, so the result does not depend on
+// scheduling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,18 +31,21 @@ constexpr int kBlock = 256;
 // chunks of kHeavyChunk arcs, one block each; medium vertices get a wave;
 // light vertices (at most kLightMax neighbours) get kLightGroup lanes.
 //
-// Bit scatter: every lane owns a private W-word bitmap in LDS and sets the bit
-// of each hashed neighbour with a plain read-OR-write (no atomics, no lane
-// ever touches another lane's words). The lanes serving one vertex are then
-// combined by OR-ing their bitmaps word by word. Each lane issues U neighbour
-// loads before hashing any of them.
+// Bit scatter: the lanes serving one vertex share one W-word bitmap in LDS and
+// set the bit of each hashed neighbour with an LDS atomic OR (one LDS
+// instruction per hash, no read-modify-write round trip). OR is commutative
+// and idempotent, so the bitmap does not depend on the order in which lanes
+// land. Each lane issues U neighbour loads before hashing any of them. The
+// group then writes its bitmap out as the row, W lanes one word each. Waves
+// and blocks (medium and heavy tiers) keep kBfCopies bitmaps, lane l using
+// copy l mod kBfCopies, so that fewer lanes of one instruction collide on the
+// same word; the copies are OR-ed when the row is written.
+constexpr int kBfCopies = 8;
 
-constexpr int kLdsStride = kBlock + 1;  // words of one bitmap slot across the block; odd stride spreads banks
-
-template <int W, int U, int G>
+template <int U, int G>
 __device__ __forceinline__ void bf_scatter(const int32_t* __restrict__ adj, int64_t beg, int64_t end, int lane,
                                            uint32_t B, uint32_t b, const uint64_t* __restrict__ ha,
-                                           const uint64_t* __restrict__ hc, uint64_t* __restrict__ mine) {
+                                           const uint64_t* __restrict__ hc, uint64_t* __restrict__ bits) {
   for (int64_t p0 = beg + lane; p0 < end; p0 += (int64_t)G * U) {
     uint32_t x[U];
 #pragma unroll
@@ -55,21 +58,18 @@ __device__ __forceinline__ void bf_scatter(const int32_t* __restrict__ adj, int6
       if (p0 + (int64_t)j * G < end) {
         for (uint32_t i = 0; i < b; ++i) {
           const uint32_t idx = bf_index(ha[i], hc[i], x[j], B);
-          mine[(idx >> 6) * kLdsStride] |= 1ull << (idx & 63u);
+          atomicOr((unsigned long long*)&bits[idx >> 6], 1ull << (idx & 63u));
         }
       }
     }
   }
 }
 
-// OR of the G lane bitmaps starting at thread `first`, for word k.
-template <int G>
-__device__ __forceinline__ uint64_t bf_gather_word(const uint64_t* __restrict__ lds, int first, int k) {
-  uint64_t acc = 0;
-  const uint64_t* p = lds + k * kLdsStride + first;
-#pragma unroll 8
-  for (int i = 0; i < G; ++i) acc |= p[i];
-  return acc;
+// LDS visibility among the lanes of one wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int W>
@@ -78,50 +78,54 @@ __global__ __launch_bounds__(kBlock) void k_bf_build_plan(PlanView P, const int3
                                                           const uint64_t* __restrict__ ha,
                                                           const uint64_t* __restrict__ hc, uint64_t* __restrict__ words,
                                                           uint32_t* __restrict__ pc, uint64_t* __restrict__ part) {
-  __shared__ uint64_t lds[W * kLdsStride];
-  __shared__ uint32_t ones_lds[kBlock / kWave][W];
+  constexpr int kLightWords = (kBlock / kLightGroup) * W;       // one bitmap per light group
+  constexpr int kWaveWords = (kBlock / kWave) * kBfCopies * W;  // kBfCopies bitmaps per wave
+  __shared__ uint64_t lds[kLightWords > kWaveWords ? kLightWords : kWaveWords];
   const int64_t blk = blockIdx.x;
   const int tid = threadIdx.x;
-  uint64_t* mine = lds + tid;
-#pragma unroll
-  for (int k = 0; k < W; ++k) mine[k * kLdsStride] = 0;
 
   if (blk < P.n_chunks) {  // ---- heavy chunk: the whole block; partial row to `part`
-    bf_scatter<W, 8, kBlock>(adj, P.chunk_begin[blk], P.chunk_end[blk], tid, B, b, ha, hc, mine);
+    for (int i = tid; i < kBfCopies * W; i += kBlock) lds[i] = 0;
     __syncthreads();
-    if (tid < W) part[blk * W + tid] = bf_gather_word<kBlock>(lds, 0, tid);
+    bf_scatter<8, kBlock>(adj, P.chunk_begin[blk], P.chunk_end[blk], tid, B, b, ha, hc,
+                          lds + (tid % kBfCopies) * W);
+    __syncthreads();
+    if (tid < W) {
+      uint64_t w = 0;
+#pragma unroll
+      for (int c = 0; c < kBfCopies; ++c) w |= lds[c * W + tid];
+      part[blk * W + tid] = w;
+    }
     return;
   }
   const int64_t mb = blk - P.n_chunks;
   if (mb < P.n_medium_blocks) {  // ---- medium: one wave per vertex
     const int wv = tid / kWave;
+    const int lane = lane_id();
+    uint64_t* bits = lds + wv * kBfCopies * W;
     const int64_t idx = mb * (kBlock / kWave) + wv;
     const bool active = idx < P.n_medium;
     const int32_t v = active ? P.medium[idx] : 0;
-    if (active) bf_scatter<W, 8, kWave>(adj, off[v], off[v + 1], lane_id(), B, b, ha, hc, mine);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int lane = lane_id();
+    for (int i = lane; i < kBfCopies * W; i += kWave) bits[i] = 0;
+    wave_sync();
+    if (active) bf_scatter<8, kWave>(adj, off[v], off[v + 1], lane, B, b, ha, hc, bits + (lane % kBfCopies) * W);
+    wave_sync();
+    uint32_t ones = 0;
     if (active && lane < W) {
-      const uint64_t w = bf_gather_word<kWave>(lds, wv * kWave, lane);
-      words[bf_row_offset(v, W) + lane] = w;
-      ones_lds[wv][lane] = (uint32_t)__popcll(w);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (active && lane == 0) {
-      uint32_t ones = 0;
+      uint64_t w = 0;
 #pragma unroll
-      for (int k = 0; k < W; ++k) ones += ones_lds[wv][k];
-      pc[v] = ones;
+      for (int c = 0; c < kBfCopies; ++c) w |= bits[c * W + lane];
+      words[bf_row_offset(v, W) + lane] = w;
+      ones = (uint32_t)__popcll(w);
     }
+    ones = group_sum_u32<kWave>(ones);
+    if (active && lane == 0) pc[v] = ones;
     return;
   }
   // ---- light: kLightGroup lanes per vertex of the light list
   const int64_t idx = ((mb - P.n_medium_blocks) * kBlock + tid) / kLightGroup;
   const int lane = tid % kLightGroup;
+  uint64_t* bits = lds + (tid / kLightGroup) * W;
   bool active = idx < P.n_light;
   const int32_t v = active ? (P.light ? P.light[idx] : (int32_t)idx) : 0;
   int64_t beg = 0, end = 0;
@@ -130,15 +134,15 @@ __global__ __launch_bounds__(kBlock) void k_bf_build_plan(PlanView P, const int3
     end = off[v + 1];
     active = P.light || end - beg <= kLightMax;
   }
-  if (active) bf_scatter<W, 4, kLightGroup>(adj, beg, end, lane, B, b, ha, hc, mine);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int k = lane; k < W; k += kLightGroup) bits[k] = 0;
+  wave_sync();
+  if (active) bf_scatter<4, kLightGroup>(adj, beg, end, lane, B, b, ha, hc, bits);
+  wave_sync();
   uint32_t ones = 0;
   if (active) {
     uint64_t* row = words + bf_row_offset(v, W);
     for (int k = lane; k < W; k += kLightGroup) {
-      const uint64_t w = bf_gather_word<kLightGroup>(lds, tid - lane, k);
+      const uint64_t w = bits[k];
       row[k] = w;
       ones += (uint32_t)__popcll(w);
     }

@@ -437,6 +437,34 @@ __global__ void k_sum_chunks(const double* __restrict__ chunks, int64_t nchunks,
   if (threadIdx.x == 0) out[0] = r / divisor;
 }
 
+// One block of kWideBlock threads over up to kWideMax partials: thread t sums
+// entries t, t + kWideBlock, ... into four accumulators in a fixed pattern,
+// then a fixed tree. One launch instead of two for the usual partial counts.
+constexpr int kWideBlock = 1024;
+constexpr int64_t kWideMax = 1 << 17;
+
+__global__ __launch_bounds__(kWideBlock) void k_sum_wide(const double* __restrict__ chunks, int64_t nchunks,
+                                                         double divisor, double* out) {
+  __shared__ double lds[kWideBlock / kWave];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t i = threadIdx.x;
+  for (; i + 3 * kWideBlock < nchunks; i += 4 * kWideBlock) {
+    a0 += chunks[i];
+    a1 += chunks[i + kWideBlock];
+    a2 += chunks[i + 2 * kWideBlock];
+    a3 += chunks[i + 3 * kWideBlock];
+  }
+  for (; i < nchunks; i += kWideBlock) a0 += chunks[i];
+  double acc = group_sum<kWave>((a0 + a1) + (a2 + a3));
+  if (lane_id() == 0) lds[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < kWideBlock / kWave; ++w) r += lds[w];
+    out[0] = r / divisor;
+  }
+}
+
 // Partials of a plain array over fixed chunks of 2048 entries.
 __global__ void k_array_chunks(const double* __restrict__ x, int64_t count, double* __restrict__ chunks) {
   __shared__ double lds[kBlock / kWave];
@@ -489,6 +517,11 @@ int fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s) {
 
 int sum_chunks(const double* chunks, int64_t nchunks, double divisor, double* out, hipStream_t s) {
   ProfScope ps(s, "sum_chunks");
+  if (nchunks > 4 * kScanTile && nchunks <= kWideMax) {
+    hipLaunchKernelGGL(k_sum_wide, dim3(1), dim3(kWideBlock), 0, s, chunks, nchunks, divisor, out);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+  }
   if (nchunks > 4 * kScanTile) {
     // two levels: fixed tiles of kScanTile partials, then the tile sums
     const int64_t nt = (nchunks + kScanTile - 1) / kScanTile;

@@ -68,7 +68,7 @@ constexpr int kBinGroup[kNumBins] = {4, 16, 64, 256};
 constexpr int32_t kLightMax = 64;
 constexpr int32_t kMediumMax = 2048;
 constexpr int64_t kHeavyChunk = 2048;
-constexpr int kLightGroup = 8;
+constexpr int kLightGroup = 4;
 
 struct VertexPlan {
   int64_t n_light = 0;
