@@ -1,0 +1,178 @@
+"""Full size R-MAT scale 24, edge factor 32 (about 1.02e9 arcs) on the GPU:
+1024-bit Bloom filters and 1-hash MinHash with k = 64, triangle count, local
+clustering coefficient and the exact merge baseline, in the launch
+configuration the library uses for every graph.
+
+At this size the oracle checks sampled outputs one by one: sketch rows of
+sampled vertices (bit-exact), integer counts and estimates of sampled edges,
+exact intersections of sampled edges, and the clustering coefficient of
+sampled vertices. Whole-graph results are checked through identities that hold
+at any size: the triangle-count estimate is one third of the sum of the
+per-edge estimates, and the exact triangle count is one third of the sum of
+the exact per-edge intersections."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import pggen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2208_11469_amd as pg  # noqa: E402
+
+RTOL = 1e-6
+SEED = 1
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def big():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("generating R-MAT scale 24, edge factor 32")
+    g = pggen.rmat(24, 32, seed=1)
+    say(f"n {g.n} nnz {g.nnz}")
+    ctx = pg.Context(0)
+    dg = pg.Graph(ctx, g.offsets, g.adj)
+    say(f"graph on device: m {dg.m}")
+    eu, ev = dg.upper_edges()
+    rng = np.random.default_rng(24)
+    # sampled upper edges: random ones plus the first edges in CSR order (those
+    # of vertex 0, the largest R-MAT hub)
+    hub = int(np.argmax(g.degrees()))
+    idx = np.unique(np.concatenate([rng.integers(0, dg.m, 3000), np.arange(200)]))
+    idx_t = torch.from_numpy(idx).to(eu.device)
+    su = eu[idx_t].cpu().numpy().astype(np.int64)
+    sv = ev[idx_t].cpu().numpy().astype(np.int64)
+    del eu, ev
+    verts = np.unique(np.concatenate([rng.integers(0, g.n, 2000), np.argsort(-g.degrees())[:20], [hub]]))
+    yield g, ctx, dg, idx, idx_t, su, sv, verts
+    dg.close()
+    ctx.close()
+
+
+def _pair_rows(g, su, sv, kind, size, b):
+    """Oracle rows of the endpoints of sampled pairs and the pairs re-indexed into them."""
+    ends = np.unique(np.concatenate([su, sv]))
+    ref = oracle.sketch_rows(g, ends, kind, size, b, SEED)
+    return ref, np.searchsorted(ends, su), np.searchsorted(ends, sv)
+
+
+def _cc_samples(g, rng, count=20, max_deg=500):
+    d = g.degrees()
+    cand = np.flatnonzero((d >= 2) & (d <= max_deg))
+    return np.sort(rng.choice(cand, size=min(count, cand.shape[0]), replace=False))
+
+
+def _oracle_cc(g, v, kind, size, b, est):
+    """Local clustering coefficient of v from oracle rows of v and N_v."""
+    nb = g.adj[g.offsets[v]:g.offsets[v + 1]].astype(np.int64)
+    ref = oracle.sketch_rows(g, np.concatenate([[v], nb]), kind, size, b, SEED)
+    d = nb.shape[0]
+    vals = ref.estimate(np.zeros(d, np.int64), np.arange(1, d + 1), est)
+    return float(np.sum(vals)) / (d * (d - 1))
+
+
+def _close(got, want, rtol):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    assert np.all(np.abs(got - want) <= rtol * np.abs(want) + 1e-30), (got, want)
+
+
+@pytest.mark.timeout(900)
+def test_scale24_bloom_1024(big):
+    g, ctx, dg, idx, idx_t, su, sv, verts = big
+    say("bf 1024 build")
+    sk = dg.build_sketches("bf", 1024, 1, seed=SEED)
+    rows, pc = sk.export()
+    vt = torch.from_numpy(verts).to(rows.device)
+    got_rows = rows[vt].cpu().numpy()
+    got_pc = pc[vt].cpu().numpy().astype(np.uint32)
+    del rows, pc
+    ref = oracle.sketch_rows(g, verts, oracle.KIND_BF, 1024, 1, SEED)
+    assert np.array_equal(got_rows, ref.words.view(np.uint8).reshape(len(verts), 128))
+    assert np.array_equal(got_pc, ref.pc)
+
+    say("bf 1024 all-edge estimates, sampled against the oracle")
+    est, raw = sk.intersect("and")
+    pref, iu, iv = _pair_rows(g, su, sv, oracle.KIND_BF, 1024, 1)
+    want_c = pref.counts(iu, iv)[0]
+    assert np.array_equal(raw[idx_t].cpu().numpy().astype(np.uint32), want_c)
+    _close(est[idx_t].cpu().numpy(), pref.estimate(iu, iv, "and"), RTOL)
+    total = float(est.sum().item())
+    del est, raw
+
+    say("bf 1024 triangle count: one third of the edge sum")
+    _close([sk.tc("and")], [total / 3.0], 1e-9)
+
+    say("bf 1024 clustering coefficient, sampled vertices")
+    cc = sk.cc("and")
+    rng = np.random.default_rng(240)
+    for v in _cc_samples(g, rng):
+        want = _oracle_cc(g, v, oracle.KIND_BF, 1024, 1, "and")
+        got = float(cc[int(v)].item())
+        assert abs(got - want) <= (RTOL + 2.0**-23) * abs(want) + 1e-30, (v, got, want)
+    sk.close()
+
+
+@pytest.mark.timeout(900)
+def test_scale24_onehash_64(big):
+    g, ctx, dg, idx, idx_t, su, sv, verts = big
+    say("1-hash k=64 build")
+    sk = dg.build_sketches("1h", 64, seed=SEED)
+    rows, _ = sk.export()
+    vt = torch.from_numpy(verts).to(rows.device)
+    got_rows = rows[vt].cpu().numpy()
+    del rows
+    ref = oracle.sketch_rows(g, verts, oracle.KIND_1H, 64, 1, SEED)
+    assert np.array_equal(got_rows, ref.sig.view(np.uint8).reshape(len(verts), 256))
+
+    say("1-hash all-edge estimates, sampled against the oracle")
+    est, raw = sk.intersect("1h")
+    pref, iu, iv = _pair_rows(g, su, sv, oracle.KIND_1H, 64, 1)
+    su_ref, _, _ = pref.counts(iu, iv)
+    assert np.array_equal(raw[idx_t].cpu().numpy().astype(np.uint32), su_ref)
+    _close(est[idx_t].cpu().numpy(), pref.estimate(iu, iv, "1h"), RTOL)
+    total = float(est.sum().item())
+    del est, raw
+
+    say("1-hash triangle count: one third of the edge sum")
+    _close([sk.tc("1h")], [total / 3.0], 1e-9)
+
+    say("1-hash clustering coefficient, sampled vertices")
+    cc = sk.cc("1h")
+    rng = np.random.default_rng(241)
+    for v in _cc_samples(g, rng):
+        want = _oracle_cc(g, v, oracle.KIND_1H, 64, 1, "1h")
+        got = float(cc[int(v)].item())
+        assert abs(got - want) <= (RTOL + 2.0**-23) * abs(want) + 1e-30, (v, got, want)
+    sk.close()
+
+
+@pytest.mark.timeout(900)
+def test_scale24_exact_baseline(big):
+    g, ctx, dg, idx, idx_t, su, sv, verts = big
+    say("exact per-edge intersections, sampled against the oracle")
+    ex = dg.exact_intersect()
+    assert np.array_equal(ex[idx_t].cpu().numpy().astype(np.uint32), oracle.exact_pairs(g, su, sv))
+    total = int(ex.to(torch.int64).sum().item())
+    del ex
+    say("exact triangle count: one third of the edge sum")
+    t = dg.exact_tc()
+    assert 3 * t == total
+    say("exact clustering coefficient, sampled vertices")
+    cc = dg.exact_cc()
+    rng = np.random.default_rng(242)
+    for v in _cc_samples(g, rng):
+        nb = g.adj[g.offsets[v]:g.offsets[v + 1]].astype(np.int64)
+        d = nb.shape[0]
+        want = float(np.sum(oracle.exact_pairs(g, np.full(d, v, np.int64), nb))) / (d * (d - 1))
+        got = float(cc[int(v)].item())
+        assert abs(got - want) <= (1e-12 + 2.0**-23) * abs(want) + 1e-30, (v, got, want)
