@@ -178,6 +178,38 @@ def measure_serving(args, pg, pggen, np, log):
             "requests": st["completed"]}
 
 
+def measure_scale24(args, pg, pggen, torch, ctx, sync, log):
+    """R-MAT scale 24, edge factor 32 (about 1e9 arcs): 1024-bit Bloom filters and
+    1-hash k = 64, triangle count and clustering coefficient, exact GPU baseline.
+    Opt-in (--scale24): generating the graph takes about a minute."""
+    t = time.perf_counter()
+    g = pggen.rmat(24, 32, seed=args.seed)
+    log(f"scale24: generated n={g.n} nnz={g.nnz} ({time.perf_counter() - t:.1f}s)")
+    dg = pg.Graph(ctx, g.offsets, g.adj)
+    m = dg.m
+    out = {"workload": f"R-MAT s24 ef32 (0.57,0.19,0.19,0.05) seed {args.seed}; n={g.n} m={m} nnz={g.nnz}"}
+    exact_tc = dg.exact_tc()  # builds the degree orientation once
+    exact_ms = timed(lambda: dg.exact_tc(), 3, sync)
+    out["exact"] = {"tc": exact_tc, "tc_ms": round(exact_ms, 3), "intersections_per_s": m / (exact_ms * 1e-3)}
+    ms = timed(lambda: dg.exact_cc(), 3, sync)
+    out["exact"]["cc_ms"] = round(ms, 3)
+    for name, kind, size, est in (("bf1024", "bf", 1024, "and"), ("onehash64", "1h", 64, "1h")):
+        sk = dg.build_sketches(kind, size, 1, seed=args.seed)
+        tc = sk.tc(est)  # first call builds the triangle-count plan
+        b_ms = timed(lambda: sk.rebuild(), 5, sync)
+        t_ms = timed(lambda: sk.tc(est), 5, sync)
+        c_ms = timed(lambda: sk.cc(est), 3, sync)
+        out[name] = {"build_ms": round(b_ms, 3), "tc_ms": round(t_ms, 3), "cc_ms": round(c_ms, 3),
+                     "step_intersections_per_s": m / ((b_ms + t_ms) * 1e-3),
+                     "estimate_intersections_per_s": m / (t_ms * 1e-3), "tc": tc,
+                     "rel_err": abs(tc - exact_tc) / exact_tc, "speedup_vs_exact": exact_ms / (b_ms + t_ms)}
+        log(f"scale24 {name}: build {b_ms:.2f} ms, TC {t_ms:.2f} ms, CC {c_ms:.2f} ms, "
+            f"rel err {abs(tc - exact_tc) / exact_tc:.3e}")
+        sk.close()
+    dg.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +227,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=10000)
     ap.add_argument("--skip-batch", action="store_true", help="leave out the batched-graphs measurement")
     ap.add_argument("--batch-graphs", type=int, default=512)
+    ap.add_argument("--scale24", action="store_true",
+                    help="also time the R-MAT s24 ef32 configuration (BF-1024, 1-hash-64, exact)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -353,6 +387,8 @@ def main():
     if not args.skip_serving:
         serving = measure_serving(args, pg, pggen, np, log)
 
+    scale24 = measure_scale24(args, pg, pggen, torch, ctx, sync, log) if args.scale24 else None
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -386,6 +422,7 @@ def main():
         "rows": rows,
         "serving": serving,
         "batch": batch,
+        "scale24": scale24,
     }
     print(json.dumps(out), flush=True)
     sk.close()

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "pg_device.h"
 #include "pg_internal.h"
@@ -259,6 +260,229 @@ __global__ __launch_bounds__(kBlock) void k_bf_tc_slab(SlabPlan P, SkView s, con
   if (tid == 0) partials[blockIdx.x] = r;
 }
 
+// ---- 1-hash MinHash: vertex-centric union counts (Section 4.4) ---------------
+//
+// The per-pair union walk costs one dependent load per step. Here a wave
+// serves one vertex v at a time: the keys of M_v (ascending: a 1-hash
+// signature lists its bottom-k IDs in key order) go to LDS once; for each
+// neighbour u the wave loads M_u, element e in lane e mod 64, computes each
+// element's key and finds by binary search over M_v's keys the number `lo` of
+// smaller keys and whether the key itself is there. In the union walk element
+// e of M_u comes after e elements of M_u and lo of M_v, of which the common
+// ones (counted by a ballot prefix) appear once: its position is e + lo minus
+// the common elements before it. The common elements, those among the first k
+// positions, and the union size follow from ballots. Distinct IDs have
+// distinct keys (odd multiplier, bijective mix), so equal keys are the same
+// element. The counts equal the per-pair walk's exactly.
+
+constexpr int kOhAhead = 4;  // neighbour rows in flight per wave
+
+template <int E>
+__device__ __forceinline__ void oh_keys_to_lds(const SkView& s, int32_t v, uint32_t nv, uint64_t* keys) {
+  const uint32_t* row = s.sig + (size_t)v * s.size;
+  const int l = lane_id();
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint32_t e = (uint32_t)(j * kWave + l);
+    if (e < nv) keys[e] = mh_key(s.a1, s.c1, row[e]);
+  }
+}
+
+// Estimate for the pair (v, u) given M_v's nv keys in LDS and this lane's
+// elements of M_u (x[j] = element j*64 + lane); the same in every lane.
+template <int E>
+__device__ __forceinline__ double oh_wave_estimate(const SkView& s, const uint64_t* keys_v, uint32_t nv, int32_t dv,
+                                                   int32_t du, const uint32_t (&x)[E]) {
+  const uint32_t nu = (uint32_t)du < s.size ? (uint32_t)du : s.size;
+  const int l = lane_id();
+  const uint64_t below = (1ull << l) - 1ull;  // lanes holding earlier elements of this batch
+  uint32_t com = 0, comk = 0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint32_t e = (uint32_t)(j * kWave + l);
+    bool found = false;
+    uint32_t lo = 0;
+    if (e < nu) {
+      const uint64_t key = mh_key(s.a1, s.c1, x[j]);
+      uint32_t hi = nv;  // lo: first position whose key is not below `key`
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (keys_v[mid] < key)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      found = lo < nv && keys_v[lo] == key;
+    }
+    const uint64_t fb = __ballot(found);
+    const uint32_t before = com + (uint32_t)__popcll(fb & below);  // common elements ahead of e
+    const bool first_k = found && e + lo - before < s.size;
+    com += (uint32_t)__popcll(fb);
+    comk += (uint32_t)__popcll(__ballot(first_k));
+  }
+  if (s.est == PG_EST_MH_1HASH_LITERAL) return minhash_estimate(com, s.size, du, dv);
+  const uint32_t uni = nu + nv - com;
+  const uint32_t kp = uni < s.size ? uni : s.size;
+  return minhash_estimate(uni >= s.size ? comk : com, kp, du, dv);
+}
+
+// Sum of the estimates of (v, adj[p]) over p in [beg, end), one wave.
+template <int E>
+__device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const int32_t* __restrict__ adj,
+                                               int64_t beg, int64_t end, uint64_t* keys) {
+  const int32_t dv = s.deg[v];
+  const uint32_t nv = (uint32_t)dv < s.size ? (uint32_t)dv : s.size;
+  oh_keys_to_lds<E>(s, v, nv, keys);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // kOhAhead neighbours at a time: their degrees and rows are loaded before
+  // any of them is evaluated
+  const int l = lane_id();
+  double acc = 0.0;
+  for (int64_t p0 = beg; p0 < end; p0 += kOhAhead) {
+    int32_t du[kOhAhead];
+    uint32_t x[kOhAhead][E];
+#pragma unroll
+    for (int t = 0; t < kOhAhead; ++t) {
+      const int32_t u = p0 + t < end ? adj[p0 + t] : -1;
+      du[t] = u >= 0 ? s.deg[u] : -1;
+      const uint32_t nu = u < 0 ? 0u : ((uint32_t)du[t] < s.size ? (uint32_t)du[t] : s.size);
+      const uint32_t* row = s.sig + (size_t)(u < 0 ? 0 : u) * s.size;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const uint32_t e = (uint32_t)(j * kWave + l);
+        x[t][j] = e < nu ? row[e] : 0u;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kOhAhead; ++t)
+      if (du[t] >= 0) acc += oh_wave_estimate<E>(s, keys, nv, dv, du[t], x[t]);
+  }
+  return acc;
+}
+
+// Blocks of slab x when every light or medium item gets one wave.
+__host__ __device__ inline int64_t oh_slab_blocks(const SlabPlan& p, int x) {
+  return p.n_chunks[x] + (p.n_medium[x] + 3) / 4 + (p.n_light[x] + 3) / 4;
+}
+
+// Triangle count over the slab plan: block i < grid_slabs serves slab i mod
+// kSlabs; a heavy chunk is split among the block's four waves in contiguous
+// quarters. Blocks from grid_slabs on take the whole vertices. One partial per wave.
+template <int E>
+__global__ __launch_bounds__(kBlock) void k_oh_tc_slab(SlabPlan P, SkView s, const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ ustart,
+                                                       const int32_t* __restrict__ adj, int64_t grid_slabs,
+                                                       double* __restrict__ partials) {
+  __shared__ uint64_t keys[kBlock / kWave][kWave * E];
+  const int w = threadIdx.x / kWave;
+  const size_t n = (size_t)s.n;
+  double acc = 0.0;
+  if ((int64_t)blockIdx.x >= grid_slabs) {  // whole vertices, one wave each
+    const int64_t idx = ((int64_t)blockIdx.x - grid_slabs) * (kBlock / kWave) + w;
+    if (idx < P.n_whole) {
+      const int32_t v = P.verts[P.whole_at + idx];
+      acc = oh_wave_item<E>(s, v, adj, ustart[v], off[v + 1], keys[w]);
+    }
+  } else {
+    const int x = (int)(blockIdx.x % kSlabs);
+    const int64_t blk = blockIdx.x / kSlabs;
+    const int64_t nmb = (P.n_medium[x] + 3) / 4;
+    if (blk < P.n_chunks[x]) {
+      const int64_t c = P.chunk_at[x] + blk;
+      const int64_t cb = P.chunk_begin[c], ce = P.chunk_end[c];
+      const int64_t q = (ce - cb + 3) / 4;
+      const int64_t b0 = cb + w * q;
+      const int64_t e0 = b0 + q < ce ? b0 + q : ce;
+      if (b0 < e0) acc = oh_wave_item<E>(s, P.chunk_vertex[c], adj, b0, e0, keys[w]);
+    } else if (blk - P.n_chunks[x] < nmb) {
+      const int64_t idx = (blk - P.n_chunks[x]) * (kBlock / kWave) + w;
+      if (idx < P.n_medium[x]) {
+        const int32_t v = P.verts[P.medium_at[x] + idx];
+        acc = oh_wave_item<E>(s, v, adj, slab_begin(ustart, P.split, n, x, v), slab_end(off, P.split, n, x, v),
+                              keys[w]);
+      }
+    } else {
+      const int64_t idx = (blk - P.n_chunks[x] - nmb) * (kBlock / kWave) + w;
+      if (idx < P.n_light[x]) {
+        const int32_t v = P.verts[P.light_at[x] + idx];
+        acc = oh_wave_item<E>(s, v, adj, slab_begin(ustart, P.split, n, x, v), slab_end(off, P.split, n, x, v),
+                              keys[w]);
+      }
+    }
+  }
+  if (lane_id() == 0) partials[(int64_t)blockIdx.x * (kBlock / kWave) + w] = acc;
+}
+
+// Clustering coefficient over the full-neighbourhood plan: light vertices
+// (natural order) and medium ones get a wave, heavy vertices are split into
+// chunks whose four waves write one partial sum per chunk (combined below).
+template <int E>
+__global__ __launch_bounds__(kBlock) void k_oh_cc_plan(PlanView P, SkView s, const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ adj, float* __restrict__ cc,
+                                                       double* __restrict__ vsum, double* __restrict__ part) {
+  __shared__ uint64_t keys[kBlock / kWave][kWave * E];
+  __shared__ double red[kBlock / kWave];
+  const int w = threadIdx.x / kWave;
+  const int64_t blk = blockIdx.x;
+  if (blk < P.n_chunks) {
+    const int64_t cb = P.chunk_begin[blk], ce = P.chunk_end[blk];
+    const int64_t q = (ce - cb + 3) / 4;
+    const int64_t b0 = cb + w * q;
+    const int64_t e0 = b0 + q < ce ? b0 + q : ce;
+    double acc = 0.0;
+    if (b0 < e0) acc = oh_wave_item<E>(s, P.chunk_vertex[blk], adj, b0, e0, keys[w]);
+    if (lane_id() == 0) red[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blk] = (red[0] + red[1]) + (red[2] + red[3]);
+    return;
+  }
+  const int64_t mb = blk - P.n_chunks;
+  int32_t v = -1;
+  if (mb < P.n_medium_blocks) {
+    const int64_t idx = mb * (kBlock / kWave) + w;
+    if (idx < P.n_medium) v = P.medium[idx];
+  } else {
+    const int64_t idx = (mb - P.n_medium_blocks) * (kBlock / kWave) + w;
+    if (idx < P.n_light) {
+      v = P.light ? P.light[idx] : (int32_t)idx;
+      if (off[v + 1] - off[v] > kLightMax) v = -1;  // a medium or heavy vertex in natural order
+    }
+  }
+  if (v < 0) return;
+  const double tot = oh_wave_item<E>(s, v, adj, off[v], off[v + 1], keys[w]);
+  if (lane_id() == 0) {
+    const int32_t d = s.deg[v];
+    cc[v] = (float)(d >= 2 ? tot / ((double)d * ((double)d - 1.0)) : 0.0);
+    if (vsum) vsum[v] = tot;
+  }
+}
+
+// Heavy vertices: chunk partials summed in chunk order.
+__global__ void k_oh_cc_combine(PlanView P, const double* __restrict__ part, int64_t n_heavy,
+                                const int32_t* __restrict__ deg, float* __restrict__ cc, double* __restrict__ vsum) {
+  const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (h >= n_heavy) return;
+  const int32_t c0 = P.heavy_first[h], c1 = P.heavy_first[h + 1];
+  const int32_t v = P.chunk_vertex[c0];
+  double tot = 0.0;
+  for (int32_t c = c0; c < c1; ++c) tot += part[c];
+  const int32_t d = deg[v];
+  cc[v] = (float)(d >= 2 ? tot / ((double)d * ((double)d - 1.0)) : 0.0);
+  if (vsum) vsum[v] = tot;
+}
+
+template <typename F>
+int oh_dispatch_e(uint32_t k, F&& launch) {
+  const uint32_t e = (k + kWave - 1) / kWave;
+  if (e <= 1) return launch(std::integral_constant<int, 1>());
+  if (e <= 2) return launch(std::integral_constant<int, 2>());
+  if (e <= 4) return launch(std::integral_constant<int, 4>());
+  if (e <= 8) return launch(std::integral_constant<int, 8>());
+  return launch(std::integral_constant<int, 16>());
+}
+
 __global__ void k_make_table(double* __restrict__ t, uint32_t B, uint32_t b, int est) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c > B) return;
@@ -439,6 +663,30 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
     PG_TRY(sum_chunks(partials, nblk, 3.0, d_out, s));
     return dfree(partials, s);
   }
+  if (sk->kind == PG_MH_1HASH && g->n > 0) {
+    PG_TRY(graph_slabs(const_cast<pg_graph*>(g), s));
+    const SlabPlan& P = g->slabs;
+    int64_t busiest = 0;
+    for (int x = 0; x < kSlabs; ++x) busiest = std::max(busiest, oh_slab_blocks(P, x));
+    const int64_t grid_slabs = busiest * kSlabs;
+    const int64_t nblk = std::max<int64_t>(grid_slabs + (P.n_whole + 3) / 4, 1);
+    if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one launch");
+    const int64_t nparts = nblk * (kBlock / kWave);
+    double* partials = nullptr;
+    PG_TRY(dmalloc((void**)&partials, sizeof(double) * (size_t)nparts, s));
+    const SkView view = make_view(sk, est);
+    {
+      ProfScope ps(s, "oh_tc");
+      PG_TRY(oh_dispatch_e(sk->size, [&](auto e) {
+        hipLaunchKernelGGL((k_oh_tc_slab<decltype(e)::value>), dim3((unsigned)nblk), dim3(kBlock), 0, s, P, view,
+                           g->off, g->ustart, g->adj, grid_slabs, partials);
+        PG_LAUNCH_CHECK();
+        return PG_OK;
+      }));
+    }
+    PG_TRY(sum_chunks(partials, nparts, 3.0, d_out, s));
+    return dfree(partials, s);
+  }
   // general path: one lane per upper edge, fixed chunks
   const int64_t nchunks = std::max<int64_t>(chunk_count(g->m), 1);
   double* chunks = nullptr;
@@ -455,6 +703,27 @@ int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStre
   const pg_graph* g = sk->g;
   const SkView view = make_view(sk, est);
   ProfScope ps(s, "cc");
+  if (sk->kind == PG_MH_1HASH) {
+    const VertexPlan& P = g->plan_all;
+    const PlanView pv = plan_view(P);
+    const int64_t nblk = P.n_chunks + pv.n_medium_blocks + (P.n_light + 3) / 4;
+    if (nblk <= 0) return PG_OK;
+    if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one launch");
+    double* part = nullptr;
+    PG_TRY(dmalloc((void**)&part, sizeof(double) * (size_t)std::max<int64_t>(P.n_chunks, 1), s));
+    PG_TRY(oh_dispatch_e(sk->size, [&](auto e) {
+      hipLaunchKernelGGL((k_oh_cc_plan<decltype(e)::value>), dim3((unsigned)nblk), dim3(kBlock), 0, s, pv, view,
+                         g->off, g->adj, cc, vsum, part);
+      PG_LAUNCH_CHECK();
+      return PG_OK;
+    }));
+    if (P.n_heavy > 0) {
+      hipLaunchKernelGGL(k_oh_cc_combine, dim3((unsigned)((P.n_heavy + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pv,
+                         (const double*)part, P.n_heavy, g->deg, cc, vsum);
+      PG_LAUNCH_CHECK();
+    }
+    return dfree(part, s);
+  }
   for (int bin = 0; bin < kNumBins; ++bin) {
     const int64_t cnt = g->bin_start[bin + 1] - g->bin_start[bin];
     if (cnt <= 0) continue;

@@ -343,18 +343,20 @@ __global__ void k_scan_add(int64_t* __restrict__ out, int64_t count, const int64
   }
 }
 
-// Incoming upper arcs of v from sliced vertices (neighbours u below v with
-// more than kSliceMin upper neighbours).
+// Incoming upper arcs from sliced vertices (those with more than kSliceMin
+// upper neighbours): every upper arc (u, v) of a sliced u adds one to cnt[v].
+// G lanes per vertex u; integer atomics, so the counts are exact.
+template <int G>
 __global__ void k_in_sliced(const int32_t* __restrict__ off, const int32_t* __restrict__ ustart,
-                            const int32_t* __restrict__ adj, int32_t n, int64_t* __restrict__ cnt) {
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    int64_t c = 0;
-    for (int64_t p = off[v]; p < ustart[v]; ++p) {
-      const int32_t u = adj[p];
-      c += (off[u + 1] - ustart[u]) > kSliceMin;
-    }
-    cnt[v] = c;
-  }
+                            const int32_t* __restrict__ adj, const int32_t* __restrict__ verts, int64_t nverts,
+                            unsigned long long* __restrict__ cnt) {
+  const int64_t grp = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  if (grp >= nverts) return;
+  const int32_t u = verts[grp];
+  const int64_t beg = ustart[u], end = off[u + 1];
+  if (end - beg <= kSliceMin) return;
+  for (int64_t p = beg + lane; p < end; p += G) atomicAdd(&cnt[adj[p]], 1ull);
 }
 
 // Slab boundaries: lo[x] is the first vertex whose exclusive prefix of
@@ -894,9 +896,8 @@ int graph_slabs(pg_graph* g, hipStream_t s) {
     PG_TRY(dmalloc((void**)&cnt, sizeof(int64_t) * 2 * (size_t)n + 16 * sizeof(int32_t), s));
     int64_t* pre = cnt + n;
     int32_t* lo = (int32_t*)(pre + n);
-    hipLaunchKernelGGL(k_in_sliced, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, g->off, g->ustart, g->adj, n,
-                       cnt);
-    PG_LAUNCH_CHECK();
+    PG_TRY(fill_u64((uint64_t*)cnt, 0, n, s));
+    PG_FOR_BINS(k_in_sliced, g, s, g->off, g->ustart, g->adj, verts_, cnt_, (unsigned long long*)cnt);
     PG_TRY(exclusive_scan_i64(cnt, pre, n, s));
     hipLaunchKernelGGL(k_slab_bounds, dim3(1), dim3(64), 0, s, (const int64_t*)pre, (const int64_t*)cnt, n, lo);
     PG_LAUNCH_CHECK();
