@@ -460,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_oh_cc_plan(PlanView P, SkView s, con
 }
 
 // Heavy vertices: chunk partials summed in chunk order.
-__global__ void k_oh_cc_combine(PlanView P, const double* __restrict__ part, int64_t n_heavy,
+__global__ void k_cc_combine(PlanView P, const double* __restrict__ part, int64_t n_heavy,
                                 const int32_t* __restrict__ deg, float* __restrict__ cc, double* __restrict__ vsum) {
   const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (h >= n_heavy) return;
@@ -481,6 +481,63 @@ int oh_dispatch_e(uint32_t k, F&& launch) {
   if (e <= 4) return launch(std::integral_constant<int, 4>());
   if (e <= 8) return launch(std::integral_constant<int, 8>());
   return launch(std::integral_constant<int, 16>());
+}
+
+// ---- clustering coefficient over the full-neighbourhood plan (Bloom filters) --
+//
+// The triangle count's vertex-centric item (B_v in registers, two-lane row
+// reads, estimator table in LDS) over all of N_v: light vertices (natural
+// order) get kWholeGroup lanes, medium ones a wave, heavy ones chunks whose
+// block sums are combined per vertex afterwards.
+template <int W, bool OR>
+__global__ __launch_bounds__(kBlock) void k_bf_cc_plan(PlanView P, SkView s, const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ adj, float* __restrict__ cc,
+                                                       double* __restrict__ vsum, double* __restrict__ part) {
+  extern __shared__ double tab[];
+  __shared__ double red[kBlock / kWave];
+  for (uint32_t i = threadIdx.x; i <= s.size; i += kBlock) tab[i] = s.table[i];
+  __syncthreads();
+  constexpr int U = RowUnroll<W>::value;
+  const int64_t blk = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (blk < P.n_chunks) {
+    const double acc = bf_item<W, U, kBlock, OR>(s, P.chunk_vertex[blk], adj, P.chunk_begin[blk], P.chunk_end[blk],
+                                                 tid, tab);
+    const double r = block_sum_256(acc, red);
+    if (tid == 0) part[blk] = r;
+    return;
+  }
+  const int64_t mb = blk - P.n_chunks;
+  int32_t v = -1;
+  double tot = 0.0;
+  bool lead = false;
+  if (mb < P.n_medium_blocks) {  // one wave per vertex
+    const int64_t idx = mb * (kBlock / kWave) + tid / kWave;
+    double acc = 0.0;
+    if (idx < P.n_medium) {
+      v = P.medium[idx];
+      acc = bf_item<W, U, kWave, OR>(s, v, adj, off[v], off[v + 1], lane_id(), tab);
+    }
+    tot = group_sum<kWave>(acc);
+    lead = lane_id() == 0;
+  } else {  // light: kWholeGroup lanes per vertex, natural order
+    const int64_t idx = ((mb - P.n_medium_blocks) * kBlock + tid) / kWholeGroup;
+    double acc = 0.0;
+    if (idx < P.n_light) {
+      const int32_t u = P.light ? P.light[idx] : (int32_t)idx;
+      if (off[u + 1] - off[u] <= kLightMax) {
+        v = u;
+        acc = bf_item<W, U, kWholeGroup, OR>(s, v, adj, off[v], off[v + 1], tid % kWholeGroup, tab);
+      }
+    }
+    tot = group_sum<kWholeGroup>(acc);
+    lead = tid % kWholeGroup == 0;
+  }
+  if (v >= 0 && lead) {
+    const int32_t d = s.deg[v];
+    cc[v] = (float)(d >= 2 ? tot / ((double)d * ((double)d - 1.0)) : 0.0);
+    if (vsum) vsum[v] = tot;
+  }
 }
 
 __global__ void k_make_table(double* __restrict__ t, uint32_t B, uint32_t b, int est) {
@@ -718,7 +775,52 @@ int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStre
       return PG_OK;
     }));
     if (P.n_heavy > 0) {
-      hipLaunchKernelGGL(k_oh_cc_combine, dim3((unsigned)((P.n_heavy + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pv,
+      hipLaunchKernelGGL(k_cc_combine, dim3((unsigned)((P.n_heavy + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pv,
+                         (const double*)part, P.n_heavy, g->deg, cc, vsum);
+      PG_LAUNCH_CHECK();
+    }
+    return dfree(part, s);
+  }
+  if (sk->kind == PG_BF && sk->W <= 16) {
+    const VertexPlan& P = g->plan_all;
+    const PlanView pv = plan_view(P);
+    const int64_t nblk = P.n_chunks + pv.n_medium_blocks + (P.n_light * kWholeGroup + kBlock - 1) / kBlock;
+    if (nblk <= 0) return PG_OK;
+    if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one launch");
+    double* part = nullptr;
+    PG_TRY(dmalloc((void**)&part, sizeof(double) * (size_t)std::max<int64_t>(P.n_chunks, 1), s));
+    const size_t shmem = sizeof(double) * ((size_t)sk->size + 1);
+#define PG_CCP(WW)                                                                                                 \
+  do {                                                                                                             \
+    if (est == PG_EST_BF_OR)                                                                                       \
+      hipLaunchKernelGGL((k_bf_cc_plan<WW, true>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, pv, view, g->off, \
+                         g->adj, cc, vsum, part);                                                                  \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_bf_cc_plan<WW, false>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, pv, view,        \
+                         g->off, g->adj, cc, vsum, part);                                                          \
+  } while (0)
+    switch (sk->W) {
+      case 1: PG_CCP(1); break;
+      case 2: PG_CCP(2); break;
+      case 3: PG_CCP(3); break;
+      case 4: PG_CCP(4); break;
+      case 5: PG_CCP(5); break;
+      case 6: PG_CCP(6); break;
+      case 7: PG_CCP(7); break;
+      case 8: PG_CCP(8); break;
+      case 9: PG_CCP(9); break;
+      case 10: PG_CCP(10); break;
+      case 11: PG_CCP(11); break;
+      case 12: PG_CCP(12); break;
+      case 13: PG_CCP(13); break;
+      case 14: PG_CCP(14); break;
+      case 15: PG_CCP(15); break;
+      default: PG_CCP(16); break;
+    }
+#undef PG_CCP
+    PG_LAUNCH_CHECK();
+    if (P.n_heavy > 0) {
+      hipLaunchKernelGGL(k_cc_combine, dim3((unsigned)((P.n_heavy + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pv,
                          (const double*)part, P.n_heavy, g->deg, cc, vsum);
       PG_LAUNCH_CHECK();
     }
