@@ -4,11 +4,12 @@
 // the byte budget allows. An engine thread keeps up to K batches in flight,
 // one stream each (default priority). Whenever a batch slot is free and
 // requests wait, it packs as many of them as fit into one launch: pairs go to
-// pinned staging, a segment table tells each pair its request's sketch set,
-// estimator and operation, and one fused kernel answers every pair of the
-// batch. When a batch's event completes, its results are copied into the
-// requests' host buffers and its slot and bytes are released, so requests that
-// arrived meanwhile start in the next launch.
+// the slot's pinned, coherent host buffers, a segment table tells each pair its
+// request's sketch set, estimator and operation, and one fused kernel reads the
+// pairs from host memory and writes every answer back there (no copy calls:
+// a batch is one launch and one event). When a batch's event completes, its
+// results are copied into the requests' host buffers and its slot and bytes are
+// released, so requests that arrived meanwhile start in the next launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,31 +35,40 @@ namespace {
 constexpr int kMaxSegments = 1024;  // requests per batch
 constexpr int kEstSlots = 8;        // view slots per sketch set, indexed by estimator id
 
+constexpr int kArgSegments = 16;    // segment tables this small travel as kernel arguments
+
 struct SegDesc {
   int64_t begin;  // first pair of the segment in the batch
   int32_t view;   // index into the server's views (sketch * kEstSlots + estimator)
   int32_t op;     // PG_OP_CN or PG_OP_JACCARD
 };
 
+struct SegArgs {
+  int32_t nseg;
+  SegDesc seg[kArgSegments];  // used when nseg <= kArgSegments
+};
+
 // One lane per pair; the segment is found by binary search over the batch's
-// segment starts held in LDS.
-__global__ __launch_bounds__(256) void k_serve_batch(const SkView* __restrict__ views,
-                                                     const SegDesc* __restrict__ segs, int32_t nseg,
-                                                     const int32_t* __restrict__ pu, const int32_t* __restrict__ pv,
-                                                     int64_t total, double* __restrict__ out) {
-  __shared__ int64_t begins[kMaxSegments];
-  for (int i = threadIdx.x; i < nseg; i += blockDim.x) begins[i] = segs[i].begin;
+// segment starts held in LDS. `pu`, `pv` and `out` are pinned host memory.
+__global__ __launch_bounds__(256) void k_serve_batch(const SkView* __restrict__ views, SegArgs a,
+                                                     const SegDesc* __restrict__ big, const int32_t* __restrict__ pu,
+                                                     const int32_t* __restrict__ pv, int64_t total,
+                                                     double* __restrict__ out) {
+  __shared__ SegDesc table[kMaxSegments];
+  const int32_t nseg = a.nseg;
+  const SegDesc* segs = nseg <= kArgSegments ? a.seg : big;
+  for (int i = threadIdx.x; i < nseg; i += blockDim.x) table[i] = segs[i];
   __syncthreads();
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     int lo = 0, hi = nseg;  // last segment with begin <= e
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (begins[mid] <= e)
+      if (table[mid].begin <= e)
         lo = mid;
       else
         hi = mid;
     }
-    const SegDesc sd = segs[lo];
+    const SegDesc sd = table[lo];
     const SkView& s = views[sd.view];
     const int32_t u = pu[e], v = pv[e];
     uint32_t raw;
@@ -83,13 +93,10 @@ struct Request {
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t event = nullptr;
-  int32_t* h_u = nullptr;  // pinned staging
+  int32_t* h_u = nullptr;  // pinned, coherent: the batch kernel reads the pairs here
   int32_t* h_v = nullptr;
-  double* h_out = nullptr;
-  SegDesc* h_seg = nullptr;
-  int32_t* d_u = nullptr;
-  int32_t* d_v = nullptr;
-  double* d_out = nullptr;
+  double* h_out = nullptr;  // and writes the answers here
+  SegDesc* h_seg = nullptr;  // segment tables larger than kArgSegments, staged for d_seg
   SegDesc* d_seg = nullptr;
   std::vector<Request*> reqs;
   bool busy = false;
@@ -128,13 +135,10 @@ int slot_init(pg_server* srv, Slot& sl) {
   const int64_t cap = srv->p.max_batch_pairs;
   PG_HIP(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
   PG_HIP(hipEventCreateWithFlags(&sl.event, hipEventDisableTiming));
-  PG_HIP(hipHostMalloc((void**)&sl.h_u, sizeof(int32_t) * cap, hipHostMallocDefault));
-  PG_HIP(hipHostMalloc((void**)&sl.h_v, sizeof(int32_t) * cap, hipHostMallocDefault));
-  PG_HIP(hipHostMalloc((void**)&sl.h_out, sizeof(double) * cap, hipHostMallocDefault));
+  PG_HIP(hipHostMalloc((void**)&sl.h_u, sizeof(int32_t) * cap, hipHostMallocCoherent));
+  PG_HIP(hipHostMalloc((void**)&sl.h_v, sizeof(int32_t) * cap, hipHostMallocCoherent));
+  PG_HIP(hipHostMalloc((void**)&sl.h_out, sizeof(double) * cap, hipHostMallocCoherent));
   PG_HIP(hipHostMalloc((void**)&sl.h_seg, sizeof(SegDesc) * kMaxSegments, hipHostMallocDefault));
-  PG_TRY(palloc((void**)&sl.d_u, sizeof(int32_t) * cap));
-  PG_TRY(palloc((void**)&sl.d_v, sizeof(int32_t) * cap));
-  PG_TRY(palloc((void**)&sl.d_out, sizeof(double) * cap));
   PG_TRY(palloc((void**)&sl.d_seg, sizeof(SegDesc) * kMaxSegments));
   return PG_OK;
 }
@@ -145,33 +149,34 @@ void slot_free(Slot& sl) {
   if (sl.h_v) (void)hipHostFree(sl.h_v);
   if (sl.h_out) (void)hipHostFree(sl.h_out);
   if (sl.h_seg) (void)hipHostFree(sl.h_seg);
-  pfree(sl.d_u);
-  pfree(sl.d_v);
-  pfree(sl.d_out);
   pfree(sl.d_seg);
   if (sl.event) (void)hipEventDestroy(sl.event);
   if (sl.stream) (void)hipStreamDestroy(sl.stream);
   sl = Slot();
 }
 
-// Pack requests into the slot and enqueue copy-in, kernel, copy-out, event.
+// Pack requests into the slot's host buffers and enqueue the kernel and the
+// event (plus one small copy when the segment table is too big for arguments).
 int launch_batch(pg_server* srv, Slot& sl) {
   int64_t total = 0;
-  int32_t nseg = 0;
+  SegArgs a{};
+  a.nseg = (int32_t)sl.reqs.size();
+  int32_t i = 0;
   for (Request* r : sl.reqs) {
     std::memcpy(sl.h_u + total, r->u.data(), sizeof(int32_t) * r->npairs);
     std::memcpy(sl.h_v + total, r->v.data(), sizeof(int32_t) * r->npairs);
-    sl.h_seg[nseg++] = SegDesc{total, r->view, r->op};
+    const SegDesc sd{total, r->view, r->op};
+    sl.h_seg[i] = sd;
+    if (i < kArgSegments) a.seg[i] = sd;
+    ++i;
     total += r->npairs;
   }
-  PG_HIP(hipMemcpyAsync(sl.d_u, sl.h_u, sizeof(int32_t) * total, hipMemcpyHostToDevice, sl.stream));
-  PG_HIP(hipMemcpyAsync(sl.d_v, sl.h_v, sizeof(int32_t) * total, hipMemcpyHostToDevice, sl.stream));
-  PG_HIP(hipMemcpyAsync(sl.d_seg, sl.h_seg, sizeof(SegDesc) * nseg, hipMemcpyHostToDevice, sl.stream));
+  if (a.nseg > kArgSegments)
+    PG_HIP(hipMemcpyAsync(sl.d_seg, sl.h_seg, sizeof(SegDesc) * a.nseg, hipMemcpyHostToDevice, sl.stream));
   const unsigned grid = grid_for(total, 256, 16384);
-  hipLaunchKernelGGL(k_serve_batch, dim3(grid), dim3(256), 0, sl.stream, (const SkView*)srv->d_views,
-                     (const SegDesc*)sl.d_seg, nseg, (const int32_t*)sl.d_u, (const int32_t*)sl.d_v, total, sl.d_out);
+  hipLaunchKernelGGL(k_serve_batch, dim3(grid), dim3(256), 0, sl.stream, (const SkView*)srv->d_views, a,
+                     (const SegDesc*)sl.d_seg, (const int32_t*)sl.h_u, (const int32_t*)sl.h_v, total, sl.h_out);
   PG_LAUNCH_CHECK();
-  PG_HIP(hipMemcpyAsync(sl.h_out, sl.d_out, sizeof(double) * total, hipMemcpyDeviceToHost, sl.stream));
   PG_HIP(hipEventRecord(sl.event, sl.stream));
   return PG_OK;
 }
