@@ -193,6 +193,9 @@ def measure_scale24(args, pg, pggen, torch, ctx, sync, log):
     out["exact"] = {"tc": exact_tc, "tc_ms": round(exact_ms, 3), "intersections_per_s": m / (exact_ms * 1e-3)}
     ms = timed(lambda: dg.exact_cc(), 3, sync)
     out["exact"]["cc_ms"] = round(ms, 3)
+    assert dg.exact_tc(algo=pg.PG_EXACT_BITMAP) == exact_tc
+    ms = timed(lambda: dg.exact_tc(algo=pg.PG_EXACT_BITMAP), 3, sync)
+    out["exact"]["tc_bitmap_ms"] = round(ms, 3)
     for name, kind, size, est in (("bf1024", "bf", 1024, "and"), ("onehash64", "1h", 64, "1h")):
         sk = dg.build_sketches(kind, size, 1, seed=args.seed)
         tc = sk.tc(est)  # first call builds the triangle-count plan
@@ -361,6 +364,12 @@ def main():
         rows["exact_edges"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
         ms = timed(lambda: dg.exact_cc(), 3, sync)
         rows["exact_cc"] = {"ms": round(ms, 4)}
+        # the bitmap variant of the exact baseline (all upper edges; triangle count)
+        ms = timed(lambda: dg.exact_intersect(algo=pg.PG_EXACT_BITMAP), 3, sync)
+        rows["exact_edges_bitmap"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
+        assert dg.exact_tc(algo=pg.PG_EXACT_BITMAP) == exact_tc
+        ms = timed(lambda: dg.exact_tc(algo=pg.PG_EXACT_BITMAP), 3, sync)
+        rows["exact_tc_bitmap"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
 
     cpu = None
     if not args.skip_cpu:

@@ -175,12 +175,17 @@ int pg_jaccard(pg_ctx* ctx, const pg_sketches* sk, int estimator, const int32_t*
                int64_t npairs, float* out, void* stream);
 
 /* ---- exact baselines on the same graph ---------------------------------- */
-/* Exact |N_u cap N_v| per pair (u = v = NULL: the m upper edges). */
+/* Exact |N_u cap N_v| per pair (u = v = NULL: the m upper edges, in CSR
+ * order). algo PG_EXACT_MERGE: binary search of the shorter list in the longer
+ * one, any pair list. PG_EXACT_BITMAP: each vertex's list is marked in an
+ * on-chip bitmap and its upper neighbours' lists are probed against it; it
+ * serves u = v = NULL only and returns PG_E_UNSUPPORTED for explicit pairs. */
 int pg_exact_intersect_edges(pg_ctx* ctx, const pg_graph* g, int algo, const int32_t* u, const int32_t* v,
                              int64_t npairs, uint32_t* out, void* stream);
 /* Exact triangle count by the degree-ordered node iterator (Listing
  * "lst:tc"): orient every edge towards the endpoint of larger (degree, ID)
- * and sum |N+_v cap N+_u| over the oriented edges. *tc host; waits. */
+ * and sum |N+_v cap N+_u| over the oriented edges, each intersection by merge
+ * (PG_EXACT_MERGE) or by bitmap (PG_EXACT_BITMAP). *tc host; waits. */
 int pg_exact_tc(pg_ctx* ctx, const pg_graph* g, int algo, uint64_t* tc, void* stream);
 /* Exact local clustering coefficient (FP32) and, optionally, transitivity (host; waits). */
 int pg_exact_cc(pg_ctx* ctx, const pg_graph* g, float* cc, double* transitivity, void* stream);

@@ -8,6 +8,12 @@
 // 64 lanes regardless of which pair they belong to, and each item is
 // binary-searched in the longer list. This balances skewed degree mixes inside
 // a wave, and the cost per pair is min(d_u, d_v) * log max(d_u, d_v).
+//
+// Bitmap variant (PG_EXACT_BITMAP): a block marks the list of one vertex v in
+// an LDS bitmap of 2^20 IDs and every wave probes the list of one of v's
+// neighbours against it, counting hits with ballots; then the block clears the
+// bits it set. IDs beyond 2^20 are handled window by window. Cost per pair:
+// d_u probes, no search.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -179,11 +185,107 @@ __global__ void k_exact_jaccard(const uint32_t* __restrict__ inter, const int32_
   }
 }
 
+constexpr int kBmBlock = 1024;
+constexpr int kBmWaves = kBmBlock / kWave;
+constexpr int kWinShift = 20;                    // IDs per window: 2^20 (a 128 KB bitmap)
+constexpr int kWinWords = (1 << kWinShift) / 32;
+
+// First position in a[lo, hi) with a[p] >= key.
+__device__ __forceinline__ int64_t lower_bound_id(const int32_t* __restrict__ a, int64_t lo, int64_t hi, int64_t key) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)a[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// TC = false: for every vertex v, the counts |N_u cap N_v| of its upper
+// neighbours u go to out[upoff[v] + j] (marked list N_v, probe lists N_u).
+// TC = true: lists are the degree-oriented N+ (moff/madj); the counts of all
+// oriented edges are summed into *tc. Blocks take vertices v = block, block +
+// grid, ...; the bitmap starts clear and every pass clears what it set.
+template <bool TC>
+__global__ __launch_bounds__(kBmBlock) void k_exact_bitmap(const int32_t* __restrict__ moff,
+                                                           const int32_t* __restrict__ madj,
+                                                           const int32_t* __restrict__ ustart,
+                                                           const int64_t* __restrict__ upoff, int32_t n,
+                                                           uint32_t* __restrict__ out,
+                                                           unsigned long long* __restrict__ tc) {
+  extern __shared__ uint32_t bm[];
+  for (int i = threadIdx.x; i < kWinWords; i += kBmBlock) bm[i] = 0;
+  __syncthreads();
+  const int w = threadIdx.x / kWave;
+  const int lane = lane_id();
+  unsigned long long acc = 0;
+  for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
+    const int64_t lb = moff[v], le = moff[v + 1];                  // marked list
+    const int64_t pb = TC ? lb : (int64_t)ustart[v], pe = le;       // its neighbours to probe
+    if (lb == le || pb == pe) continue;                             // uniform over the block
+    const int64_t w_first = (int64_t)madj[lb] >> kWinShift, w_last = (int64_t)madj[le - 1] >> kWinShift;
+    int64_t mlo = lb;
+    for (int64_t win = w_first; win <= w_last; ++win) {
+      const int64_t base = win << kWinShift;
+      const int64_t mhi = lower_bound_id(madj, mlo, le, base + (1 << kWinShift));
+      if (mhi == mlo) continue;  // no element of v's list in this window (uniform)
+      for (int64_t q = mlo + threadIdx.x; q < mhi; q += kBmBlock) {
+        const int32_t x = (int32_t)(madj[q] - base);
+        atomicOr(&bm[x >> 5], 1u << (x & 31));
+      }
+      __syncthreads();
+      for (int64_t j = pb + w; j < pe; j += kBmWaves) {  // one wave per neighbour u
+        const int32_t u = madj[j];
+        const int64_t ub = moff[u], ue = moff[u + 1];
+        const int64_t a = win == 0 ? ub : lower_bound_id(madj, ub, ue, base);
+        const int64_t b = lower_bound_id(madj, a, ue, base + (1 << kWinShift));
+        uint32_t c = 0;
+        for (int64_t q = a + lane; q < b + (kWave - 1) - ((b - a + kWave - 1) % kWave); q += kWave) {
+          bool hit = false;
+          if (q < b) {
+            const int32_t x = (int32_t)(madj[q] - base);
+            hit = (bm[x >> 5] >> (x & 31)) & 1u;
+          }
+          c += (uint32_t)__popcll(__ballot(hit));
+        }
+        if (lane == 0) {
+          if constexpr (TC) {
+            acc += c;
+          } else {
+            uint32_t* o = out + upoff[v] + (j - pb);
+            *o = win == w_first ? c : *o + c;
+          }
+        }
+      }
+      __syncthreads();
+      for (int64_t q = mlo + threadIdx.x; q < mhi; q += kBmBlock) bm[(madj[q] - base) >> 5] = 0;
+      __syncthreads();
+      mlo = mhi;
+    }
+  }
+  if constexpr (TC) {
+    if (lane == 0 && acc) atomicAdd(tc, acc);
+  }
+}
+
 }  // namespace
 
 int exact_pairs(const pg_graph* g, int algo, const int32_t* u, const int32_t* v, int64_t npairs, uint32_t* out,
                 hipStream_t s) {
-  if (algo != PG_EXACT_MERGE) return fail(PG_E_UNSUPPORTED, "only PG_EXACT_MERGE is implemented for pair lists");
+  if (algo == PG_EXACT_BITMAP) {
+    // resolve_pairs turns u = v = NULL into the graph's own upper-edge lists
+    if (u != g->eu || v != g->ev)
+      return fail(PG_E_UNSUPPORTED, "PG_EXACT_BITMAP needs u = v = NULL (the m upper edges)");
+    if (g->m <= 0 || g->n <= 0) return PG_OK;
+    const unsigned grid = (unsigned)std::max(1, std::min(g->ctx->num_cus, g->n));
+    ProfScope ps(s, "exact_bitmap");
+    hipLaunchKernelGGL((k_exact_bitmap<false>), dim3(grid), dim3(kBmBlock), sizeof(uint32_t) * kWinWords, s, g->off,
+                       g->adj, g->ustart, g->upoff, g->n, out, (unsigned long long*)nullptr);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+  }
+  if (algo != PG_EXACT_MERGE) return fail(PG_E_INVALID, "unknown exact algorithm");
   if (npairs <= 0) return PG_OK;
   const unsigned grid = grid_for((npairs + kWave - 1) / kWave * kWave, kBlock, 65536);
   ProfScope ps(s, "exact_pairs");
@@ -194,10 +296,19 @@ int exact_pairs(const pg_graph* g, int algo, const int32_t* u, const int32_t* v,
 }
 
 int exact_tc(pg_graph* g, int algo, uint64_t* d_tc, hipStream_t s) {
-  if (algo != PG_EXACT_MERGE) return fail(PG_E_UNSUPPORTED, "only PG_EXACT_MERGE is implemented for triangle counting");
+  if (algo != PG_EXACT_MERGE && algo != PG_EXACT_BITMAP) return fail(PG_E_INVALID, "unknown exact algorithm");
   PG_TRY(graph_orient(g, s));
   PG_TRY(fill_u64(d_tc, 0, 1, s));
   if (g->m <= 0) return PG_OK;
+  if (algo == PG_EXACT_BITMAP) {
+    const unsigned grid = (unsigned)std::max(1, std::min(g->ctx->num_cus, g->n));
+    ProfScope ps(s, "exact_tc_bitmap");
+    hipLaunchKernelGGL((k_exact_bitmap<true>), dim3(grid), dim3(kBmBlock), sizeof(uint32_t) * kWinWords, s, g->poff,
+                       g->padj, (const int32_t*)nullptr, (const int64_t*)nullptr, g->n, (uint32_t*)nullptr,
+                       (unsigned long long*)d_tc);
+    PG_LAUNCH_CHECK();
+    return PG_OK;
+  }
   const unsigned grid = grid_for((g->m + kWave - 1) / kWave * kWave, kBlock, 65536);
   ProfScope ps(s, "exact_tc");
   hipLaunchKernelGGL(k_exact_tc, dim3(grid), dim3(kBlock), 0, s, g->poff, g->padj, g->parc_src, g->m,

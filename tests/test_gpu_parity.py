@@ -331,6 +331,44 @@ def test_exact_baseline(ctx, name):
     dg.close()
 
 
+@pytest.mark.parametrize("name", ["er4096", "rmat12", "hub", "k40", "wheel7", "isolated", "single_edge"])
+def test_exact_bitmap(ctx, name):
+    """The bitmap intersection: every upper edge and the triangle count, bit-exact."""
+    g, dg = dgraph(ctx, name)
+    say(f"exact bitmap {name}")
+    eu, ev = oracle.upper_edges(g)
+    got = dg.exact_intersect(algo=pg.PG_EXACT_BITMAP)
+    torch.cuda.synchronize()
+    assert np.array_equal(np_(got).astype(np.uint32), oracle.exact_pairs(g, eu, ev))
+    assert dg.exact_tc(algo=pg.PG_EXACT_BITMAP) == oracle.exact_tc(g)
+    if g.n > 1:  # explicit pair lists are the merge kernel's
+        dev = torch.device("cuda", 0)
+        t = torch.zeros(1, dtype=torch.int32, device=dev)
+        with pytest.raises(pg.PGError) as ei:
+            dg.exact_intersect(t, t, algo=pg.PG_EXACT_BITMAP)
+        assert ei.value.code == pg.PG_E_UNSUPPORTED
+    dg.close()
+
+
+def test_exact_bitmap_several_windows(ctx):
+    """IDs beyond 2^20 take several bitmap windows: a sparse G(n, p) with n = 2^20 + 3000
+    (uniform IDs, so most lists span both windows) plus a star and a clique."""
+    n = (1 << 20) + 3000
+    base = pggen.er(n, 6, seed=9)
+    hubs = pggen.disjoint_union(pggen.star(4000), pggen.complete(60))
+    g = pggen.disjoint_union(base, hubs)
+    say(f"exact bitmap, several windows: n={g.n} nnz={g.nnz}")
+    dg = pg.Graph(ctx, g.offsets, g.adj)
+    eu, ev = oracle.upper_edges(g)
+    got = dg.exact_intersect(algo=pg.PG_EXACT_BITMAP)
+    torch.cuda.synchronize()
+    assert np.array_equal(np_(got).astype(np.uint32), oracle.exact_pairs(g, eu, ev))
+    tc = oracle.exact_tc(g)
+    assert dg.exact_tc(algo=pg.PG_EXACT_BITMAP) == tc
+    assert dg.exact_tc() == tc
+    dg.close()
+
+
 def test_closed_forms_on_gpu(ctx):
     for n in (5, 33):
         g = pggen.complete(n)
