@@ -238,8 +238,10 @@ __global__ __launch_bounds__(kBmBlock) void k_exact_bitmap(const int32_t* __rest
       for (int64_t j = pb + w; j < pe; j += kBmWaves) {  // one wave per neighbour u
         const int32_t u = madj[j];
         const int64_t ub = moff[u], ue = moff[u + 1];
-        const int64_t a = win == 0 ? ub : lower_bound_id(madj, ub, ue, base);
-        const int64_t b = lower_bound_id(madj, a, ue, base + (1 << kWinShift));
+        // one window holds every ID when n <= 2^20: the whole list, no search
+        const bool whole = n <= (1 << kWinShift);
+        const int64_t a = (whole || win == 0) ? ub : lower_bound_id(madj, ub, ue, base);
+        const int64_t b = whole ? ue : lower_bound_id(madj, a, ue, base + (1 << kWinShift));
         uint32_t c = 0;
         for (int64_t q = a + lane; q < b + (kWave - 1) - ((b - a + kWave - 1) % kWave); q += kWave) {
           bool hit = false;
