@@ -29,7 +29,7 @@ constexpr int kBlock = 256;
 //
 // One launch, three tiers (heavy chunks first): heavy vertices are split into
 // chunks of kHeavyChunk arcs, one block each; medium vertices get a wave;
-// light vertices (at most kLightMax neighbours) get kLightGroup lanes.
+// light vertices (at most kLightMax neighbours) get kLightGroup lanes each.
 //
 // Bit scatter: the lanes serving one vertex share one W-word bitmap in LDS and
 // set the bit of each hashed neighbour with an LDS atomic OR (one LDS
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_bf_build_plan(PlanView P, const int3
                                                           const uint64_t* __restrict__ hc, uint64_t* __restrict__ words,
                                                           uint32_t* __restrict__ pc, uint64_t* __restrict__ part) {
   constexpr int kLightWords = (kBlock / kLightGroup) * W;       // one bitmap per light group
-  constexpr int kWaveWords = (kBlock / kWave) * kBfCopies * W;  // kBfCopies bitmaps per wave
+  constexpr int kWaveWords = (kBlock / kWave) * kBfCopies * W;  // kBfCopies bitmaps per wave (or per heavy block)
   __shared__ uint64_t lds[kLightWords > kWaveWords ? kLightWords : kWaveWords];
   const int64_t blk = blockIdx.x;
   const int tid = threadIdx.x;
@@ -122,18 +122,14 @@ __global__ __launch_bounds__(kBlock) void k_bf_build_plan(PlanView P, const int3
     if (active && lane == 0) pc[v] = ones;
     return;
   }
-  // ---- light: kLightGroup lanes per vertex of the light list
+  // ---- light: kLightGroup lanes per vertex of the light list (sorted by
+  // degree, so the groups of a wave walk about equally many arcs)
   const int64_t idx = ((mb - P.n_medium_blocks) * kBlock + tid) / kLightGroup;
   const int lane = tid % kLightGroup;
   uint64_t* bits = lds + (tid / kLightGroup) * W;
-  bool active = idx < P.n_light;
-  const int32_t v = active ? (P.light ? P.light[idx] : (int32_t)idx) : 0;
-  int64_t beg = 0, end = 0;
-  if (active) {
-    beg = off[v];
-    end = off[v + 1];
-    active = P.light || end - beg <= kLightMax;
-  }
+  const bool active = idx < P.n_light;
+  const int32_t v = active ? P.light[idx] : 0;
+  const int64_t beg = active ? off[v] : 0, end = active ? off[v + 1] : 0;
   for (int k = lane; k < W; k += kLightGroup) bits[k] = 0;
   wave_sync();
   if (active) bf_scatter<4, kLightGroup>(adj, beg, end, lane, B, b, ha, hc, bits);

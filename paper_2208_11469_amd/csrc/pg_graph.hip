@@ -395,8 +395,8 @@ __global__ void k_slab_split(const int32_t* __restrict__ off, const int32_t* __r
   }
 }
 
-// Arc count of listed items: of (x, v) for slab x >= 0, of v's upper
-// neighbours for x < 0 (whole vertices). Counts are at most kSliceMin.
+// Arc count of listed items: of (x, v) for slab x >= 0, else off[v+1] -
+// ustart[v] (upper neighbours, or all of N_v when ustart = off). At most 255.
 __global__ void k_item_keys(const int32_t* __restrict__ verts, int64_t count, int x, const int32_t* __restrict__ off,
                             const int32_t* __restrict__ ustart, const int32_t* __restrict__ split, int32_t n,
                             uint8_t* __restrict__ key) {
@@ -653,12 +653,13 @@ int sort_desc_small(int32_t* vals, uint8_t* key, int64_t count, hipStream_t s) {
 
 // Sorts a light list (slab x, or whole vertices for x < 0) by descending arc
 // count, so the lanes of a wave walk about equally many arcs.
-int sort_light_list(int32_t* verts, int64_t count, int x, pg_graph* g, const int32_t* split, hipStream_t s) {
+int sort_light_list(int32_t* verts, int64_t count, int x, pg_graph* g, const int32_t* off, const int32_t* ustart,
+                    const int32_t* split, hipStream_t s) {
   if (count <= 1) return PG_OK;
   uint8_t* key = nullptr;
   PG_TRY(dmalloc((void**)&key, (size_t)count, s));
   hipLaunchKernelGGL(k_item_keys, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     (const int32_t*)verts, count, x, g->off, g->ustart, split, g->n, key);
+                     (const int32_t*)verts, count, x, off, ustart, split, g->n, key);
   PG_LAUNCH_CHECK();
   PG_TRY(sort_desc_small(verts, key, count, s));
   return dfree(key, s);
@@ -720,9 +721,9 @@ int build_plan(pg_graph* g, VertexPlan* P, hipStream_t s) {
   PG_TRY(palloc((void**)&P->sorted, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
   int64_t starts[kNumBins + 1];
   PG_TRY(partition(g, true, P->sorted, starts, s));
-  // nearly every vertex is light over N_v: natural order saves the list lookup
-  P->light = nullptr;
-  P->n_light = n;
+  P->light = P->sorted + starts[1];
+  P->n_light = starts[2] - starts[1];
+  PG_TRY(sort_light_list(P->light, P->n_light, -1, g, g->off, g->off, nullptr, s));  // by full degree
   P->medium = P->sorted + starts[2];
   P->n_medium = starts[3] - starts[2];
   P->n_heavy = starts[4] - starts[3];
@@ -941,8 +942,8 @@ int graph_slabs(pg_graph* g, hipStream_t s) {
       at += cnt_x;
     }
     for (int x = 0; x < kSlabs; ++x)
-      PG_TRY(sort_light_list(Q.verts + Q.light_at[x], Q.n_light[x], x, g, Q.split, s));
-    PG_TRY(sort_light_list(Q.verts + Q.whole_at, Q.n_whole, -1, g, Q.split, s));
+      PG_TRY(sort_light_list(Q.verts + Q.light_at[x], Q.n_light[x], x, g, g->off, g->ustart, Q.split, s));
+    PG_TRY(sort_light_list(Q.verts + Q.whole_at, Q.n_whole, -1, g, g->off, g->ustart, Q.split, s));
     // 5. heavy items in chunks
     std::vector<int32_t> cv, cslot, first;
     std::vector<int64_t> cb, ce;

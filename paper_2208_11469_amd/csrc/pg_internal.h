@@ -62,9 +62,11 @@ constexpr int kBinGroup[kNumBins] = {4, 16, 64, 256};
 // heaviest first:
 //   heavy  (d_v >  kMediumMax): chunks of kHeavyChunk arcs, one block each
 //   medium (kLightMax < d_v <= kMediumMax): one wave per vertex
-//   light  (d_v <= kLightMax): kLightGroup lanes per vertex
+//   light  (d_v <= kLightMax): kLightGroup lanes per vertex in the filter
+//          build (the clustering kernels pick their own group size)
 // Isolated vertices stay in the light tier (their sketch rows still have to
-// be written).
+// be written). The light list is sorted by descending degree, so the lanes of
+// a wave walk about equally many arcs.
 constexpr int32_t kLightMax = 64;
 constexpr int32_t kMediumMax = 2048;
 constexpr int64_t kHeavyChunk = 2048;
@@ -72,8 +74,7 @@ constexpr int kLightGroup = 4;
 
 struct VertexPlan {
   int64_t n_light = 0;
-  int32_t* light = nullptr;       // [n_light] light vertices, ascending; nullptr: every vertex in natural
-                                  // order, the kernel skipping those above kLightMax (n_light = n)
+  int32_t* light = nullptr;       // [n_light] light vertices, by descending degree
   int64_t n_medium = 0;
   int32_t* medium = nullptr;      // [n_medium] medium vertices, ascending
   int64_t n_chunks = 0;
