@@ -9,7 +9,9 @@
 // kBatchHeavy arcs) is one item processed by a whole block; the other vertices
 // form tiles of tile_vertices consecutive vertices, kBatchGroup lanes per
 // vertex. Persistent blocks take items from a counter reset at the start of
-// every run and leave when the list is exhausted.
+// every run and leave when the list is exhausted. The estimate runs one
+// launch per row width W present (its items grouped by W), so W is a
+// compile-time constant of that launch.
 //
 // Each vertex is always reduced by the same lanes in the same order (its tier
 // is fixed by its degree), so results do not depend on the tile size, the grid
@@ -67,11 +69,13 @@ struct BatchView {
   double* S;
   double* Splus;
   float* cc;
-  uint32_t* counters;  // [0] build queue, [1] estimate queue
+  uint32_t* counters;  // [0] build queue, [1 + W] estimate queue of row width W
 };
 
+constexpr int kCounters = 2 + kMaxW;
+
 __global__ void k_batch_reset(uint32_t* counters) {
-  if (threadIdx.x < 2) counters[threadIdx.x] = 0;
+  if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
 }
 
 // One block per graph: T_g[c] for c = 0..B_g (same formulas as the single-graph tables).
@@ -180,41 +184,73 @@ __global__ __launch_bounds__(kBlock) void k_batch_build(BatchView bv) {
   }
 }
 
-// Sum of the estimate over the arcs of v (all, and those to larger IDs).
+// Sums of the estimate over the arcs of v (all, and those to larger IDs) for a
+// group of G lanes, rows of W words. v's row stays in registers; a neighbour's
+// row is read by a team of T lanes side by side (Q words each; the last member
+// may read up to Q - 1 words past the row, which the zero words of v's row
+// cancel), and the team's counts meet in quad DPP adds.
+template <int W, int G>
 __device__ __forceinline__ void vertex_sums(const BatchView& bv, const GraphDesc& gd, int32_t v, int64_t beg,
-                                            int64_t end, int lane, int G, double& all, double& up) {
-  const uint32_t W = gd.W;
-  uint64_t rv[kMaxW];
-  const uint64_t* row = bv.words + gd.wbase + (int64_t)v * W;
+                                            int64_t end, int lane, double& all, double& up) {
+  constexpr int T = W <= 2 ? 1 : 2;
+  constexpr int Q = (W + T - 1) / T;
+  constexpr int NT = G / T;
+  constexpr int U = W <= 4 ? 8 : (W <= 8 ? 4 : 2);
+  const int k = lane % T;
+  const bool reads = k * Q < W;
+  const uint64_t* rows = bv.words + gd.wbase;
+  uint64_t rv[Q];
 #pragma unroll
-  for (int k = 0; k < kMaxW; ++k) rv[k] = (uint32_t)k < W ? row[k] : 0ull;
+  for (int i = 0; i < Q; ++i) rv[i] = (k * Q + i < W) ? rows[(int64_t)v * W + k * Q + i] : 0ull;
   const double* tab = bv.tables + gd.tbase;
-  for (int64_t p = beg + lane; p < end; p += G) {
-    const int32_t u = bv.adj[p];
-    const uint64_t* ru = bv.words + gd.wbase + (int64_t)u * W;
-    uint32_t c = 0;
+  for (int64_t p0 = beg + lane / T; p0 < end; p0 += (int64_t)NT * U) {
+    int32_t x[U];
 #pragma unroll
-    for (int k = 0; k < kMaxW; ++k)
-      if ((uint32_t)k < W) c += (uint32_t)__popcll(rv[k] & ru[k]);
-    const double t = tab[c];
-    all += t;
-    if (u > v) up += t;
+    for (int j = 0; j < U; ++j) {
+      const int64_t p = p0 + (int64_t)j * NT;
+      x[j] = p < end ? bv.adj[p] : -1;
+    }
+    uint64_t w[U][Q];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) w[j][i] = 0;
+      if (x[j] >= 0 && reads) {
+        const uint64_t* r = rows + (int64_t)x[j] * W + k * Q;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) w[j][i] = r[i];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) c += (uint32_t)__popcll(rv[i] & w[j][i]);
+      c = team_sum<T>(c);
+      if (k == 0 && x[j] >= 0) {
+        const double t = tab[c];
+        all += t;
+        if (x[j] > v) up += t;
+      }
+    }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch_estimate(BatchView bv) {
+// Estimate items [begin, end) of one row width W (graphs with B = 64 W).
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_batch_estimate(BatchView bv, int64_t begin, int64_t end) {
   __shared__ double red[kBlock / kWave];
   __shared__ int64_t slot;
   const int tid = threadIdx.x;
   for (;;) {
-    const int64_t it = next_item(&bv.counters[1], &slot);
-    if (it >= bv.nitems) return;
+    const int64_t it = begin + next_item(&bv.counters[1 + W], &slot);
+    if (it >= end) return;
     const Item item = bv.items[it];
     const GraphDesc gd = bv.gd[item.graph];
     if (item.heavy) {
       const int64_t gv = gd.vbase + item.v0;
       double all = 0.0, up = 0.0;
-      vertex_sums(bv, gd, item.v0, bv.off[gv], bv.off[gv + 1], tid, kBlock, all, up);
+      vertex_sums<W, kBlock>(bv, gd, item.v0, bv.off[gv], bv.off[gv + 1], tid, all, up);
       all = block_sum_256(all, red);
       up = block_sum_256(up, red);
       if (tid == 0) {
@@ -228,14 +264,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_estimate(BatchView bv) {
     const int grp = tid / kBatchGroup, lane = tid % kBatchGroup;
     for (int32_t v = item.v0 + grp; v < item.v1; v += kGroups) {
       const int64_t gv = gd.vbase + v;
-      const int64_t beg = bv.off[gv], end = bv.off[gv + 1];
-      if (end - beg > kBatchHeavy) continue;
+      const int64_t beg = bv.off[gv], e = bv.off[gv + 1];
+      if (e - beg > kBatchHeavy) continue;
       double all = 0.0, up = 0.0;
-      vertex_sums(bv, gd, v, beg, end, lane, kBatchGroup, all, up);
+      vertex_sums<W, kBatchGroup>(bv, gd, v, beg, e, lane, all, up);
       all = group_sum<kBatchGroup>(all);
       up = group_sum<kBatchGroup>(up);
       if (lane == 0) {
-        const int64_t d = end - beg;
+        const int64_t d = e - beg;
         bv.S[gv] = all;
         bv.Splus[gv] = up;
         bv.cc[gv] = d >= 2 ? (float)(all / ((double)d * ((double)d - 1.0))) : 0.0f;
@@ -269,9 +305,11 @@ struct pg_batch {
   std::vector<pg::GraphDesc> h_gd;
   std::vector<int64_t> h_off;  // host copy of the global offsets (work-list construction)
   pg::GraphDesc* gd = nullptr;
-  pg::Item* items = nullptr;
+  pg::Item* items = nullptr;   // build work list (heaviest first)
   int64_t items_cap = 0;
   int64_t nitems = 0;
+  pg::Item* eitems = nullptr;  // estimate work list: by row width W, heaviest first inside
+  int64_t w_begin[pg::kMaxW + 2] = {};  // items of width W: eitems[w_begin[W] .. w_begin[W + 1])
   int64_t* off = nullptr;
   int32_t* adj = nullptr;
   uint64_t* words = nullptr;
@@ -310,16 +348,30 @@ int build_items(pg_batch* bt) {
     }
   }
   std::stable_sort(list.begin(), list.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-  std::vector<Item> items(list.size());
+  std::vector<Item> items(list.size()), eitems;
   for (size_t i = 0; i < list.size(); ++i) items[i] = list[i].second;
+  eitems.reserve(items.size());
+  for (int w = 0; w <= kMaxW + 1; ++w) bt->w_begin[w] = 0;
+  for (uint32_t w = 1; w <= (uint32_t)kMaxW; ++w) {  // stable: heaviest first inside a width
+    bt->w_begin[w] = (int64_t)eitems.size();
+    for (const Item& it : items)
+      if (bt->h_gd[it.graph].W == w) eitems.push_back(it);
+  }
+  bt->w_begin[kMaxW + 1] = (int64_t)eitems.size();
   if ((int64_t)items.size() > bt->items_cap) {
     pfree(bt->items);
+    pfree(bt->eitems);
     bt->items = nullptr;
+    bt->eitems = nullptr;
     bt->items_cap = (int64_t)items.size();
     PG_TRY(palloc((void**)&bt->items, sizeof(Item) * std::max<size_t>(items.size(), 1)));
+    PG_TRY(palloc((void**)&bt->eitems, sizeof(Item) * std::max<size_t>(items.size(), 1)));
   }
   bt->nitems = (int64_t)items.size();
-  if (!items.empty()) PG_HIP(hipMemcpy(bt->items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
+  if (!items.empty()) {
+    PG_HIP(hipMemcpy(bt->items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
+    PG_HIP(hipMemcpy(bt->eitems, eitems.data(), sizeof(Item) * eitems.size(), hipMemcpyHostToDevice));
+  }
   return PG_OK;
 }
 
@@ -356,8 +408,35 @@ int enqueue_run(pg_batch* bt, int est, hipStream_t s) {
   PG_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_batch_build, dim3(persistent), dim3(kBlock), 0, s, bv);
   PG_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_batch_estimate, dim3(persistent), dim3(kBlock), 0, s, bv);
-  PG_LAUNCH_CHECK();
+  BatchView ev = bv;
+  ev.items = bt->eitems;
+  for (int w = 1; w <= kMaxW; ++w) {
+    const int64_t b0 = bt->w_begin[w], b1 = bt->w_begin[w + 1];
+    if (b1 <= b0) continue;
+    const unsigned grid = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>(b1 - b0, (int64_t)std::max(1, bt->ctx->num_cus) * bt->params.blocks_per_cu));
+#define PG_BE(WW) hipLaunchKernelGGL((k_batch_estimate<WW>), dim3(grid), dim3(kBlock), 0, s, ev, b0, b1)
+    switch (w) {
+      case 1: PG_BE(1); break;
+      case 2: PG_BE(2); break;
+      case 3: PG_BE(3); break;
+      case 4: PG_BE(4); break;
+      case 5: PG_BE(5); break;
+      case 6: PG_BE(6); break;
+      case 7: PG_BE(7); break;
+      case 8: PG_BE(8); break;
+      case 9: PG_BE(9); break;
+      case 10: PG_BE(10); break;
+      case 11: PG_BE(11); break;
+      case 12: PG_BE(12); break;
+      case 13: PG_BE(13); break;
+      case 14: PG_BE(14); break;
+      case 15: PG_BE(15); break;
+      default: PG_BE(16); break;
+    }
+#undef PG_BE
+    PG_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(k_batch_tc, dim3((unsigned)bt->count), dim3(kBlock), 0, s, (const GraphDesc*)bt->gd,
                      (const double*)bt->Splus, bt->tc);
   PG_LAUNCH_CHECK();
@@ -375,6 +454,7 @@ void free_batch(pg_batch* bt) {
   drop_graph(bt);
   pfree(bt->gd);
   pfree(bt->items);
+  pfree(bt->eitems);
   pfree(bt->off);
   pfree(bt->adj);
   pfree(bt->words);
@@ -468,7 +548,7 @@ int pg_batch_create(pg_ctx* ctx, int32_t count, const int32_t* const* offsets, c
   P((void**)&bt->gd, sizeof(GraphDesc) * count);
   P((void**)&bt->off, sizeof(int64_t) * (N + 1));
   P((void**)&bt->adj, sizeof(int32_t) * A);
-  P((void**)&bt->words, sizeof(uint64_t) * words);
+  P((void**)&bt->words, sizeof(uint64_t) * (words + kBfSlackWords));  // team readers may read past the last row
   P((void**)&bt->pc, sizeof(uint32_t) * N);
   P((void**)&bt->ha, sizeof(uint64_t) * b);
   P((void**)&bt->hc, sizeof(uint64_t) * b);
@@ -477,7 +557,7 @@ int pg_batch_create(pg_ctx* ctx, int32_t count, const int32_t* const* offsets, c
   P((void**)&bt->Splus, sizeof(double) * N);
   P((void**)&bt->cc, sizeof(float) * N);
   P((void**)&bt->tc, sizeof(double) * count);
-  P((void**)&bt->counters, sizeof(uint32_t) * 2);
+  P((void**)&bt->counters, sizeof(uint32_t) * kCounters);
   if (rc == PG_OK) {
     hipError_t e = hipMemcpy(bt->gd, bt->h_gd.data(), sizeof(GraphDesc) * count, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(bt->off, bt->h_off.data(), sizeof(int64_t) * (N + 1), hipMemcpyHostToDevice);

@@ -86,6 +86,16 @@ __device__ __forceinline__ uint32_t group_sum_u32(uint32_t x) {
   return x;
 }
 
+// Sum over the T lanes of a team (T in {1, 2, 4}, teams aligned to quads) by
+// quad DPP moves; every lane of the team ends with the sum. The lanes of a team
+// must be active together.
+template <int T>
+__device__ __forceinline__ uint32_t team_sum(uint32_t c) {
+  if constexpr (T >= 2) c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0xB1, 0xF, 0xF, false);  // lane ^ 1
+  if constexpr (T >= 4) c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0x4E, 0xF, 0xF, false);  // lane ^ 2
+  return c;
+}
+
 // Block-wide deterministic FP64 sum for blockDim.x == 256 (4 waves); result
 // valid in thread 0.
 __device__ __forceinline__ double block_sum_256(double x, double* lds4) {

@@ -131,14 +131,6 @@ struct TcTeam {
   static constexpr int words = (W + value - 1) / value;  // Q
 };
 
-// Sum over the T lanes of a team (T in {1, 2, 4}, teams aligned to quads).
-template <int T>
-__device__ __forceinline__ uint32_t team_sum(uint32_t c) {
-  if constexpr (T >= 2) c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0xB1, 0xF, 0xF, false);  // lane ^ 1
-  if constexpr (T >= 4) c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0x4E, 0xF, 0xF, false);  // lane ^ 2
-  return c;
-}
-
 // Words [kQ, kQ + Q) of row v for team member k, zero past the row's end.
 template <int W, int G>
 __device__ __forceinline__ void load_team_row(const uint64_t* __restrict__ words, int32_t v, int k,
