@@ -361,6 +361,106 @@ def jaccard(sk: Sketches, est: str, u, v) -> np.ndarray:
     return jaccard_from_intersection(sk.deg[u], sk.deg[v], sk.estimate(u, v, est))
 
 
+# ---------------------------------------------------------------- similarity and clustering
+
+SIM_COMMON, SIM_JACCARD, SIM_OVERLAP, SIM_TOTAL = 0, 1, 2, 3
+SIMILARITIES = {"cn": SIM_COMMON, "jaccard": SIM_JACCARD, "overlap": SIM_OVERLAP, "total": SIM_TOTAL}
+
+
+def similarity_from_intersection(du, dv, inter, measure: int) -> np.ndarray:
+    """Vertex similarity of two neighbourhoods A = N_u, B = N_v from |A cap B|
+    (Listing "lst:sim"):
+
+    * common neighbours: |A cap B| itself (an estimate is passed on as it is);
+    * Jaccard: |A cap B| / (|A| + |B| - |A cap B|), 0 when the union is empty;
+    * overlap: |A cap B| / min(|A|, |B|), 0 when the smaller set is empty;
+    * total neighbours: |A cup B| = |A| + |B| - |A cap B|.
+
+    For Jaccard, overlap and total neighbours an estimate is clamped to
+    [0, min(d_u, d_v)] first, the range of a true intersection (no other value
+    gives a consistent union)."""
+    inter = np.asarray(inter, dtype=np.float64)
+    if measure == SIM_COMMON:
+        return inter.copy()
+    if measure == SIM_JACCARD:
+        return jaccard_from_intersection(du, dv, inter)
+    du = np.asarray(du, dtype=np.float64)
+    dv = np.asarray(dv, dtype=np.float64)
+    lo = np.minimum(du, dv)
+    ic = np.clip(inter, 0.0, lo)
+    if measure == SIM_OVERLAP:
+        out = np.zeros_like(ic)
+        ok = lo > 0
+        out[ok] = ic[ok] / lo[ok]
+        return out
+    if measure == SIM_TOTAL:
+        return (du + dv) - ic
+    raise ValueError(f"unknown similarity measure {measure}")
+
+
+def exact_similarity(g, u, v, measure: int) -> np.ndarray:
+    """Exact vertex similarity per pair (exact intersections by merge)."""
+    deg = g.degrees()
+    u, v = _i32(u), _i32(v)
+    return similarity_from_intersection(deg[u], deg[v], exact_pairs(g, u, v), measure)
+
+
+def similarity(sk: Sketches, est: str, u, v, measure: int) -> np.ndarray:
+    """Estimated vertex similarity per pair: the estimate of |N_u cap N_v| in
+    place of the exact intersection."""
+    u, v = _i32(u), _i32(v)
+    return similarity_from_intersection(sk.deg[u], sk.deg[v], sk.estimate(u, v, est), measure)
+
+
+def jarvis_patrick(values, tau: float) -> np.ndarray:
+    """Jarvis-Patrick clustering (Listing "lst:cl"): an edge belongs to the
+    clustering C when the similarity of its endpoints is greater than the
+    threshold tau. ``values`` holds the similarity of the m upper edges;
+    returns C as a 0/1 uint8 mask over them."""
+    return (np.asarray(values, dtype=np.float64) > tau).astype(np.uint8)
+
+
+def exact_jarvis_patrick(g, measure: int, tau: float) -> np.ndarray:
+    eu, ev = upper_edges(g)
+    return jarvis_patrick(exact_similarity(g, eu, ev, measure), tau)
+
+
+def estimated_jarvis_patrick(sk: Sketches, est: str, measure: int, tau: float) -> np.ndarray:
+    eu, ev = upper_edges(sk.g)
+    return jarvis_patrick(similarity(sk, est, eu, ev, measure), tau)
+
+
+def clusters(n: int, eu, ev, keep=None) -> np.ndarray:
+    """The clusters of an edge set C: the connected components of (V, C), every
+    vertex labelled with the smallest vertex ID of its component (a vertex
+    without an edge in C is a cluster of its own). ``keep`` selects C among the
+    edges (eu, ev); None takes them all.
+
+    label_v is the smallest ID reachable from v; it is reached by repeating
+    label_v <- min(label_v, label_u) over the edges of C (both directions)
+    until no label changes."""
+    eu = np.asarray(eu, dtype=np.int64)
+    ev = np.asarray(ev, dtype=np.int64)
+    if keep is not None:
+        sel = np.asarray(keep).astype(bool)
+        eu, ev = eu[sel], ev[sel]
+    label = np.arange(n, dtype=np.int64)
+    while True:
+        low = np.minimum(label[eu], label[ev])
+        new = label.copy()
+        np.minimum.at(new, eu, low)
+        np.minimum.at(new, ev, low)
+        if np.array_equal(new, label):
+            return label.astype(np.int32)
+        label = new
+
+
+def cluster_count(labels) -> int:
+    """Number of clusters: the vertices that label themselves."""
+    labels = np.asarray(labels)
+    return int(np.count_nonzero(labels == np.arange(labels.shape[0])))
+
+
 def bits_for_budget(g, s: float) -> int:
     """Bloom-filter size for storage budget s (Section 5.1): the largest
     multiple of 64 bits with n * B <= s * 8 * CSR bytes, at least 64."""
