@@ -370,6 +370,24 @@ def main():
         assert dg.exact_tc(algo=pg.PG_EXACT_BITMAP) == exact_tc
         ms = timed(lambda: dg.exact_tc(algo=pg.PG_EXACT_BITMAP), 3, sync)
         rows["exact_tc_bitmap"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
+        # Jarvis-Patrick clustering over all m edges (similarity > tau) and its
+        # clusters, from the filters and exactly (merge); accuracy as the
+        # relative error of the counts
+        for mname, tau in (("cn", 8.5), ("jaccard", 0.05), ("overlap", 0.5)):
+            keep_b, kept_b = sk.jarvis_patrick("and", mname, tau)
+            ms_b = timed(lambda: sk.jarvis_patrick("and", mname, tau), reps, sync)
+            ncl_b = dg.clusters(keep_b)[1]
+            ms_c = timed(lambda: dg.clusters(keep_b), reps, sync)
+            keep_x, kept_x = dg.exact_jarvis_patrick(mname, tau)
+            ms_x = timed(lambda: dg.exact_jarvis_patrick(mname, tau), 3, sync)
+            ncl_x = dg.clusters(keep_x)[1]
+            rows[f"jarvis_patrick_{mname}"] = {
+                "tau": tau, "bf_ms": round(ms_b, 4), "bf_edges_per_s": m / (ms_b * 1e-3),
+                "clusters_ms": round(ms_c, 4), "exact_ms": round(ms_x, 4),
+                "speedup_bf_vs_exact": (ms_x + ms_c) / (ms_b + ms_c),
+                "kept_bf": kept_b, "kept_exact": kept_x, "clusters_bf": ncl_b, "clusters_exact": ncl_x,
+                "cluster_count_rel_err": abs(ncl_b - ncl_x) / max(ncl_x, 1)}
+            del keep_b, keep_x
 
     cpu = None
     if not args.skip_cpu:

@@ -193,6 +193,48 @@ int pg_exact_cc(pg_ctx* ctx, const pg_graph* g, float* cc, double* transitivity,
 int pg_exact_jaccard(pg_ctx* ctx, const pg_graph* g, const int32_t* u, const int32_t* v, int64_t npairs,
                      float* out, void* stream);
 
+/* ---- vertex similarity and Jarvis-Patrick clustering ---------------------- */
+/* Similarity of two neighbourhoods A = N_u, B = N_v (Listing "lst:sim"). */
+#define PG_SIM_COMMON 0  /* |A cap B| (common neighbours); an estimate is passed on as it is */
+#define PG_SIM_JACCARD 1 /* |A cap B| / |A cup B|; 0 when the union is empty */
+#define PG_SIM_OVERLAP 2 /* |A cap B| / min(|A|, |B|); 0 when the smaller set is empty */
+#define PG_SIM_TOTAL 3   /* |A cup B| = |A| + |B| - |A cap B| (total neighbours) */
+
+/* Estimated similarity per pair, FP32 rounded once from FP64. For Jaccard,
+ * overlap and total neighbours the intersection estimate is first clamped to
+ * [0, min(d_u, d_v)], the range of a true intersection. u = v = NULL: the m
+ * upper edges in CSR order; pairs with an ID outside [0, n) give NaN. An
+ * unknown measure gives PG_E_INVALID. */
+int pg_similarity(pg_ctx* ctx, const pg_sketches* sk, int estimator, int measure, const int32_t* u,
+                  const int32_t* v, int64_t npairs, float* out, void* stream);
+/* Exact similarity per pair (FP32) from exact intersections by merge. */
+int pg_exact_similarity(pg_ctx* ctx, const pg_graph* g, int measure, const int32_t* u, const int32_t* v,
+                        int64_t npairs, float* out, void* stream);
+
+/* Jarvis-Patrick clustering (Listing "lst:cl"): the clustering C holds the
+ * edges whose endpoints' similarity (`measure`, computed from the estimate) is
+ * greater than tau; the comparison is made in FP64. keep (device, m bytes,
+ * nullable) receives 1 for the upper edges in C and 0 for the others, in CSR
+ * upper-edge order; kept (host, nullable) receives |C|, and then the call
+ * waits for `stream`. At least one of keep and kept must be given. */
+int pg_jarvis_patrick(pg_ctx* ctx, const pg_sketches* sk, int estimator, int measure, double tau, uint8_t* keep,
+                      int64_t* kept, void* stream);
+/* The same clustering from exact intersections; algo PG_EXACT_MERGE or
+ * PG_EXACT_BITMAP (see pg_exact_intersect_edges). Needs m 4-byte words of
+ * temporary device memory. */
+int pg_exact_jarvis_patrick(pg_ctx* ctx, const pg_graph* g, int algo, int measure, double tau, uint8_t* keep,
+                            int64_t* kept, void* stream);
+
+/* Clusters of an edge set C: the connected components of (V, C). label
+ * (device, n int32) receives for every vertex the smallest vertex ID of its
+ * component, so a vertex with no edge in C labels itself. keep (device, m
+ * bytes) selects C among the m upper edges (nonzero = in C); NULL takes every
+ * edge of the graph. nclusters (host, nullable) receives the number of
+ * components, and then the call waits for `stream`. The labels are unique, so
+ * they do not depend on scheduling. */
+int pg_clusters(pg_ctx* ctx, const pg_graph* g, const uint8_t* keep, int32_t* label, int64_t* nclusters,
+                void* stream);
+
 /* Recompute the rows of existing sketches in place (same kind, size and b;
  * new hash constants from `seed`), e.g. after the graph's arrays changed or to
  * draw a fresh sketch set. Allocates nothing. */

@@ -45,12 +45,18 @@ PG_VALIDATE = 4
 # exact algorithms
 PG_EXACT_MERGE = 1
 PG_EXACT_BITMAP = 2
+# similarity measures (Listing "lst:sim")
+PG_SIM_COMMON = 0
+PG_SIM_JACCARD = 1
+PG_SIM_OVERLAP = 2
+PG_SIM_TOTAL = 3
 
 ESTIMATORS = {
     "and": PG_EST_BF_AND, "l": PG_EST_BF_L, "or": PG_EST_BF_OR, "pap": PG_EST_BF_PAPAPETROU,
     "kh": PG_EST_MH_KHASH, "1h": PG_EST_MH_1HASH, "1h_lit": PG_EST_MH_1HASH_LITERAL,
 }
 KINDS = {"bf": PG_BF, "kh": PG_MH_KHASH, "1h": PG_MH_1HASH}
+SIMILARITIES = {"cn": PG_SIM_COMMON, "jaccard": PG_SIM_JACCARD, "overlap": PG_SIM_OVERLAP, "total": PG_SIM_TOTAL}
 
 
 class PGError(RuntimeError):
@@ -127,6 +133,11 @@ def _declare(lib):
         "pg_exact_tc": (i, [_vp, _vp, i, P(u64), _vp]),
         "pg_exact_cc": (i, [_vp, _vp, _vp, P(ctypes.c_double), _vp]),
         "pg_exact_jaccard": (i, [_vp, _vp, _vp, _vp, i64, _vp, _vp]),
+        "pg_similarity": (i, [_vp, _vp, i, i, _vp, _vp, i64, _vp, _vp]),
+        "pg_exact_similarity": (i, [_vp, _vp, i, _vp, _vp, i64, _vp, _vp]),
+        "pg_jarvis_patrick": (i, [_vp, _vp, i, i, ctypes.c_double, _vp, P(i64), _vp]),
+        "pg_exact_jarvis_patrick": (i, [_vp, _vp, i, i, ctypes.c_double, _vp, P(i64), _vp]),
+        "pg_clusters": (i, [_vp, _vp, _vp, _vp, P(i64), _vp]),
         "pg_sketches_rebuild": (i, [_vp, _vp, u64, _vp]),
         "pg_profile_enable": (i, [_vp, i]),
         "pg_profile_read": (i, [_vp, P(_KernelTime), i, P(i)]),
@@ -320,6 +331,36 @@ def pg_exact_jaccard(ctx, g, u, v, npairs, out, stream=None):
     _check(load().pg_exact_jaccard(ctx, g, _dptr(u), _dptr(v), npairs, _dptr(out), _stream(stream)))
 
 
+def pg_similarity(ctx, sk, estimator, measure, u, v, npairs, out, stream=None):
+    _check(load().pg_similarity(ctx, sk, estimator, measure, _dptr(u), _dptr(v), npairs, _dptr(out),
+                                _stream(stream)))
+
+
+def pg_exact_similarity(ctx, g, measure, u, v, npairs, out, stream=None):
+    _check(load().pg_exact_similarity(ctx, g, measure, _dptr(u), _dptr(v), npairs, _dptr(out), _stream(stream)))
+
+
+def pg_jarvis_patrick(ctx, sk, estimator, measure, tau, keep, want_count=True, stream=None):
+    kept = ctypes.c_int64(-1)
+    _check(load().pg_jarvis_patrick(ctx, sk, estimator, measure, float(tau), _dptr(keep),
+                                    ctypes.byref(kept) if want_count else None, _stream(stream)))
+    return kept.value if want_count else None
+
+
+def pg_exact_jarvis_patrick(ctx, g, algo, measure, tau, keep, want_count=True, stream=None):
+    kept = ctypes.c_int64(-1)
+    _check(load().pg_exact_jarvis_patrick(ctx, g, algo, measure, float(tau), _dptr(keep),
+                                          ctypes.byref(kept) if want_count else None, _stream(stream)))
+    return kept.value if want_count else None
+
+
+def pg_clusters(ctx, g, keep, label, want_count=True, stream=None):
+    count = ctypes.c_int64(-1)
+    _check(load().pg_clusters(ctx, g, _dptr(keep), _dptr(label), ctypes.byref(count) if want_count else None,
+                              _stream(stream)))
+    return count.value if want_count else None
+
+
 def pg_sketches_rebuild(ctx, sk, seed, stream=None):
     _check(load().pg_sketches_rebuild(ctx, sk, seed & (2**64 - 1), _stream(stream)))
 
@@ -499,6 +540,37 @@ class Graph:
         pg_exact_jaccard(self.ctx.h, self.h, u, v, npairs, out, stream)
         return out
 
+    def exact_similarity(self, measure, u=None, v=None, stream=None):
+        """Exact similarity (``measure``: "cn", "jaccard", "overlap", "total" or a PG_SIM_* value), FP32."""
+        torch = _torch()
+        u, v, npairs = _pairs(u, v)
+        count = self.m if u is None else npairs
+        out = torch.empty(max(count, 1), dtype=torch.float32, device=self._dev())[:count]
+        if _is_empty_explicit(u):
+            return out
+        pg_exact_similarity(self.ctx.h, self.h, SIMILARITIES.get(measure, measure), u, v, npairs,
+                            out if count else None, stream)
+        return out
+
+    def exact_jarvis_patrick(self, measure, tau, algo=PG_EXACT_MERGE, stream=None):
+        """(keep, kept): uint8 mask over the m upper edges of the exact clustering, and its size."""
+        torch = _torch()
+        keep = torch.empty(max(self.m, 1), dtype=torch.uint8, device=self._dev())[: self.m]
+        kept = pg_exact_jarvis_patrick(self.ctx.h, self.h, algo, SIMILARITIES.get(measure, measure), tau,
+                                       keep if self.m else None, True, stream)
+        return keep, kept
+
+    def clusters(self, keep=None, stream=None):
+        """(labels, count): connected components of the kept upper edges (all edges if keep is None),
+        each vertex labelled with the smallest vertex ID of its component."""
+        torch = _torch()
+        label = torch.empty(max(self.n, 1), dtype=torch.int32, device=self._dev())[: self.n]
+        if keep is not None and keep.numel() != self.m:
+            raise ValueError("keep must hold one byte per upper edge")
+        count = pg_clusters(self.ctx.h, self.h, keep if (keep is not None and self.m) else None,
+                            label if self.n else None, True, stream)
+        return label, count
+
 
 class Sketches:
     def __init__(self, graph: Graph, h):
@@ -569,6 +641,27 @@ class Sketches:
         pg_jaccard(self.graph.ctx.h, self.h, ESTIMATORS.get(estimator, estimator), u, v, npairs,
                    out if count else None, stream)
         return out
+
+    def similarity(self, estimator, measure, u=None, v=None, stream=None):
+        """Estimated similarity (``measure``: "cn", "jaccard", "overlap", "total" or a PG_SIM_* value), FP32."""
+        torch = _torch()
+        u, v, npairs = _pairs(u, v)
+        count = self.graph.m if u is None else npairs
+        out = torch.empty(max(count, 1), dtype=torch.float32, device=self.graph._dev())[:count]
+        if _is_empty_explicit(u):
+            return out
+        pg_similarity(self.graph.ctx.h, self.h, ESTIMATORS.get(estimator, estimator),
+                      SIMILARITIES.get(measure, measure), u, v, npairs, out if count else None, stream)
+        return out
+
+    def jarvis_patrick(self, estimator, measure, tau, stream=None):
+        """(keep, kept): uint8 mask over the m upper edges of the clustering (similarity > tau), and its size."""
+        torch = _torch()
+        m = self.graph.m
+        keep = torch.empty(max(m, 1), dtype=torch.uint8, device=self.graph._dev())[:m]
+        kept = pg_jarvis_patrick(self.graph.ctx.h, self.h, ESTIMATORS.get(estimator, estimator),
+                                 SIMILARITIES.get(measure, measure), tau, keep if m else None, True, stream)
+        return keep, kept
 
 
 class Server:

@@ -130,6 +130,13 @@ int resolve_pairs(const pg_graph* g, const int32_t*& u, const int32_t*& v, int64
   return PG_OK;
 }
 
+// count (<= 8) 64-bit integers from the device into the context's pinned slot; waits.
+int counts_to_host(pg_ctx* ctx, const unsigned long long* d, int count, hipStream_t s) {
+  PG_HIP(hipMemcpyAsync(ctx->h_scalar, d, sizeof(unsigned long long) * (size_t)count, hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  return PG_OK;
+}
+
 int scalar_to_host(pg_ctx* ctx, const double* d_val, double* out, hipStream_t s) {
   PG_HIP(hipMemcpyAsync(ctx->h_scalar, d_val, sizeof(double), hipMemcpyDeviceToHost, s));
   PG_HIP(hipStreamSynchronize(s));
@@ -397,7 +404,7 @@ int pg_intersect_edges(pg_ctx* ctx, const pg_sketches* sk, int estimator, const 
   if (!ctx || !sk) return fail(PG_E_INVALID, "NULL argument");
   PG_TRY(resolve_pairs(sk->g, u, v, npairs));
   PG_TRY(use_device(ctx));
-  return estimate_pairs(sk, estimator, u, v, npairs, est, raw, nullptr, (hipStream_t)stream);
+  return estimate_pairs(sk, estimator, u, v, npairs, est, raw, nullptr, PG_SIM_COMMON, (hipStream_t)stream);
 }
 
 int pg_tc(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* tc, void* stream) {
@@ -447,7 +454,35 @@ int pg_jaccard(pg_ctx* ctx, const pg_sketches* sk, int estimator, const int32_t*
   PG_TRY(resolve_pairs(sk->g, u, v, npairs));
   if (npairs > 0 && !out) return fail(PG_E_INVALID, "out is NULL");
   PG_TRY(use_device(ctx));
-  return estimate_pairs(sk, estimator, u, v, npairs, nullptr, nullptr, out, (hipStream_t)stream);
+  return estimate_pairs(sk, estimator, u, v, npairs, nullptr, nullptr, out, PG_SIM_JACCARD, (hipStream_t)stream);
+}
+
+int pg_similarity(pg_ctx* ctx, const pg_sketches* sk, int estimator, int measure, const int32_t* u, const int32_t* v,
+                  int64_t npairs, float* out, void* stream) {
+  clear_error();
+  if (!ctx || !sk) return fail(PG_E_INVALID, "NULL argument");
+  if (measure < PG_SIM_COMMON || measure > PG_SIM_TOTAL) return fail(PG_E_INVALID, "unknown similarity measure");
+  PG_TRY(resolve_pairs(sk->g, u, v, npairs));
+  if (npairs > 0 && !out) return fail(PG_E_INVALID, "out is NULL");
+  PG_TRY(use_device(ctx));
+  return estimate_pairs(sk, estimator, u, v, npairs, nullptr, nullptr, out, measure, (hipStream_t)stream);
+}
+
+int pg_jarvis_patrick(pg_ctx* ctx, const pg_sketches* sk, int estimator, int measure, double tau, uint8_t* keep,
+                      int64_t* kept, void* stream) {
+  clear_error();
+  if (!ctx || !sk) return fail(PG_E_INVALID, "NULL argument");
+  if (!keep && !kept) return fail(PG_E_INVALID, "keep and kept are both NULL");
+  if (std::isnan(tau)) return fail(PG_E_INVALID, "tau is NaN");
+  PG_TRY(use_device(ctx));
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* d = nullptr;
+  PG_TRY(dmalloc((void**)&d, sizeof(unsigned long long), s));
+  int rc = estimate_jp(sk, estimator, measure, tau, keep, d, s);
+  if (rc == PG_OK && kept) rc = counts_to_host(ctx, d, 1, s);
+  if (rc == PG_OK && kept) *kept = (int64_t)((const unsigned long long*)ctx->h_scalar)[0];
+  dfree(d, s);
+  return rc;
 }
 
 int pg_exact_intersect_edges(pg_ctx* ctx, const pg_graph* g, int algo, const int32_t* u, const int32_t* v,
@@ -496,12 +531,55 @@ int pg_exact_cc(pg_ctx* ctx, const pg_graph* gc, float* cc, double* transitivity
 
 int pg_exact_jaccard(pg_ctx* ctx, const pg_graph* g, const int32_t* u, const int32_t* v, int64_t npairs, float* out,
                      void* stream) {
+  return pg_exact_similarity(ctx, g, PG_SIM_JACCARD, u, v, npairs, out, stream);
+}
+
+int pg_exact_similarity(pg_ctx* ctx, const pg_graph* g, int measure, const int32_t* u, const int32_t* v,
+                        int64_t npairs, float* out, void* stream) {
   clear_error();
   if (!ctx || !g) return fail(PG_E_INVALID, "NULL argument");
+  if (measure < PG_SIM_COMMON || measure > PG_SIM_TOTAL) return fail(PG_E_INVALID, "unknown similarity measure");
   PG_TRY(resolve_pairs(g, u, v, npairs));
   if (npairs > 0 && !out) return fail(PG_E_INVALID, "out is NULL");
   PG_TRY(use_device(ctx));
-  return exact_jaccard(g, u, v, npairs, out, (hipStream_t)stream);
+  return exact_similarity(g, measure, u, v, npairs, out, (hipStream_t)stream);
+}
+
+int pg_exact_jarvis_patrick(pg_ctx* ctx, const pg_graph* g, int algo, int measure, double tau, uint8_t* keep,
+                            int64_t* kept, void* stream) {
+  clear_error();
+  if (!ctx || !g) return fail(PG_E_INVALID, "NULL argument");
+  if (!keep && !kept) return fail(PG_E_INVALID, "keep and kept are both NULL");
+  if (std::isnan(tau)) return fail(PG_E_INVALID, "tau is NaN");
+  PG_TRY(use_device(ctx));
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* d = nullptr;
+  PG_TRY(dmalloc((void**)&d, sizeof(unsigned long long), s));
+  int rc = exact_jp(g, algo, measure, tau, keep, d, s);
+  if (rc == PG_OK && kept) rc = counts_to_host(ctx, d, 1, s);
+  if (rc == PG_OK && kept) *kept = (int64_t)((const unsigned long long*)ctx->h_scalar)[0];
+  dfree(d, s);
+  return rc;
+}
+
+int pg_clusters(pg_ctx* ctx, const pg_graph* g, const uint8_t* keep, int32_t* label, int64_t* nclusters,
+                void* stream) {
+  clear_error();
+  if (!ctx || !g) return fail(PG_E_INVALID, "NULL argument");
+  if (g->n > 0 && !label) return fail(PG_E_INVALID, "label is NULL");
+  PG_TRY(use_device(ctx));
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* d = nullptr;
+  PG_TRY(dmalloc((void**)&d, 2 * sizeof(unsigned long long), s));
+  int rc = clusters(g, keep, label, d, s);
+  if (rc == PG_OK && nclusters) {
+    rc = counts_to_host(ctx, d, 2, s);
+    const unsigned long long* h = (const unsigned long long*)ctx->h_scalar;
+    if (rc == PG_OK && h[1]) rc = fail(PG_E_DEVICE, "cluster union did not settle");
+    if (rc == PG_OK) *nclusters = (int64_t)h[0];
+  }
+  dfree(d, s);
+  return rc;
 }
 
 }  // extern "C"

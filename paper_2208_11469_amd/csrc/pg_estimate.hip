@@ -1,6 +1,7 @@
 // Intersection estimates over vertex pairs (Sections 4.2-4.4) and the
 // quantities built from them: the triangle-count sum (Section 7), local
-// clustering coefficients and Jaccard similarities (Listing "lst:sim").
+// clustering coefficients, vertex similarities (Listing "lst:sim") and
+// Jarvis-Patrick clustering (Listing "lst:cl").
 //
 // Every pair is independent: one lane per pair gathers the two sketch rows,
 // reduces them to an integer count (ones of the AND or OR of two filters,
@@ -30,18 +31,43 @@ template <int KIND, int WT>
 __global__ __launch_bounds__(kBlock) void k_pairs(SkView s, const int32_t* __restrict__ pu,
                                                   const int32_t* __restrict__ pv, int64_t npairs,
                                                   double* __restrict__ est_out, uint32_t* __restrict__ raw_out,
-                                                  float* __restrict__ jac_out) {
+                                                  float* __restrict__ sim_out, int measure) {
   for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < npairs; e += (int64_t)gridDim.x * kBlock) {
     const int32_t u = pu[e], v = pv[e];
     uint32_t raw;
     const double est = eval_pair<KIND, WT>(s, u, v, raw);
     if (est_out) est_out[e] = est;
     if (raw_out) raw_out[e] = raw;
-    if (jac_out) {
+    if (sim_out) {
       const bool ok = (uint32_t)u < (uint32_t)s.n && (uint32_t)v < (uint32_t)s.n;
-      jac_out[e] = ok ? (float)jaccard_of(est, s.deg[u], s.deg[v]) : __int_as_float(0x7FC00000);
+      sim_out[e] = ok ? (float)similarity_of(measure, est, s.deg[u], s.deg[v]) : __int_as_float(0x7FC00000);
     }
   }
+}
+
+// Jarvis-Patrick selection over the m upper edges: keep[e] = (similarity > tau)
+// in FP64, and |C| added to *kept once per block (integer atomics, so the
+// count does not depend on scheduling).
+template <int KIND, int WT>
+__global__ __launch_bounds__(kBlock) void k_pairs_jp(SkView s, const int32_t* __restrict__ pu,
+                                                     const int32_t* __restrict__ pv, int64_t npairs, int measure,
+                                                     double tau, uint8_t* __restrict__ keep,
+                                                     unsigned long long* __restrict__ kept) {
+  __shared__ uint32_t block_kept;
+  if (threadIdx.x == 0) block_kept = 0;
+  __syncthreads();
+  uint32_t mine = 0;
+  for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < npairs; e += (int64_t)gridDim.x * kBlock) {
+    const int32_t u = pu[e], v = pv[e];
+    uint32_t raw;
+    const double est = eval_pair<KIND, WT>(s, u, v, raw);
+    const bool in = similarity_of(measure, est, s.deg[u], s.deg[v]) > tau;
+    if (keep) keep[e] = in ? 1 : 0;
+    mine += in ? 1u : 0u;
+  }
+  if (mine) atomicAdd(&block_kept, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && block_kept) atomicAdd(kept, (unsigned long long)block_kept);
 }
 
 // Partial sums over fixed chunks of kChunk pairs: thread t of the chunk adds
@@ -632,17 +658,42 @@ int ensure_table(pg_sketches* sk, int est, hipStream_t s) {
 }
 
 int estimate_pairs(const pg_sketches* sk, int est, const int32_t* u, const int32_t* v, int64_t npairs,
-                   double* est_out, uint32_t* raw_out, float* jac_out, hipStream_t s) {
+                   double* est_out, uint32_t* raw_out, float* sim_out, int measure, hipStream_t s) {
   PG_TRY(check_estimator(sk, est));
+  if (sim_out && (measure < PG_SIM_COMMON || measure > PG_SIM_TOTAL))
+    return fail(PG_E_INVALID, "unknown similarity measure");
   PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
   if (npairs <= 0) return PG_OK;
   const SkView view = make_view(sk, est);
   const unsigned grid = grid_for(npairs, kBlock, 65536);
   ProfScope ps(s, "pairs");
-#define PG_LAUNCH_PAIRS(KIND, WT) \
-  hipLaunchKernelGGL((k_pairs<KIND, WT>), dim3(grid), dim3(kBlock), 0, s, view, u, v, npairs, est_out, raw_out, jac_out)
+#define PG_LAUNCH_PAIRS(KIND, WT)                                                                                   \
+  hipLaunchKernelGGL((k_pairs<KIND, WT>), dim3(grid), dim3(kBlock), 0, s, view, u, v, npairs, est_out, raw_out, \
+                     sim_out, measure)
   PG_DISPATCH(sk, PG_LAUNCH_PAIRS);
 #undef PG_LAUNCH_PAIRS
+  PG_LAUNCH_CHECK();
+  return PG_OK;
+}
+
+int estimate_jp(const pg_sketches* sk, int est, int measure, double tau, uint8_t* keep, unsigned long long* d_kept,
+                hipStream_t s) {
+  PG_TRY(check_estimator(sk, est));
+  if (measure < PG_SIM_COMMON || measure > PG_SIM_TOTAL) return fail(PG_E_INVALID, "unknown similarity measure");
+  PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
+  PG_TRY(fill_u64((uint64_t*)d_kept, 0, 1, s));
+  const pg_graph* g = sk->g;
+  if (g->m <= 0) return PG_OK;
+  const SkView view = make_view(sk, est);
+  const unsigned grid = grid_for(g->m, kBlock, 65536);
+  const int32_t* eu = g->eu;
+  const int32_t* ev = g->ev;
+  const int64_t m = g->m;
+  ProfScope ps(s, "jarvis_patrick");
+#define PG_LAUNCH_JP(KIND, WT) \
+  hipLaunchKernelGGL((k_pairs_jp<KIND, WT>), dim3(grid), dim3(kBlock), 0, s, view, eu, ev, m, measure, tau, keep, d_kept)
+  PG_DISPATCH(sk, PG_LAUNCH_JP);
+#undef PG_LAUNCH_JP
   PG_LAUNCH_CHECK();
   return PG_OK;
 }

@@ -20,6 +20,7 @@
 
 #include "pg_device.h"
 #include "pg_internal.h"
+#include "pg_pair.h"
 
 namespace pg {
 namespace {
@@ -170,19 +171,40 @@ __global__ void k_exact_cc_finish(const unsigned long long* __restrict__ vsum, c
   cc[v] = d >= 2 ? (float)((double)vsum[v] / ((double)d * ((double)d - 1.0))) : 0.0f;
 }
 
-__global__ void k_exact_jaccard(const uint32_t* __restrict__ inter, const int32_t* __restrict__ deg, int32_t n,
-                                const int32_t* __restrict__ pu, const int32_t* __restrict__ pv, int64_t npairs,
-                                float* __restrict__ out) {
+// Similarity (Listing "lst:sim") of each pair from its exact intersection.
+__global__ void k_exact_sim(const uint32_t* __restrict__ inter, const int32_t* __restrict__ deg, int32_t n,
+                            const int32_t* __restrict__ pu, const int32_t* __restrict__ pv, int64_t npairs,
+                            int measure, float* __restrict__ out) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < npairs; e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t u = pu[e], v = pv[e];
     if ((uint32_t)u >= (uint32_t)n || (uint32_t)v >= (uint32_t)n) {
       out[e] = __int_as_float(0x7FC00000);
       continue;
     }
-    const double i = (double)inter[e];
-    const double den = ((double)deg[u] + (double)deg[v]) - i;
-    out[e] = den > 0.0 ? (float)(i / den) : 0.0f;
+    out[e] = (float)similarity_of(measure, (double)inter[e], deg[u], deg[v]);
   }
+}
+
+// Jarvis-Patrick selection (Listing "lst:cl") of the m upper edges from their
+// exact intersections: keep[e] = (similarity > tau) in FP64; |C| by integer
+// atomics, one per block.
+__global__ __launch_bounds__(kBlock) void k_exact_jp(const uint32_t* __restrict__ inter,
+                                                     const int32_t* __restrict__ deg,
+                                                     const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                                                     int64_t m, int measure, double tau, uint8_t* __restrict__ keep,
+                                                     unsigned long long* __restrict__ kept) {
+  __shared__ uint32_t block_kept;
+  if (threadIdx.x == 0) block_kept = 0;
+  __syncthreads();
+  uint32_t mine = 0;
+  for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < m; e += (int64_t)gridDim.x * kBlock) {
+    const bool in = similarity_of(measure, (double)inter[e], deg[eu[e]], deg[ev[e]]) > tau;
+    if (keep) keep[e] = in ? 1 : 0;
+    mine += in ? 1u : 0u;
+  }
+  if (mine) atomicAdd(&block_kept, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && block_kept) atomicAdd(kept, (unsigned long long)block_kept);
 }
 
 constexpr int kBmBlock = 1024;
@@ -337,15 +359,39 @@ int exact_cc(pg_graph* g, float* cc, hipStream_t s) {
   return dfree(vsum, s);
 }
 
-int exact_jaccard(const pg_graph* g, const int32_t* u, const int32_t* v, int64_t npairs, float* out, hipStream_t s) {
+int exact_similarity(const pg_graph* g, int measure, const int32_t* u, const int32_t* v, int64_t npairs, float* out,
+                     hipStream_t s) {
+  if (measure < PG_SIM_COMMON || measure > PG_SIM_TOTAL) return fail(PG_E_INVALID, "unknown similarity measure");
   if (npairs <= 0) return PG_OK;
   uint32_t* inter = nullptr;
   PG_TRY(dmalloc((void**)&inter, sizeof(uint32_t) * (size_t)npairs, s));
-  PG_TRY(exact_pairs(g, PG_EXACT_MERGE, u, v, npairs, inter, s));
-  hipLaunchKernelGGL(k_exact_jaccard, dim3(grid_for(npairs, kBlock, 65536)), dim3(kBlock), 0, s, inter, g->deg, g->n,
-                     u, v, npairs, out);
-  PG_LAUNCH_CHECK();
-  return dfree(inter, s);
+  int rc = exact_pairs(g, PG_EXACT_MERGE, u, v, npairs, inter, s);
+  if (rc == PG_OK) {
+    hipLaunchKernelGGL(k_exact_sim, dim3(grid_for(npairs, kBlock, 65536)), dim3(kBlock), 0, s, inter, g->deg, g->n,
+                       u, v, npairs, measure, out);
+    if (hipGetLastError() != hipSuccess) rc = fail(PG_E_DEVICE, "k_exact_sim launch failed");
+  }
+  dfree(inter, s);
+  return rc;
+}
+
+int exact_jp(const pg_graph* g, int algo, int measure, double tau, uint8_t* keep, unsigned long long* d_kept,
+             hipStream_t s) {
+  if (measure < PG_SIM_COMMON || measure > PG_SIM_TOTAL) return fail(PG_E_INVALID, "unknown similarity measure");
+  if (algo != PG_EXACT_MERGE && algo != PG_EXACT_BITMAP) return fail(PG_E_INVALID, "unknown exact algorithm");
+  PG_TRY(fill_u64((uint64_t*)d_kept, 0, 1, s));
+  if (g->m <= 0) return PG_OK;
+  uint32_t* inter = nullptr;
+  PG_TRY(dmalloc((void**)&inter, sizeof(uint32_t) * (size_t)g->m, s));
+  int rc = exact_pairs(g, algo, g->eu, g->ev, g->m, inter, s);
+  if (rc == PG_OK) {
+    ProfScope ps(s, "exact_jarvis_patrick");
+    hipLaunchKernelGGL(k_exact_jp, dim3(grid_for(g->m, kBlock, 65536)), dim3(kBlock), 0, s, inter, g->deg, g->eu,
+                       g->ev, g->m, measure, tau, keep, d_kept);
+    if (hipGetLastError() != hipSuccess) rc = fail(PG_E_DEVICE, "k_exact_jp launch failed");
+  }
+  dfree(inter, s);
+  return rc;
 }
 
 }  // namespace pg

@@ -257,9 +257,12 @@ int bf_unpack(const pg_sketches* sk, void* rows, hipStream_t s);
 int ensure_table(pg_sketches* sk, int est, hipStream_t s);
 // Estimator table of a Bloom-filter size into a caller-owned [B+1] array.
 int fill_table(double* table, uint32_t B, uint32_t b, int est, hipStream_t s);
-// Per pair: est / raw / Jaccard outputs (each nullable).
+// Per pair: est / raw / similarity (PG_SIM_* measure) outputs, each nullable.
 int estimate_pairs(const pg_sketches* sk, int est, const int32_t* u, const int32_t* v, int64_t npairs,
-                   double* est_out, uint32_t* raw_out, float* jac_out, hipStream_t s);
+                   double* est_out, uint32_t* raw_out, float* sim_out, int measure, hipStream_t s);
+// Jarvis-Patrick over the m upper edges: keep[m] (nullable) and |C| into d_kept[0].
+int estimate_jp(const pg_sketches* sk, int est, int measure, double tau, uint8_t* keep, unsigned long long* d_kept,
+                hipStream_t s);
 // Deterministic sum of the estimate over pairs into chunk partials; nchunks_out
 // receives the number of partials written to `chunks` (sized by chunk_count()).
 int64_t chunk_count(int64_t npairs);
@@ -274,8 +277,15 @@ int exact_pairs(const pg_graph* g, int algo, const int32_t* u, const int32_t* v,
                 uint32_t* out, hipStream_t s);
 int exact_tc(pg_graph* g, int algo, uint64_t* d_tc, hipStream_t s);
 int exact_cc(pg_graph* g, float* cc, hipStream_t s);
-int exact_jaccard(const pg_graph* g, const int32_t* u, const int32_t* v, int64_t npairs, float* out,
-                  hipStream_t s);
+int exact_similarity(const pg_graph* g, int measure, const int32_t* u, const int32_t* v, int64_t npairs, float* out,
+                     hipStream_t s);
+int exact_jp(const pg_graph* g, int algo, int measure, double tau, uint8_t* keep, unsigned long long* d_kept,
+             hipStream_t s);
+
+// ---- launchers (pg_cluster.hip) ----------------------------------------------
+// Connected components of the kept upper edges (keep NULL: all); label[v] =
+// smallest vertex ID of v's component; the component count into d_count[0].
+int clusters(const pg_graph* g, const uint8_t* keep, int32_t* label, unsigned long long* d_count, hipStream_t s);
 
 // ---- host utilities (pg_api.hip) ---------------------------------------------
 uint64_t splitmix64(uint64_t key, uint64_t i);

@@ -143,12 +143,26 @@ __device__ __forceinline__ double eval_pair(const SkView& s, int32_t u, int32_t 
   }
 }
 
-// J = I_c / (d_u + d_v - I_c), I_c = clamp(I^, 0, min(d_u, d_v)); 0 on an empty union.
+// Similarity of N_u and N_v from an intersection value I (Listing "lst:sim"):
+// common neighbours I itself; for the others I_c = clamp(I, 0, min(d_u, d_v)),
+// Jaccard I_c / (d_u + d_v - I_c) (0 on an empty union), overlap
+// I_c / min(d_u, d_v) (0 when the smaller set is empty), total neighbours
+// d_u + d_v - I_c.
+__device__ __forceinline__ double similarity_of(int measure, double est, int32_t du, int32_t dv) {
+  if (measure == PG_SIM_COMMON) return est;
+  const double hi = (double)(du < dv ? du : dv);
+  const double ic = est < 0.0 ? 0.0 : (est > hi ? hi : est);
+  const double sum = (double)du + (double)dv;
+  if (measure == PG_SIM_JACCARD) {
+    const double den = sum - ic;
+    return den > 0.0 ? ic / den : 0.0;
+  }
+  if (measure == PG_SIM_OVERLAP) return hi > 0.0 ? ic / hi : 0.0;
+  return sum - ic;  // PG_SIM_TOTAL
+}
+
 __device__ __forceinline__ double jaccard_of(double est, int32_t du, int32_t dv) {
-  const double lo = 0.0, hi = (double)(du < dv ? du : dv);
-  const double ic = est < lo ? lo : (est > hi ? hi : est);
-  const double den = ((double)du + (double)dv) - ic;
-  return den > 0.0 ? ic / den : 0.0;
+  return similarity_of(PG_SIM_JACCARD, est, du, dv);
 }
 
 
