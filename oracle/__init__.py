@@ -361,6 +361,36 @@ def jaccard(sk: Sketches, est: str, u, v) -> np.ndarray:
     return jaccard_from_intersection(sk.deg[u], sk.deg[v], sk.estimate(u, v, est))
 
 
+# ---------------------------------------------------------------- oriented sketches
+
+def oriented(g):
+    """The degree-oriented neighbourhoods of Listing "lst:tc": with the order R
+    that ranks vertices by (degree, ID) ascending, N+_v = {u in N_v : R(v) < R(u)},
+    each list ascending by ID. Returned as a CSR over the same n vertices (m arcs
+    in all) that the sketch builders take like any graph; ``degrees()`` gives d+."""
+    import types
+    deg = np.diff(g.offsets).astype(np.int64)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    dst = np.asarray(g.adj, dtype=np.int64)
+    keep = (deg[dst] > deg[src]) | ((deg[dst] == deg[src]) & (dst > src))
+    lens = np.bincount(src[keep], minlength=g.n).astype(np.int64)
+    off = np.zeros(g.n + 1, dtype=np.int32)
+    off[1:] = np.cumsum(lens)
+    adj = dst[keep].astype(np.int32)  # CSR order: by source, then ascending ID
+    return types.SimpleNamespace(n=g.n, offsets=off, adj=adj, nnz=int(adj.shape[0]),
+                                 degrees=lambda: lens.copy(), name=f"{getattr(g, 'name', '')}+")
+
+
+def tc_oriented(g, sk_plus: Sketches, est: str) -> float:
+    """TC^ from sketches of the oriented sets (Listing "lst:tc"): the sum over
+    the oriented edges (v, u), u in N+_v, of the estimate of |N+_v cap N+_u|,
+    with no factor 1/3 (a triangle a, b, c with R(a) < R(b) < R(c) lies in
+    N+_a cap N+_b only). The intersection is symmetric in its two sets, so the
+    sum runs over the m undirected edges of g, each once."""
+    eu, ev = upper_edges(g)
+    return float(np.sum(sk_plus.estimate(eu, ev, est)))
+
+
 # ---------------------------------------------------------------- similarity and clustering
 
 SIM_COMMON, SIM_JACCARD, SIM_OVERLAP, SIM_TOTAL = 0, 1, 2, 3
