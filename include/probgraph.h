@@ -51,6 +51,10 @@ extern "C" {
 #define PG_BF 1        /* Bloom filter of B bits with b hash functions */
 #define PG_MH_KHASH 2  /* k-hash MinHash: k minima of k hash functions */
 #define PG_MH_1HASH 3  /* 1-hash MinHash: k smallest elements under one hash */
+/* Flag OR-ed into the kind of pg_build_sketches: sketch the degree-oriented
+ * sets N+_v = {u in N_v : R(v) < R(u)}, R = (degree, ID) ascending (Listing
+ * "lst:tc"), instead of N_v. */
+#define PG_ORIENTED 256 /* bit 8 */
 
 /* ---- estimators of |X cap Y| --------------------------------------------- */
 #define PG_EST_BF_AND 1           /* -(B/b) ln(1 - c~/B), c = ones(B_X AND B_Y): Eq. "bf_int", divergence fix of Appendix C */
@@ -138,7 +142,13 @@ int pg_sketch_bits_for_budget(const pg_graph* g, double s, uint32_t* bits);
  * (0xFFFFFFFF = empty slot); k-hash slot i holds the argmin of key_i; 1-hash
  * rows hold the min(k, d_v) smallest keys' elements in ascending key order.
  * (Inside the library BF rows are packed so that none crosses a 128-byte
- * line; export returns them dense.) */
+ * line; export returns them dense.)
+ * With kind | PG_ORIENTED the rows sketch N+_v (degree order, see
+ * PG_ORIENTED) and the estimators take d+_v = |N+_v| as the set sizes. Such a
+ * set serves pg_intersect_edges (estimates of |N+_u cap N+_v|), pg_tc (the
+ * oriented form below) and pg_sketches_rebuild / export; pg_cc, pg_jaccard,
+ * pg_similarity, pg_jarvis_patrick and servers are defined on N_v and return
+ * PG_E_UNSUPPORTED for it. pg_sketches_get_info reports kind | PG_ORIENTED. */
 int pg_build_sketches(pg_ctx* ctx, const pg_graph* g, int kind, uint32_t size, uint32_t b, uint64_t seed,
                       void* stream, pg_sketches** out);
 int pg_sketches_destroy(pg_sketches* sk);
@@ -155,7 +165,11 @@ int pg_intersect_edges(pg_ctx* ctx, const pg_sketches* sk, int estimator, const 
                        int64_t npairs, double* est, uint32_t* raw, void* stream);
 
 /* Estimated triangle count TC^ = (1/3) sum over the m edges of the estimate
- * (Section 7). *tc is a host pointer; waits for `stream`. */
+ * (Section 7). For an oriented sketch set (PG_ORIENTED) TC^ = sum over the m
+ * edges of the estimate of |N+_u cap N+_v|, without the 1/3: the node
+ * iterator of Listing "lst:tc" counts each triangle once, at its two
+ * lowest-ranked vertices, and the intersection is symmetric, so each edge
+ * counts once. *tc is a host pointer; waits for `stream`. */
 int pg_tc(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* tc, void* stream);
 
 /* Same estimate written to d_tc[0] (device FP64); enqueued on `stream`

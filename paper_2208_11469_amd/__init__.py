@@ -29,6 +29,7 @@ PG_E_BUSY = -6
 PG_BF = 1
 PG_MH_KHASH = 2
 PG_MH_1HASH = 3
+PG_ORIENTED = 256  # flag: sketch the degree-oriented sets N+_v
 # estimators
 PG_EST_BF_AND = 1
 PG_EST_BF_L = 2
@@ -504,8 +505,10 @@ class Graph:
     def bits_for_budget(self, s: float) -> int:
         return pg_sketch_bits_for_budget(self.h, s)
 
-    def build_sketches(self, kind, size: int, b: int = 1, seed: int = 1, stream=None) -> "Sketches":
-        kind = KINDS.get(kind, kind)
+    def build_sketches(self, kind, size: int, b: int = 1, seed: int = 1, oriented: bool = False,
+                       stream=None) -> "Sketches":
+        """Sketches of every N_v, or with oriented=True of the degree-oriented sets N+_v."""
+        kind = KINDS.get(kind, kind) | (PG_ORIENTED if oriented else 0)
         return Sketches(self, pg_build_sketches(self.ctx.h, self.h, kind, size, b, seed, stream))
 
     def _dev(self):
@@ -577,7 +580,8 @@ class Sketches:
         self.graph = graph
         self.h = h
         info = pg_sketches_get_info(h)
-        self.kind, self.size, self.b, self.row_bytes = info.kind, info.size, info.b, info.row_bytes
+        self.oriented = bool(info.kind & PG_ORIENTED)
+        self.kind, self.size, self.b, self.row_bytes = info.kind & ~PG_ORIENTED, info.size, info.b, info.row_bytes
         self.seed, self.total_bytes = info.seed, info.total_bytes
 
     def close(self):

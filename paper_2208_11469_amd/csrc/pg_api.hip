@@ -86,6 +86,7 @@ int use_device(const pg_ctx* ctx) {
 
 void free_graph(pg_graph* g) {
   if (!g) return;
+  free_graph(g->oriented);  // borrows poff/padj: freed before them
   if (g->owns_csr) {
     pfree(g->off);
     pfree(g->adj);
@@ -282,6 +283,8 @@ int pg_build_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, 
   if (!ctx || !gc || !out) return fail(PG_E_INVALID, "NULL argument");
   *out = nullptr;
   pg_graph* g = const_cast<pg_graph*>(gc);
+  const bool oriented = (kind & PG_ORIENTED) != 0;
+  kind &= ~PG_ORIENTED;
   if (kind == PG_BF) {
     if (size < 64 || size > 4096 || size % 64 != 0)
       return fail(PG_E_INVALID, "Bloom-filter size must be a multiple of 64 bits in [64, 4096]");
@@ -294,9 +297,13 @@ int pg_build_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, 
   }
   PG_TRY(use_device(ctx));
   hipStream_t s = (hipStream_t)stream;
+  if (oriented) PG_TRY(graph_oriented(g, s));
+  pg_graph* rows = oriented ? g->oriented : g;
   pg_sketches* sk = new (std::nothrow) pg_sketches();
   if (!sk) return fail(PG_E_NOMEM, "host allocation failed");
   sk->g = g;
+  sk->rows = rows;
+  sk->oriented = oriented;
   sk->kind = kind;
   sk->size = size;
   sk->b = b;
@@ -319,7 +326,7 @@ int pg_build_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, 
     if (rc == PG_OK) rc = palloc((void**)&sk->pc, sizeof(uint32_t) * n);
     if (rc == PG_OK) rc = palloc((void**)&sk->table, sizeof(double) * (size + 1));
     if (rc == PG_OK)
-      rc = palloc((void**)&sk->scratch, sizeof(uint64_t) * sk->W * (size_t)std::max<int64_t>(g->plan_all.n_chunks, 1));
+      rc = palloc((void**)&sk->scratch, sizeof(uint64_t) * sk->W * (size_t)std::max<int64_t>(rows->plan_all.n_chunks, 1));
 
     if (rc == PG_OK && g->n > 0) rc = build_bf(sk, s);
   } else {
@@ -369,7 +376,7 @@ int pg_sketches_destroy(pg_sketches* sk) {
 int pg_sketches_get_info(const pg_sketches* sk, pg_sketch_info* out) {
   clear_error();
   if (!sk || !out) return fail(PG_E_INVALID, "NULL argument");
-  out->kind = sk->kind;
+  out->kind = sk->kind | (sk->oriented ? PG_ORIENTED : 0);
   out->size = sk->size;
   out->b = sk->b;
   out->seed = sk->seed;

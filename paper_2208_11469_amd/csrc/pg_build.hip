@@ -411,7 +411,7 @@ __global__ void k_bf_unpack(const uint64_t* __restrict__ words, int64_t n, uint3
 }  // namespace
 
 int bf_unpack(const pg_sketches* sk, void* rows, hipStream_t s) {
-  const int64_t n = sk->g->n;
+  const int64_t n = sk->rows->n;
   if (n <= 0) return PG_OK;
   hipLaunchKernelGGL(k_bf_unpack, dim3(grid_for(n * sk->W, kBlock, 65536)), dim3(kBlock), 0, s,
                      (const uint64_t*)sk->words, n, sk->W, (uint64_t*)rows);
@@ -420,7 +420,7 @@ int bf_unpack(const pg_sketches* sk, void* rows, hipStream_t s) {
 }
 
 int build_bf(pg_sketches* sk, hipStream_t s) {
-  const pg_graph* g = sk->g;
+  const pg_graph* g = sk->rows;  // the lists the rows sketch (N_v or N+_v)
   ProfScope ps(s, "bf_build");
   const uint32_t W = sk->W;
   if (W <= 16 && g->n > 0) {
@@ -467,7 +467,7 @@ int build_bf(pg_sketches* sk, hipStream_t s) {
 }
 
 int build_khash(pg_sketches* sk, hipStream_t s) {
-  const pg_graph* g = sk->g;
+  const pg_graph* g = sk->rows;  // the lists the rows sketch (N_v or N+_v)
   ProfScope ps(s, "kh_build");
   for (int bin = 0; bin < kNumBins; ++bin) {
     const int64_t cnt = g->bin_start[bin + 1] - g->bin_start[bin];
@@ -493,7 +493,7 @@ int build_khash(pg_sketches* sk, hipStream_t s) {
 }
 
 int build_onehash(pg_sketches* sk, hipStream_t s) {
-  const pg_graph* g = sk->g;
+  const pg_graph* g = sk->rows;  // the lists the rows sketch (N_v or N+_v)
   const int64_t nv = g->n;
   if (nv <= 0) return PG_OK;
   const size_t shmem = (size_t)kOhWaves * oh_wave_bytes(sk->size);

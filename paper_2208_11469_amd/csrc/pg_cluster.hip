@@ -130,7 +130,9 @@ int clusters(const pg_graph* g, const uint8_t* keep, int32_t* label, unsigned lo
                        label, (int64_t)g->n + 1, d_count + 1);
     PG_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_uf_flatten, dim3(grid_for(g->n, kBlock, 65536)), dim3(kBlock), 0, s, label, g->n, d_count);
+  // a few blocks per CU: each block adds its root count to one shared counter
+  const unsigned flat_grid = grid_for(g->n, kBlock, (int64_t)std::max(1, g->ctx->num_cus) * 8);
+  hipLaunchKernelGGL(k_uf_flatten, dim3(flat_grid), dim3(kBlock), 0, s, label, g->n, d_count);
   PG_LAUNCH_CHECK();
   return PG_OK;
 }

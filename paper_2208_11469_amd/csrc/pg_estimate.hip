@@ -24,6 +24,9 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kChunkItems = 8;
 constexpr int64_t kChunk = (int64_t)kBlock * kChunkItems;  // pairs per chunk partial
+constexpr int kCountBlocksPerCu = 8;  // grid of kernels that count into one global counter
+constexpr const char* kOrientedNeedsNv =
+    "defined on N_v: an oriented sketch set (PG_ORIENTED) serves intersections and the triangle count";
 
 // ---- kernels -------------------------------------------------------------------
 
@@ -626,7 +629,7 @@ SkView make_view(const pg_sketches* sk, int est) {
   v.pc = sk->pc;
   v.sig = sk->sig;
   v.table = sk->table;
-  v.deg = sk->g->deg;
+  v.deg = sk->rows->deg;  // sizes of the sketched sets: d_v, or d+_v for oriented rows
   if (sk->kind == PG_MH_1HASH) hash_constants(PG_MH_1HASH, sk->seed, 1, &v.a1, &v.c1);
   return v;
 }
@@ -660,6 +663,7 @@ int ensure_table(pg_sketches* sk, int est, hipStream_t s) {
 int estimate_pairs(const pg_sketches* sk, int est, const int32_t* u, const int32_t* v, int64_t npairs,
                    double* est_out, uint32_t* raw_out, float* sim_out, int measure, hipStream_t s) {
   PG_TRY(check_estimator(sk, est));
+  if (sim_out && sk->oriented) return fail(PG_E_UNSUPPORTED, kOrientedNeedsNv);
   if (sim_out && (measure < PG_SIM_COMMON || measure > PG_SIM_TOTAL))
     return fail(PG_E_INVALID, "unknown similarity measure");
   PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
@@ -679,13 +683,16 @@ int estimate_pairs(const pg_sketches* sk, int est, const int32_t* u, const int32
 int estimate_jp(const pg_sketches* sk, int est, int measure, double tau, uint8_t* keep, unsigned long long* d_kept,
                 hipStream_t s) {
   PG_TRY(check_estimator(sk, est));
+  if (sk->oriented) return fail(PG_E_UNSUPPORTED, kOrientedNeedsNv);
   if (measure < PG_SIM_COMMON || measure > PG_SIM_TOTAL) return fail(PG_E_INVALID, "unknown similarity measure");
   PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
   PG_TRY(fill_u64((uint64_t*)d_kept, 0, 1, s));
   const pg_graph* g = sk->g;
   if (g->m <= 0) return PG_OK;
   const SkView view = make_view(sk, est);
-  const unsigned grid = grid_for(g->m, kBlock, 65536);
+  // a few blocks per CU: every block adds its count to one shared counter,
+  // and device-scope atomics on one address serialise
+  const unsigned grid = grid_for(g->m, kBlock, (int64_t)std::max(1, g->ctx->num_cus) * kCountBlocksPerCu);
   const int32_t* eu = g->eu;
   const int32_t* ev = g->ev;
   const int64_t m = g->m;
@@ -719,6 +726,9 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
   PG_TRY(check_estimator(sk, est));
   PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
   const pg_graph* g = sk->g;
+  // every kernel below sums the estimate over the m edges, each once: a triangle
+  // contributes three edges over N_v, one over N+_v (Listing "lst:tc")
+  const double divisor = sk->oriented ? 1.0 : 3.0;
   if (sk->kind == PG_BF && sk->W <= 16 && g->n > 0) {
     PG_TRY(graph_slabs(const_cast<pg_graph*>(g), s));
     const SlabPlan& P = g->slabs;
@@ -760,7 +770,7 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
 #undef PG_TCP
       PG_LAUNCH_CHECK();
     }
-    PG_TRY(sum_chunks(partials, nblk, 3.0, d_out, s));
+    PG_TRY(sum_chunks(partials, nblk, divisor, d_out, s));
     return dfree(partials, s);
   }
   if (sk->kind == PG_MH_1HASH && g->n > 0) {
@@ -784,7 +794,7 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
         return PG_OK;
       }));
     }
-    PG_TRY(sum_chunks(partials, nparts, 3.0, d_out, s));
+    PG_TRY(sum_chunks(partials, nparts, divisor, d_out, s));
     return dfree(partials, s);
   }
   // general path: one lane per upper edge, fixed chunks
@@ -793,12 +803,13 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
   PG_TRY(dmalloc((void**)&chunks, sizeof(double) * (size_t)nchunks, s));
   PG_TRY(fill_u64((uint64_t*)chunks, 0, nchunks, s));
   if (g->m > 0) PG_TRY(estimate_sum(sk, est, g->eu, g->ev, g->m, chunks, s));
-  PG_TRY(sum_chunks(chunks, nchunks, 3.0, d_out, s));
+  PG_TRY(sum_chunks(chunks, nchunks, divisor, d_out, s));
   return dfree(chunks, s);
 }
 
 int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStream_t s) {
   PG_TRY(check_estimator(sk, est));
+  if (sk->oriented) return fail(PG_E_UNSUPPORTED, kOrientedNeedsNv);
   PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
   const pg_graph* g = sk->g;
   const SkView view = make_view(sk, est);

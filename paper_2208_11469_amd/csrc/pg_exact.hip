@@ -386,7 +386,9 @@ int exact_jp(const pg_graph* g, int algo, int measure, double tau, uint8_t* keep
   int rc = exact_pairs(g, algo, g->eu, g->ev, g->m, inter, s);
   if (rc == PG_OK) {
     ProfScope ps(s, "exact_jarvis_patrick");
-    hipLaunchKernelGGL(k_exact_jp, dim3(grid_for(g->m, kBlock, 65536)), dim3(kBlock), 0, s, inter, g->deg, g->eu,
+    // a few blocks per CU: each block adds its count to one shared counter
+    const unsigned grid = grid_for(g->m, kBlock, (int64_t)std::max(1, g->ctx->num_cus) * 8);
+    hipLaunchKernelGGL(k_exact_jp, dim3(grid), dim3(kBlock), 0, s, inter, g->deg, g->eu,
                        g->ev, g->m, measure, tau, keep, d_kept);
     if (hipGetLastError() != hipSuccess) rc = fail(PG_E_DEVICE, "k_exact_jp launch failed");
   }

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <new>
 #include <vector>
 
 #include "pg_device.h"
@@ -741,6 +742,31 @@ int build_plan(pg_graph* g, VertexPlan* P, hipStream_t s) {
   return PG_OK;
 }
 
+// Degrees from the offsets, the largest degree, sum_v C(d_v, 2), and the
+// stable partition of the vertices by degree bin. d_maxdeg and d_wedges are
+// zeroed device scratch.
+static int degrees_and_bins(pg_graph* g, int* d_maxdeg, unsigned long long* d_wedges, hipStream_t s) {
+  const int32_t n = g->n;
+  PG_TRY(palloc((void**)&g->deg, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
+  if (n > 0) {
+    hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, g->off, n, g->deg, d_maxdeg,
+                       d_wedges);
+    PG_LAUNCH_CHECK();
+  }
+  PG_TRY(palloc((void**)&g->bin_verts, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
+  int64_t hbase[kNumBins + 1] = {};
+  PG_TRY(partition(g, false, g->bin_verts, hbase, s));
+  int h_max = 0;
+  unsigned long long h_wedges = 0;
+  PG_HIP(hipMemcpyAsync(&h_max, d_maxdeg, sizeof(int), hipMemcpyDeviceToHost, s));
+  PG_HIP(hipMemcpyAsync(&h_wedges, d_wedges, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j <= kNumBins; ++j) g->bin_start[j] = hbase[j];
+  g->max_degree = h_max;
+  g->wedges = h_wedges;
+  return PG_OK;
+}
+
 int graph_prepare(pg_graph* g, bool validate, hipStream_t s) {
   const int32_t n = g->n;
   int* d_flags = nullptr;
@@ -789,26 +815,8 @@ int graph_prepare(pg_graph* g, bool validate, hipStream_t s) {
     return fail(PG_E_GRAPH, "CSR rejected:" + why);
   }
 
-  // 2. degrees, max degree, wedge count
-  PG_TRY(palloc((void**)&g->deg, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
-  if (n > 0) {
-    hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, g->off, n, g->deg, d_maxdeg,
-                       d_wedges);
-    PG_LAUNCH_CHECK();
-  }
-
-  // 3. degree bins (stable)
-  PG_TRY(palloc((void**)&g->bin_verts, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
-  int64_t hbase[kNumBins + 1] = {};
-  PG_TRY(partition(g, false, g->bin_verts, hbase, s));
-  int h_max = 0;
-  unsigned long long h_wedges = 0;
-  PG_HIP(hipMemcpyAsync(&h_max, d_maxdeg, sizeof(int), hipMemcpyDeviceToHost, s));
-  PG_HIP(hipMemcpyAsync(&h_wedges, d_wedges, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-  PG_HIP(hipStreamSynchronize(s));
-  for (int j = 0; j <= kNumBins; ++j) g->bin_start[j] = hbase[j];
-  g->max_degree = h_max;
-  g->wedges = h_wedges;
+  // 2-3. degrees, max degree, wedge count, degree bins
+  PG_TRY(degrees_and_bins(g, d_maxdeg, d_wedges, s));
 
   // 4. upper edges: ustart, upper-edge offsets, (eu, ev) in CSR order
   int64_t* up = nullptr;
@@ -874,6 +882,35 @@ int graph_orient(pg_graph* g, hipStream_t s) {
                      (int64_t)n + 1);
   PG_LAUNCH_CHECK();
   return dfree(cnt, s);
+}
+
+int graph_oriented(pg_graph* g, hipStream_t s) {
+  if (g->oriented) return PG_OK;
+  PG_TRY(graph_orient(g, s));
+  pg_graph* o = new (std::nothrow) pg_graph();
+  if (!o) return fail(PG_E_NOMEM, "host allocation failed");
+  o->ctx = g->ctx;
+  o->n = g->n;
+  o->nnz = g->m;  // every undirected edge once, at its lower-ranked end
+  o->owns_csr = false;
+  o->off = g->poff;
+  o->adj = g->padj;
+  int* d_scratch = nullptr;
+  int rc = dmalloc((void**)&d_scratch, 64, s);
+  if (rc == PG_OK && hipMemsetAsync(d_scratch, 0, 64, s) != hipSuccess) rc = fail(PG_E_DEVICE, "hipMemsetAsync failed");
+  if (rc == PG_OK) rc = degrees_and_bins(o, d_scratch + 1, (unsigned long long*)(d_scratch + 2), s);
+  if (rc == PG_OK) rc = build_plan(o, &o->plan_all, s);
+  if (d_scratch) dfree(d_scratch, s);
+  if (rc != PG_OK) {
+    (void)hipStreamSynchronize(s);
+    pfree(o->deg);
+    pfree(o->bin_verts);
+    free_plan(&o->plan_all);
+    delete o;
+    return rc;
+  }
+  g->oriented = o;
+  return PG_OK;
 }
 
 void free_slabs(SlabPlan* p) {

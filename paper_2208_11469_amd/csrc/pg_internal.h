@@ -211,11 +211,16 @@ struct pg_graph {
   int32_t* poff = nullptr;     // [n+1]
   int32_t* padj = nullptr;     // [m]
   int32_t* parc_src = nullptr; // [m]
+  // the oriented lists as a graph of their own (off/adj borrow poff/padj; own
+  // degrees d+, degree bins and plan_all), built on first use by oriented sketches
+  pg_graph* oriented = nullptr;
   int live_sketches = 0;
 };
 
 struct pg_sketches {
-  pg_graph* g = nullptr;
+  pg_graph* g = nullptr;     // the graph: its edges are the pairs of TC and the all-edge calls
+  pg_graph* rows = nullptr;  // whose lists the rows sketch: g, or g->oriented (PG_ORIENTED)
+  bool oriented = false;
   int kind = 0;
   uint32_t size = 0;   // B or k
   uint32_t b = 1;
@@ -237,6 +242,7 @@ namespace pg {
 int graph_prepare(pg_graph* g, bool validate, hipStream_t s);
 int graph_arc_sources(pg_graph* g, hipStream_t s);
 int graph_orient(pg_graph* g, hipStream_t s);
+int graph_oriented(pg_graph* g, hipStream_t s);  // g->oriented (and the oriented CSR) on first use
 int graph_slabs(pg_graph* g, hipStream_t s);
 int build_plan(pg_graph* g, pg::VertexPlan* plan, hipStream_t s);
 void free_plan(pg::VertexPlan* plan);

@@ -272,8 +272,11 @@ int pg_server_create(pg_ctx* ctx, const pg_graph* g, pg_sketches* const* sketche
   if (!ctx || !g || !out || (nsketches > 0 && !sketches)) return fail(PG_E_INVALID, "NULL argument");
   *out = nullptr;
   if (nsketches < 1 || nsketches > 64) return fail(PG_E_INVALID, "nsketches must be in [1, 64]");
-  for (int i = 0; i < nsketches; ++i)
+  for (int i = 0; i < nsketches; ++i) {
     if (!sketches[i] || sketches[i]->g != g) return fail(PG_E_INVALID, "every sketch set must be built on the graph");
+    if (sketches[i]->oriented)
+      return fail(PG_E_UNSUPPORTED, "servers answer queries on N_v; an oriented sketch set sketches N+_v");
+  }
   PG_HIP(hipSetDevice(ctx->device));
   pg_server* srv = new (std::nothrow) pg_server();
   if (!srv) return fail(PG_E_NOMEM, "host allocation failed");
