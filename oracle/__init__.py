@@ -30,7 +30,7 @@ BOTTOM = 0xFFFFFFFF
 KIND_BF, KIND_KH, KIND_1H = 1, 2, 3
 
 BF_ESTIMATORS = ("and", "l", "or", "pap")
-MH_ESTIMATORS = {"kh": KIND_KH, "1h": KIND_1H, "1h_lit": KIND_1H}
+MH_ESTIMATORS = {"kh": KIND_KH, "1h": KIND_1H, "1h_lit": KIND_1H, "kmv": KIND_1H, "kmv_est": KIND_1H}
 
 
 def build() -> str:
@@ -307,7 +307,32 @@ class Sketches:
         if est == "1h_lit":
             _, _, sl = self.counts(u, v)
             return est_minhash(sl, self.size, du, dv)
+        if est in ("kmv", "kmv_est"):
+            return self.kmv_estimate(u, v, est)
         raise ValueError(f"estimator {est} does not apply to 1-hash sketches")
+
+    def kmv_keys(self):
+        """Per row, the MinHash keys of its elements (ascending: a 1-hash row
+        lists its elements in key order); empty slots are dropped."""
+        a, c = hash_consts(KIND_1H, self.seed, 1)
+        out = []
+        for v in range(self.sig.shape[0]):
+            row = self.sig[v]
+            row = row[row != BOTTOM]
+            out.append(mh_keys(int(a[0]), int(c[0]), row))
+        return out
+
+    def kmv_estimate(self, u, v, est: str) -> np.ndarray:
+        """KMV estimate of |N_u cap N_v| from the rows' keys (Section "Beyond
+        Bloom Filter and MinHash", Appendix "KMV Sketches"); parity: see
+        kmv_intersection."""
+        keys = self.kmv_keys()
+        u, v = _i32(u), _i32(v)
+        out = np.empty(u.shape[0], dtype=np.float64)
+        for i in range(u.shape[0]):
+            out[i] = kmv_intersection(keys[u[i]], keys[v[i]], self.size, int(self.deg[u[i]]),
+                                      int(self.deg[v[i]]), est == "kmv")
+        return out
 
 
 def build_sketches(g, kind: int, size: int, b: int = 1, seed: int = 1) -> Sketches:
@@ -359,6 +384,71 @@ def jaccard(sk: Sketches, est: str, u, v) -> np.ndarray:
     """Estimated Jaccard similarity (Listing "lst:sim") per pair."""
     u, v = _i32(u), _i32(v)
     return jaccard_from_intersection(sk.deg[u], sk.deg[v], sk.estimate(u, v, est))
+
+
+# ---------------------------------------------------------------- KMV
+
+def _mix64(z):
+    """SplitMix64's output mix (Steele, Lea, Flood 2014) on uint64 arrays."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def mh_keys(a: int, c: int, xs) -> np.ndarray:
+    """MinHash keys mix64(a x + c mod 2^64) of the IDs xs (the array form of mh_key)."""
+    xs = np.asarray(xs, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return _mix64(np.uint64(a) * xs + np.uint64(c))
+
+
+def kmv_hash(keys) -> np.ndarray:
+    """The KMV hash h: X -> (0, 1] (Section "Beyond Bloom Filter and MinHash"):
+    the top 53 bits of the MinHash key, plus one, times 2^-53."""
+    k = np.asarray(keys, dtype=np.uint64)
+    return ((k >> np.uint64(11)) + np.uint64(1)).astype(np.float64) * 2.0 ** -53
+
+
+def kmv_of_set(xs, k: int, seed: int) -> np.ndarray:
+    """K_X: the k smallest hashes of the elements of X (all when |X| <= k), ascending."""
+    a, c = hash_consts(KIND_1H, seed, 1)
+    keys = np.sort(mh_keys(int(a[0]), int(c[0]), np.unique(np.asarray(xs, dtype=np.int64))))
+    return kmv_hash(keys[:k])
+
+
+def kmv_size(kx, k: int) -> float:
+    """|X|^ = (k - 1) / max K_X (Eq. "est_ss_kmv"). A KMV holding fewer than k
+    values holds the whole set, and its size is that count."""
+    kx = np.asarray(kx, dtype=np.float64)
+    if kx.shape[0] < k:
+        return float(kx.shape[0])
+    return (k - 1) / float(kx[k - 1])
+
+
+def kmv_intersection(kx, ky, k: int, dx: int, dy: int, exact_sizes: bool) -> float:
+    """KMV estimate of |X cap Y| from the sorted keys of the two rows.
+
+    The union sketch K_{X u Y} is the k smallest values of K_X u K_Y (values
+    are the injective 64-bit keys, so equal keys are the same element), and
+    |X u Y|^ = (k - 1) / max K_{X u Y}; if both rows hold fewer than k values
+    they hold the whole sets, and the union is counted. Then
+    |X cap Y|^ = |X| + |Y| - |X u Y|^ with the exact sizes d_X, d_Y
+    (Eq. "est_inter_set_kmv_exactsets", exact_sizes=True) or with the KMV size
+    estimates (Eq. "est_inter_set_kmv"). An empty set gives 0."""
+    if dx == 0 or dy == 0:
+        return 0.0
+    kx = np.asarray(kx, dtype=np.uint64)
+    ky = np.asarray(ky, dtype=np.uint64)
+    union = np.union1d(kx, ky)
+    if kx.shape[0] < k and ky.shape[0] < k:
+        u_hat = float(union.shape[0])
+    else:
+        u_hat = (k - 1) / float(kmv_hash(union[k - 1:k])[0])
+    if exact_sizes:
+        return (float(dx) + float(dy)) - u_hat
+    return (kmv_size(kmv_hash(kx), k) + kmv_size(kmv_hash(ky), k)) - u_hat
 
 
 # ---------------------------------------------------------------- oriented sketches
