@@ -367,6 +367,17 @@ def main():
                                        "intersections_per_s": m / ((ms_b + ms_t) * 1e-3), "tc": tco,
                                        "rel_err": abs(tco - exact_tc) / exact_tc}
         sko.close()
+        # KMV estimators on 1-hash rows, k = 32 (per-pair union walk), full and oriented sets
+        for key, oriented in (("kmv32_tc", False), ("kmv32_oriented_tc", True)):
+            skm = dg.build_sketches("1h", 32, seed=args.seed, oriented=oriented)
+            ms_b = timed(lambda: skm.rebuild(), reps, sync)
+            ms_t = timed(lambda: skm.tc("kmv"), reps, sync)
+            tcm = skm.tc("kmv")
+            rows[key] = {"build_ms": round(ms_b, 4), "tc_ms": round(ms_t, 4),
+                         "intersections_per_s": m / ((ms_b + ms_t) * 1e-3), "tc": tcm,
+                         "rel_err": abs(tcm - exact_tc) / exact_tc,
+                         "tc_1hash_union": skm.tc("1h"), "tc_kmv_sketch_sizes": skm.tc("kmv_est")}
+            skm.close()
         # clustering coefficient and Jaccard (BF AND, b = 1)
         ms = timed(lambda: sk.cc("and"), reps, sync)
         rows["bf_cc"] = {"ms": round(ms, 4), "arc_intersections_per_s": nnz / (ms * 1e-3)}

@@ -64,6 +64,13 @@ extern "C" {
 #define PG_EST_MH_KHASH 5         /* s = #positions i with M_X[i] = M_Y[i]; J = s/k; I = J/(1+J)(|X|+|Y|): Eq. "est_int_mh" */
 #define PG_EST_MH_1HASH 6         /* s = |U cap M_X cap M_Y|, U = bottom-k' of M_X u M_Y, k' = min(k, |M_X u M_Y|); J = s/k' (Section 4.4) */
 #define PG_EST_MH_1HASH_LITERAL 7 /* s = |M_X cap M_Y|, J = s/k (Section 4.4, as printed) */
+/* KMV (Section "Beyond Bloom Filter and MinHash") on 1-hash rows: the KMV of X
+ * is the hashes h(x) = ((key(x) >> 11) + 1) * 2^-53 of the row's elements (the
+ * k smallest keys of X). K_{X u Y} = the k smallest of K_X u K_Y, and
+ * |X u Y|^ = (k - 1) / max K_{X u Y}; when both rows hold fewer than k values
+ * they hold the whole sets and the union is counted. An empty set gives 0. */
+#define PG_EST_KMV 8              /* |X| + |Y| - |X u Y|^, exact sizes: Eq. "est_inter_set_kmv_exactsets" */
+#define PG_EST_KMV_SKETCH_SIZES 9 /* |X|^ + |Y|^ - |X u Y|^, |X|^ = (k - 1) / max K_X (or the count below k): Eq. "est_inter_set_kmv" */
 
 /* ---- graph flags -------------------------------------------------------- */
 #define PG_MEM_HOST 0u   /* offsets/adj are host pointers (copied to the device) */
@@ -159,7 +166,8 @@ int pg_sketches_export(const pg_sketches* sk, void* rows, uint32_t* pc, void* st
 
 /* Estimate |N_u cap N_v| for npairs pairs (u[i], v[i]); u = v = NULL means the
  * graph's m upper edges in CSR order (npairs ignored). est (FP64) and raw
- * (the integer count the estimator consumes: c, c_or or s) may each be NULL.
+ * (the integer count the estimator consumes: c, c_or or s; for the KMV
+ * estimators min(k, |M_u u M_v|)) may each be NULL.
  * The estimator must match the sketch kind. */
 int pg_intersect_edges(pg_ctx* ctx, const pg_sketches* sk, int estimator, const int32_t* u, const int32_t* v,
                        int64_t npairs, double* est, uint32_t* raw, void* stream);

@@ -314,12 +314,16 @@ class Sketches:
     def kmv_keys(self):
         """Per row, the MinHash keys of its elements (ascending: a 1-hash row
         lists its elements in key order); empty slots are dropped."""
+        cached = self.__dict__.get("_kmv_keys")
+        if cached is not None:
+            return cached
         a, c = hash_consts(KIND_1H, self.seed, 1)
         out = []
         for v in range(self.sig.shape[0]):
             row = self.sig[v]
             row = row[row != BOTTOM]
             out.append(mh_keys(int(a[0]), int(c[0]), row))
+        self.__dict__["_kmv_keys"] = out
         return out
 
     def kmv_estimate(self, u, v, est: str) -> np.ndarray:

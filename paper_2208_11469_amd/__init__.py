@@ -38,6 +38,8 @@ PG_EST_BF_PAPAPETROU = 4
 PG_EST_MH_KHASH = 5
 PG_EST_MH_1HASH = 6
 PG_EST_MH_1HASH_LITERAL = 7
+PG_EST_KMV = 8
+PG_EST_KMV_SKETCH_SIZES = 9
 # graph flags
 PG_MEM_HOST = 0
 PG_MEM_DEVICE = 1
@@ -55,6 +57,7 @@ PG_SIM_TOTAL = 3
 ESTIMATORS = {
     "and": PG_EST_BF_AND, "l": PG_EST_BF_L, "or": PG_EST_BF_OR, "pap": PG_EST_BF_PAPAPETROU,
     "kh": PG_EST_MH_KHASH, "1h": PG_EST_MH_1HASH, "1h_lit": PG_EST_MH_1HASH_LITERAL,
+    "kmv": PG_EST_KMV, "kmv_est": PG_EST_KMV_SKETCH_SIZES,
 }
 KINDS = {"bf": PG_BF, "kh": PG_MH_KHASH, "1h": PG_MH_1HASH}
 SIMILARITIES = {"cn": PG_SIM_COMMON, "jaccard": PG_SIM_JACCARD, "overlap": PG_SIM_OVERLAP, "total": PG_SIM_TOTAL}

@@ -25,6 +25,10 @@ constexpr int kBlock = 256;
 constexpr int kChunkItems = 8;
 constexpr int64_t kChunk = (int64_t)kBlock * kChunkItems;  // pairs per chunk partial
 constexpr int kCountBlocksPerCu = 8;  // grid of kernels that count into one global counter
+// The vertex-centric 1-hash kernels count matches of the union walk (union
+// and literal readings); the KMV estimators take the general per-pair path.
+inline bool is_minhash_ratio(int est) { return est == PG_EST_MH_1HASH || est == PG_EST_MH_1HASH_LITERAL; }
+
 constexpr const char* kOrientedNeedsNv =
     "defined on N_v: an oriented sketch set (PG_ORIENTED) serves intersections and the triangle count";
 
@@ -638,7 +642,9 @@ int check_estimator(const pg_sketches* sk, int est) {
   const bool bf = est == PG_EST_BF_AND || est == PG_EST_BF_L || est == PG_EST_BF_OR || est == PG_EST_BF_PAPAPETROU;
   if (sk->kind == PG_BF && bf) return PG_OK;
   if (sk->kind == PG_MH_KHASH && est == PG_EST_MH_KHASH) return PG_OK;
-  if (sk->kind == PG_MH_1HASH && (est == PG_EST_MH_1HASH || est == PG_EST_MH_1HASH_LITERAL)) return PG_OK;
+  if (sk->kind == PG_MH_1HASH && (est == PG_EST_MH_1HASH || est == PG_EST_MH_1HASH_LITERAL || est == PG_EST_KMV ||
+                                  est == PG_EST_KMV_SKETCH_SIZES))
+    return PG_OK;
   return fail(PG_E_INVALID, "estimator does not match the sketch kind");
 }
 
@@ -773,7 +779,7 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
     PG_TRY(sum_chunks(partials, nblk, divisor, d_out, s));
     return dfree(partials, s);
   }
-  if (sk->kind == PG_MH_1HASH && g->n > 0) {
+  if (sk->kind == PG_MH_1HASH && is_minhash_ratio(est) && g->n > 0) {
     PG_TRY(graph_slabs(const_cast<pg_graph*>(g), s));
     const SlabPlan& P = g->slabs;
     int64_t busiest = 0;
@@ -814,7 +820,7 @@ int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStre
   const pg_graph* g = sk->g;
   const SkView view = make_view(sk, est);
   ProfScope ps(s, "cc");
-  if (sk->kind == PG_MH_1HASH) {
+  if (sk->kind == PG_MH_1HASH && is_minhash_ratio(est)) {
     const VertexPlan& P = g->plan_all;
     const PlanView pv = plan_view(P);
     const int64_t nblk = P.n_chunks + pv.n_medium_blocks + (P.n_light + 3) / 4;

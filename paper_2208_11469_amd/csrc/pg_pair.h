@@ -73,14 +73,18 @@ __device__ __forceinline__ uint32_t kh_matches(const uint32_t* __restrict__ mu, 
 //   common      = |M_u cap M_v|
 //   kprime      = min(k, |M_u cup M_v|)
 //   s_union     = commons among the kprime smallest of the union
+//   kth_key     = key of the k-th smallest element of the union (~0 if fewer)
 __device__ __forceinline__ void oh_counts(const uint32_t* __restrict__ mu, const uint32_t* __restrict__ mv, uint32_t k,
                                           uint32_t nu, uint32_t nv, uint64_t a, uint64_t c, uint32_t& s_union,
-                                          uint32_t& kprime, uint32_t& common) {
+                                          uint32_t& kprime, uint32_t& common, uint64_t& kth_key) {
   uint32_t i = 0, j = 0, rank = 0, com = 0, com_k = 0;
   uint64_t ku = nu ? mh_key(a, c, mu[0]) : ~0ull;
   uint64_t kv = nv ? mh_key(a, c, mv[0]) : ~0ull;
+  uint64_t kth = ~0ull;
   while (i < nu || j < nv) {
+    uint64_t cur;
     if (i < nu && j < nv && mu[i] == mv[j]) {
+      cur = ku;
       com_k += rank < k ? 1u : 0u;
       ++com;
       ++i;
@@ -88,18 +92,43 @@ __device__ __forceinline__ void oh_counts(const uint32_t* __restrict__ mu, const
       ku = i < nu ? mh_key(a, c, mu[i]) : ~0ull;
       kv = j < nv ? mh_key(a, c, mv[j]) : ~0ull;
     } else if (j >= nv || (i < nu && ku < kv)) {
+      cur = ku;
       ++i;
       ku = i < nu ? mh_key(a, c, mu[i]) : ~0ull;
     } else {
+      cur = kv;
       ++j;
       kv = j < nv ? mh_key(a, c, mv[j]) : ~0ull;
     }
+    if (rank + 1 == k) kth = cur;
     ++rank;
   }
   const uint32_t uni = nu + nv - com;
   kprime = uni < k ? uni : k;
   s_union = uni >= k ? com_k : com;
   common = com;
+  kth_key = kth;
+}
+
+// KMV hash in (0, 1]: the top 53 bits of a MinHash key, plus one, times 2^-53.
+__device__ __forceinline__ double kmv_hash(uint64_t key) {
+  return (double)((key >> 11) + 1ull) * 0x1.0p-53;
+}
+
+// KMV estimate of |X cap Y| (Section "Beyond Bloom Filter and MinHash",
+// Eqs. "est_inter_set_kmv_exactsets" and "est_inter_set_kmv"): nx, ny values
+// in the rows (min(k, d)), uni = |M_X u M_Y|, kth_key the k-th smallest union
+// key, max_x / max_y the largest key of each row.
+__device__ __forceinline__ double kmv_estimate(bool exact_sizes, uint32_t k, int32_t dx, int32_t dy, uint32_t nx,
+                                               uint32_t ny, uint32_t uni, uint64_t kth_key, uint64_t max_x,
+                                               uint64_t max_y) {
+  if (dx == 0 || dy == 0) return 0.0;
+  const double km1 = (double)k - 1.0;
+  const double u_hat = (nx < k && ny < k) ? (double)uni : km1 / kmv_hash(kth_key);
+  if (exact_sizes) return ((double)dx + (double)dy) - u_hat;
+  const double sx = nx < k ? (double)nx : km1 / kmv_hash(max_x);
+  const double sy = ny < k ? (double)ny : km1 / kmv_hash(max_y);
+  return (sx + sy) - u_hat;
 }
 
 // J^ = s / kk, I^ = J^ / (1 + J^) (|X| + |Y|)  (Eq. "est_int_mh", Section 4.4)
@@ -133,7 +162,17 @@ __device__ __forceinline__ double eval_pair(const SkView& s, int32_t u, int32_t 
     const uint32_t nu = (uint32_t)du < s.size ? (uint32_t)du : s.size;
     const uint32_t nv = (uint32_t)dv < s.size ? (uint32_t)dv : s.size;
     uint32_t su, kp, com;
-    oh_counts(s.sig + (size_t)u * s.size, s.sig + (size_t)v * s.size, s.size, nu, nv, s.a1, s.c1, su, kp, com);
+    uint64_t kth;
+    const uint32_t* mu = s.sig + (size_t)u * s.size;
+    const uint32_t* mv = s.sig + (size_t)v * s.size;
+    oh_counts(mu, mv, s.size, nu, nv, s.a1, s.c1, su, kp, com, kth);
+    if (s.est == PG_EST_KMV || s.est == PG_EST_KMV_SKETCH_SIZES) {
+      raw = kp;
+      const bool exact_sizes = s.est == PG_EST_KMV;
+      const uint64_t max_u = (!exact_sizes && nu) ? mh_key(s.a1, s.c1, mu[nu - 1]) : 0ull;
+      const uint64_t max_v = (!exact_sizes && nv) ? mh_key(s.a1, s.c1, mv[nv - 1]) : 0ull;
+      return kmv_estimate(exact_sizes, s.size, du, dv, nu, nv, nu + nv - com, kth, max_u, max_v);
+    }
     if (s.est == PG_EST_MH_1HASH_LITERAL) {
       raw = com;
       return minhash_estimate(com, s.size, du, dv);
