@@ -61,6 +61,7 @@ def _load():
         "or_upper_edges": (i64, [i32, i32p, i32p, i32p, i32p]),
         "or_exact_pairs": (None, [i32, i32p, i32p, i64, i32p, i32p, u32p]),
         "or_exact_tc_listing": (u64, [i32, i32p, i32p]),
+        "or_four_cliques": (u64, [i32, i32p, i32p, i32p, ctypes.c_void_p, u32, u32, u64]),
         "or_bf_build": (None, [i32, i32p, i32p, u32, u32, u64, u64p, u32p]),
         "or_bf_of_set": (None, [i32, i32p, u32, u32, u64, u64p]),
         "or_bf_counts": (None, [u32, u64p, i64, i32p, i32p, u32p, u32p]),
@@ -473,6 +474,34 @@ def oriented(g):
     adj = dst[keep].astype(np.int32)  # CSR order: by source, then ascending ID
     return types.SimpleNamespace(n=g.n, offsets=off, adj=adj, nnz=int(adj.shape[0]),
                                  degrees=lambda: lens.copy(), name=f"{getattr(g, 'name', '')}+")
+
+
+def four_cliques(g) -> int:
+    """Exact number of 4-cliques by the reformulated listing (Listing
+    "lst:fcl"): for every u and v in N+_u, C3 = N+_u cap N+_v, and for every w
+    in C3 add |N+_w cap C3| (each 4-clique once, at its three lowest-ranked
+    vertices)."""
+    o = oriented(g)
+    deg = _i32(np.diff(g.offsets))
+    po, pa = _i32(o.offsets), _i32(o.adj)
+    return int(_load().or_four_cliques(g.n, _ptr(po, ctypes.c_int32), _ptr(pa, ctypes.c_int32),
+                                       _ptr(deg, ctypes.c_int32), None, 64, 1, 0))
+
+
+def four_cliques_bf(g, sk_plus: Sketches) -> int:
+    """4-cliques with |N+_w cap C3| estimated from the Bloom filter of N+_w
+    (``sk_plus``: filters of the oriented sets): the number of x in C3 ranked
+    above w (the only elements N+_w can hold) that pass the membership query of
+    the filter. Membership queries have false positives only, so the estimate
+    is never below the exact count."""
+    assert sk_plus.kind == KIND_BF
+    o = oriented(g)
+    deg = _i32(np.diff(g.offsets))
+    po, pa = _i32(o.offsets), _i32(o.adj)
+    words = np.ascontiguousarray(sk_plus.words)
+    return int(_load().or_four_cliques(g.n, _ptr(po, ctypes.c_int32), _ptr(pa, ctypes.c_int32),
+                                       _ptr(deg, ctypes.c_int32), words.ctypes.data_as(ctypes.c_void_p),
+                                       sk_plus.size, sk_plus.b, sk_plus.seed & (2**64 - 1)))
 
 
 def tc_oriented(g, sk_plus: Sketches, est: str) -> float:

@@ -160,7 +160,78 @@ uint64_t or_exact_tc_listing(int32_t n, const int32_t* off, const int32_t* adj) 
   return tc;
 }
 
-/* ----------------------------------------------------------- Bloom filters */
+/* ------------------------------------------------------------- 4-cliques */
+
+static int or_rank_below(const int32_t* deg, int32_t v, int32_t u) {
+  return deg[v] < deg[u] || (deg[v] == deg[u] && v < u);
+}
+
+/* Reformulated 4-clique count (Listing "lst:fcl"). With the degree order R of
+ * the triangle count and the lists N+_v (ID order) given as poff/padj: for
+ * every u and v in N+_u, C3 = N+_u intersect N+_v; for every w in C3 add
+ * |N+_w intersect C3|. A 4-clique is counted once, at its three lowest-ranked
+ * vertices. deg holds the full degrees (the order R).
+ *
+ * With words != NULL (Bloom filters of the N+ sets: B bits, b hash functions
+ * of seed) |N+_w intersect C3| is replaced by the number of x in C3 ranked
+ * above w whose b bits are all set in the filter of N+_w: a membership query
+ * per element (Section 2.4), answered with false positives only. */
+uint64_t or_four_cliques(int32_t n, const int32_t* poff, const int32_t* padj, const int32_t* deg,
+                         const uint64_t* words, uint32_t B, uint32_t b, uint64_t seed) {
+  int32_t maxd = 0;
+  for (int32_t v = 0; v < n; ++v)
+    if (poff[v + 1] - poff[v] > maxd) maxd = poff[v + 1] - poff[v];
+  const uint32_t W = B / 64;
+  uint64_t a[64], c[64];
+  if (words) or_hash_consts(1, seed, (int)b, a, c);
+  uint64_t total = 0;
+#pragma omp parallel reduction(+ : total)
+  {
+    int32_t* c3 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(maxd > 0 ? maxd : 1));
+    int32_t u;
+#pragma omp for schedule(dynamic, 64)
+    for (u = 0; u < n; ++u) {
+      for (int32_t p = poff[u]; p < poff[u + 1]; ++p) {
+        const int32_t v = padj[p];
+        /* C3 by merging N+_u and N+_v (both in ID order) */
+        int32_t i = poff[u], j = poff[v], s = 0;
+        while (i < poff[u + 1] && j < poff[v + 1]) {
+          if (padj[i] < padj[j])
+            ++i;
+          else if (padj[i] > padj[j])
+            ++j;
+          else {
+            c3[s++] = padj[i];
+            ++i;
+            ++j;
+          }
+        }
+        for (int32_t t = 0; t < s; ++t) {
+          const int32_t w = c3[t];
+          if (!words) {
+            total += or_merge_count(padj + poff[w], poff[w + 1] - poff[w], c3, s);
+            continue;
+          }
+          const uint64_t* bw = words + (size_t)w * W;
+          for (int32_t q = 0; q < s; ++q) {
+            const int32_t x = c3[q];
+            if (!or_rank_below(deg, w, x)) continue;
+            int member = 1;
+            for (uint32_t h = 0; h < b && member; ++h) {
+              const uint32_t idx = or_bf_index(a[h], c[h], (uint32_t)x, B);
+              member = (int)((bw[idx >> 6] >> (idx & 63)) & 1ull);
+            }
+            total += (uint64_t)member;
+          }
+        }
+      }
+    }
+    free(c3);
+  }
+  return total;
+}
+
+/* ----------------------------------------------------------- Bloom filters *//* ----------------------------------------------------------- Bloom filters */
 
 /* B_v: B bits (W = B/64 words), for each x in N_v and each of the b hash
  * functions set bit idx_i(x) (Section 2.4, "Bloom filters"). pc[v] is the
