@@ -378,6 +378,15 @@ def main():
                          "rel_err": abs(tcm - exact_tc) / exact_tc,
                          "tc_1hash_union": skm.tc("1h"), "tc_kmv_sketch_sizes": skm.tc("kmv_est")}
             skm.close()
+        # 4-cliques: exact, and with membership queries on the filters of N+_v
+        sko = dg.build_sketches("bf", B, 1, seed=args.seed, oriented=True)
+        ck_bf = sko.four_cliques()
+        ms_bf = timed(lambda: sko.four_cliques(), 5, sync)
+        ck_ex = dg.exact_four_cliques()
+        ms_ex = timed(lambda: dg.exact_four_cliques(), 3, sync)
+        rows["four_cliques"] = {"bf_ms": round(ms_bf, 4), "exact_ms": round(ms_ex, 4), "bf": ck_bf, "exact": ck_ex,
+                                "rel_err": (ck_bf - ck_ex) / max(ck_ex, 1), "speedup_bf_vs_exact": ms_ex / ms_bf}
+        sko.close()
         # clustering coefficient and Jaccard (BF AND, b = 1)
         ms = timed(lambda: sk.cc("and"), reps, sync)
         rows["bf_cc"] = {"ms": round(ms, 4), "arc_intersections_per_s": nnz / (ms * 1e-3)}

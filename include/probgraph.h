@@ -257,6 +257,22 @@ int pg_exact_jarvis_patrick(pg_ctx* ctx, const pg_graph* g, int algo, int measur
 int pg_clusters(pg_ctx* ctx, const pg_graph* g, const uint8_t* keep, int32_t* label, int64_t* nclusters,
                 void* stream);
 
+/* ---- 4-clique counting ----------------------------------------------------- */
+/* Reformulated 4-clique count (Listing "lst:fcl"): with the degree order R of
+ * the triangle count, for every oriented edge (u, v), C3 = N+_u cap N+_v, and
+ * every w in C3 adds |N+_w cap C3|; each 4-clique counts once. *count is a
+ * host pointer; the calls wait for `stream`. The triangle lists C3 are held
+ * on chip: graphs whose largest oriented degree exceeds 4096 give
+ * PG_E_UNSUPPORTED. */
+/* Exact: |N+_w cap C3| by binary search in N+_w. */
+int pg_exact_four_cliques(pg_ctx* ctx, const pg_graph* g, uint64_t* count, void* stream);
+/* Estimated: |N+_w cap C3| = the number of x in C3 ranked above w (the only
+ * elements N+_w can hold) whose b bits are all set in the Bloom filter of
+ * N+_w (membership queries, Section 2.4; false positives only, so the
+ * estimate is never below the exact count). sk must hold Bloom filters of the
+ * oriented sets (PG_BF | PG_ORIENTED), else PG_E_INVALID. */
+int pg_four_cliques(pg_ctx* ctx, const pg_sketches* sk, uint64_t* count, void* stream);
+
 /* Recompute the rows of existing sketches in place (same kind, size and b;
  * new hash constants from `seed`), e.g. after the graph's arrays changed or to
  * draw a fresh sketch set. Allocates nothing. */

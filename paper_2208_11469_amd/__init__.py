@@ -142,6 +142,8 @@ def _declare(lib):
         "pg_jarvis_patrick": (i, [_vp, _vp, i, i, ctypes.c_double, _vp, P(i64), _vp]),
         "pg_exact_jarvis_patrick": (i, [_vp, _vp, i, i, ctypes.c_double, _vp, P(i64), _vp]),
         "pg_clusters": (i, [_vp, _vp, _vp, _vp, P(i64), _vp]),
+        "pg_exact_four_cliques": (i, [_vp, _vp, P(u64), _vp]),
+        "pg_four_cliques": (i, [_vp, _vp, P(u64), _vp]),
         "pg_sketches_rebuild": (i, [_vp, _vp, u64, _vp]),
         "pg_profile_enable": (i, [_vp, i]),
         "pg_profile_read": (i, [_vp, P(_KernelTime), i, P(i)]),
@@ -365,6 +367,18 @@ def pg_clusters(ctx, g, keep, label, want_count=True, stream=None):
     return count.value if want_count else None
 
 
+def pg_exact_four_cliques(ctx, g, stream=None) -> int:
+    out = ctypes.c_uint64(0)
+    _check(load().pg_exact_four_cliques(ctx, g, ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def pg_four_cliques(ctx, sk, stream=None) -> int:
+    out = ctypes.c_uint64(0)
+    _check(load().pg_four_cliques(ctx, sk, ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
 def pg_sketches_rebuild(ctx, sk, seed, stream=None):
     _check(load().pg_sketches_rebuild(ctx, sk, seed & (2**64 - 1), _stream(stream)))
 
@@ -566,6 +580,10 @@ class Graph:
                                        keep if self.m else None, True, stream)
         return keep, kept
 
+    def exact_four_cliques(self, stream=None) -> int:
+        """Exact 4-clique count (node iterator over oriented edges, Listing "lst:fcl")."""
+        return pg_exact_four_cliques(self.ctx.h, self.h, stream)
+
     def clusters(self, keep=None, stream=None):
         """(labels, count): connected components of the kept upper edges (all edges if keep is None),
         each vertex labelled with the smallest vertex ID of its component."""
@@ -660,6 +678,10 @@ class Sketches:
         pg_similarity(self.graph.ctx.h, self.h, ESTIMATORS.get(estimator, estimator),
                       SIMILARITIES.get(measure, measure), u, v, npairs, out if count else None, stream)
         return out
+
+    def four_cliques(self, stream=None) -> int:
+        """4-clique estimate from Bloom filters of the oriented sets (build with oriented=True)."""
+        return pg_four_cliques(self.graph.ctx.h, self.h, stream)
 
     def jarvis_patrick(self, estimator, measure, tau, stream=None):
         """(keep, kept): uint8 mask over the m upper edges of the clustering (similarity > tau), and its size."""

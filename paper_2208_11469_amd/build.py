@@ -29,7 +29,7 @@ COMMON_FLAGS = [
 ]
 
 SOURCES = ["pg_api.hip", "pg_graph.hip", "pg_build.hip", "pg_estimate.hip", "pg_exact.hip", "pg_prof.hip",
-           "pg_server.hip", "pg_batch.hip", "pg_cluster.hip"]
+           "pg_server.hip", "pg_batch.hip", "pg_cluster.hip", "pg_clique.hip"]
 
 
 def _compile(src: str) -> str:

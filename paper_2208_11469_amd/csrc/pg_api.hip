@@ -569,6 +569,36 @@ int pg_exact_jarvis_patrick(pg_ctx* ctx, const pg_graph* g, int algo, int measur
   return rc;
 }
 
+int pg_exact_four_cliques(pg_ctx* ctx, const pg_graph* gc, uint64_t* count, void* stream) {
+  clear_error();
+  if (!ctx || !gc || !count) return fail(PG_E_INVALID, "NULL argument");
+  PG_TRY(use_device(ctx));
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* d = nullptr;
+  PG_TRY(dmalloc((void**)&d, sizeof(unsigned long long), s));
+  int rc = four_cliques(const_cast<pg_graph*>(gc), nullptr, d, s);
+  if (rc == PG_OK) rc = counts_to_host(ctx, d, 1, s);
+  if (rc == PG_OK) *count = (uint64_t)((const unsigned long long*)ctx->h_scalar)[0];
+  dfree(d, s);
+  return rc;
+}
+
+int pg_four_cliques(pg_ctx* ctx, const pg_sketches* sk, uint64_t* count, void* stream) {
+  clear_error();
+  if (!ctx || !sk || !count) return fail(PG_E_INVALID, "NULL argument");
+  if (sk->kind != PG_BF || !sk->oriented)
+    return fail(PG_E_INVALID, "4-cliques need Bloom filters of the oriented sets (PG_BF | PG_ORIENTED)");
+  PG_TRY(use_device(ctx));
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* d = nullptr;
+  PG_TRY(dmalloc((void**)&d, sizeof(unsigned long long), s));
+  int rc = four_cliques(sk->g, sk, d, s);
+  if (rc == PG_OK) rc = counts_to_host(ctx, d, 1, s);
+  if (rc == PG_OK) *count = (uint64_t)((const unsigned long long*)ctx->h_scalar)[0];
+  dfree(d, s);
+  return rc;
+}
+
 int pg_clusters(pg_ctx* ctx, const pg_graph* g, const uint8_t* keep, int32_t* label, int64_t* nclusters,
                 void* stream) {
   clear_error();

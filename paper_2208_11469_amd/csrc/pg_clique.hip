@@ -1,0 +1,186 @@
+// 4-clique counting (Listing "lst:fcl"): with the degree order R of the
+// triangle count, for every oriented edge (u, v), v in N+_u, the third
+// vertices of its triangles are C3 = N+_u cap N+_v, and every w in C3
+// contributes |N+_w cap C3|; each 4-clique is counted once, at its three
+// lowest-ranked vertices. The count |N+_w cap C3| is exact (binary search of
+// x in N+_w) or, from Bloom filters of the oriented sets, the number of x in
+// C3 ranked above w (the only elements N+_w can hold) that pass the
+// membership query of the filter of N+_w (Section 2.4: all b bits set; false
+// positives only).
+//
+// One wave per oriented edge, edges dealt round-robin to the waves of a
+// persistent grid. The wave builds C3 in its LDS slice: lanes take 64
+// elements of the shorter list at a time, binary-search them in the longer
+// list, and a ballot appends the hits in ID order (with their degrees, for
+// the rank test). The |C3|^2 ordered pairs (w, x) are then spread over the
+// lanes: for |C3| <= 64 each lane keeps one x and walks the w rows
+// 64 / |C3| apart, otherwise lanes stride over x for one w at a time.
+// Counts are integers: the result does not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "pg_device.h"
+#include "pg_internal.h"
+
+namespace pg {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / kWave;
+constexpr int kMaxLdsBytes = 128 * 1024;
+
+struct CliqueFilters {
+  const uint64_t* words;  // line-packed rows of the filters of N+_v
+  const uint64_t* ha;
+  const uint64_t* hc;
+  uint32_t B, W, b;
+};
+
+// LDS visibility among the lanes of one wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// x in the ascending list[0, len)?
+__device__ __forceinline__ bool sorted_contains(const int32_t* __restrict__ list, int32_t len, int32_t x) {
+  int32_t lo = 0, hi = len;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (list[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < len && list[lo] == x;
+}
+
+// 1 if x counts towards |N+_w cap C3|.
+template <bool BF>
+__device__ __forceinline__ uint32_t pair_counts(const int32_t* __restrict__ poff, const int32_t* __restrict__ padj,
+                                                const CliqueFilters& f, int32_t w, int32_t dw, int32_t x,
+                                                int32_t dx) {
+  if (!(dw < dx || (dw == dx && w < x))) return 0;  // N+_w holds only vertices ranked above w
+  if constexpr (!BF) {
+    const int32_t b0 = poff[w];
+    return sorted_contains(padj + b0, poff[w + 1] - b0, x) ? 1u : 0u;
+  } else {
+    const uint64_t* row = f.words + bf_row_offset(w, f.W);
+    for (uint32_t h = 0; h < f.b; ++h) {
+      const uint32_t idx = bf_index(f.ha[h], f.hc[h], (uint32_t)x, f.B);
+      if (!((row[idx >> 6] >> (idx & 63u)) & 1ull)) return 0;
+    }
+    return 1;
+  }
+}
+
+template <bool BF>
+__global__ __launch_bounds__(kBlock) void k_four_cliques(const int32_t* __restrict__ poff,
+                                                         const int32_t* __restrict__ padj,
+                                                         const int32_t* __restrict__ parc_src, int64_t m,
+                                                         const int32_t* __restrict__ deg, int32_t cap, CliqueFilters f,
+                                                         unsigned long long* __restrict__ count) {
+  extern __shared__ int32_t lds[];  // per wave: C3 IDs [cap], then their degrees [cap]
+  __shared__ unsigned long long block_count;
+  if (threadIdx.x == 0) block_count = 0;
+  __syncthreads();
+  const int wave = (int)threadIdx.x / kWave;
+  const int lane = lane_id();
+  int32_t* ids = lds + (size_t)wave * 2 * cap;
+  int32_t* dg = ids + cap;
+  unsigned long long mine = 0;
+  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  for (int64_t e = (int64_t)blockIdx.x * kWaves + wave; e < m; e += nwaves) {
+    const int32_t u = parc_src[e], v = padj[e];
+    const int32_t* A = padj + poff[u];
+    int32_t na = poff[u + 1] - poff[u];
+    const int32_t* L = padj + poff[v];
+    int32_t nl = poff[v + 1] - poff[v];
+    if (na > nl) {
+      const int32_t* t = A;
+      A = L;
+      L = t;
+      const int32_t tn = na;
+      na = nl;
+      nl = tn;
+    }
+    // C3 = A cap L in ID order; |C3| <= na <= cap
+    int32_t s = 0;
+    for (int32_t base = 0; base < na; base += kWave) {
+      const int32_t i = base + lane;
+      int32_t a = 0;
+      bool hit = false;
+      if (i < na) {
+        a = A[i];
+        hit = sorted_contains(L, nl, a);
+      }
+      const uint64_t ball = __ballot(hit);
+      if (hit) {
+        const int32_t pos = s + (int32_t)__popcll(ball & ((1ull << lane) - 1ull));
+        ids[pos] = a;
+        dg[pos] = deg[a];
+      }
+      s += (int32_t)__popcll(ball);
+    }
+    wave_sync();
+    if (s >= 2) {
+      if (s <= kWave) {
+        const int per = kWave / s;
+        const int wi0 = lane / s;
+        if (wi0 < per) {
+          const int xi = lane - wi0 * s;
+          const int32_t x = ids[xi], dx = dg[xi];
+          for (int wi = wi0; wi < s; wi += per) mine += pair_counts<BF>(poff, padj, f, ids[wi], dg[wi], x, dx);
+        }
+      } else {
+        for (int32_t wi = 0; wi < s; ++wi) {
+          const int32_t w = ids[wi], dw = dg[wi];
+          for (int32_t xi = lane; xi < s; xi += kWave) mine += pair_counts<BF>(poff, padj, f, w, dw, ids[xi], dg[xi]);
+        }
+      }
+    }
+    wave_sync();  // the next edge overwrites this wave's slice
+  }
+  if (mine) atomicAdd(&block_count, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && block_count) atomicAdd(count, block_count);
+}
+
+}  // namespace
+
+// The 4-clique count into d_count[0]: exact (sk == nullptr) or with Bloom
+// filters of the oriented sets.
+int four_cliques(pg_graph* g, const pg_sketches* sk, unsigned long long* d_count, hipStream_t s) {
+  PG_TRY(graph_oriented(g, s));
+  PG_TRY(fill_u64((uint64_t*)d_count, 0, 1, s));
+  if (g->m <= 0) return PG_OK;
+  const int32_t cap = std::max(1, g->oriented->max_degree);
+  const size_t shmem = sizeof(int32_t) * 2 * (size_t)cap * kWaves;
+  if (shmem > (size_t)kMaxLdsBytes)
+    return fail(PG_E_UNSUPPORTED, "4-cliques: the largest oriented degree exceeds the on-chip C3 buffer (4096)");
+  CliqueFilters f{};
+  if (sk) {
+    f.words = sk->words;
+    f.ha = sk->ha;
+    f.hc = sk->hc;
+    f.B = sk->size;
+    f.W = sk->W;
+    f.b = sk->b;
+  }
+  const int64_t waves_needed = g->m;
+  const unsigned grid = (unsigned)std::max<int64_t>(
+      1, std::min<int64_t>((waves_needed + kWaves - 1) / kWaves, (int64_t)std::max(1, g->ctx->num_cus) * 8));
+  ProfScope ps(s, sk ? "four_cliques_bf" : "four_cliques_exact");
+  if (sk)
+    hipLaunchKernelGGL(k_four_cliques<true>, dim3(grid), dim3(kBlock), shmem, s, g->poff, g->padj, g->parc_src, g->m,
+                       g->deg, cap, f, d_count);
+  else
+    hipLaunchKernelGGL(k_four_cliques<false>, dim3(grid), dim3(kBlock), shmem, s, g->poff, g->padj, g->parc_src,
+                       g->m, g->deg, cap, f, d_count);
+  PG_LAUNCH_CHECK();
+  return PG_OK;
+}
+
+}  // namespace pg

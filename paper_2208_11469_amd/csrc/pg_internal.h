@@ -288,6 +288,10 @@ int exact_similarity(const pg_graph* g, int measure, const int32_t* u, const int
 int exact_jp(const pg_graph* g, int algo, int measure, double tau, uint8_t* keep, unsigned long long* d_kept,
              hipStream_t s);
 
+// ---- launchers (pg_clique.hip) -----------------------------------------------
+// 4-clique count into d_count[0]: exact (sk NULL) or from Bloom filters of N+.
+int four_cliques(pg_graph* g, const pg_sketches* sk, unsigned long long* d_count, hipStream_t s);
+
 // ---- launchers (pg_cluster.hip) ----------------------------------------------
 // Connected components of the kept upper edges (keep NULL: all); label[v] =
 // smallest vertex ID of v's component; the component count into d_count[0].
