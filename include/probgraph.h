@@ -262,8 +262,8 @@ int pg_clusters(pg_ctx* ctx, const pg_graph* g, const uint8_t* keep, int32_t* la
  * the triangle count, for every oriented edge (u, v), C3 = N+_u cap N+_v, and
  * every w in C3 adds |N+_w cap C3|; each 4-clique counts once. *count is a
  * host pointer; the calls wait for `stream`. The triangle lists C3 are held
- * on chip: graphs whose largest oriented degree exceeds 4096 give
- * PG_E_UNSUPPORTED. */
+ * on chip: graphs whose largest oriented degree exceeds 4080 (exact) or 2720
+ * (filters) give PG_E_UNSUPPORTED. */
 /* Exact: |N+_w cap C3| by binary search in N+_w. */
 int pg_exact_four_cliques(pg_ctx* ctx, const pg_graph* g, uint64_t* count, void* stream);
 /* Estimated: |N+_w cap C3| = the number of x in C3 ranked above w (the only

@@ -12,10 +12,13 @@
 // persistent grid. The wave builds C3 in its LDS slice: lanes take 64
 // elements of the shorter list at a time, binary-search them in the longer
 // list, and a ballot appends the hits in ID order (with their degrees, for
-// the rank test). The |C3|^2 ordered pairs (w, x) are then spread over the
-// lanes: for |C3| <= 64 each lane keeps one x and walks the w rows
-// 64 / |C3| apart, otherwise lanes stride over x for one w at a time.
-// Counts are integers: the result does not depend on scheduling.
+// the rank test, and with filters the first hash function's bit index, so
+// each element is hashed once per edge rather than once per pair). The
+// |C3|^2 ordered pairs (w, x) are then spread over the lanes: for |C3| <= 64
+// each lane keeps one x and walks the w rows 64 / |C3| apart; otherwise the
+// wave takes one w at a time (with filters its row is staged in LDS) and the
+// lanes stride over x. Counts are integers: the result does not depend on
+// scheduling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,6 +32,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kMaxLdsBytes = 128 * 1024;
+constexpr int kRowInts = 32;  // staged filter row: up to 16 words
 
 struct CliqueFilters {
   const uint64_t* words;  // line-packed rows of the filters of N+_v
@@ -57,39 +61,51 @@ __device__ __forceinline__ bool sorted_contains(const int32_t* __restrict__ list
   return lo < len && list[lo] == x;
 }
 
-// 1 if x counts towards |N+_w cap C3|.
-template <bool BF>
-__device__ __forceinline__ uint32_t pair_counts(const int32_t* __restrict__ poff, const int32_t* __restrict__ padj,
-                                                const CliqueFilters& f, int32_t w, int32_t dw, int32_t x,
-                                                int32_t dx) {
-  if (!(dw < dx || (dw == dx && w < x))) return 0;  // N+_w holds only vertices ranked above w
-  if constexpr (!BF) {
-    const int32_t b0 = poff[w];
-    return sorted_contains(padj + b0, poff[w + 1] - b0, x) ? 1u : 0u;
-  } else {
-    const uint64_t* row = f.words + bf_row_offset(w, f.W);
-    for (uint32_t h = 0; h < f.b; ++h) {
-      const uint32_t idx = bf_index(f.ha[h], f.hc[h], (uint32_t)x, f.B);
-      if (!((row[idx >> 6] >> (idx & 63u)) & 1ull)) return 0;
-    }
-    return 1;
-  }
+// Rows of the filters: WT the row width as a compile-time constant (1..16,
+// line-packed rows), or 0 for rows wider than 16 words (dense: row v at v * W).
+template <int WT>
+__device__ __forceinline__ const uint64_t* filter_row(const CliqueFilters& f, int32_t w) {
+  return f.words + (WT > 0 ? bf_row_offset(w, (uint32_t)WT) : (size_t)w * f.W);
 }
 
-template <bool BF>
+// Membership of x in the filter `row`: bit i0 (the first hash function's,
+// precomputed) and the bits of the other b - 1 functions all set.
+__device__ __forceinline__ uint32_t member(const uint64_t* row, const CliqueFilters& f, int32_t x, uint32_t i0) {
+  if (!((row[i0 >> 6] >> (i0 & 63u)) & 1ull)) return 0;
+  for (uint32_t h = 1; h < f.b; ++h) {
+    const uint32_t idx = bf_index(f.ha[h], f.hc[h], (uint32_t)x, f.B);
+    if (!((row[idx >> 6] >> (idx & 63u)) & 1ull)) return 0;
+  }
+  return 1;
+}
+
+__device__ __forceinline__ bool ranked_below(int32_t w, int32_t dw, int32_t x, int32_t dx) {
+  return dw < dx || (dw == dx && w < x);
+}
+
+// WT = -1: exact count; otherwise filters of row width WT (see filter_row).
+// LDS slice of a wave: [staged row: kRowInts] [ids: cap] [degrees: cap]
+// [first bit indices: cap, filters only]; cap is even, so slices stay 8-byte
+// aligned.
+template <int WT>
 __global__ __launch_bounds__(kBlock) void k_four_cliques(const int32_t* __restrict__ poff,
                                                          const int32_t* __restrict__ padj,
                                                          const int32_t* __restrict__ parc_src, int64_t m,
                                                          const int32_t* __restrict__ deg, int32_t cap, CliqueFilters f,
                                                          unsigned long long* __restrict__ count) {
-  extern __shared__ int32_t lds[];  // per wave: C3 IDs [cap], then their degrees [cap]
+  constexpr bool kBf = WT >= 0;
+  constexpr int kArrays = kBf ? 3 : 2;
+  extern __shared__ int32_t lds[];
   __shared__ unsigned long long block_count;
   if (threadIdx.x == 0) block_count = 0;
   __syncthreads();
   const int wave = (int)threadIdx.x / kWave;
   const int lane = lane_id();
-  int32_t* ids = lds + (size_t)wave * 2 * cap;
+  int32_t* slice = lds + (size_t)wave * ((size_t)kRowInts + (size_t)kArrays * cap);
+  uint64_t* rowbuf = reinterpret_cast<uint64_t*>(slice);
+  int32_t* ids = slice + kRowInts;
   int32_t* dg = ids + cap;
+  uint32_t* hx = reinterpret_cast<uint32_t*>(dg + cap);  // filters only
   unsigned long long mine = 0;
   const int64_t nwaves = (int64_t)gridDim.x * kWaves;
   for (int64_t e = (int64_t)blockIdx.x * kWaves + wave; e < m; e += nwaves) {
@@ -121,6 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_four_cliques(const int32_t* __restri
         const int32_t pos = s + (int32_t)__popcll(ball & ((1ull << lane) - 1ull));
         ids[pos] = a;
         dg[pos] = deg[a];
+        if constexpr (kBf) hx[pos] = bf_index(f.ha[0], f.hc[0], (uint32_t)a, f.B);
       }
       s += (int32_t)__popcll(ball);
     }
@@ -132,12 +149,43 @@ __global__ __launch_bounds__(kBlock) void k_four_cliques(const int32_t* __restri
         if (wi0 < per) {
           const int xi = lane - wi0 * s;
           const int32_t x = ids[xi], dx = dg[xi];
-          for (int wi = wi0; wi < s; wi += per) mine += pair_counts<BF>(poff, padj, f, ids[wi], dg[wi], x, dx);
+          uint32_t i0 = 0;
+          if constexpr (kBf) i0 = hx[xi];
+          for (int wi = wi0; wi < s; wi += per) {
+            const int32_t w = ids[wi], dw = dg[wi];
+            if (!ranked_below(w, dw, x, dx)) continue;  // N+_w holds only vertices ranked above w
+            if constexpr (kBf) {
+              mine += member(filter_row<WT>(f, w), f, x, i0);
+            } else {
+              const int32_t b0 = poff[w];
+              mine += sorted_contains(padj + b0, poff[w + 1] - b0, x) ? 1u : 0u;
+            }
+          }
         }
       } else {
         for (int32_t wi = 0; wi < s; ++wi) {
           const int32_t w = ids[wi], dw = dg[wi];
-          for (int32_t xi = lane; xi < s; xi += kWave) mine += pair_counts<BF>(poff, padj, f, w, dw, ids[xi], dg[xi]);
+          const uint64_t* row = nullptr;
+          if constexpr (kBf) {
+            if constexpr (WT > 0) {
+              if (lane < WT) rowbuf[lane] = filter_row<WT>(f, w)[lane];
+              wave_sync();
+              row = rowbuf;
+            } else {
+              row = filter_row<WT>(f, w);
+            }
+          }
+          for (int32_t xi = lane; xi < s; xi += kWave) {
+            const int32_t x = ids[xi];
+            if (!ranked_below(w, dw, x, dg[xi])) continue;
+            if constexpr (kBf) {
+              mine += member(row, f, x, hx[xi]);
+            } else {
+              const int32_t b0 = poff[w];
+              mine += sorted_contains(padj + b0, poff[w + 1] - b0, x) ? 1u : 0u;
+            }
+          }
+          if constexpr (WT > 0) wave_sync();  // before the next row overwrites the staged one
         }
       }
     }
@@ -156,10 +204,11 @@ int four_cliques(pg_graph* g, const pg_sketches* sk, unsigned long long* d_count
   PG_TRY(graph_oriented(g, s));
   PG_TRY(fill_u64((uint64_t*)d_count, 0, 1, s));
   if (g->m <= 0) return PG_OK;
-  const int32_t cap = std::max(1, g->oriented->max_degree);
-  const size_t shmem = sizeof(int32_t) * 2 * (size_t)cap * kWaves;
+  const int32_t cap = (std::max(1, g->oriented->max_degree) + 1) & ~1;  // even: 8-byte aligned wave slices
+  const size_t shmem = sizeof(int32_t) * ((size_t)kRowInts + (size_t)(sk ? 3 : 2) * cap) * kWaves;
   if (shmem > (size_t)kMaxLdsBytes)
-    return fail(PG_E_UNSUPPORTED, "4-cliques: the largest oriented degree exceeds the on-chip C3 buffer (4096)");
+    return fail(PG_E_UNSUPPORTED, sk ? "4-cliques: the largest oriented degree exceeds the on-chip C3 buffer (2720 with filters)"
+                                     : "4-cliques: the largest oriented degree exceeds the on-chip C3 buffer (4080)");
   CliqueFilters f{};
   if (sk) {
     f.words = sk->words;
@@ -173,12 +222,33 @@ int four_cliques(pg_graph* g, const pg_sketches* sk, unsigned long long* d_count
   const unsigned grid = (unsigned)std::max<int64_t>(
       1, std::min<int64_t>((waves_needed + kWaves - 1) / kWaves, (int64_t)std::max(1, g->ctx->num_cus) * 8));
   ProfScope ps(s, sk ? "four_cliques_bf" : "four_cliques_exact");
-  if (sk)
-    hipLaunchKernelGGL(k_four_cliques<true>, dim3(grid), dim3(kBlock), shmem, s, g->poff, g->padj, g->parc_src, g->m,
-                       g->deg, cap, f, d_count);
-  else
-    hipLaunchKernelGGL(k_four_cliques<false>, dim3(grid), dim3(kBlock), shmem, s, g->poff, g->padj, g->parc_src,
-                       g->m, g->deg, cap, f, d_count);
+#define PG_CK(WW)                                                                                                  \
+  hipLaunchKernelGGL(k_four_cliques<WW>, dim3(grid), dim3(kBlock), shmem, s, g->poff, g->padj, g->parc_src, g->m, \
+                     g->deg, cap, f, d_count)
+  if (!sk) {
+    PG_CK(-1);
+  } else {
+    switch (sk->W) {
+      case 1: PG_CK(1); break;
+      case 2: PG_CK(2); break;
+      case 3: PG_CK(3); break;
+      case 4: PG_CK(4); break;
+      case 5: PG_CK(5); break;
+      case 6: PG_CK(6); break;
+      case 7: PG_CK(7); break;
+      case 8: PG_CK(8); break;
+      case 9: PG_CK(9); break;
+      case 10: PG_CK(10); break;
+      case 11: PG_CK(11); break;
+      case 12: PG_CK(12); break;
+      case 13: PG_CK(13); break;
+      case 14: PG_CK(14); break;
+      case 15: PG_CK(15); break;
+      case 16: PG_CK(16); break;
+      default: PG_CK(0); break;  // rows wider than 16 words are dense
+    }
+  }
+#undef PG_CK
   PG_LAUNCH_CHECK();
   return PG_OK;
 }
