@@ -393,6 +393,10 @@ typedef struct pg_kernel_time {
 /* Per-kernel device timing: while enabled, every kernel launch of the library
  * is bracketed by two HIP events on its stream. Process-wide. */
 int pg_profile_enable(pg_ctx* ctx, int enable);
+/* Record only the launch site `name` (host string, copied; NULL: every site).
+ * Each recorded launch adds two events to its stream, which costs device time
+ * between launches; selecting one site keeps that cost off the others. */
+int pg_profile_select(pg_ctx* ctx, const char* name);
 /* Wait for the recorded events and return up to `capacity` entries (host
  * array); *count receives the number of distinct launch sites. */
 int pg_profile_read(pg_ctx* ctx, pg_kernel_time* out, int capacity, int* count);

@@ -146,6 +146,7 @@ def _declare(lib):
         "pg_four_cliques": (i, [_vp, _vp, P(u64), _vp]),
         "pg_sketches_rebuild": (i, [_vp, _vp, u64, _vp]),
         "pg_profile_enable": (i, [_vp, i]),
+        "pg_profile_select": (i, [_vp, ctypes.c_char_p]),
         "pg_profile_read": (i, [_vp, P(_KernelTime), i, P(i)]),
         "pg_profile_reset": (i, [_vp]),
         "pg_copy": (i, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -385,6 +386,11 @@ def pg_sketches_rebuild(ctx, sk, seed, stream=None):
 
 def pg_profile_enable(ctx, enable: bool):
     _check(load().pg_profile_enable(ctx, 1 if enable else 0))
+
+
+def pg_profile_select(ctx, name=None):
+    """Record only the launch site `name` (None: all)."""
+    _check(load().pg_profile_select(ctx, name.encode() if name else None))
 
 
 def pg_profile_read(ctx) -> dict:

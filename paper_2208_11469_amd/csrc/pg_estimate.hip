@@ -257,11 +257,11 @@ __global__ __launch_bounds__(kBlock) void k_bf_tc_slab(SlabPlan P, SkView s, con
   const size_t n = (size_t)s.n;
   const int tid = threadIdx.x;
   double acc = 0.0;
-  if (whole) {  // kWholeGroup lanes per whole vertex, all its upper neighbours
-    const int64_t idx = (blk * kBlock + tid) / kWholeGroup;
+  if (whole) {  // kSlabWholeGroup lanes per whole vertex, all its upper neighbours
+    const int64_t idx = (blk * kBlock + tid) / kSlabWholeGroup;
     if (idx < P.n_whole) {
       const int32_t v = P.verts[P.whole_at + idx];
-      acc = bf_item<W, U, kWholeGroup, OR>(s, v, adj, ustart[v], off[v + 1], tid % kWholeGroup, tab);
+      acc = bf_item<W, U, kSlabWholeGroup, OR>(s, v, adj, ustart[v], off[v + 1], tid % kSlabWholeGroup, tab);
     }
   } else if (blk < n_chunks) {  // heavy chunk: the whole block
     const int64_t c = P.chunk_at[x] + blk;

@@ -142,7 +142,8 @@ inline int64_t plan_blocks(const VertexPlan& p) {
 constexpr int kSlabs = 8;
 constexpr int32_t kSliceMin = 64;
 constexpr int kSlabLightGroup = 8;
-constexpr int kWholeGroup = 8;
+constexpr int kWholeGroup = 8;      // lanes per light vertex of the clustering-coefficient plan
+constexpr int kSlabWholeGroup = 4;  // lanes per whole (unsliced) vertex of the triangle-count slab plan
 
 struct SlabPlan {
   int32_t* split = nullptr;  // [(kSlabs-1) * n]: split[(x-1)*n + v] = first arc of v into slab x >= 1
@@ -167,7 +168,7 @@ __host__ __device__ inline int64_t slab_blocks(const SlabPlan& p, int x) {
 }
 // Blocks of the whole launch.
 inline int64_t slab_plan_blocks(const SlabPlan& p) {
-  return p.slab_grid + (p.n_whole * kWholeGroup + 255) / 256;
+  return p.slab_grid + (p.n_whole * kSlabWholeGroup + 255) / 256;
 }
 
 __device__ __forceinline__ int64_t slab_begin(const int32_t* __restrict__ ustart, const int32_t* __restrict__ split,

@@ -22,6 +22,8 @@ struct Pending {
 
 std::mutex g_mu;
 bool g_enabled = false;
+bool g_selected = false;  // record only the launch site g_only
+std::string g_only;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
 std::map<std::string, std::pair<int64_t, double>> g_totals;
@@ -65,6 +67,7 @@ bool prof_enabled() { return g_enabled; }
 
 ProfScope::ProfScope(hipStream_t s, const char* name) : s_(s), name_(name) {
   if (!g_enabled) return;
+  if (g_selected && g_only != name) return;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -97,6 +100,15 @@ int pg_profile_enable(pg_ctx* ctx, int enable) {
   clear_error();
   if (!ctx) return fail(PG_E_INVALID, "ctx is NULL");
   g_enabled = enable != 0;
+  return PG_OK;
+}
+
+int pg_profile_select(pg_ctx* ctx, const char* name) {
+  clear_error();
+  if (!ctx) return fail(PG_E_INVALID, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_selected = name != nullptr;
+  g_only = name ? name : "";
   return PG_OK;
 }
 
