@@ -36,7 +36,6 @@ constexpr int kBatchGroup = 8;
 constexpr int kGroups = kBlock / kBatchGroup;
 constexpr int32_t kBatchHeavy = 512;
 constexpr int kMaxW = 16;
-constexpr int kStride = kBlock + 1;
 
 struct GraphDesc {
   int64_t vbase;  // first global vertex
@@ -103,8 +102,11 @@ __device__ __forceinline__ int64_t next_item(uint32_t* counter, int64_t* slot) {
   return it;
 }
 
+// Bits of the neighbours adj[beg, end) into `bits`, G lanes: LDS atomic OR,
+// which is order-independent, so the row does not depend on which lane
+// lands first.
 __device__ __forceinline__ void scatter_arcs(const BatchView& bv, int64_t beg, int64_t end, int lane, int G,
-                                             uint32_t B, uint64_t* __restrict__ mine) {
+                                             uint32_t B, uint64_t* __restrict__ bits) {
   for (int64_t p0 = beg + lane; p0 < end; p0 += (int64_t)G * 4) {
     uint32_t x[4];
 #pragma unroll
@@ -117,19 +119,31 @@ __device__ __forceinline__ void scatter_arcs(const BatchView& bv, int64_t beg, i
       if (p0 + (int64_t)j * G < end) {
         for (uint32_t i = 0; i < bv.b; ++i) {
           const uint32_t idx = bf_index(bv.ha[i], bv.hc[i], x[j], B);
-          mine[(idx >> 6) * kStride] |= 1ull << (idx & 63u);
+          atomicOr((unsigned long long*)&bits[idx >> 6], 1ull << (idx & 63u));
         }
       }
     }
   }
 }
 
+// LDS visibility among the lanes of one wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Heavy items: the block shares kBuildCopies bitmaps (lane l uses copy
+// l mod kBuildCopies, so fewer lanes of one instruction collide on a word);
+// tiles: each group of kBatchGroup lanes shares one bitmap per vertex.
+constexpr int kBuildCopies = 8;
+constexpr int kBuildWords = (kGroups > kBuildCopies ? kGroups : kBuildCopies) * kMaxW;
+
 __global__ __launch_bounds__(kBlock) void k_batch_build(BatchView bv) {
-  __shared__ uint64_t lds[kMaxW * kStride];
+  __shared__ uint64_t lds[kBuildWords];
   __shared__ uint32_t ones_sh[kMaxW];
   __shared__ int64_t slot;
   const int tid = threadIdx.x;
-  uint64_t* mine = lds + tid;
   for (;;) {
     const int64_t it = next_item(&bv.counters[0], &slot);
     if (it >= bv.nitems) return;
@@ -137,13 +151,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_build(BatchView bv) {
     const GraphDesc gd = bv.gd[item.graph];
     const uint32_t W = gd.W;
     if (item.heavy) {
-      for (uint32_t k = 0; k < W; ++k) mine[k * kStride] = 0;
+      for (uint32_t i = tid; i < kBuildCopies * W; i += kBlock) lds[i] = 0;
+      __syncthreads();
       const int64_t gv = gd.vbase + item.v0;
-      scatter_arcs(bv, bv.off[gv], bv.off[gv + 1], tid, kBlock, gd.B, mine);
+      scatter_arcs(bv, bv.off[gv], bv.off[gv + 1], tid, kBlock, gd.B, lds + (tid % kBuildCopies) * W);
       __syncthreads();
       if ((uint32_t)tid < W) {
         uint64_t w = 0;
-        for (int i = 0; i < kBlock; ++i) w |= lds[tid * kStride + i];
+#pragma unroll
+        for (int c = 0; c < kBuildCopies; ++c) w |= lds[c * W + tid];
         bv.words[gd.wbase + (int64_t)item.v0 * W + tid] = w;
         ones_sh[tid] = (uint32_t)__popcll(w);
       }
@@ -157,28 +173,24 @@ __global__ __launch_bounds__(kBlock) void k_batch_build(BatchView bv) {
       continue;
     }
     const int grp = tid / kBatchGroup, lane = tid % kBatchGroup;
+    uint64_t* bits = lds + grp * kMaxW;
     for (int32_t v = item.v0 + grp; v < item.v1; v += kGroups) {
       const int64_t gv = gd.vbase + v;
       const int64_t beg = bv.off[gv], end = bv.off[gv + 1];
       if (end - beg > kBatchHeavy) continue;  // a heavy item of its own
-      for (uint32_t k = 0; k < W; ++k) mine[k * kStride] = 0;
-      scatter_arcs(bv, beg, end, lane, kBatchGroup, gd.B, mine);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (uint32_t k = lane; k < W; k += kBatchGroup) bits[k] = 0;
+      wave_sync();
+      scatter_arcs(bv, beg, end, lane, kBatchGroup, gd.B, bits);
+      wave_sync();
       uint32_t ones = 0;
       for (uint32_t k = lane; k < W; k += kBatchGroup) {
-        uint64_t w = 0;
-#pragma unroll
-        for (int i = 0; i < kBatchGroup; ++i) w |= lds[k * kStride + (tid - lane) + i];
+        const uint64_t w = bits[k];
         bv.words[gd.wbase + (int64_t)v * W + k] = w;
         ones += (uint32_t)__popcll(w);
       }
       ones = group_sum_u32<kBatchGroup>(ones);
       if (lane == 0) bv.pc[gv] = ones;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      wave_sync();  // before the next vertex clears the bitmap
     }
     __syncthreads();
   }
