@@ -163,6 +163,15 @@ int pg_sketches_get_info(const pg_sketches* sk, pg_sketch_info* out /* host */);
 /* Copy the rows (n * row_bytes bytes) and, for PG_BF, the per-vertex
  * popcounts (pc[n]) into caller device buffers; either may be NULL. */
 int pg_sketches_export(const pg_sketches* sk, void* rows, uint32_t* pc, void* stream);
+/* Checkpoint / resume: a sketch set on graph g from rows exported by
+ * pg_sketches_export, without hashing. kind (with PG_ORIENTED if set), size,
+ * b and seed are those pg_sketches_get_info reports for the exported set (the
+ * seed keeps pg_sketches_rebuild and the 1-hash estimators consistent); rows
+ * (device, n * row_bytes, the export layout) and, for PG_BF, pc (device, n;
+ * NULL counts the ones of the rows). On the graph the rows were built on, the
+ * set is bit-identical to the exported one. */
+int pg_sketches_import(pg_ctx* ctx, const pg_graph* g, int kind, uint32_t size, uint32_t b, uint64_t seed,
+                       const void* rows, const uint32_t* pc, void* stream, pg_sketches** out);
 
 /* Estimate |N_u cap N_v| for npairs pairs (u[i], v[i]); u = v = NULL means the
  * graph's m upper edges in CSR order (npairs ignored). est (FP64) and raw

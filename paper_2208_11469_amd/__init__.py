@@ -60,6 +60,8 @@ ESTIMATORS = {
     "kmv": PG_EST_KMV, "kmv_est": PG_EST_KMV_SKETCH_SIZES,
 }
 KINDS = {"bf": PG_BF, "kh": PG_MH_KHASH, "1h": PG_MH_1HASH}
+SKETCH_FILE_FORMAT = "probgraph-sketches-1"
+HASH_FAMILY = "splitmix64-affine-1"  # the seeded hash family of pg_build_sketches (see probgraph.h)
 SIMILARITIES = {"cn": PG_SIM_COMMON, "jaccard": PG_SIM_JACCARD, "overlap": PG_SIM_OVERLAP, "total": PG_SIM_TOTAL}
 
 
@@ -128,6 +130,7 @@ def _declare(lib):
         "pg_sketches_destroy": (i, [_vp]),
         "pg_sketches_get_info": (i, [_vp, P(_SketchInfo)]),
         "pg_sketches_export": (i, [_vp, _vp, _vp, _vp]),
+        "pg_sketches_import": (i, [_vp, _vp, i, u32, u32, u64, _vp, _vp, _vp, P(_vp)]),
         "pg_intersect_edges": (i, [_vp, _vp, i, _vp, _vp, i64, _vp, _vp, _vp]),
         "pg_tc": (i, [_vp, _vp, i, P(ctypes.c_double), _vp]),
         "pg_tc_async": (i, [_vp, _vp, i, _vp, _vp]),
@@ -274,6 +277,13 @@ def pg_sketch_bits_for_budget(g, s: float) -> int:
 def pg_build_sketches(ctx, g, kind, size, b, seed, stream=None):
     h = _vp()
     _check(load().pg_build_sketches(ctx, g, kind, size, b, seed & (2**64 - 1), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def pg_sketches_import(ctx, g, kind, size, b, seed, rows, pc=None, stream=None):
+    h = _vp()
+    _check(load().pg_sketches_import(ctx, g, kind, size, b, seed & (2**64 - 1), _dptr(rows), _dptr(pc),
+                                     _stream(stream), ctypes.byref(h)))
     return h
 
 
@@ -586,6 +596,33 @@ class Graph:
                                        keep if self.m else None, True, stream)
         return keep, kept
 
+    def import_sketches(self, kind, size: int, b: int, seed: int, rows, pc=None, oriented: bool = False,
+                        stream=None) -> "Sketches":
+        """A sketch set from exported rows (device uint8 [n, row_bytes]) without hashing."""
+        kind = KINDS.get(kind, kind) | (PG_ORIENTED if oriented else 0)
+        return Sketches(self, pg_sketches_import(self.ctx.h, self.h, kind, size, b, seed,
+                                                 rows if self.n else None, pc if self.n else None, stream))
+
+    def load_sketches(self, path, stream=None) -> "Sketches":
+        """Resume a sketch set saved by Sketches.save (checks the graph's n and m)."""
+        import json
+        torch = _torch()
+        with np.load(path, allow_pickle=False) as f:
+            header = json.loads(bytes(f["header"]).decode())
+            rows = np.array(f["rows"])
+            pc = np.array(f["pc"]) if "pc" in f.files else None
+        if header.get("format") != SKETCH_FILE_FORMAT or header.get("hash_family") != HASH_FAMILY:
+            raise ValueError(f"{path}: not a sketch file of this library's format and hash family")
+        if header["n"] != self.n or header["m"] != self.m:
+            raise ValueError(f"{path}: saved for a graph with n={header['n']} m={header['m']}, not n={self.n} m={self.m}")
+        dev = self._dev()
+        d_rows = torch.from_numpy(rows).to(dev)
+        d_pc = torch.from_numpy(pc).to(dev) if pc is not None else None
+        sk = self.import_sketches(header["kind"], header["size"], header["b"], header["seed"], d_rows, d_pc,
+                                  oriented=header["oriented"], stream=stream)
+        torch.cuda.synchronize(dev)
+        return sk
+
     def exact_four_cliques(self, stream=None) -> int:
         """Exact 4-clique count (node iterator over oriented edges, Listing "lst:fcl")."""
         return pg_exact_four_cliques(self.ctx.h, self.h, stream)
@@ -684,6 +721,22 @@ class Sketches:
         pg_similarity(self.graph.ctx.h, self.h, ESTIMATORS.get(estimator, estimator),
                       SIMILARITIES.get(measure, measure), u, v, npairs, out if count else None, stream)
         return out
+
+    def save(self, path, stream=None):
+        """Checkpoint: the rows (and BF popcounts) with the parameters that rebuild them, as an .npz
+        file (numeric arrays and a JSON header; loaded without pickle)."""
+        import json
+        rows, pc = self.export(stream)
+        _torch().cuda.synchronize(rows.device)
+        header = {"format": SKETCH_FILE_FORMAT, "hash_family": HASH_FAMILY, "kind": self.kind,
+                  "oriented": self.oriented, "size": self.size, "b": self.b, "seed": self.seed,
+                  "n": self.graph.n, "m": self.graph.m}
+        arrays = {"header": np.frombuffer(json.dumps(header).encode(), dtype=np.uint8),
+                  "rows": rows.cpu().numpy()}
+        if pc is not None:
+            arrays["pc"] = pc.cpu().numpy()
+        with open(path, "wb") as f:
+            np.savez(f, **arrays)
 
     def four_cliques(self, stream=None) -> int:
         """4-clique estimate from Bloom filters of the oriented sets (build with oriented=True)."""

@@ -277,9 +277,14 @@ int pg_sketch_bits_for_budget(const pg_graph* g, double s, uint32_t* bits) {
   return PG_OK;
 }
 
-int pg_build_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, uint32_t b, uint64_t seed,
-                      void* stream, pg_sketches** out) {
-  clear_error();
+}  // extern "C"
+
+namespace {
+
+// A sketch set of the given parameters with its arrays allocated and hash
+// constants in place; the rows are built (build = true) or left to the caller.
+int make_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, uint32_t b, uint64_t seed,
+                  hipStream_t s, bool build, pg_sketches** out) {
   if (!ctx || !gc || !out) return fail(PG_E_INVALID, "NULL argument");
   *out = nullptr;
   pg_graph* g = const_cast<pg_graph*>(gc);
@@ -296,7 +301,6 @@ int pg_build_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, 
     return fail(PG_E_INVALID, "unknown sketch kind");
   }
   PG_TRY(use_device(ctx));
-  hipStream_t s = (hipStream_t)stream;
   if (oriented) PG_TRY(graph_oriented(g, s));
   pg_graph* rows = oriented ? g->oriented : g;
   pg_sketches* sk = new (std::nothrow) pg_sketches();
@@ -327,18 +331,56 @@ int pg_build_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, 
     if (rc == PG_OK) rc = palloc((void**)&sk->table, sizeof(double) * (size + 1));
     if (rc == PG_OK)
       rc = palloc((void**)&sk->scratch, sizeof(uint64_t) * sk->W * (size_t)std::max<int64_t>(rows->plan_all.n_chunks, 1));
-
-    if (rc == PG_OK && g->n > 0) rc = build_bf(sk, s);
+    if (rc == PG_OK && build && g->n > 0) rc = build_bf(sk, s);
   } else {
     if (rc == PG_OK) rc = palloc((void**)&sk->sig, sizeof(uint32_t) * size * n);
-    if (rc == PG_OK && g->n > 0) rc = kind == PG_MH_KHASH ? build_khash(sk, s) : build_onehash(sk, s);
+    if (rc == PG_OK && build && g->n > 0) rc = kind == PG_MH_KHASH ? build_khash(sk, s) : build_onehash(sk, s);
   }
   if (rc != PG_OK) {
     (void)hipStreamSynchronize(s);
     free_sketches(sk);
     return rc;
   }
-  g->live_sketches++;
+  *out = sk;
+  return PG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pg_build_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, uint32_t b, uint64_t seed,
+                      void* stream, pg_sketches** out) {
+  clear_error();
+  pg_sketches* sk = nullptr;
+  PG_TRY(make_sketches(ctx, gc, kind, size, b, seed, (hipStream_t)stream, true, &sk));
+  sk->g->live_sketches++;
+  *out = sk;
+  return PG_OK;
+}
+
+int pg_sketches_import(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, uint32_t b, uint64_t seed,
+                       const void* rows, const uint32_t* pc, void* stream, pg_sketches** out) {
+  clear_error();
+  if (gc && gc->n > 0 && !rows) return fail(PG_E_INVALID, "rows is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  pg_sketches* sk = nullptr;
+  PG_TRY(make_sketches(ctx, gc, kind, size, b, seed, s, false, &sk));
+  const size_t n = (size_t)sk->g->n;
+  int rc = PG_OK;
+  if (n > 0) {
+    if (sk->kind == PG_BF) {
+      rc = bf_pack(sk, rows, pc, s);
+    } else if (hipMemcpyAsync(sk->sig, rows, n * sk->size * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+      rc = fail(PG_E_DEVICE, "row copy failed");
+    }
+  }
+  if (rc != PG_OK) {
+    (void)hipStreamSynchronize(s);
+    free_sketches(sk);
+    return rc;
+  }
+  sk->g->live_sketches++;
   *out = sk;
   return PG_OK;
 }

@@ -408,7 +408,41 @@ __global__ void k_bf_unpack(const uint64_t* __restrict__ words, int64_t n, uint3
   }
 }
 
+// Line-packed rows from a dense copy (row v at v * W words).
+__global__ void k_bf_pack(const uint64_t* __restrict__ dense, int64_t n, uint32_t W, uint64_t* __restrict__ words) {
+  const int64_t total = n * (int64_t)W;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = i / W;
+    words[bf_row_offset(v, W) + (i - v * W)] = dense[i];
+  }
+}
+
+// Ones of each dense row.
+__global__ void k_bf_popcounts(const uint64_t* __restrict__ dense, int64_t n, uint32_t W, uint32_t* __restrict__ pc) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t ones = 0;
+    for (uint32_t k = 0; k < W; ++k) ones += (uint32_t)__popcll(dense[v * W + k]);
+    pc[v] = ones;
+  }
+}
+
 }  // namespace
+
+int bf_pack(pg_sketches* sk, const void* rows, const uint32_t* pc, hipStream_t s) {
+  const int64_t n = sk->rows->n;
+  if (n <= 0) return PG_OK;
+  hipLaunchKernelGGL(k_bf_pack, dim3(grid_for(n * sk->W, kBlock, 65536)), dim3(kBlock), 0, s,
+                     (const uint64_t*)rows, n, sk->W, sk->words);
+  PG_LAUNCH_CHECK();
+  if (pc) {
+    PG_HIP(hipMemcpyAsync(sk->pc, pc, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+  } else {
+    hipLaunchKernelGGL(k_bf_popcounts, dim3(grid_for(n, kBlock, 65536)), dim3(kBlock), 0, s,
+                       (const uint64_t*)rows, n, sk->W, sk->pc);
+    PG_LAUNCH_CHECK();
+  }
+  return PG_OK;
+}
 
 int bf_unpack(const pg_sketches* sk, void* rows, hipStream_t s) {
   const int64_t n = sk->rows->n;

@@ -259,6 +259,9 @@ int build_khash(pg_sketches* sk, hipStream_t s);
 int build_onehash(pg_sketches* sk, hipStream_t s);
 // Dense row-major copy (n * W words) of line-packed Bloom-filter rows.
 int bf_unpack(const pg_sketches* sk, void* rows, hipStream_t s);
+// The inverse: line-packed rows from a dense copy, and the popcounts (copied
+// from pc, or counted from the rows when pc is NULL).
+int bf_pack(pg_sketches* sk, const void* rows, const uint32_t* pc, hipStream_t s);
 
 // ---- launchers (pg_estimate.hip) ---------------------------------------------
 int ensure_table(pg_sketches* sk, int est, hipStream_t s);
