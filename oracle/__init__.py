@@ -62,6 +62,7 @@ def _load():
         "or_exact_pairs": (None, [i32, i32p, i32p, i64, i32p, i32p, u32p]),
         "or_exact_tc_listing": (u64, [i32, i32p, i32p]),
         "or_four_cliques": (u64, [i32, i32p, i32p, i32p, ctypes.c_void_p, u32, u32, u64]),
+        "or_four_cliques_filters": (None, [i32, i32p, i32p, u64p, u32, u32, u64, u64p, u64p, u64p]),
         "or_bf_build": (None, [i32, i32p, i32p, u32, u32, u64, u64p, u32p]),
         "or_bf_of_set": (None, [i32, i32p, u32, u32, u64, u64p]),
         "or_bf_counts": (None, [u32, u64p, i64, i32p, i32p, u32p, u32p]),
@@ -502,6 +503,49 @@ def four_cliques_bf(g, sk_plus: Sketches) -> int:
     return int(_load().or_four_cliques(g.n, _ptr(po, ctypes.c_int32), _ptr(pa, ctypes.c_int32),
                                        _ptr(deg, ctypes.c_int32), words.ctypes.data_as(ctypes.c_void_p),
                                        sk_plus.size, sk_plus.b, sk_plus.seed & (2**64 - 1)))
+
+
+def four_cliques_filter_counts(g, sk_plus: Sketches):
+    """For every oriented edge (u, v) and every w in C3 = N+_u cap N+_v, the
+    ones c of (filter of N+_w) AND (filter of C3) and c_or of their OR, the
+    filter of C3 built with the hash functions of ``sk_plus`` (filters of the
+    oriented sets). Returns (hist_and, hist_or, sizes): how often each value
+    of c and of c_or occurs (B + 1 entries each) and the sum of |N+_w| + |C3|
+    over all (edge, w)."""
+    assert sk_plus.kind == KIND_BF
+    o = oriented(g)
+    po, pa = _i32(o.offsets), _i32(o.adj)
+    words = np.ascontiguousarray(sk_plus.words, dtype=np.uint64)
+    B = sk_plus.size
+    ha = np.zeros(B + 1, np.uint64)
+    ho = np.zeros(B + 1, np.uint64)
+    sizes = ctypes.c_uint64(0)
+    _load().or_four_cliques_filters(g.n, _ptr(po, ctypes.c_int32), _ptr(pa, ctypes.c_int32),
+                                    _ptr(words, ctypes.c_uint64), B, sk_plus.b, sk_plus.seed & (2**64 - 1),
+                                    _ptr(ha, ctypes.c_uint64), _ptr(ho, ctypes.c_uint64), ctypes.byref(sizes))
+    return ha, ho, int(sizes.value)
+
+
+def four_cliques_estimate(g, sk_plus: Sketches, est: str) -> float:
+    """4-cliques with |N+_w cap C3| estimated by a Bloom-filter estimator of
+    the intersection of N+_w and C3 (Listing "lst:fcl" with sketch
+    intersections): the sum over all (edge, w) of the estimate, formed as the
+    count of each value of c (or c_or) times the estimator at that value, plus
+    the exact integer sum of |N+_w| + |C3| for the OR estimator."""
+    ha, ho, sizes = four_cliques_filter_counts(g, sk_plus)
+    B, b = sk_plus.size, sk_plus.b
+    c = np.arange(B + 1)
+    if est == "and":
+        t = est_bf_and(c, B, b)
+    elif est == "l":
+        t = est_bf_limit(c, B, b)
+    elif est == "pap":
+        t = est_bf_papapetrou(c, B, b)
+    elif est == "or":
+        return float(sizes) + float(np.sum(ho.astype(np.float64) * est_bf_or(c, 0, 0, B, b)))
+    else:
+        raise ValueError(f"estimator {est} does not apply to Bloom filters")
+    return float(np.sum(ha.astype(np.float64) * t))
 
 
 def tc_oriented(g, sk_plus: Sketches, est: str) -> float:

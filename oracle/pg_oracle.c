@@ -231,7 +231,85 @@ uint64_t or_four_cliques(int32_t n, const int32_t* poff, const int32_t* padj, co
   return total;
 }
 
-/* ----------------------------------------------------------- Bloom filters *//* ----------------------------------------------------------- Bloom filters */
+/* 4-cliques with |N+_w intersect C3| estimated from two Bloom filters (the
+ * sketch-intersection form of Listing "lst:fcl", whose work bound counts
+ * B/W word operations per w): the filter of N+_w (words, B bits, b hash
+ * functions of seed) and, for each oriented edge, the filter of C3 built
+ * with the same functions. c is the number of ones of their AND and c_or of
+ * their OR. The AND, limit and existing-filter estimators are functions of c
+ * alone and the OR estimator of c_or and the sizes |N+_w| + |C3|, so the
+ * routine returns how often each value occurs over all (edge, w in C3):
+ * hist_and[c] and hist_or[c_or] (B + 1 entries each, overwritten), and the
+ * sum of |N+_w| + |C3| in *sizes. Every w in C3 takes part (no rank test):
+ * the filter of N+_w holds only vertices ranked above w anyway. */
+void or_four_cliques_filters(int32_t n, const int32_t* poff, const int32_t* padj, const uint64_t* words, uint32_t B,
+                             uint32_t b, uint64_t seed, uint64_t* hist_and, uint64_t* hist_or, uint64_t* sizes) {
+  int32_t maxd = 0;
+  for (int32_t v = 0; v < n; ++v)
+    if (poff[v + 1] - poff[v] > maxd) maxd = poff[v + 1] - poff[v];
+  const uint32_t W = B / 64;
+  uint64_t a[64], c[64];
+  or_hash_consts(1, seed, (int)b, a, c);
+  for (uint32_t t = 0; t <= B; ++t) hist_and[t] = hist_or[t] = 0;
+  uint64_t size_sum = 0;
+#pragma omp parallel reduction(+ : size_sum)
+  {
+    int32_t* c3 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(maxd > 0 ? maxd : 1));
+    uint64_t* f = (uint64_t*)malloc(sizeof(uint64_t) * W);
+    uint64_t* ha = (uint64_t*)calloc((size_t)B + 1, sizeof(uint64_t));
+    uint64_t* ho = (uint64_t*)calloc((size_t)B + 1, sizeof(uint64_t));
+    int32_t u;
+#pragma omp for schedule(dynamic, 64)
+    for (u = 0; u < n; ++u) {
+      for (int32_t p = poff[u]; p < poff[u + 1]; ++p) {
+        const int32_t v = padj[p];
+        int32_t i = poff[u], j = poff[v], s = 0;
+        while (i < poff[u + 1] && j < poff[v + 1]) {
+          if (padj[i] < padj[j])
+            ++i;
+          else if (padj[i] > padj[j])
+            ++j;
+          else {
+            c3[s++] = padj[i];
+            ++i;
+            ++j;
+          }
+        }
+        if (s == 0) continue;
+        for (uint32_t q = 0; q < W; ++q) f[q] = 0;
+        for (int32_t t = 0; t < s; ++t)
+          for (uint32_t h = 0; h < b; ++h) {
+            const uint32_t idx = or_bf_index(a[h], c[h], (uint32_t)c3[t], B);
+            f[idx >> 6] |= 1ull << (idx & 63);
+          }
+        for (int32_t t = 0; t < s; ++t) {
+          const int32_t w = c3[t];
+          const uint64_t* bw = words + (size_t)w * W;
+          uint32_t ones_and = 0, ones_or = 0;
+          for (uint32_t q = 0; q < W; ++q) {
+            ones_and += (uint32_t)__builtin_popcountll(bw[q] & f[q]);
+            ones_or += (uint32_t)__builtin_popcountll(bw[q] | f[q]);
+          }
+          ++ha[ones_and];
+          ++ho[ones_or];
+          size_sum += (uint64_t)(poff[w + 1] - poff[w]) + (uint64_t)s;
+        }
+      }
+    }
+#pragma omp critical
+    for (uint32_t t = 0; t <= B; ++t) {
+      hist_and[t] += ha[t];
+      hist_or[t] += ho[t];
+    }
+    free(ho);
+    free(ha);
+    free(f);
+    free(c3);
+  }
+  *sizes = size_sum;
+}
+
+/* ----------------------------------------------------------- Bloom filters */
 
 /* B_v: B bits (W = B/64 words), for each x in N_v and each of the b hash
  * functions set bit idx_i(x) (Section 2.4, "Bloom filters"). pc[v] is the

@@ -14,6 +14,8 @@ void or_exact_pairs(int32_t n, const int32_t* off, const int32_t* adj, int64_t n
 uint64_t or_exact_tc_listing(int32_t n, const int32_t* off, const int32_t* adj);
 uint64_t or_four_cliques(int32_t n, const int32_t* poff, const int32_t* padj, const int32_t* deg,
                          const uint64_t* words, uint32_t B, uint32_t b, uint64_t seed);
+void or_four_cliques_filters(int32_t n, const int32_t* poff, const int32_t* padj, const uint64_t* words, uint32_t B,
+                             uint32_t b, uint64_t seed, uint64_t* hist_and, uint64_t* hist_or, uint64_t* sizes);
 void or_bf_build(int32_t n, const int32_t* off, const int32_t* adj, uint32_t B, uint32_t b, uint64_t seed,
                  uint64_t* words, uint32_t* pc);
 void or_bf_counts(uint32_t W, const uint64_t* words, int64_t npairs, const int32_t* pu, const int32_t* pv,
@@ -85,11 +87,19 @@ int main(int argc, char** argv) {
   uint32_t* ppc = malloc(sizeof(uint32_t) * (size_t)n);
   or_bf_build(n, poff, padj, 128, 1, 5, pwords, ppc);
   const uint64_t ck_bf = or_four_cliques(n, poff, padj, deg, pwords, 128, 1, 5);
+  uint64_t hist_and[129], hist_or[129], ck_sizes = 0, ck_and = 0, ck_or = 0;
+  or_four_cliques_filters(n, poff, padj, pwords, 128, 1, 5, hist_and, hist_or, &ck_sizes);
+  for (int t = 0; t <= 128; ++t) {
+    ck_and += (uint64_t)t * hist_and[t];
+    ck_or += (uint64_t)t * hist_or[t];
+  }
 
-  printf("%lld %llu %llu %llu %llu %llu %llu %llu %llu %llu %llu %llu\n", (long long)m, (unsigned long long)tc,
+  printf("%lld %llu %llu %llu %llu %llu %llu %llu %llu %llu %llu %llu %llu %llu %llu\n", (long long)m,
+         (unsigned long long)tc,
          (unsigned long long)exact_sum, (unsigned long long)bf_and, (unsigned long long)bf_or,
          (unsigned long long)bf_pc, (unsigned long long)kh, (unsigned long long)oh_su, (unsigned long long)oh_kp,
-         (unsigned long long)oh_lit, (unsigned long long)ck, (unsigned long long)ck_bf);
+         (unsigned long long)oh_lit, (unsigned long long)ck, (unsigned long long)ck_bf,
+         (unsigned long long)ck_and, (unsigned long long)ck_or, (unsigned long long)ck_sizes);
   free(off); free(adj); free(poff); free(padj); free(deg); free(eu); free(ev); free(a); free(b); free(c);
   free(words); free(pc); free(sig); free(pwords); free(ppc);
   return 0;

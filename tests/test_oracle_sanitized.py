@@ -57,4 +57,7 @@ def test_oracle_c_under_sanitizers(tmp_path):
     want = [eu.shape[0], oracle.exact_tc_listing(g), int(oracle.exact_pairs(g, eu, ev).sum()), int(ca.sum()),
             int(co.sum()), int(bf.pc.sum()), int(kh.counts(eu, ev).sum()), int(su.sum()), int(kp.sum()),
             int(sl.sum()), oracle.four_cliques(g), oracle.four_cliques_bf(g, pbf)]
+    ha, ho, sizes = oracle.four_cliques_filter_counts(g, pbf)
+    c = np.arange(ha.shape[0], dtype=np.uint64)
+    want += [int((ha * c).sum()), int((ho * c).sum()), sizes]
     assert got == want
