@@ -404,10 +404,17 @@ def main():
         sko = dg.build_sketches("bf", B, 1, seed=args.seed, oriented=True)
         ck_bf = sko.four_cliques()
         ms_bf = timed(lambda: sko.four_cliques(), 5, sync)
+        ck_and = sko.four_cliques_estimate("and")
+        ms_and = timed(lambda: sko.four_cliques_estimate("and"), 5, sync)
+        ck_l = sko.four_cliques_estimate("l")
         ck_ex = dg.exact_four_cliques()
         ms_ex = timed(lambda: dg.exact_four_cliques(), 3, sync)
         rows["four_cliques"] = {"bf_ms": round(ms_bf, 4), "exact_ms": round(ms_ex, 4), "bf": ck_bf, "exact": ck_ex,
-                                "rel_err": (ck_bf - ck_ex) / max(ck_ex, 1), "speedup_bf_vs_exact": ms_ex / ms_bf}
+                                "rel_err": (ck_bf - ck_ex) / max(ck_ex, 1), "speedup_bf_vs_exact": ms_ex / ms_bf,
+                                "bf_and_ms": round(ms_and, 4), "bf_and": ck_and, "bf_limit": ck_l,
+                                "rel_err_and": (ck_and - ck_ex) / max(ck_ex, 1),
+                                "rel_err_limit": (ck_l - ck_ex) / max(ck_ex, 1),
+                                "speedup_bf_and_vs_exact": ms_ex / ms_and}
         sko.close()
         # clustering coefficient and Jaccard (BF AND, b = 1)
         ms = timed(lambda: sk.cc("and"), reps, sync)

@@ -272,7 +272,7 @@ int pg_clusters(pg_ctx* ctx, const pg_graph* g, const uint8_t* keep, int32_t* la
  * every w in C3 adds |N+_w cap C3|; each 4-clique counts once. *count is a
  * host pointer; the calls wait for `stream`. The triangle lists C3 are held
  * on chip: graphs whose largest oriented degree exceeds 4080 (exact) or 2720
- * (filters) give PG_E_UNSUPPORTED. */
+ * (membership queries) give PG_E_UNSUPPORTED. */
 /* Exact: |N+_w cap C3| by binary search in N+_w. */
 int pg_exact_four_cliques(pg_ctx* ctx, const pg_graph* g, uint64_t* count, void* stream);
 /* Estimated: |N+_w cap C3| = the number of x in C3 ranked above w (the only
@@ -281,6 +281,20 @@ int pg_exact_four_cliques(pg_ctx* ctx, const pg_graph* g, uint64_t* count, void*
  * estimate is never below the exact count). sk must hold Bloom filters of the
  * oriented sets (PG_BF | PG_ORIENTED), else PG_E_INVALID. */
 int pg_four_cliques(pg_ctx* ctx, const pg_sketches* sk, uint64_t* count, void* stream);
+/* Estimated with sketch intersections (the form whose work the paper bounds
+ * by B/W word operations per w): for every oriented edge the library builds a
+ * Bloom filter of C3 with the hash functions of sk, and |N+_w cap C3| is
+ * estimated from it and the filter of N+_w by `estimator`: PG_EST_BF_AND,
+ * PG_EST_BF_L or PG_EST_BF_PAPAPETROU (from the ones of the AND, Eqs.
+ * "bf_int", "limit_xs" and Section 8.1) or PG_EST_BF_OR (|N+_w| + |C3| and the
+ * ones of the OR, Eq. "bf_int_union"). *count (host) receives the FP64 sum
+ * over all (edge, w); it does not depend on scheduling. sk must hold Bloom
+ * filters of the oriented sets (PG_BF | PG_ORIENTED), else PG_E_INVALID; any
+ * other estimator gives PG_E_INVALID. PG_E_UNSUPPORTED when the estimator
+ * table (8 (B + 1) bytes) and four C3 buffers (8 W + 4 (d+_max + 1) bytes
+ * each, d+_max the largest oriented degree) exceed 128 KiB of LDS. Synchronises
+ * `stream`. */
+int pg_four_cliques_estimate(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* count, void* stream);
 
 /* Recompute the rows of existing sketches in place (same kind, size and b;
  * new hash constants from `seed`), e.g. after the graph's arrays changed or to

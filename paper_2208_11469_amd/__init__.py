@@ -147,6 +147,7 @@ def _declare(lib):
         "pg_clusters": (i, [_vp, _vp, _vp, _vp, P(i64), _vp]),
         "pg_exact_four_cliques": (i, [_vp, _vp, P(u64), _vp]),
         "pg_four_cliques": (i, [_vp, _vp, P(u64), _vp]),
+        "pg_four_cliques_estimate": (i, [_vp, _vp, i, P(ctypes.c_double), _vp]),
         "pg_sketches_rebuild": (i, [_vp, _vp, u64, _vp]),
         "pg_profile_enable": (i, [_vp, i]),
         "pg_profile_select": (i, [_vp, ctypes.c_char_p]),
@@ -387,6 +388,12 @@ def pg_exact_four_cliques(ctx, g, stream=None) -> int:
 def pg_four_cliques(ctx, sk, stream=None) -> int:
     out = ctypes.c_uint64(0)
     _check(load().pg_four_cliques(ctx, sk, ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def pg_four_cliques_estimate(ctx, sk, estimator, stream=None) -> float:
+    out = ctypes.c_double(0.0)
+    _check(load().pg_four_cliques_estimate(ctx, sk, estimator, ctypes.byref(out), _stream(stream)))
     return out.value
 
 
@@ -741,6 +748,11 @@ class Sketches:
     def four_cliques(self, stream=None) -> int:
         """4-clique estimate from Bloom filters of the oriented sets (build with oriented=True)."""
         return pg_four_cliques(self.graph.ctx.h, self.h, stream)
+
+    def four_cliques_estimate(self, estimator="and", stream=None) -> float:
+        """4-clique estimate with sketch intersections: |N+_w cap C3| from the filter of N+_w and a
+        filter of C3 (estimators "and", "l", "pap" or "or"; Bloom filters of the oriented sets)."""
+        return pg_four_cliques_estimate(self.graph.ctx.h, self.h, ESTIMATORS.get(estimator, estimator), stream)
 
     def jarvis_patrick(self, estimator, measure, tau, stream=None):
         """(keep, kept): uint8 mask over the m upper edges of the clustering (similarity > tau), and its size."""

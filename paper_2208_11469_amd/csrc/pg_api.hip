@@ -641,6 +641,21 @@ int pg_four_cliques(pg_ctx* ctx, const pg_sketches* sk, uint64_t* count, void* s
   return rc;
 }
 
+int pg_four_cliques_estimate(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* count, void* stream) {
+  clear_error();
+  if (!ctx || !sk || !count) return fail(PG_E_INVALID, "NULL argument");
+  if (sk->kind != PG_BF || !sk->oriented)
+    return fail(PG_E_INVALID, "4-cliques need Bloom filters of the oriented sets (PG_BF | PG_ORIENTED)");
+  PG_TRY(use_device(ctx));
+  hipStream_t s = (hipStream_t)stream;
+  double* d = nullptr;
+  PG_TRY(dmalloc((void**)&d, sizeof(double), s));
+  int rc = four_cliques_estimate(sk, estimator, d, s);
+  if (rc == PG_OK) rc = scalar_to_host(ctx, d, count, s);
+  dfree(d, s);
+  return rc;
+}
+
 int pg_clusters(pg_ctx* ctx, const pg_graph* g, const uint8_t* keep, int32_t* label, int64_t* nclusters,
                 void* stream) {
   clear_error();

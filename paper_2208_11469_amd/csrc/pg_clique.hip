@@ -196,7 +196,155 @@ __global__ __launch_bounds__(kBlock) void k_four_cliques(const int32_t* __restri
   if (threadIdx.x == 0 && block_count) atomicAdd(count, block_count);
 }
 
+// ---- sketch intersections: |N+_w cap C3| from two filters -------------------
+//
+// The estimate of Listing "lst:fcl" with a sketch intersection per w: the
+// wave builds C3 as above and, in the same pass, the filter of C3 in its LDS
+// slice (B bits, the b hash functions of the sketch set, set with LDS
+// atomics); every w in C3 then takes one lane, which reads the filter row of
+// N+_w and counts the ones of its AND (or OR) with the filter of C3. The
+// estimator table (B + 1 entries) sits in LDS. Each lane adds its estimates in
+// a fixed order and every block writes one partial, so the FP64 result does
+// not depend on scheduling.
+template <int WT, bool OR>
+__global__ __launch_bounds__(kBlock) void k_four_cliques_filters(const int32_t* __restrict__ poff,
+                                                                 const int32_t* __restrict__ padj,
+                                                                 const int32_t* __restrict__ parc_src, int64_t m,
+                                                                 int32_t cap, CliqueFilters f,
+                                                                 const double* __restrict__ table,
+                                                                 double* __restrict__ partials) {
+  extern __shared__ double tab[];  // [estimator table: B + 1] then the wave slices
+  __shared__ double red[kWaves];
+  const uint32_t W = WT > 0 ? (uint32_t)WT : f.W;
+  for (uint32_t i = threadIdx.x; i <= f.B; i += kBlock) tab[i] = table[i];
+  const int wave = (int)threadIdx.x / kWave;
+  const int lane = lane_id();
+  // wave slice: [filter of C3: W words] [ids: cap], cap even
+  uint64_t* fc = reinterpret_cast<uint64_t*>(tab + f.B + 1) + (size_t)wave * ((size_t)W + (size_t)cap / 2);
+  uint32_t* fc32 = reinterpret_cast<uint32_t*>(fc);
+  int32_t* ids = reinterpret_cast<int32_t*>(fc + W);
+  __syncthreads();
+  double acc = 0.0;
+  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  for (int64_t e = (int64_t)blockIdx.x * kWaves + wave; e < m; e += nwaves) {
+    const int32_t u = parc_src[e], v = padj[e];
+    const int32_t* A = padj + poff[u];
+    int32_t na = poff[u + 1] - poff[u];
+    const int32_t* L = padj + poff[v];
+    int32_t nl = poff[v + 1] - poff[v];
+    if (na > nl) {
+      const int32_t* t = A;
+      A = L;
+      L = t;
+      const int32_t tn = na;
+      na = nl;
+      nl = tn;
+    }
+    for (uint32_t i = (uint32_t)lane; i < 2 * W; i += kWave) fc32[i] = 0;
+    wave_sync();
+    int32_t s = 0;
+    for (int32_t base = 0; base < na; base += kWave) {
+      const int32_t i = base + lane;
+      int32_t a = 0;
+      bool hit = false;
+      if (i < na) {
+        a = A[i];
+        hit = sorted_contains(L, nl, a);
+      }
+      const uint64_t ball = __ballot(hit);
+      if (hit) {
+        ids[s + (int32_t)__popcll(ball & ((1ull << lane) - 1ull))] = a;
+        for (uint32_t h = 0; h < f.b; ++h) {
+          const uint32_t idx = bf_index(f.ha[h], f.hc[h], (uint32_t)a, f.B);
+          atomicOr(&fc32[idx >> 5], 1u << (idx & 31u));  // bit t: bit t & 63 of word t >> 6
+        }
+      }
+      s += (int32_t)__popcll(ball);
+    }
+    wave_sync();
+    for (int32_t i = lane; i < s; i += kWave) {
+      const int32_t w = ids[i];
+      const uint64_t* row = filter_row<WT>(f, w);
+      uint32_t c = 0;
+      if constexpr (WT > 0) {
+        uint64_t r[WT];
+#pragma unroll
+        for (int j = 0; j < WT; ++j) r[j] = row[j];
+#pragma unroll
+        for (int j = 0; j < WT; ++j) c += (uint32_t)__popcll(OR ? (r[j] | fc[j]) : (r[j] & fc[j]));
+      } else {
+        for (uint32_t j = 0; j < W; ++j) c += (uint32_t)__popcll(OR ? (row[j] | fc[j]) : (row[j] & fc[j]));
+      }
+      if constexpr (OR)
+        acc += ((double)(poff[w + 1] - poff[w]) + (double)s) + tab[c];
+      else
+        acc += tab[c];
+    }
+    wave_sync();  // the next edge clears this wave's slice
+  }
+  const double r = block_sum_256(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
 }  // namespace
+
+// The 4-clique estimate from sketch intersections into d_out[0] (device FP64):
+// est is PG_EST_BF_AND, _L or _PAPAPETROU (a function of the ones of the AND)
+// or PG_EST_BF_OR (|N+_w| + |C3| and the ones of the OR).
+int four_cliques_estimate(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
+  if (est != PG_EST_BF_AND && est != PG_EST_BF_L && est != PG_EST_BF_OR && est != PG_EST_BF_PAPAPETROU)
+    return fail(PG_E_INVALID, "4-clique estimates take a Bloom-filter estimator");
+  pg_graph* g = sk->g;
+  PG_TRY(graph_oriented(g, s));
+  PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
+  PG_TRY(fill_u64((uint64_t*)d_out, 0, 1, s));  // 0.0
+  if (g->m <= 0) return PG_OK;
+  const int32_t cap = (std::max(1, g->oriented->max_degree) + 1) & ~1;
+  const size_t shmem =
+      sizeof(double) * ((size_t)sk->size + 1) + sizeof(uint64_t) * ((size_t)sk->W + (size_t)cap / 2) * kWaves;
+  if (shmem > (size_t)kMaxLdsBytes)
+    return fail(PG_E_UNSUPPORTED, "4-cliques: the filter size and the largest oriented degree exceed the on-chip buffers");
+  CliqueFilters f{sk->words, sk->ha, sk->hc, sk->size, sk->W, sk->b};
+  const unsigned grid = (unsigned)std::max<int64_t>(
+      1, std::min<int64_t>((g->m + kWaves - 1) / kWaves, (int64_t)std::max(1, g->ctx->num_cus) * 8));
+  double* partials = nullptr;
+  PG_TRY(dmalloc((void**)&partials, sizeof(double) * grid, s));
+  {
+    ProfScope ps(s, "four_cliques_filters");
+#define PG_CKF(WW)                                                                                                \
+  do {                                                                                                            \
+    if (est == PG_EST_BF_OR)                                                                                      \
+      hipLaunchKernelGGL((k_four_cliques_filters<WW, true>), dim3(grid), dim3(kBlock), shmem, s, g->poff, g->padj, \
+                         g->parc_src, g->m, cap, f, (const double*)sk->table, partials);                          \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_four_cliques_filters<WW, false>), dim3(grid), dim3(kBlock), shmem, s, g->poff,        \
+                         g->padj, g->parc_src, g->m, cap, f, (const double*)sk->table, partials);                 \
+  } while (0)
+    switch (sk->W) {
+      case 1: PG_CKF(1); break;
+      case 2: PG_CKF(2); break;
+      case 3: PG_CKF(3); break;
+      case 4: PG_CKF(4); break;
+      case 5: PG_CKF(5); break;
+      case 6: PG_CKF(6); break;
+      case 7: PG_CKF(7); break;
+      case 8: PG_CKF(8); break;
+      case 9: PG_CKF(9); break;
+      case 10: PG_CKF(10); break;
+      case 11: PG_CKF(11); break;
+      case 12: PG_CKF(12); break;
+      case 13: PG_CKF(13); break;
+      case 14: PG_CKF(14); break;
+      case 15: PG_CKF(15); break;
+      case 16: PG_CKF(16); break;
+      default: PG_CKF(0); break;  // rows wider than 16 words are dense
+    }
+#undef PG_CKF
+    PG_LAUNCH_CHECK();
+  }
+  PG_TRY(sum_chunks(partials, grid, 1.0, d_out, s));
+  return dfree(partials, s);
+}
 
 // The 4-clique count into d_count[0]: exact (sk == nullptr) or with Bloom
 // filters of the oriented sets.

@@ -295,6 +295,9 @@ int exact_jp(const pg_graph* g, int algo, int measure, double tau, uint8_t* keep
 // ---- launchers (pg_clique.hip) -----------------------------------------------
 // 4-clique count into d_count[0]: exact (sk NULL) or from Bloom filters of N+.
 int four_cliques(pg_graph* g, const pg_sketches* sk, unsigned long long* d_count, hipStream_t s);
+// 4-clique estimate from the AND / OR of the filter of N+_w and a filter of C3,
+// FP64 into d_out[0] (device); sk holds Bloom filters of the oriented sets.
+int four_cliques_estimate(const pg_sketches* sk, int est, double* d_out, hipStream_t s);
 
 // ---- launchers (pg_cluster.hip) ----------------------------------------------
 // Connected components of the kept upper edges (keep NULL: all); label[v] =

@@ -1,6 +1,9 @@
 """GPU parity of 4-clique counting (Listing "lst:fcl"), exact and from Bloom
-filters of the oriented sets, through the C ABI, against the oracle: both
-counts are integers and must match bit for bit."""
+filters of the oriented sets, through the C ABI, against the oracle: the exact
+and membership counts are integers and must match bit for bit; the estimates
+from sketch intersections (filter of N+_w against a filter of C3) are FP64
+sums that must match within 1e-9 relative (reassociation only), and bit for
+bit for the limit estimator with b <= 2 (sums of multiples of 1/2)."""
 import math
 import sys
 
@@ -103,5 +106,93 @@ def test_rmat18_four_cliques(ctx):
     sk = dg.build_sketches("bf", B, 1, seed=1, oriented=True)
     ref = oracle.build_sketches(oracle.oriented(g), oracle.KIND_BF, B, 1, seed=1)
     assert sk.four_cliques() == oracle.four_cliques_bf(g, ref)
+    sk.close()
+    dg.close()
+
+
+FILTER_ESTS = ("and", "l", "pap", "or")
+
+
+def _check_estimates(g, sk, ref, b):
+    for est in FILTER_ESTS:
+        got = sk.four_cliques_estimate(est)
+        want = oracle.four_cliques_estimate(g, ref, est)
+        if est == "l" and b <= 2:
+            assert got == want, (est, got, want)
+        else:
+            assert abs(got - want) <= 1e-9 * max(abs(want), 1.0), (est, got, want)
+        assert sk.four_cliques_estimate(est) == got  # independent of scheduling
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_four_clique_filter_estimates_match_oracle(ctx, name):
+    g = GRAPHS[name]()
+    B, b = BF[name]
+    say(f"4-clique filter estimates {name} B={B} b={b}")
+    dg = pg.Graph(ctx, g.offsets, g.adj)
+    sk = dg.build_sketches("bf", B, b, seed=7, oriented=True)
+    ref = oracle.build_sketches(oracle.oriented(g), oracle.KIND_BF, B, b, seed=7)
+    _check_estimates(g, sk, ref, b)
+    if name in ("no_k4", "isolated"):
+        assert sk.four_cliques_estimate("l") == oracle.four_cliques_estimate(g, ref, "l")
+    sk.close()
+    dg.close()
+
+
+def test_four_clique_filter_limit_exact_with_injective_hash(ctx):
+    # every vertex on its own bit: c = |N+_w cap C3| and the limit estimate is the exact count
+    g = pggen.er(100, 20, seed=4)
+    B = 4096
+    for seed in range(1, 400):
+        a, c = oracle.hash_consts(oracle.KIND_BF, seed, 1)
+        if len({oracle.bf_index(int(a[0]), int(c[0]), x, B) for x in range(g.n)}) == g.n:
+            break
+    else:
+        raise AssertionError("no injective seed found")
+    dg = pg.Graph(ctx, g.offsets, g.adj)
+    sk = dg.build_sketches("bf", B, 1, seed=seed, oriented=True)
+    exact = dg.exact_four_cliques()
+    assert exact > 0 and sk.four_cliques_estimate("l") == float(exact)
+    sk.close()
+    dg.close()
+
+
+def test_four_clique_filter_estimates_refusals(ctx):
+    g = GRAPHS["rmat12"]()
+    dg = pg.Graph(ctx, g.offsets, g.adj)
+    for kind, oriented in (("bf", False), ("kh", True)):
+        sk = dg.build_sketches(kind, 64, 1, seed=1, oriented=oriented)
+        with pytest.raises(pg.PGError) as err:
+            sk.four_cliques_estimate("and")
+        assert err.value.code == pg.PG_E_INVALID
+        sk.close()
+    sk = dg.build_sketches("bf", 256, 1, seed=1, oriented=True)
+    with pytest.raises(pg.PGError) as err:
+        sk.four_cliques_estimate("kh")
+    assert err.value.code == pg.PG_E_INVALID
+    sk.close()
+    dg.close()
+    # K_6100 with 4096-bit filters: the table (32.8 KB) and four C3 buffers of
+    # oriented degree up to 6099 (24.9 KB each) exceed 128 KiB of LDS
+    g = pggen.complete(6100)
+    dg = pg.Graph(ctx, g.offsets, g.adj)
+    sk = dg.build_sketches("bf", 4096, 1, seed=1, oriented=True)
+    with pytest.raises(pg.PGError) as err:
+        sk.four_cliques_estimate("and")
+    assert err.value.code == pg.PG_E_UNSUPPORTED
+    sk.close()
+    dg.close()
+
+
+@pytest.mark.timeout(600)
+def test_rmat18_four_clique_filter_estimates(ctx):
+    say("generating R-MAT scale 18, edge factor 16")
+    g = pggen.rmat(18, 16, seed=1)
+    dg = pg.Graph(ctx, g.offsets, g.adj)
+    B = dg.bits_for_budget(0.33)
+    say(f"BF-{B} 4-clique filter estimates")
+    sk = dg.build_sketches("bf", B, 1, seed=1, oriented=True)
+    ref = oracle.build_sketches(oracle.oriented(g), oracle.KIND_BF, B, 1, seed=1)
+    _check_estimates(g, sk, ref, 1)
     sk.close()
     dg.close()
