@@ -124,10 +124,14 @@ def _check_estimates(g, sk, ref, b):
         assert sk.four_cliques_estimate(est) == got  # independent of scheduling
 
 
-@pytest.mark.parametrize("name", list(GRAPHS))
+FILTER_GRAPHS = dict(GRAPHS, k1200=lambda: pggen.complete(1200))  # C3 of up to 1198 elements
+FILTER_BF = dict(BF, k1200=(320, 1))
+
+
+@pytest.mark.parametrize("name", list(FILTER_GRAPHS))
 def test_four_clique_filter_estimates_match_oracle(ctx, name):
-    g = GRAPHS[name]()
-    B, b = BF[name]
+    g = FILTER_GRAPHS[name]()
+    B, b = FILTER_BF[name]
     say(f"4-clique filter estimates {name} B={B} b={b}")
     dg = pg.Graph(ctx, g.offsets, g.adj)
     sk = dg.build_sketches("bf", B, b, seed=7, oriented=True)
