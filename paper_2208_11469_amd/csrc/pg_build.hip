@@ -430,6 +430,7 @@ __global__ void k_bf_popcounts(const uint64_t* __restrict__ dense, int64_t n, ui
 
 int bf_pack(pg_sketches* sk, const void* rows, const uint32_t* pc, hipStream_t s) {
   const int64_t n = sk->rows->n;
+  sk->empty_rows_zero = false;  // the next build writes every row again
   if (n <= 0) return PG_OK;
   hipLaunchKernelGGL(k_bf_pack, dim3(grid_for(n * sk->W, kBlock, 65536)), dim3(kBlock), 0, s,
                      (const uint64_t*)rows, n, sk->W, sk->words);
@@ -459,8 +460,12 @@ int build_bf(pg_sketches* sk, hipStream_t s) {
   const uint32_t W = sk->W;
   if (W <= 16 && g->n > 0) {
     const VertexPlan& P = g->plan_all;
-    const PlanView pv = plan_view(P);
-    const unsigned grid = (unsigned)plan_blocks(P);
+    PlanView pv = plan_view(P);
+    // the rows of vertices without arcs (the tail of the light list) are
+    // zero under every seed: once written, later builds leave them
+    if (sk->empty_rows_zero) pv.n_light -= P.n_empty;
+    const unsigned grid = (unsigned)(P.n_chunks + pv.n_medium_blocks + (pv.n_light * kLightGroup + kBlock - 1) / kBlock);
+    if (grid == 0) return PG_OK;  // every vertex without arcs, rows already zero
     const unsigned cgrid = (unsigned)((P.n_heavy * kWave + kBlock - 1) / kBlock);
 #define PG_BFP(WW)                                                                                                 \
   do {                                                                                                             \
@@ -490,6 +495,7 @@ int build_bf(pg_sketches* sk, hipStream_t s) {
     }
 #undef PG_BFP
     PG_LAUNCH_CHECK();
+    sk->empty_rows_zero = true;
     return PG_OK;
   }
   if (g->n > 0) {  // filters wider than 16 words

@@ -353,7 +353,7 @@ int exact_cc(pg_graph* g, float* cc, hipStream_t s) {
                        (uint32_t*)nullptr, (unsigned long long*)vsum);
     PG_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_exact_cc_finish, dim3(grid_for(g->n, kBlock)), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(k_exact_cc_finish, dim3(grid_for(g->n, kBlock, INT32_MAX)), dim3(kBlock), 0, s,
                      (const unsigned long long*)vsum, g->deg, g->n, cc);
   PG_LAUNCH_CHECK();
   return dfree(vsum, s);

@@ -113,6 +113,13 @@ __global__ void k_degree_bin_keys(const int32_t* __restrict__ deg, int32_t n, ui
 // Plan tier of a count of arcs: 1 light, 2 medium, 3 heavy.
 __device__ __forceinline__ uint8_t plan_tier(int64_t d) { return d <= kLightMax ? 1 : (d <= kMediumMax ? 2 : 3); }
 
+// Vertices without arcs, added into *count (one atomic per wave).
+__global__ void k_count_empty(const int32_t* __restrict__ off, int32_t n, unsigned long long* __restrict__ count) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const uint64_t ball = __ballot(v < n && off[v + 1] == off[v]);
+  if (lane_id() == 0 && ball) atomicAdd(count, (unsigned long long)__popcll(ball));
+}
+
 __global__ void k_plan_keys(const int32_t* __restrict__ off, int32_t n, uint8_t* __restrict__ key) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v < n) key[v] = plan_tier(off[v + 1] - off[v]);
@@ -725,6 +732,20 @@ int build_plan(pg_graph* g, VertexPlan* P, hipStream_t s) {
   P->light = P->sorted + starts[1];
   P->n_light = starts[2] - starts[1];
   PG_TRY(sort_light_list(P->light, P->n_light, -1, g, g->off, g->off, nullptr, s));  // by full degree
+  {  // vertices without arcs: light, and last in the descending order
+    unsigned long long* d_empty = nullptr;
+    PG_TRY(dmalloc((void**)&d_empty, sizeof(unsigned long long), s));
+    PG_TRY(fill_u64((uint64_t*)d_empty, 0, 1, s));
+    if (n > 0) {
+      hipLaunchKernelGGL(k_count_empty, dim3(grid_for(n, kBlock, INT32_MAX)), dim3(kBlock), 0, s, g->off, n, d_empty);
+      PG_LAUNCH_CHECK();
+    }
+    unsigned long long h_empty = 0;
+    PG_HIP(hipMemcpyAsync(&h_empty, d_empty, sizeof(h_empty), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    PG_TRY(dfree(d_empty, s));
+    P->n_empty = (int64_t)h_empty;
+  }
   P->medium = P->sorted + starts[2];
   P->n_medium = starts[3] - starts[2];
   P->n_heavy = starts[4] - starts[3];
@@ -749,7 +770,7 @@ static int degrees_and_bins(pg_graph* g, int* d_maxdeg, unsigned long long* d_we
   const int32_t n = g->n;
   PG_TRY(palloc((void**)&g->deg, sizeof(int32_t) * (size_t)std::max<int32_t>(n, 1)));
   if (n > 0) {
-    hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, g->off, n, g->deg, d_maxdeg,
+    hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, kBlock, INT32_MAX)), dim3(kBlock), 0, s, g->off, n, g->deg, d_maxdeg,
                        d_wedges);
     PG_LAUNCH_CHECK();
   }
@@ -779,7 +800,7 @@ int graph_prepare(pg_graph* g, bool validate, hipStream_t s) {
 
   // 1. bounds: offsets monotone in [0, nnz], IDs in [0, n). After this every
   //    later kernel's indexing stays inside the arrays.
-  hipLaunchKernelGGL(k_check_offsets, dim3(grid_for((int64_t)n + 1, kBlock)), dim3(kBlock), 0, s, g->off, n, g->nnz,
+  hipLaunchKernelGGL(k_check_offsets, dim3(grid_for((int64_t)n + 1, kBlock, INT32_MAX)), dim3(kBlock), 0, s, g->off, n, g->nnz,
                      d_flags);
   PG_LAUNCH_CHECK();
   int h_flags = 0;

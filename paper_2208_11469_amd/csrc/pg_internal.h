@@ -75,6 +75,7 @@ constexpr int kLightGroup = 4;
 struct VertexPlan {
   int64_t n_light = 0;
   int32_t* light = nullptr;       // [n_light] light vertices, by descending degree
+  int64_t n_empty = 0;            // vertices without arcs: the last n_empty of the light list
   int64_t n_medium = 0;
   int32_t* medium = nullptr;      // [n_medium] medium vertices, ascending
   int64_t n_chunks = 0;
@@ -233,6 +234,7 @@ struct pg_sketches {
   uint64_t* ha = nullptr;     // device hash multipliers
   uint64_t* hc = nullptr;     // device hash increments
   double* table = nullptr;    // [B+1]  estimator table (Bloom filters)
+  bool empty_rows_zero = false;  // Bloom filters: the rows of vertices without arcs are known to be zero
   uint64_t* scratch = nullptr;    // partial rows of heavy chunks (plan_all.n_chunks * W words)
   int table_est = 0;          // estimator the table holds
 };

@@ -130,3 +130,35 @@ def test_import_rejects_bad_parameters(ctx, graph):
     h = pg._vp()
     assert lib.pg_sketches_import(ctx.h, dg.h, pg.PG_BF, 320, 1, 1, None, None, None,
                                   pg.ctypes.byref(h)) == pg.PG_E_INVALID
+
+
+@pytest.mark.parametrize("oriented", [False, True])
+def test_rebuilds_keep_rows_of_empty_sets_zero(ctx, oriented):
+    """Builds after the first leave the rows of vertices without neighbours (in
+    the sketched lists) untouched, as they are zero under every seed; an import
+    can bring other rows, so the build after it writes every row again."""
+    g = pggen.disjoint_union(pggen.er(500, 8, seed=2), pggen.from_pairs(300, [], []), pggen.star(40))
+    dg = pg.Graph(ctx, g.offsets, g.adj)
+    src = oracle.oriented(g) if oriented else g
+    empty = np.flatnonzero(np.diff(src.offsets) == 0)
+    assert empty.size >= 300
+    sk = dg.build_sketches("bf", 320, 1, seed=3, oriented=oriented)
+    for seed in (4, 5, 3):  # consecutive rebuilds: every row is the oracle's
+        sk.rebuild(seed)
+        rows, pc = sk.export()
+        torch.cuda.synchronize()
+        ref = oracle.build_sketches(src, oracle.KIND_BF, 320, 1, seed=seed)
+        assert np.array_equal(np_(rows), ref.words.view(np.uint8).reshape(g.n, -1))
+        assert np.array_equal(np_(pc).astype(np.uint32), ref.pc)
+    noisy = rows.clone()
+    noisy[torch.from_numpy(empty).to(noisy.device)] = 0xA5
+    sk2 = dg.import_sketches("bf", 320, 1, 3, noisy, None, oriented=oriented)
+    r_noisy, _ = sk2.export()
+    assert torch.equal(r_noisy, noisy)
+    sk2.rebuild()
+    r2, p2 = sk2.export()
+    torch.cuda.synchronize()
+    assert torch.equal(r2, rows) and torch.equal(p2, pc)
+    sk2.close()
+    sk.close()
+    dg.close()
