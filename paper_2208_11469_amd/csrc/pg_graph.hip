@@ -553,7 +553,7 @@ int sum_array(const double* x, int64_t count, double divisor, double* out, hipSt
   const int64_t nchunks = std::max<int64_t>(1, (count + kScanTile - 1) / kScanTile);
   double* chunks = nullptr;
   PG_TRY(dmalloc((void**)&chunks, sizeof(double) * nchunks, s));
-  PG_HIP(hipMemsetAsync(chunks, 0, sizeof(double) * nchunks, s));
+  PG_TRY(fill_u64((uint64_t*)chunks, 0, nchunks, s));  // a kernel, not a memset node, under graph capture
   if (count > 0) {
     hipLaunchKernelGGL(k_array_chunks, dim3((unsigned)std::min<int64_t>(nchunks, 65536)), dim3(kBlock), 0, s, x, count,
                        chunks);
