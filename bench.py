@@ -24,6 +24,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import statistics
 import sys
@@ -221,6 +222,26 @@ def measure_scale24(args, pg, pggen, torch, ctx, sync, log):
     return out
 
 
+def median_ci95(x):
+    """Median of the samples and a distribution-free 95% confidence interval
+    for it: the order statistics x_(k), x_(n-k+1) with k the largest rank
+    such that P(Bin(n, 1/2) <= k - 1) <= 0.025 (coverage >= 95%)."""
+    x = sorted(x)
+    n = len(x)
+    cdf, k = 0.0, 0
+    while cdf + math.comb(n, k) / 2.0**n <= 0.025:
+        cdf += math.comb(n, k) / 2.0**n
+        k += 1
+    if k >= 1:
+        lo, hi, coverage = x[k - 1], x[n - k], 1.0 - 2.0 * cdf
+    else:  # too few samples: the whole range, whose coverage falls short of 95%
+        lo, hi, coverage = x[0], x[-1], 1.0 - 2.0 / 2.0**n
+    med = x[n // 2] if n % 2 else 0.5 * (x[n // 2 - 1] + x[n // 2])
+    return {"median_ms_per_step": round(med, 5), "ci95_ms_per_step": [round(lo, 5), round(hi, 5)],
+            "ci_coverage": round(coverage, 4), "min_ms_per_step": round(x[0], 5),
+            "max_ms_per_step": round(x[-1], 5)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,6 +330,20 @@ def main():
     pg.pg_profile_enable(ctx.h, False)
     prof_phases = pg.pg_profile_read(ctx.h)
     pg.pg_profile_reset(ctx.h)
+    # repetitions for the median and its 95% non-parametric confidence
+    # interval (the paper's reporting), each rep of 10 steps bracketed by HIP
+    # events on the launch stream; `value` stays the timed region above
+    rep_ms = []
+    for _ in range(30):
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        r0.record()
+        for _ in range(10):
+            step()
+        r1.record()
+        r1.synchronize()
+        rep_ms.append(r0.elapsed_time(r1) / 10)
+    step_stats = {"reps": len(rep_ms), "steps_per_rep": 10, **median_ci95(rep_ms),
+                  "timer": "HIP events on the launch stream"}
     value = m / (ms_per_step * 1e-3)
     tc_bf = float(d_tc.item())
     tc_sync = sk.tc("and")
@@ -511,6 +546,7 @@ def main():
         "ms_per_step_synchronous": round(sync_ms, 4),
         "copy_kernel_gbs": round(copy_gbs, 1),
         "phases": phases,
+        "step_stats": step_stats,
         "rows": rows,
         "serving": serving,
         "batch": batch,
