@@ -464,6 +464,26 @@ def main():
         rows["exact_edges"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
         ms = timed(lambda: dg.exact_cc(), 3, sync)
         rows["exact_cc"] = {"ms": round(ms, 4)}
+        # accuracy of the BF AND estimates on every edge and vertex: per-edge
+        # relative error where I > 0, mean absolute error where I = 0, CC mean
+        # absolute error, Jaccard absolute error quantiles
+        qs = (0.05, 0.25, 0.5, 0.75, 0.95)
+
+        def quantiles(t):
+            t = torch.sort(t.flatten())[0]
+            return [round(float(t[int(q * (t.numel() - 1))]), 5) for q in qs] if t.numel() else []
+
+        i_ex = dg.exact_intersect().double()
+        i_bf = sk.intersect("and", want_raw=False)[0].double()
+        pos = i_ex > 0
+        rows["accuracy_bf_and"] = {
+            "quantiles": list(qs),
+            "edges_I_pos": int(pos.sum()), "edges_I_zero": int((~pos).sum()),
+            "intersection_rel_err_I_pos": quantiles((i_bf[pos] - i_ex[pos]).abs() / i_ex[pos]),
+            "intersection_mae_I_zero": round(float(i_bf[~pos].abs().mean()), 5) if bool((~pos).any()) else None,
+            "cc_mae": round(float((sk.cc("and").double() - dg.exact_cc().double()).abs().mean()), 6),
+            "jaccard_abs_err": quantiles((sk.jaccard("and").double() - dg.exact_jaccard().double()).abs())}
+        del i_ex, i_bf, pos
         # the bitmap variant of the exact baseline (all upper edges; triangle count)
         ms = timed(lambda: dg.exact_intersect(algo=pg.PG_EXACT_BITMAP), 3, sync)
         rows["exact_edges_bitmap"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
