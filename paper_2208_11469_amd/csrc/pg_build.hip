@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_bf_build_plan(PlanView P, const int3
   const int64_t beg = active ? off[v] : 0, end = active ? off[v + 1] : 0;
   for (int k = lane; k < W; k += kLightGroup) bits[k] = 0;
   wave_sync();
-  if (active) bf_scatter<4, kLightGroup>(adj, beg, end, lane, B, b, ha, hc, bits);
+  if (active) bf_scatter<kLightUnroll, kLightGroup>(adj, beg, end, lane, B, b, ha, hc, bits);
   wave_sync();
   uint32_t ones = 0;
   if (active) {

@@ -403,9 +403,11 @@ __global__ void k_slab_split(const int32_t* __restrict__ off, const int32_t* __r
   }
 }
 
-// Arc count of listed items: of (x, v) for slab x >= 0, else off[v+1] -
-// ustart[v] (upper neighbours, or all of N_v when ustart = off). At most 255.
-__global__ void k_item_keys(const int32_t* __restrict__ verts, int64_t count, int x, const int32_t* __restrict__ off,
+// Sort key of listed items: ceil(arcs / bucket), the arcs of (x, v) for slab
+// x >= 0, else off[v+1] - ustart[v] (upper neighbours, or all of N_v when
+// ustart = off). At most 255 arcs.
+__global__ void k_item_keys(const int32_t* __restrict__ verts, int64_t count, int x, int bucket,
+                            const int32_t* __restrict__ off,
                             const int32_t* __restrict__ ustart, const int32_t* __restrict__ split, int32_t n,
                             uint8_t* __restrict__ key) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -413,7 +415,7 @@ __global__ void k_item_keys(const int32_t* __restrict__ verts, int64_t count, in
   const int32_t v = verts[i];
   const int64_t d = x < 0 ? off[v + 1] - ustart[v]
                           : slab_end(off, split, (size_t)n, x, v) - slab_begin(ustart, split, (size_t)n, x, v);
-  key[i] = (uint8_t)d;
+  key[i] = (uint8_t)((d + bucket - 1) / bucket);  // ceil(d / bucket): 0 only without arcs
 }
 
 // Complemented 2-bit digit `pass` of a key: partitioning by it, least
@@ -659,15 +661,19 @@ int sort_desc_small(int32_t* vals, uint8_t* key, int64_t count, hipStream_t s) {
   return dfree(perm, s);
 }
 
-// Sorts a light list (slab x, or whole vertices for x < 0) by descending arc
-// count, so the lanes of a wave walk about equally many arcs.
-int sort_light_list(int32_t* verts, int64_t count, int x, pg_graph* g, const int32_t* off, const int32_t* ustart,
-                    const int32_t* split, hipStream_t s) {
+// Sorts a light list (slab x, or whole vertices for x < 0) by descending
+// ceil(arcs / bucket), keeping ID order among equal keys (stable radix). With
+// bucket = the arcs a group of the consuming kernel covers per pass, the
+// groups of a wave take equally many passes while neighbouring groups keep
+// nearby IDs, so their offsets, rows and outputs share cache lines. Items
+// without arcs end the list.
+int sort_light_list(int32_t* verts, int64_t count, int x, int bucket, pg_graph* g, const int32_t* off,
+                    const int32_t* ustart, const int32_t* split, hipStream_t s) {
   if (count <= 1) return PG_OK;
   uint8_t* key = nullptr;
   PG_TRY(dmalloc((void**)&key, (size_t)count, s));
   hipLaunchKernelGGL(k_item_keys, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     (const int32_t*)verts, count, x, off, ustart, split, g->n, key);
+                     (const int32_t*)verts, count, x, bucket, off, ustart, split, g->n, key);
   PG_LAUNCH_CHECK();
   PG_TRY(sort_desc_small(verts, key, count, s));
   return dfree(key, s);
@@ -731,7 +737,7 @@ int build_plan(pg_graph* g, VertexPlan* P, hipStream_t s) {
   PG_TRY(partition(g, true, P->sorted, starts, s));
   P->light = P->sorted + starts[1];
   P->n_light = starts[2] - starts[1];
-  PG_TRY(sort_light_list(P->light, P->n_light, -1, g, g->off, g->off, nullptr, s));  // by full degree
+  PG_TRY(sort_light_list(P->light, P->n_light, -1, kLightGroup * kLightUnroll, g, g->off, g->off, nullptr, s));
   {  // vertices without arcs: light, and last in the descending order
     unsigned long long* d_empty = nullptr;
     PG_TRY(dmalloc((void**)&d_empty, sizeof(unsigned long long), s));
@@ -1000,8 +1006,9 @@ int graph_slabs(pg_graph* g, hipStream_t s) {
       at += cnt_x;
     }
     for (int x = 0; x < kSlabs; ++x)
-      PG_TRY(sort_light_list(Q.verts + Q.light_at[x], Q.n_light[x], x, g, g->off, g->ustart, Q.split, s));
-    PG_TRY(sort_light_list(Q.verts + Q.whole_at, Q.n_whole, -1, g, g->off, g->ustart, Q.split, s));
+      PG_TRY(sort_light_list(Q.verts + Q.light_at[x], Q.n_light[x], x, kSlabLightBucket, g, g->off, g->ustart,
+                             Q.split, s));
+    PG_TRY(sort_light_list(Q.verts + Q.whole_at, Q.n_whole, -1, kSlabWholeBucket, g, g->off, g->ustart, Q.split, s));
     // 5. heavy items in chunks
     std::vector<int32_t> cv, cslot, first;
     std::vector<int64_t> cb, ce;

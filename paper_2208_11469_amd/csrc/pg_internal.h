@@ -65,12 +65,15 @@ constexpr int kBinGroup[kNumBins] = {4, 16, 64, 256};
 //   light  (d_v <= kLightMax): kLightGroup lanes per vertex in the filter
 //          build (the clustering kernels pick their own group size)
 // Isolated vertices stay in the light tier (their sketch rows still have to
-// be written). The light list is sorted by descending degree, so the lanes of
-// a wave walk about equally many arcs.
+// be written; they end the light list). The light list is sorted by
+// descending passes of the filter build, ceil(d_v / (kLightGroup *
+// kLightUnroll)), in ID order within a pass count: the groups of a wave take
+// equally many passes and neighbouring groups keep nearby IDs.
 constexpr int32_t kLightMax = 64;
 constexpr int32_t kMediumMax = 2048;
 constexpr int64_t kHeavyChunk = 2048;
 constexpr int kLightGroup = 4;
+constexpr int kLightUnroll = 4;  // arcs each lane of a light group loads per pass of the filter build
 
 struct VertexPlan {
   int64_t n_light = 0;
@@ -145,6 +148,10 @@ constexpr int32_t kSliceMin = 64;
 constexpr int kSlabLightGroup = 8;
 constexpr int kWholeGroup = 8;      // lanes per light vertex of the clustering-coefficient plan
 constexpr int kSlabWholeGroup = 4;  // lanes per whole (unsliced) vertex of the triangle-count slab plan
+// Sort buckets of the slab plan's lists (see sort_light_list): light items
+// by exact arc count, whole vertices by ceil(upper degree / 16).
+constexpr int kSlabLightBucket = 1;
+constexpr int kSlabWholeBucket = 16;
 
 struct SlabPlan {
   int32_t* split = nullptr;  // [(kSlabs-1) * n]: split[(x-1)*n + v] = first arc of v into slab x >= 1
