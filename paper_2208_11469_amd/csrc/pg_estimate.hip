@@ -285,6 +285,113 @@ __global__ __launch_bounds__(kBlock) void k_bf_tc_slab(SlabPlan P, SkView s, con
   if (tid == 0) partials[blockIdx.x] = r;
 }
 
+// ---- k-hash MinHash: triangle count over the slab plan (Section 4.3) --------
+//
+// Same plan and tiers as the Bloom-filter kernel: the group owning v keeps
+// sig_v in registers and walks the upper neighbours x from the CSR. A team of
+// kKhTeam lanes reads sig_x side by side (K / kKhTeam slots each, 16-byte
+// loads), counts the positions where both signatures hold the same element,
+// and the counts meet in quad DPP adds. Lane 0 of the team adds the estimate
+// s (d_v + d_x) / (k + s) in FP64, the same operations as the per-pair path,
+// so every edge's estimate is bit-identical to it; each block writes one
+// partial.
+constexpr int kKhTeam = 4;
+
+template <int K, int U, int G>
+__device__ __forceinline__ double kh_item(const SkView& s, int32_t v, const int32_t* __restrict__ adj, int64_t beg,
+                                          int64_t end, int lane) {
+  static_assert(G % kKhTeam == 0 && K % (4 * kKhTeam) == 0, "whole teams, whole 16-byte loads");
+  constexpr int T = kKhTeam;
+  constexpr int Q4 = K / T / 4;  // 16-byte loads per lane and row
+  constexpr int NT = G / T;      // teams in the group
+  const int k = lane % T;
+  uint4 mv[Q4];
+  const uint4* pv = reinterpret_cast<const uint4*>(s.sig + (size_t)v * K) + k * Q4;
+#pragma unroll
+  for (int i = 0; i < Q4; ++i) mv[i] = pv[i];
+  const int32_t dv = s.deg[v];
+  double acc = 0.0;
+  for (int64_t p0 = beg + lane / T; p0 < end; p0 += (int64_t)NT * U) {
+    int32_t x[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int64_t p = p0 + (int64_t)j * NT;
+      x[j] = p < end ? adj[p] : -1;
+    }
+    uint4 r[U][Q4];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (x[j] >= 0) {
+        const uint4* px = reinterpret_cast<const uint4*>(s.sig + (size_t)x[j] * K) + k * Q4;
+#pragma unroll
+        for (int i = 0; i < Q4; ++i) r[j][i] = px[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q4; ++i) r[j][i] = make_uint4(kBottom, kBottom, kBottom, kBottom);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int i = 0; i < Q4; ++i) {
+        const uint4 a = mv[i], b = r[j][i];
+        c += (uint32_t)(a.x == b.x && a.x != kBottom) + (uint32_t)(a.y == b.y && a.y != kBottom) +
+             (uint32_t)(a.z == b.z && a.z != kBottom) + (uint32_t)(a.w == b.w && a.w != kBottom);
+      }
+      c = team_sum<T>(c);
+      if (k == 0 && x[j] >= 0) acc += minhash_estimate(c, (uint32_t)K, dv, s.deg[x[j]]);
+    }
+  }
+  return acc;
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_kh_tc_slab(SlabPlan P, SkView s, const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ ustart,
+                                                       const int32_t* __restrict__ adj, double* __restrict__ partials) {
+  const bool whole = (int64_t)blockIdx.x >= P.slab_grid;
+  const int x = (int)(blockIdx.x % kSlabs);
+  const int64_t blk = whole ? (int64_t)blockIdx.x - P.slab_grid : (int64_t)(blockIdx.x / kSlabs);
+  const int64_t n_chunks = whole ? 0 : P.n_chunks[x];
+  const int64_t n_medium_blocks = whole ? 0 : (P.n_medium[x] + 3) / 4;
+  if (!whole && blk >= slab_blocks(P, x)) {
+    if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+    return;
+  }
+  __shared__ double red[kBlock / kWave];
+  constexpr int U = K <= 32 ? 4 : 2;
+  const size_t n = (size_t)s.n;
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  if (whole) {
+    const int64_t idx = (blk * kBlock + tid) / kSlabWholeGroup;
+    if (idx < P.n_whole) {
+      const int32_t v = P.verts[P.whole_at + idx];
+      acc = kh_item<K, U, kSlabWholeGroup>(s, v, adj, ustart[v], off[v + 1], tid % kSlabWholeGroup);
+    }
+  } else if (blk < n_chunks) {
+    const int64_t c = P.chunk_at[x] + blk;
+    acc = kh_item<K, U, kBlock>(s, P.chunk_vertex[c], adj, P.chunk_begin[c], P.chunk_end[c], tid);
+  } else if (blk - n_chunks < n_medium_blocks) {
+    const int64_t idx = (blk - n_chunks) * (kBlock / kWave) + tid / kWave;
+    if (idx < P.n_medium[x]) {
+      const int32_t v = P.verts[P.medium_at[x] + idx];
+      acc = kh_item<K, U, kWave>(s, v, adj, slab_begin(ustart, P.split, n, x, v), slab_end(off, P.split, n, x, v),
+                                 lane_id());
+    }
+  } else {
+    const int64_t idx = ((blk - n_chunks - n_medium_blocks) * kBlock + tid) / kSlabLightGroup;
+    if (idx < P.n_light[x]) {
+      const int32_t v = P.verts[P.light_at[x] + idx];
+      acc = kh_item<K, U, kSlabLightGroup>(s, v, adj, slab_begin(ustart, P.split, n, x, v),
+                                           slab_end(off, P.split, n, x, v), tid % kSlabLightGroup);
+    }
+  }
+  const double r = block_sum_256(acc, red);
+  if (tid == 0) partials[blockIdx.x] = r;
+}
+
 // ---- 1-hash MinHash: vertex-centric union counts (Section 4.4) ---------------
 //
 // The per-pair union walk costs one dependent load per step. Here a wave
@@ -774,6 +881,30 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
         default: PG_TCP(16); break;
       }
 #undef PG_TCP
+      PG_LAUNCH_CHECK();
+    }
+    PG_TRY(sum_chunks(partials, nblk, divisor, d_out, s));
+    return dfree(partials, s);
+  }
+  if (sk->kind == PG_MH_KHASH && (sk->size == 16 || sk->size == 32 || sk->size == 64) && g->n > 0) {
+    PG_TRY(graph_slabs(const_cast<pg_graph*>(g), s));
+    const SlabPlan& P = g->slabs;
+    const int64_t nblk = std::max<int64_t>(slab_plan_blocks(P), 1);
+    if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one triangle-count launch");
+    double* partials = nullptr;
+    PG_TRY(dmalloc((void**)&partials, sizeof(double) * (size_t)nblk, s));
+    const SkView view = make_view(sk, est);
+    {
+      ProfScope ps(s, "kh_tc");
+      if (sk->size == 16)
+        hipLaunchKernelGGL(k_kh_tc_slab<16>, dim3((unsigned)nblk), dim3(kBlock), 0, s, P, view, g->off, g->ustart, g->adj,
+                           partials);
+      else if (sk->size == 32)
+        hipLaunchKernelGGL(k_kh_tc_slab<32>, dim3((unsigned)nblk), dim3(kBlock), 0, s, P, view, g->off, g->ustart, g->adj,
+                           partials);
+      else
+        hipLaunchKernelGGL(k_kh_tc_slab<64>, dim3((unsigned)nblk), dim3(kBlock), 0, s, P, view, g->off, g->ustart, g->adj,
+                           partials);
       PG_LAUNCH_CHECK();
     }
     PG_TRY(sum_chunks(partials, nblk, divisor, d_out, s));

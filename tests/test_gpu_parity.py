@@ -213,6 +213,8 @@ EST_CASES = [
     ("rmat10", "bf", 2048, 2, ("and", "pap")),
     ("rmat12", "kh", 32, 1, ("kh",)),
     ("hub", "kh", 20, 1, ("kh",)),
+    ("hub", "kh", 16, 1, ("kh",)),
+    ("er4096", "kh", 64, 1, ("kh",)),
     ("rmat12", "1h", 32, 1, ("1h", "1h_lit")),
     ("er4096", "1h", 64, 1, ("1h", "1h_lit")),
     ("hub", "1h", 16, 1, ("1h", "1h_lit")),
