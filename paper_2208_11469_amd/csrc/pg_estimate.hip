@@ -28,6 +28,10 @@ constexpr int kCountBlocksPerCu = 8;  // grid of kernels that count into one glo
 // The vertex-centric 1-hash kernels count matches of the union walk (union
 // and literal readings); the KMV estimators take the general per-pair path.
 inline bool is_minhash_ratio(int est) { return est == PG_EST_MH_1HASH || est == PG_EST_MH_1HASH_LITERAL; }
+// Estimators of 1-hash rows that the vertex-centric union counts serve.
+inline bool is_onehash_union(int est) {
+  return is_minhash_ratio(est) || est == PG_EST_KMV || est == PG_EST_KMV_SKETCH_SIZES;
+}
 
 constexpr const char* kOrientedNeedsNv =
     "defined on N_v: an oriented sketch set (PG_ORIENTED) serves intersections and the triangle count";
@@ -405,7 +409,11 @@ __global__ __launch_bounds__(kBlock) void k_kh_tc_slab(SlabPlan P, SkView s, con
 // the common elements before it. The common elements, those among the first k
 // positions, and the union size follow from ballots. Distinct IDs have
 // distinct keys (odd multiplier, bijective mix), so equal keys are the same
-// element. The counts equal the per-pair walk's exactly.
+// element. The counts equal the per-pair walk's exactly. For the KMV
+// estimators the k-th smallest union key is either the key of the element of
+// M_u at position k - 1, or, when there is none, the element of M_v after
+// k - a + c - 1 others, a being the elements of M_u before position k - 1 and
+// c the common ones among them.
 
 constexpr int kOhAhead = 4;  // neighbour rows in flight per wave
 
@@ -428,14 +436,18 @@ __device__ __forceinline__ double oh_wave_estimate(const SkView& s, const uint64
   const uint32_t nu = (uint32_t)du < s.size ? (uint32_t)du : s.size;
   const int l = lane_id();
   const uint64_t below = (1ull << l) - 1ull;  // lanes holding earlier elements of this batch
-  uint32_t com = 0, comk = 0;
+  const bool kmv = s.est == PG_EST_KMV || s.est == PG_EST_KMV_SKETCH_SIZES;  // the same in every lane
+  uint32_t com = 0, comk = 0, a_k = 0, c_k = 0;
+  uint64_t kth = ~0ull, max_u = 0;
+  bool kth_in_u = false;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const uint32_t e = (uint32_t)(j * kWave + l);
     bool found = false;
     uint32_t lo = 0;
+    uint64_t key = 0;
     if (e < nu) {
-      const uint64_t key = mh_key(s.a1, s.c1, x[j]);
+      key = mh_key(s.a1, s.c1, x[j]);
       uint32_t hi = nv;  // lo: first position whose key is not below `key`
       while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -451,6 +463,26 @@ __device__ __forceinline__ double oh_wave_estimate(const SkView& s, const uint64
     const bool first_k = found && e + lo - before < s.size;
     com += (uint32_t)__popcll(fb);
     comk += (uint32_t)__popcll(__ballot(first_k));
+    if (kmv) {
+      const uint32_t pos = e + lo - before;  // union position of element e of M_u
+      const uint64_t at = __ballot(e < nu && pos == s.size - 1);
+      if (at) {
+        kth = (uint64_t)__shfl((unsigned long long)key, __ffsll((long long)at) - 1);
+        kth_in_u = true;
+      }
+      a_k += (uint32_t)__popcll(__ballot(e < nu && pos < s.size - 1));
+      c_k += (uint32_t)__popcll(__ballot(e < nu && found && pos < s.size - 1));
+      if (nu > 0 && (nu - 1) / kWave == (uint32_t)j)
+        max_u = (uint64_t)__shfl((unsigned long long)key, (int)((nu - 1) % kWave));
+    }
+  }
+  if (kmv) {
+    const uint32_t uni = nu + nv - com;
+    if (!kth_in_u && uni >= s.size) {
+      const uint32_t iv = s.size - a_k + c_k - 1;  // index in M_v of the k-th union element
+      kth = iv < nv ? keys_v[iv] : ~0ull;
+    }
+    return kmv_estimate(s.est == PG_EST_KMV, s.size, du, dv, nu, nv, uni, kth, max_u, nv ? keys_v[nv - 1] : 0ull);
   }
   if (s.est == PG_EST_MH_1HASH_LITERAL) return minhash_estimate(com, s.size, du, dv);
   const uint32_t uni = nu + nv - com;
@@ -910,7 +942,7 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
     PG_TRY(sum_chunks(partials, nblk, divisor, d_out, s));
     return dfree(partials, s);
   }
-  if (sk->kind == PG_MH_1HASH && is_minhash_ratio(est) && g->n > 0) {
+  if (sk->kind == PG_MH_1HASH && is_onehash_union(est) && g->n > 0) {
     PG_TRY(graph_slabs(const_cast<pg_graph*>(g), s));
     const SlabPlan& P = g->slabs;
     int64_t busiest = 0;
@@ -951,7 +983,7 @@ int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStre
   const pg_graph* g = sk->g;
   const SkView view = make_view(sk, est);
   ProfScope ps(s, "cc");
-  if (sk->kind == PG_MH_1HASH && is_minhash_ratio(est)) {
+  if (sk->kind == PG_MH_1HASH && is_onehash_union(est)) {
     const VertexPlan& P = g->plan_all;
     const PlanView pv = plan_view(P);
     const int64_t nblk = P.n_chunks + pv.n_medium_blocks + (P.n_light + 3) / 4;
