@@ -415,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_kh_tc_slab(SlabPlan P, SkView s, con
 // k - a + c - 1 others, a being the elements of M_u before position k - 1 and
 // c the common ones among them.
 
-constexpr int kOhAhead = 4;  // neighbour rows in flight per wave
+constexpr int kOhAhead = 2;  // neighbour rows in flight per wave (2: 4.05 ms, 4: 4.24 ms, 8: 5.19 ms for 1-hash TC at k = 32, R-MAT s20)
 
 template <int E>
 __device__ __forceinline__ void oh_keys_to_lds(const SkView& s, int32_t v, uint32_t nv, uint64_t* keys) {
