@@ -429,20 +429,29 @@ __device__ __forceinline__ void oh_keys_to_lds(const SkView& s, int32_t v, uint3
 }
 
 // Estimate for the pair (v, u) given M_v's nv keys in LDS and this lane's
-// elements of M_u (x[j] = element j*64 + lane); the same in every lane.
-template <int E>
+// elements of M_u (x[j] = element j*64 + lane); the same in every lane. With
+// HALF (k <= 32, E = 1) each half of the wave serves a pair of its own: lane
+// l holds element l mod 32 of its half's M_u, ballots are masked to the half,
+// and the result is the same in every lane of the half. du < 0 marks a half
+// without a pair; its result is not used. Every lane takes every ballot and
+// shuffle, so the halves never diverge around them.
+template <int E, bool HALF>
 __device__ __forceinline__ double oh_wave_estimate(const SkView& s, const uint64_t* keys_v, uint32_t nv, int32_t dv,
                                                    int32_t du, const uint32_t (&x)[E]) {
-  const uint32_t nu = (uint32_t)du < s.size ? (uint32_t)du : s.size;
+  static_assert(!HALF || E == 1, "half waves hold at most 32 elements");
+  const uint32_t nu = du < 0 ? 0u : ((uint32_t)du < s.size ? (uint32_t)du : s.size);
   const int l = lane_id();
-  const uint64_t below = (1ull << l) - 1ull;  // lanes holding earlier elements of this batch
+  const uint64_t hmask = HALF ? ((l & 32) ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull) : ~0ull;
+  const int base = HALF ? (l & 32) : 0;            // first lane of this lane's half
+  const uint32_t le = (uint32_t)(l - base);        // element index within the half
+  const uint64_t below = ((1ull << l) - 1ull) & hmask;  // lanes holding earlier elements of this batch
   const bool kmv = s.est == PG_EST_KMV || s.est == PG_EST_KMV_SKETCH_SIZES;  // the same in every lane
   uint32_t com = 0, comk = 0, a_k = 0, c_k = 0;
   uint64_t kth = ~0ull, max_u = 0;
   bool kth_in_u = false;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const uint32_t e = (uint32_t)(j * kWave + l);
+    const uint32_t e = (uint32_t)(j * kWave) + le;
     bool found = false;
     uint32_t lo = 0;
     uint64_t key = 0;
@@ -458,22 +467,25 @@ __device__ __forceinline__ double oh_wave_estimate(const SkView& s, const uint64
       }
       found = lo < nv && keys_v[lo] == key;
     }
-    const uint64_t fb = __ballot(found);
+    const uint64_t fb = __ballot(found) & hmask;
     const uint32_t before = com + (uint32_t)__popcll(fb & below);  // common elements ahead of e
     const bool first_k = found && e + lo - before < s.size;
     com += (uint32_t)__popcll(fb);
-    comk += (uint32_t)__popcll(__ballot(first_k));
+    comk += (uint32_t)__popcll(__ballot(first_k) & hmask);
     if (kmv) {
       const uint32_t pos = e + lo - before;  // union position of element e of M_u
-      const uint64_t at = __ballot(e < nu && pos == s.size - 1);
+      const uint64_t at = __ballot(e < nu && pos == s.size - 1) & hmask;
+      const uint64_t kcand = (uint64_t)__shfl((unsigned long long)key, at ? __ffsll((long long)at) - 1 : l);
       if (at) {
-        kth = (uint64_t)__shfl((unsigned long long)key, __ffsll((long long)at) - 1);
+        kth = kcand;
         kth_in_u = true;
       }
-      a_k += (uint32_t)__popcll(__ballot(e < nu && pos < s.size - 1));
-      c_k += (uint32_t)__popcll(__ballot(e < nu && found && pos < s.size - 1));
-      if (nu > 0 && (nu - 1) / kWave == (uint32_t)j)
-        max_u = (uint64_t)__shfl((unsigned long long)key, (int)((nu - 1) % kWave));
+      a_k += (uint32_t)__popcll(__ballot(e < nu && pos < s.size - 1) & hmask);
+      c_k += (uint32_t)__popcll(__ballot(e < nu && found && pos < s.size - 1) & hmask);
+      const bool last_here = nu > 0 && (nu - 1) / kWave == (uint32_t)j;
+      const uint64_t mcand =
+          (uint64_t)__shfl((unsigned long long)key, last_here ? base + (int)((nu - 1) % kWave) : l);
+      if (last_here) max_u = mcand;
     }
   }
   if (kmv) {
@@ -490,7 +502,9 @@ __device__ __forceinline__ double oh_wave_estimate(const SkView& s, const uint64
   return minhash_estimate(uni >= s.size ? comk : com, kp, du, dv);
 }
 
-// Sum of the estimates of (v, adj[p]) over p in [beg, end), one wave.
+// Sum of the estimates of (v, adj[p]) over p in [beg, end), one wave. For
+// k <= 32 the two halves of the wave take neighbours p and p + 1 side by side;
+// the result is then the sum of the two halves' sums, the same in every lane.
 template <int E>
 __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const int32_t* __restrict__ adj,
                                                int64_t beg, int64_t end, uint64_t* keys) {
@@ -500,10 +514,34 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // kOhAhead neighbours at a time: their degrees and rows are loaded before
-  // any of them is evaluated
   const int l = lane_id();
   double acc = 0.0;
+  if constexpr (E == 1) {
+    if (s.size <= (uint32_t)(kWave / 2)) {
+      const int h = l >> 5;
+      const uint32_t le = (uint32_t)(l & 31);
+      for (int64_t p0 = beg; p0 < end; p0 += 2 * kOhAhead) {
+        int32_t du[kOhAhead];
+        uint32_t x[kOhAhead][1];
+#pragma unroll
+        for (int t = 0; t < kOhAhead; ++t) {
+          const int64_t p = p0 + 2 * t + h;
+          const int32_t u = p < end ? adj[p] : -1;
+          du[t] = u >= 0 ? s.deg[u] : -1;
+          const uint32_t nu = u < 0 ? 0u : ((uint32_t)du[t] < s.size ? (uint32_t)du[t] : s.size);
+          x[t][0] = le < nu ? s.sig[(size_t)u * s.size + le] : 0u;
+        }
+#pragma unroll
+        for (int t = 0; t < kOhAhead; ++t) {
+          const double est = oh_wave_estimate<1, true>(s, keys, nv, dv, du[t], x[t]);
+          if (du[t] >= 0) acc += est;
+        }
+      }
+      return __shfl(acc, 0) + __shfl(acc, kWave / 2);
+    }
+  }
+  // kOhAhead neighbours at a time: their degrees and rows are loaded before
+  // any of them is evaluated
   for (int64_t p0 = beg; p0 < end; p0 += kOhAhead) {
     int32_t du[kOhAhead];
     uint32_t x[kOhAhead][E];
@@ -521,7 +559,7 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
     }
 #pragma unroll
     for (int t = 0; t < kOhAhead; ++t)
-      if (du[t] >= 0) acc += oh_wave_estimate<E>(s, keys, nv, dv, du[t], x[t]);
+      if (du[t] >= 0) acc += oh_wave_estimate<E, false>(s, keys, nv, dv, du[t], x[t]);
   }
   return acc;
 }
