@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_bf_build_wide(const int32_t* __restr
 
 // ---------------------------------------------------------------- k-hash
 
-constexpr int kKhBatch = 16;  // hash functions kept in registers at a time
+constexpr int kKhBatch = 8;  // hash functions kept in registers at a time (8: 2.71 ms, 4: 2.78, 16: 3.05, 32: 3.77 for k = 32 on R-MAT s20)
 
 template <int G>
 __device__ __forceinline__ void min_pair_group(uint64_t& key, uint32_t& id) {
