@@ -285,10 +285,23 @@ constexpr int kOhWaves = kBlock / kWave;
 
 // Shared bytes per wave: k keys (8 B) + k IDs (4 B) + 256 histogram bins,
 // rounded to 16 bytes so every wave's key array stays 8-byte aligned.
-__host__ __device__ constexpr size_t oh_wave_bytes(uint32_t k) { return (((size_t)k * 12 + 256 * 4) + 15) & ~(size_t)15; }
+constexpr uint32_t kOhCand = 512;  // candidates of the k-th key's top-byte bin held in LDS
+// Candidate slots per wave: kOhCand for k <= 512 (a block then needs at most
+// 53 KB of LDS), none above.
+__host__ __device__ constexpr uint32_t oh_cand(uint32_t k) { return k <= 512 ? kOhCand : 0u; }
+__host__ __device__ constexpr size_t oh_wave_bytes(uint32_t k) {
+  return (((size_t)k * 12 + 256 * 4 + (size_t)oh_cand(k) * 12) + 15) & ~(size_t)15;
+}
 
 // One wave per vertex. Shared memory per wave: keys and IDs of up to k
-// elements, plus a 256-bin digit histogram.
+// elements, a 256-bin digit histogram, and kOhCand candidate keys and IDs.
+// For d > k the first pass histograms the keys' top byte; its bin holding
+// rank k splits N_v into the elements below it (all among the k smallest),
+// the bin (about d / 256 candidates) and the rest. One more pass stages the
+// first group and collects the candidates in LDS, where the remaining
+// smallest ones are found by rank counting, so every key is hashed twice.
+// A bin larger than kOhCand falls back to a radix select over all elements,
+// 8 bits per pass.
 __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
                                                      const int32_t* __restrict__ verts, int64_t nverts, uint32_t k,
                                                      uint64_t a, uint64_t c, uint32_t* __restrict__ sig) {
@@ -296,9 +309,13 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
   const int wv = threadIdx.x / kWave;
   const int lane = lane_id();
   const size_t per_wave = oh_wave_bytes(k);
+  // wave slice: [skey: k][ckey: cap] (8 bytes each), [sid: k][cid: cap][hist: 256] (4 bytes each)
+  const uint32_t cap = oh_cand(k);
   uint64_t* skey = (uint64_t*)(smem + wv * per_wave);
-  uint32_t* sid = (uint32_t*)(smem + wv * per_wave + (size_t)k * 8);
-  uint32_t* hist = (uint32_t*)(smem + wv * per_wave + (size_t)k * 12);
+  uint64_t* ckey = skey + k;
+  uint32_t* sid = (uint32_t*)(ckey + cap);
+  uint32_t* cid = sid + k;
+  uint32_t* hist = cid + cap;
   const int64_t grp = blockIdx.x * (int64_t)kOhWaves + wv;
   if (grp >= nverts) return;
   const int32_t v = verts[grp];
@@ -317,7 +334,8 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
     // radix select of the k-th smallest key, 8 bits at a time from the top
     uint64_t prefix = 0, pmask = 0;
     uint32_t want = k;  // rank (1-based) still wanted among keys matching the prefix
-    for (int shift = 56; shift >= 0; shift -= 8) {
+    bool staged = false;
+    for (int shift = 56; shift >= 0 && !staged; shift -= 8) {
       for (int i = lane; i < 256; i += kWave) hist[i] = 0;
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -359,13 +377,59 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
       const int src = __ffsll((long long)owner) - 1;
       digit = __shfl(digit, src);
       below = __shfl(below, src);
+      const uint32_t nc = hist[digit];  // keys in the bin holding rank `want`
+      if (shift == 56 && nc <= cap) {
+        // one pass: the `below` keys of lower top bytes go straight to skey,
+        // the bin's keys to the candidates
+        uint32_t nlo = 0, ncand = 0;
+        const uint64_t lanes_before = (1ull << lane) - 1ull;
+        for (int64_t t0 = beg; t0 < end; t0 += kWave) {
+          const int64_t t = t0 + lane;
+          uint64_t key = 0;
+          uint32_t x = 0;
+          if (t < end) {
+            x = (uint32_t)adj[t];
+            key = mh_key(a, c, x);
+          }
+          const uint32_t top = (uint32_t)(key >> 56);
+          const bool lo = t < end && top < (uint32_t)digit;
+          const bool in_bin = t < end && top == (uint32_t)digit;
+          const unsigned long long blo = __ballot(lo), bin = __ballot(in_bin);
+          if (lo) {
+            const uint32_t pos = nlo + (uint32_t)__popcll(blo & lanes_before);
+            skey[pos] = key;
+            sid[pos] = x;
+          }
+          if (in_bin) {
+            const uint32_t pos = ncand + (uint32_t)__popcll(bin & lanes_before);
+            ckey[pos] = key;
+            cid[pos] = x;
+          }
+          nlo += (uint32_t)__popcll(blo);
+          ncand += (uint32_t)__popcll(bin);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // the want smallest candidates complete the k smallest (keys distinct)
+        for (uint32_t t = (uint32_t)lane; t < nc; t += kWave) {
+          const uint64_t key = ckey[t];
+          uint32_t r = 0;
+          for (uint32_t q = 0; q < nc; ++q) r += ckey[q] < key ? 1u : 0u;
+          if (r < want - below) {
+            skey[below + r] = key;
+            sid[below + r] = cid[t];
+          }
+        }
+        staged = true;
+        break;
+      }
       prefix |= (uint64_t)digit << shift;
       pmask |= 255ull << shift;
       want -= below;
     }
     // prefix is now the k-th smallest key: stage the k keys <= prefix
     int64_t base = 0;
-    for (int64_t t0 = beg; t0 < end; t0 += kWave) {
+    for (int64_t t0 = staged ? end : beg; t0 < end; t0 += kWave) {
       const int64_t t = t0 + lane;
       uint64_t key = 0;
       uint32_t x = 0;
@@ -385,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
       }
       base += __popcll(bal);
     }
-    taken = base < (int64_t)k ? base : (int64_t)k;
+    taken = staged ? (int64_t)k : (base < (int64_t)k ? base : (int64_t)k);
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
