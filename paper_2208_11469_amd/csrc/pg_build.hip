@@ -295,13 +295,14 @@ __host__ __device__ constexpr size_t oh_wave_bytes(uint32_t k) {
 
 // One wave per vertex. Shared memory per wave: keys and IDs of up to k
 // elements, a 256-bin digit histogram, and kOhCand candidate keys and IDs.
-// For d > k the first pass histograms the keys' top byte; its bin holding
-// rank k splits N_v into the elements below it (all among the k smallest),
-// the bin (about d / 256 candidates) and the rest. One more pass stages the
-// first group and collects the candidates in LDS, where the remaining
-// smallest ones are found by rank counting, so every key is hashed twice.
-// A bin larger than kOhCand falls back to a radix select over all elements,
-// 8 bits per pass.
+// For d > k a radix select runs over the keys, 8 bits per pass from the top:
+// each pass histograms the next byte of the keys that share the prefix found
+// so far. As soon as the bin holding rank k has at most kOhCand keys, it
+// splits N_v into the keys below the bin's prefix (all among the k smallest),
+// the bin's keys and the rest: one more pass stages the first group and
+// collects the bin in LDS, where the remaining smallest keys are found by
+// rank counting. Every key is hashed twice when the first bin fits (d up to
+// about 100,000), once more per further pass.
 __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
                                                      const int32_t* __restrict__ verts, int64_t nverts, uint32_t k,
                                                      uint64_t a, uint64_t c, uint32_t* __restrict__ sig) {
@@ -378,9 +379,13 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
       digit = __shfl(digit, src);
       below = __shfl(below, src);
       const uint32_t nc = hist[digit];  // keys in the bin holding rank `want`
-      if (shift == 56 && nc <= cap) {
-        // one pass: the `below` keys of lower top bytes go straight to skey,
-        // the bin's keys to the candidates
+      if (nc <= cap) {
+        // one pass: the keys below the bin's prefix P (k - want + below of
+        // them, all among the k smallest) go straight to skey, the bin's keys
+        // to the candidates
+        const uint64_t P = prefix | ((uint64_t)digit << shift);
+        const uint64_t M = pmask | (255ull << shift);
+        const uint32_t nbelow = k - want + below;
         uint32_t nlo = 0, ncand = 0;
         const uint64_t lanes_before = (1ull << lane) - 1ull;
         for (int64_t t0 = beg; t0 < end; t0 += kWave) {
@@ -391,9 +396,8 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
             x = (uint32_t)adj[t];
             key = mh_key(a, c, x);
           }
-          const uint32_t top = (uint32_t)(key >> 56);
-          const bool lo = t < end && top < (uint32_t)digit;
-          const bool in_bin = t < end && top == (uint32_t)digit;
+          const bool lo = t < end && key < P;
+          const bool in_bin = t < end && (key & M) == P;
           const unsigned long long blo = __ballot(lo), bin = __ballot(in_bin);
           if (lo) {
             const uint32_t pos = nlo + (uint32_t)__popcll(blo & lanes_before);
@@ -416,8 +420,8 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
           uint32_t r = 0;
           for (uint32_t q = 0; q < nc; ++q) r += ckey[q] < key ? 1u : 0u;
           if (r < want - below) {
-            skey[below + r] = key;
-            sid[below + r] = cid[t];
+            skey[nbelow + r] = key;
+            sid[nbelow + r] = cid[t];
           }
         }
         staged = true;

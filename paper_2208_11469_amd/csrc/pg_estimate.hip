@@ -415,7 +415,8 @@ __global__ __launch_bounds__(kBlock) void k_kh_tc_slab(SlabPlan P, SkView s, con
 // k - a + c - 1 others, a being the elements of M_u before position k - 1 and
 // c the common ones among them.
 
-constexpr int kOhAhead = 2;  // neighbour rows in flight per wave (2: 4.05 ms, 4: 4.24 ms, 8: 5.19 ms for 1-hash TC at k = 32, R-MAT s20)
+constexpr int kOhAhead = 4;      // neighbour rows in flight per wave, a wave per pair
+constexpr int kOhHalfAhead = 2;  // neighbour rows in flight per half wave (k <= 32)
 
 template <int E>
 __device__ __forceinline__ void oh_keys_to_lds(const SkView& s, int32_t v, uint32_t nv, uint64_t* keys) {
@@ -435,7 +436,7 @@ __device__ __forceinline__ void oh_keys_to_lds(const SkView& s, int32_t v, uint3
 // and the result is the same in every lane of the half. du < 0 marks a half
 // without a pair; its result is not used. Every lane takes every ballot and
 // shuffle, so the halves never diverge around them.
-template <int E, bool HALF>
+template <int E, bool HALF, bool KMV>
 __device__ __forceinline__ double oh_wave_estimate(const SkView& s, const uint64_t* keys_v, uint32_t nv, int32_t dv,
                                                    int32_t du, const uint32_t (&x)[E]) {
   static_assert(!HALF || E == 1, "half waves hold at most 32 elements");
@@ -445,7 +446,6 @@ __device__ __forceinline__ double oh_wave_estimate(const SkView& s, const uint64
   const int base = HALF ? (l & 32) : 0;            // first lane of this lane's half
   const uint32_t le = (uint32_t)(l - base);        // element index within the half
   const uint64_t below = ((1ull << l) - 1ull) & hmask;  // lanes holding earlier elements of this batch
-  const bool kmv = s.est == PG_EST_KMV || s.est == PG_EST_KMV_SKETCH_SIZES;  // the same in every lane
   uint32_t com = 0, comk = 0, a_k = 0, c_k = 0;
   uint64_t kth = ~0ull, max_u = 0;
   bool kth_in_u = false;
@@ -472,7 +472,7 @@ __device__ __forceinline__ double oh_wave_estimate(const SkView& s, const uint64
     const bool first_k = found && e + lo - before < s.size;
     com += (uint32_t)__popcll(fb);
     comk += (uint32_t)__popcll(__ballot(first_k) & hmask);
-    if (kmv) {
+    if constexpr (KMV) {
       const uint32_t pos = e + lo - before;  // union position of element e of M_u
       const uint64_t at = __ballot(e < nu && pos == s.size - 1) & hmask;
       const uint64_t kcand = (uint64_t)__shfl((unsigned long long)key, at ? __ffsll((long long)at) - 1 : l);
@@ -488,7 +488,7 @@ __device__ __forceinline__ double oh_wave_estimate(const SkView& s, const uint64
       if (last_here) max_u = mcand;
     }
   }
-  if (kmv) {
+  if constexpr (KMV) {
     const uint32_t uni = nu + nv - com;
     if (!kth_in_u && uni >= s.size) {
       const uint32_t iv = s.size - a_k + c_k - 1;  // index in M_v of the k-th union element
@@ -505,7 +505,7 @@ __device__ __forceinline__ double oh_wave_estimate(const SkView& s, const uint64
 // Sum of the estimates of (v, adj[p]) over p in [beg, end), one wave. For
 // k <= 32 the two halves of the wave take neighbours p and p + 1 side by side;
 // the result is then the sum of the two halves' sums, the same in every lane.
-template <int E>
+template <int E, bool HALF, bool KMV>
 __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const int32_t* __restrict__ adj,
                                                int64_t beg, int64_t end, uint64_t* keys) {
   const int32_t dv = s.deg[v];
@@ -516,15 +516,16 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int l = lane_id();
   double acc = 0.0;
-  if constexpr (E == 1) {
-    if (s.size <= (uint32_t)(kWave / 2)) {
+  if constexpr (HALF) {  // k <= 32 (the launch checks it): a separate kernel, so the wave-per-pair loop keeps its registers
+    static_assert(E == 1, "half waves hold at most 32 elements");
+    {
       const int h = l >> 5;
       const uint32_t le = (uint32_t)(l & 31);
-      for (int64_t p0 = beg; p0 < end; p0 += 2 * kOhAhead) {
-        int32_t du[kOhAhead];
-        uint32_t x[kOhAhead][1];
+      for (int64_t p0 = beg; p0 < end; p0 += 2 * kOhHalfAhead) {
+        int32_t du[kOhHalfAhead];
+        uint32_t x[kOhHalfAhead][1];
 #pragma unroll
-        for (int t = 0; t < kOhAhead; ++t) {
+        for (int t = 0; t < kOhHalfAhead; ++t) {
           const int64_t p = p0 + 2 * t + h;
           const int32_t u = p < end ? adj[p] : -1;
           du[t] = u >= 0 ? s.deg[u] : -1;
@@ -532,14 +533,14 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
           x[t][0] = le < nu ? s.sig[(size_t)u * s.size + le] : 0u;
         }
 #pragma unroll
-        for (int t = 0; t < kOhAhead; ++t) {
-          const double est = oh_wave_estimate<1, true>(s, keys, nv, dv, du[t], x[t]);
+        for (int t = 0; t < kOhHalfAhead; ++t) {
+          const double est = oh_wave_estimate<1, true, KMV>(s, keys, nv, dv, du[t], x[t]);
           if (du[t] >= 0) acc += est;
         }
       }
       return __shfl(acc, 0) + __shfl(acc, kWave / 2);
     }
-  }
+  } else {
   // kOhAhead neighbours at a time: their degrees and rows are loaded before
   // any of them is evaluated
   for (int64_t p0 = beg; p0 < end; p0 += kOhAhead) {
@@ -559,9 +560,10 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
     }
 #pragma unroll
     for (int t = 0; t < kOhAhead; ++t)
-      if (du[t] >= 0) acc += oh_wave_estimate<E, false>(s, keys, nv, dv, du[t], x[t]);
+      if (du[t] >= 0) acc += oh_wave_estimate<E, false, KMV>(s, keys, nv, dv, du[t], x[t]);
   }
   return acc;
+  }
 }
 
 // Blocks of slab x when every light or medium item gets one wave.
@@ -572,7 +574,7 @@ __host__ __device__ inline int64_t oh_slab_blocks(const SlabPlan& p, int x) {
 // Triangle count over the slab plan: block i < grid_slabs serves slab i mod
 // kSlabs; a heavy chunk is split among the block's four waves in contiguous
 // quarters. Blocks from grid_slabs on take the whole vertices. One partial per wave.
-template <int E>
+template <int E, bool HALF, bool KMV>
 __global__ __launch_bounds__(kBlock) void k_oh_tc_slab(SlabPlan P, SkView s, const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ ustart,
                                                        const int32_t* __restrict__ adj, int64_t grid_slabs,
@@ -585,7 +587,7 @@ __global__ __launch_bounds__(kBlock) void k_oh_tc_slab(SlabPlan P, SkView s, con
     const int64_t idx = ((int64_t)blockIdx.x - grid_slabs) * (kBlock / kWave) + w;
     if (idx < P.n_whole) {
       const int32_t v = P.verts[P.whole_at + idx];
-      acc = oh_wave_item<E>(s, v, adj, ustart[v], off[v + 1], keys[w]);
+      acc = oh_wave_item<E, HALF, KMV>(s, v, adj, ustart[v], off[v + 1], keys[w]);
     }
   } else {
     const int x = (int)(blockIdx.x % kSlabs);
@@ -597,19 +599,19 @@ __global__ __launch_bounds__(kBlock) void k_oh_tc_slab(SlabPlan P, SkView s, con
       const int64_t q = (ce - cb + 3) / 4;
       const int64_t b0 = cb + w * q;
       const int64_t e0 = b0 + q < ce ? b0 + q : ce;
-      if (b0 < e0) acc = oh_wave_item<E>(s, P.chunk_vertex[c], adj, b0, e0, keys[w]);
+      if (b0 < e0) acc = oh_wave_item<E, HALF, KMV>(s, P.chunk_vertex[c], adj, b0, e0, keys[w]);
     } else if (blk - P.n_chunks[x] < nmb) {
       const int64_t idx = (blk - P.n_chunks[x]) * (kBlock / kWave) + w;
       if (idx < P.n_medium[x]) {
         const int32_t v = P.verts[P.medium_at[x] + idx];
-        acc = oh_wave_item<E>(s, v, adj, slab_begin(ustart, P.split, n, x, v), slab_end(off, P.split, n, x, v),
+        acc = oh_wave_item<E, HALF, KMV>(s, v, adj, slab_begin(ustart, P.split, n, x, v), slab_end(off, P.split, n, x, v),
                               keys[w]);
       }
     } else {
       const int64_t idx = (blk - P.n_chunks[x] - nmb) * (kBlock / kWave) + w;
       if (idx < P.n_light[x]) {
         const int32_t v = P.verts[P.light_at[x] + idx];
-        acc = oh_wave_item<E>(s, v, adj, slab_begin(ustart, P.split, n, x, v), slab_end(off, P.split, n, x, v),
+        acc = oh_wave_item<E, HALF, KMV>(s, v, adj, slab_begin(ustart, P.split, n, x, v), slab_end(off, P.split, n, x, v),
                               keys[w]);
       }
     }
@@ -620,7 +622,7 @@ __global__ __launch_bounds__(kBlock) void k_oh_tc_slab(SlabPlan P, SkView s, con
 // Clustering coefficient over the full-neighbourhood plan: light vertices
 // (natural order) and medium ones get a wave, heavy vertices are split into
 // chunks whose four waves write one partial sum per chunk (combined below).
-template <int E>
+template <int E, bool HALF, bool KMV>
 __global__ __launch_bounds__(kBlock) void k_oh_cc_plan(PlanView P, SkView s, const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ adj, float* __restrict__ cc,
                                                        double* __restrict__ vsum, double* __restrict__ part) {
@@ -634,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_oh_cc_plan(PlanView P, SkView s, con
     const int64_t b0 = cb + w * q;
     const int64_t e0 = b0 + q < ce ? b0 + q : ce;
     double acc = 0.0;
-    if (b0 < e0) acc = oh_wave_item<E>(s, P.chunk_vertex[blk], adj, b0, e0, keys[w]);
+    if (b0 < e0) acc = oh_wave_item<E, HALF, KMV>(s, P.chunk_vertex[blk], adj, b0, e0, keys[w]);
     if (lane_id() == 0) red[w] = acc;
     __syncthreads();
     if (threadIdx.x == 0) part[blk] = (red[0] + red[1]) + (red[2] + red[3]);
@@ -653,7 +655,7 @@ __global__ __launch_bounds__(kBlock) void k_oh_cc_plan(PlanView P, SkView s, con
     }
   }
   if (v < 0) return;
-  const double tot = oh_wave_item<E>(s, v, adj, off[v], off[v + 1], keys[w]);
+  const double tot = oh_wave_item<E, HALF, KMV>(s, v, adj, off[v], off[v + 1], keys[w]);
   if (lane_id() == 0) {
     const int32_t d = s.deg[v];
     cc[v] = (float)(d >= 2 ? tot / ((double)d * ((double)d - 1.0)) : 0.0);
@@ -678,11 +680,12 @@ __global__ void k_cc_combine(PlanView P, const double* __restrict__ part, int64_
 template <typename F>
 int oh_dispatch_e(uint32_t k, F&& launch) {
   const uint32_t e = (k + kWave - 1) / kWave;
-  if (e <= 1) return launch(std::integral_constant<int, 1>());
-  if (e <= 2) return launch(std::integral_constant<int, 2>());
-  if (e <= 4) return launch(std::integral_constant<int, 4>());
-  if (e <= 8) return launch(std::integral_constant<int, 8>());
-  return launch(std::integral_constant<int, 16>());
+  if (k <= (uint32_t)kWave / 2) return launch(std::integral_constant<int, 1>(), std::true_type());  // half waves
+  if (e <= 1) return launch(std::integral_constant<int, 1>(), std::false_type());
+  if (e <= 2) return launch(std::integral_constant<int, 2>(), std::false_type());
+  if (e <= 4) return launch(std::integral_constant<int, 4>(), std::false_type());
+  if (e <= 8) return launch(std::integral_constant<int, 8>(), std::false_type());
+  return launch(std::integral_constant<int, 16>(), std::false_type());
 }
 
 // ---- clustering coefficient over the full-neighbourhood plan (Bloom filters) --
@@ -994,9 +997,15 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
     const SkView view = make_view(sk, est);
     {
       ProfScope ps(s, "oh_tc");
-      PG_TRY(oh_dispatch_e(sk->size, [&](auto e) {
-        hipLaunchKernelGGL((k_oh_tc_slab<decltype(e)::value>), dim3((unsigned)nblk), dim3(kBlock), 0, s, P, view,
-                           g->off, g->ustart, g->adj, grid_slabs, partials);
+      PG_TRY(oh_dispatch_e(sk->size, [&](auto e, auto half) {
+        constexpr int EE = decltype(e)::value;
+        constexpr bool HH = decltype(half)::value;
+        if (is_minhash_ratio(est))
+          hipLaunchKernelGGL((k_oh_tc_slab<EE, HH, false>), dim3((unsigned)nblk), dim3(kBlock), 0, s, P, view, g->off,
+                             g->ustart, g->adj, grid_slabs, partials);
+        else
+          hipLaunchKernelGGL((k_oh_tc_slab<EE, HH, true>), dim3((unsigned)nblk), dim3(kBlock), 0, s, P, view, g->off,
+                             g->ustart, g->adj, grid_slabs, partials);
         PG_LAUNCH_CHECK();
         return PG_OK;
       }));
@@ -1029,9 +1038,15 @@ int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStre
     if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one launch");
     double* part = nullptr;
     PG_TRY(dmalloc((void**)&part, sizeof(double) * (size_t)std::max<int64_t>(P.n_chunks, 1), s));
-    PG_TRY(oh_dispatch_e(sk->size, [&](auto e) {
-      hipLaunchKernelGGL((k_oh_cc_plan<decltype(e)::value>), dim3((unsigned)nblk), dim3(kBlock), 0, s, pv, view,
-                         g->off, g->adj, cc, vsum, part);
+    PG_TRY(oh_dispatch_e(sk->size, [&](auto e, auto half) {
+      constexpr int EE = decltype(e)::value;
+      constexpr bool HH = decltype(half)::value;
+      if (is_minhash_ratio(est))
+        hipLaunchKernelGGL((k_oh_cc_plan<EE, HH, false>), dim3((unsigned)nblk), dim3(kBlock), 0, s, pv, view, g->off,
+                           g->adj, cc, vsum, part);
+      else
+        hipLaunchKernelGGL((k_oh_cc_plan<EE, HH, true>), dim3((unsigned)nblk), dim3(kBlock), 0, s, pv, view, g->off,
+                           g->adj, cc, vsum, part);
       PG_LAUNCH_CHECK();
       return PG_OK;
     }));
