@@ -44,7 +44,7 @@ extern "C" {
 #define PG_E_GRAPH (-2)       /* CSR rejected by PG_VALIDATE (unsorted, duplicate, self-loop, asymmetric, out of range) */
 #define PG_E_NOMEM (-3)       /* device or host allocation failed */
 #define PG_E_DEVICE (-4)      /* a HIP runtime call failed */
-#define PG_E_UNSUPPORTED (-5) /* valid request this build does not implement */
+#define PG_E_UNSUPPORTED (-5) /* valid request the library does not serve (a size beyond an on-chip buffer, ...) */
 #define PG_E_BUSY (-6)        /* serving: request not admitted yet (no slot or memory) */
 
 /* ---- sketch kinds (Section 2.4) ----------------------------------------- */
