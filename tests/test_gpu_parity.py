@@ -44,6 +44,7 @@ def _graphs():
         "rmat12": lambda: pggen.rmat(12, 16, seed=1),
         "rmat_n1000": lambda: pggen.rmat(0, 8, seed=4, n=1000),
         "hub": lambda: pggen.disjoint_union(pggen.star(6000), pggen.er(2000, 10, seed=3), pggen.complete(30)),
+        "bigstar": lambda: pggen.star(200000),
         "k40": lambda: pggen.complete(40),
         "wheel7": lambda: pggen.wheel(7),
         "isolated": lambda: pggen.from_pairs(50, [], []),
@@ -179,7 +180,10 @@ def test_khash_build_bitexact(ctx, name, k):
     dg.close()
 
 
-OH_CASES = [("rmat12", 32), ("hub", 64), ("er4096", 8), ("k40", 100), ("rmat10", 1), ("wheel7", 3), ("isolated", 4)]
+# k = 600 on the hub (degree 5999): no LDS candidates above k = 512, radix select over all elements;
+# the big star's hub (degree 199,999): the first top-byte bin exceeds 512 keys, the second fits
+OH_CASES = [("rmat12", 32), ("hub", 64), ("er4096", 8), ("k40", 100), ("rmat10", 1), ("wheel7", 3), ("isolated", 4),
+            ("hub", 600), ("bigstar", 32)]
 
 
 @pytest.mark.parametrize("name,k", OH_CASES)
