@@ -458,6 +458,8 @@ def main():
         rows["bf_jaccard_edges"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
         ms = timed(lambda: skk.jaccard("kh"), reps, sync)
         rows["khash32_jaccard_edges"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
+        ms = timed(lambda: skk.cc("kh"), reps, sync)
+        rows["khash32_cc"] = {"ms": round(ms, 4), "arc_intersections_per_s": nnz / (ms * 1e-3)}
         skk.close()
         # exact per-edge intersections (all m edges) and exact CC
         ms = timed(lambda: dg.exact_intersect(), 3, sync)

@@ -745,6 +745,57 @@ __global__ __launch_bounds__(kBlock) void k_bf_cc_plan(PlanView P, SkView s, con
   }
 }
 
+// k-hash clustering coefficient over the same plan: the triangle count's
+// k-hash item (sig_v in registers, teams of kKhTeam lanes per neighbour
+// signature) over all of N_v; heavy chunks write block sums combined by
+// k_cc_combine.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_kh_cc_plan(PlanView P, SkView s, const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ adj, float* __restrict__ cc,
+                                                       double* __restrict__ vsum, double* __restrict__ part) {
+  __shared__ double red[kBlock / kWave];
+  constexpr int U = K <= 32 ? 4 : 2;
+  const int64_t blk = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (blk < P.n_chunks) {
+    const double acc = kh_item<K, U, kBlock>(s, P.chunk_vertex[blk], adj, P.chunk_begin[blk], P.chunk_end[blk], tid);
+    const double r = block_sum_256(acc, red);
+    if (tid == 0) part[blk] = r;
+    return;
+  }
+  const int64_t mb = blk - P.n_chunks;
+  int32_t v = -1;
+  double tot = 0.0;
+  bool lead = false;
+  if (mb < P.n_medium_blocks) {  // one wave per vertex
+    const int64_t idx = mb * (kBlock / kWave) + tid / kWave;
+    double acc = 0.0;
+    if (idx < P.n_medium) {
+      v = P.medium[idx];
+      acc = kh_item<K, U, kWave>(s, v, adj, off[v], off[v + 1], lane_id());
+    }
+    tot = group_sum<kWave>(acc);
+    lead = lane_id() == 0;
+  } else {  // light: kWholeGroup lanes per vertex
+    const int64_t idx = ((mb - P.n_medium_blocks) * kBlock + tid) / kWholeGroup;
+    double acc = 0.0;
+    if (idx < P.n_light) {
+      const int32_t u = P.light ? P.light[idx] : (int32_t)idx;
+      if (off[u + 1] - off[u] <= kLightMax) {
+        v = u;
+        acc = kh_item<K, U, kWholeGroup>(s, v, adj, off[v], off[v + 1], tid % kWholeGroup);
+      }
+    }
+    tot = group_sum<kWholeGroup>(acc);
+    lead = tid % kWholeGroup == 0;
+  }
+  if (v >= 0 && lead) {
+    const int32_t d = s.deg[v];
+    cc[v] = (float)(d >= 2 ? tot / ((double)d * ((double)d - 1.0)) : 0.0);
+    if (vsum) vsum[v] = tot;
+  }
+}
+
 __global__ void k_make_table(double* __restrict__ t, uint32_t B, uint32_t b, int est) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c > B) return;
@@ -1050,6 +1101,31 @@ int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStre
       PG_LAUNCH_CHECK();
       return PG_OK;
     }));
+    if (P.n_heavy > 0) {
+      hipLaunchKernelGGL(k_cc_combine, dim3((unsigned)((P.n_heavy + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pv,
+                         (const double*)part, P.n_heavy, g->deg, cc, vsum);
+      PG_LAUNCH_CHECK();
+    }
+    return dfree(part, s);
+  }
+  if (sk->kind == PG_MH_KHASH && (sk->size == 16 || sk->size == 32 || sk->size == 64)) {
+    const VertexPlan& P = g->plan_all;
+    const PlanView pv = plan_view(P);
+    const int64_t nblk = P.n_chunks + pv.n_medium_blocks + (P.n_light * kWholeGroup + kBlock - 1) / kBlock;
+    if (nblk <= 0) return PG_OK;
+    if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one launch");
+    double* part = nullptr;
+    PG_TRY(dmalloc((void**)&part, sizeof(double) * (size_t)std::max<int64_t>(P.n_chunks, 1), s));
+    if (sk->size == 16)
+      hipLaunchKernelGGL(k_kh_cc_plan<16>, dim3((unsigned)nblk), dim3(kBlock), 0, s, pv, view, g->off, g->adj, cc, vsum,
+                         part);
+    else if (sk->size == 32)
+      hipLaunchKernelGGL(k_kh_cc_plan<32>, dim3((unsigned)nblk), dim3(kBlock), 0, s, pv, view, g->off, g->adj, cc, vsum,
+                         part);
+    else
+      hipLaunchKernelGGL(k_kh_cc_plan<64>, dim3((unsigned)nblk), dim3(kBlock), 0, s, pv, view, g->off, g->adj, cc, vsum,
+                         part);
+    PG_LAUNCH_CHECK();
     if (P.n_heavy > 0) {
       hipLaunchKernelGGL(k_cc_combine, dim3((unsigned)((P.n_heavy + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pv,
                          (const double*)part, P.n_heavy, g->deg, cc, vsum);
