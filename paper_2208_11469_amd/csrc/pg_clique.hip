@@ -13,11 +13,11 @@
 // elements of the shorter list at a time, binary-search them in the longer
 // list, and a ballot appends the hits in ID order (with their degrees, for
 // the rank test, and with filters the first hash function's bit index, so
-// each element is hashed once per edge rather than once per pair). The
-// |C3|^2 ordered pairs (w, x) are then spread over the lanes: for |C3| <= 64
-// each lane keeps one x and walks the w rows 64 / |C3| apart; otherwise the
-// wave takes one w at a time (with filters its row is staged in LDS) and the
-// lanes stride over x. Counts are integers: the result does not depend on
+// each element is hashed once per edge rather than once per pair). For
+// |C3| <= 64 the |C3| (|C3| - 1) / 2 unordered pairs are dealt to the lanes,
+// the lower-ranked element of each pair playing w; otherwise the wave takes
+// one w at a time (with filters its row is staged in LDS) and the lanes
+// stride over x, testing those ranked above w. Counts are integers: the result does not depend on
 // scheduling.
 #include <hip/hip_runtime.h>
 
@@ -144,22 +144,23 @@ __global__ __launch_bounds__(kBlock) void k_four_cliques(const int32_t* __restri
     wave_sync();
     if (s >= 2) {
       if (s <= kWave) {
-        const int per = kWave / s;
-        const int wi0 = lane / s;
-        if (wi0 < per) {
-          const int xi = lane - wi0 * s;
-          const int32_t x = ids[xi], dx = dg[xi];
-          uint32_t i0 = 0;
-          if constexpr (kBf) i0 = hx[xi];
-          for (int wi = wi0; wi < s; wi += per) {
-            const int32_t w = ids[wi], dw = dg[wi];
-            if (!ranked_below(w, dw, x, dx)) continue;  // N+_w holds only vertices ranked above w
-            if constexpr (kBf) {
-              mine += member(filter_row<WT>(f, w), f, x, i0);
-            } else {
-              const int32_t b0 = poff[w];
-              mine += sorted_contains(padj + b0, poff[w + 1] - b0, x) ? 1u : 0u;
-            }
+        // the s (s - 1) / 2 unordered pairs {i, j} of C3, dealt to the lanes;
+        // w is the lower-ranked element (N+_w holds only vertices ranked above w)
+        const int32_t npairs = s * (s - 1) / 2;
+        for (int32_t p = lane; p < npairs; p += kWave) {
+          // p = j (j - 1) / 2 + i with 0 <= i < j
+          int32_t j = (int32_t)((1.0f + sqrtf(1.0f + 8.0f * (float)p)) * 0.5f);
+          while (j * (j - 1) / 2 > p) --j;
+          while ((j + 1) * j / 2 <= p) ++j;
+          const int32_t i = p - j * (j - 1) / 2;
+          const bool i_low = ranked_below(ids[i], dg[i], ids[j], dg[j]);
+          const int32_t wi = i_low ? i : j, xi = i_low ? j : i;
+          const int32_t w = ids[wi], x = ids[xi];
+          if constexpr (kBf) {
+            mine += member(filter_row<WT>(f, w), f, x, hx[xi]);
+          } else {
+            const int32_t b0 = poff[w];
+            mine += sorted_contains(padj + b0, poff[w + 1] - b0, x) ? 1u : 0u;
           }
         }
       } else {
