@@ -450,24 +450,29 @@ __global__ void k_sum_chunks(const double* __restrict__ chunks, int64_t nchunks,
 }
 
 // One block of kWideBlock threads over up to kWideMax partials: thread t sums
-// entries t, t + kWideBlock, ... into four accumulators in a fixed pattern,
-// then a fixed tree. One launch instead of two for the usual partial counts.
+// entries t, t + kWideBlock, ... in rounds of kWideLoads independent loads
+// (zero past the end) into eight accumulators in a fixed pattern, then a
+// fixed tree. One launch instead of two for the usual partial counts; the
+// loads of a round are all in flight together.
 constexpr int kWideBlock = 1024;
+constexpr int kWideLoads = 16;
 constexpr int64_t kWideMax = 1 << 17;
 
 __global__ __launch_bounds__(kWideBlock) void k_sum_wide(const double* __restrict__ chunks, int64_t nchunks,
                                                          double divisor, double* out) {
   __shared__ double lds[kWideBlock / kWave];
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int64_t i = threadIdx.x;
-  for (; i + 3 * kWideBlock < nchunks; i += 4 * kWideBlock) {
-    a0 += chunks[i];
-    a1 += chunks[i + kWideBlock];
-    a2 += chunks[i + 2 * kWideBlock];
-    a3 += chunks[i + 3 * kWideBlock];
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t i0 = threadIdx.x; i0 < nchunks; i0 += (int64_t)kWideLoads * kWideBlock) {
+    double v[kWideLoads];
+#pragma unroll
+    for (int j = 0; j < kWideLoads; ++j) {
+      const int64_t i = i0 + (int64_t)j * kWideBlock;
+      v[j] = i < nchunks ? chunks[i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kWideLoads; ++j) a[j & 7] += v[j];
   }
-  for (; i < nchunks; i += kWideBlock) a0 += chunks[i];
-  double acc = group_sum<kWave>((a0 + a1) + (a2 + a3));
+  double acc = group_sum<kWave>(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
   if (lane_id() == 0) lds[threadIdx.x / kWave] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
