@@ -147,20 +147,34 @@ __global__ __launch_bounds__(kBlock) void k_bf_build_plan(PlanView P, const int3
   if (active && lane == 0) pc[v] = ones;
 }
 
-// Heavy vertices: OR of the chunk partials in chunk order; one wave per vertex.
+// Heavy vertices: OR of the chunk partials; one wave per vertex. Lane l reads
+// word l mod W of every (64 / W)-th chunk starting at chunk l / W, so the
+// wave reads 64 / W partial rows side by side; the lanes holding the same
+// word then meet in LDS. OR is order-independent.
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_bf_combine(PlanView P, const uint64_t* __restrict__ part, int64_t n_heavy,
                                                        uint64_t* __restrict__ words, uint32_t* __restrict__ pc) {
-  const int64_t h = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;
+  __shared__ uint64_t lds[kBlock];
+  const int64_t h = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave;  // the same in every lane of a wave
   if (h >= n_heavy) return;
   const int lane = lane_id();
+  constexpr int R = kWave / W;  // partial rows in flight
+  const int word = lane % W, row = lane / W;
   const int32_t c0 = P.heavy_first[h], c1 = P.heavy_first[h + 1];
   const int32_t v = P.chunk_vertex[c0];
   uint64_t acc = 0;
-  if (lane < W)
-    for (int32_t c = c0; c < c1; ++c) acc |= part[(int64_t)c * W + lane];
-  if (lane < W) words[bf_row_offset(v, W) + lane] = acc;
-  const uint32_t ones = group_sum_u32<kWave>((uint32_t)__popcll(acc));
+  if (row < R)
+    for (int32_t c = c0 + row; c < c1; c += R) acc |= part[(int64_t)c * W + word];
+  uint64_t* mine = lds + (threadIdx.x / kWave) * kWave;
+  mine[lane] = acc;
+  wave_sync();
+  uint64_t w = 0;
+  if (lane < W) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) w |= mine[r * W + lane];
+    words[bf_row_offset(v, W) + lane] = w;
+  }
+  const uint32_t ones = group_sum_u32<kWave>((uint32_t)__popcll(w));
   if (lane == 0) pc[v] = ones;
 }
 
