@@ -328,7 +328,8 @@ int make_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, uint
     sk->W = size / 64;
     if (rc == PG_OK) rc = palloc((void**)&sk->words, sizeof(uint64_t) * (bf_total_words((int64_t)n, sk->W) + kBfSlackWords));
     if (rc == PG_OK) rc = palloc((void**)&sk->pc, sizeof(uint32_t) * n);
-    if (rc == PG_OK) rc = palloc((void**)&sk->table, sizeof(double) * (size + 1));
+    if (rc == PG_OK) rc = palloc((void**)&sk->table, sizeof(double) * kBfTables * (size + 1));
+    if (rc == PG_OK) rc = fill_tables(sk, s);
     if (rc == PG_OK)
       rc = palloc((void**)&sk->scratch, sizeof(uint64_t) * sk->W * (size_t)std::max<int64_t>(rows->plan_all.n_chunks, 1));
     if (rc == PG_OK && build && g->n > 0) rc = build_bf(sk, s);

@@ -297,7 +297,6 @@ int four_cliques_estimate(const pg_sketches* sk, int est, double* d_out, hipStre
     return fail(PG_E_INVALID, "4-clique estimates take a Bloom-filter estimator");
   pg_graph* g = sk->g;
   PG_TRY(graph_oriented(g, s));
-  PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
   PG_TRY(fill_u64((uint64_t*)d_out, 0, 1, s));  // 0.0
   if (g->m <= 0) return PG_OK;
   const int32_t cap = (std::max(1, g->oriented->max_degree) + 1) & ~1;
@@ -316,10 +315,10 @@ int four_cliques_estimate(const pg_sketches* sk, int est, double* d_out, hipStre
   do {                                                                                                            \
     if (est == PG_EST_BF_OR)                                                                                      \
       hipLaunchKernelGGL((k_four_cliques_filters<WW, true>), dim3(grid), dim3(kBlock), shmem, s, g->poff, g->padj, \
-                         g->parc_src, g->m, cap, f, (const double*)sk->table, partials);                          \
+                         g->parc_src, g->m, cap, f, bf_table(sk, est), partials);                          \
     else                                                                                                          \
       hipLaunchKernelGGL((k_four_cliques_filters<WW, false>), dim3(grid), dim3(kBlock), shmem, s, g->poff,        \
-                         g->padj, g->parc_src, g->m, cap, f, (const double*)sk->table, partials);                 \
+                         g->padj, g->parc_src, g->m, cap, f, bf_table(sk, est), partials);                 \
   } while (0)
     switch (sk->W) {
       case 1: PG_CKF(1); break;

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "pg_device.h"
@@ -863,7 +865,7 @@ SkView make_view(const pg_sketches* sk, int est) {
   v.words = sk->words;
   v.pc = sk->pc;
   v.sig = sk->sig;
-  v.table = sk->table;
+  v.table = bf_table(sk, est);
   v.deg = sk->rows->deg;  // sizes of the sketched sets: d_v, or d+_v for oriented rows
   if (sk->kind == PG_MH_1HASH) hash_constants(PG_MH_1HASH, sk->seed, 1, &v.a1, &v.c1);
   return v;
@@ -889,12 +891,16 @@ int fill_table(double* table, uint32_t B, uint32_t b, int est, hipStream_t s) {
   return PG_OK;
 }
 
-int ensure_table(pg_sketches* sk, int est, hipStream_t s) {
+int fill_tables(pg_sketches* sk, hipStream_t s) {
   if (sk->kind != PG_BF) return PG_OK;
-  if (sk->table_est == est) return PG_OK;
-  PG_TRY(fill_table(sk->table, sk->size, sk->b, est, s));
-  sk->table_est = est;
+  for (int i = 0; i < kBfTables; ++i)
+    PG_TRY(fill_table(sk->table + (size_t)i * (sk->size + 1), sk->size, sk->b, PG_EST_BF_AND + i, s));
   return PG_OK;
+}
+
+const double* bf_table(const pg_sketches* sk, int est) {
+  if (sk->kind != PG_BF || est < PG_EST_BF_AND || est > PG_EST_BF_PAPAPETROU) return nullptr;
+  return sk->table + (size_t)(est - PG_EST_BF_AND) * (sk->size + 1);
 }
 
 int estimate_pairs(const pg_sketches* sk, int est, const int32_t* u, const int32_t* v, int64_t npairs,
@@ -903,7 +909,6 @@ int estimate_pairs(const pg_sketches* sk, int est, const int32_t* u, const int32
   if (sim_out && sk->oriented) return fail(PG_E_UNSUPPORTED, kOrientedNeedsNv);
   if (sim_out && (measure < PG_SIM_COMMON || measure > PG_SIM_TOTAL))
     return fail(PG_E_INVALID, "unknown similarity measure");
-  PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
   if (npairs <= 0) return PG_OK;
   const SkView view = make_view(sk, est);
   const unsigned grid = grid_for(npairs, kBlock, 65536);
@@ -922,7 +927,6 @@ int estimate_jp(const pg_sketches* sk, int est, int measure, double tau, uint8_t
   PG_TRY(check_estimator(sk, est));
   if (sk->oriented) return fail(PG_E_UNSUPPORTED, kOrientedNeedsNv);
   if (measure < PG_SIM_COMMON || measure > PG_SIM_TOTAL) return fail(PG_E_INVALID, "unknown similarity measure");
-  PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
   PG_TRY(fill_u64((uint64_t*)d_kept, 0, 1, s));
   const pg_graph* g = sk->g;
   if (g->m <= 0) return PG_OK;
@@ -945,7 +949,6 @@ int estimate_jp(const pg_sketches* sk, int est, int measure, double tau, uint8_t
 int estimate_sum(const pg_sketches* sk, int est, const int32_t* u, const int32_t* v, int64_t npairs, double* chunks,
                  hipStream_t s) {
   PG_TRY(check_estimator(sk, est));
-  PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
   const int64_t nchunks = chunk_count(npairs);
   if (nchunks <= 0) return PG_OK;
   const SkView view = make_view(sk, est);
@@ -959,20 +962,38 @@ int estimate_sum(const pg_sketches* sk, int est, const int32_t* u, const int32_t
   return PG_OK;
 }
 
-int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
+int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s, const TcWorkspace* ws) {
   PG_TRY(check_estimator(sk, est));
-  PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
+  // partial sums (and the tiles of their sum): in the caller's workspace, or
+  // allocated for this call
+  auto get_parts = [&](int64_t count, double** parts, double** tiles) -> int {
+    *parts = *tiles = nullptr;
+    if (!ws) return dmalloc((void**)parts, sizeof(double) * (size_t)count, s);
+    if (count + sum_chunks_tiles(count) > ws->doubles)
+      return fail(PG_E_UNSUPPORTED, "triangle count: " + std::to_string(count + sum_chunks_tiles(count)) +
+                                        " partial sums exceed the fixed workspace of " + std::to_string(ws->doubles));
+    *parts = ws->ptr;
+    *tiles = ws->ptr + count;
+    return PG_OK;
+  };
+  auto put_parts = [&](double* parts) { return ws ? PG_OK : dfree(parts, s); };
+  auto plan = [&]() -> int {
+    if (ws && !sk->g->slabs.split)
+      return fail(PG_E_UNSUPPORTED, "the graph's triangle-count plan is not built yet: it is built (and allocated) by "
+                                    "the first pg_tc or pg_tc_async call on a sketch set of this graph");
+    return graph_slabs(const_cast<pg_graph*>(sk->g), s);
+  };
   const pg_graph* g = sk->g;
   // every kernel below sums the estimate over the m edges, each once: a triangle
   // contributes three edges over N_v, one over N+_v (Listing "lst:tc")
   const double divisor = sk->oriented ? 1.0 : 3.0;
   if (sk->kind == PG_BF && sk->W <= 16 && g->n > 0) {
-    PG_TRY(graph_slabs(const_cast<pg_graph*>(g), s));
+    PG_TRY(plan());
     const SlabPlan& P = g->slabs;
     const int64_t nblk = std::max<int64_t>(slab_plan_blocks(P), 1);
     if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one triangle-count launch");
-    double* partials = nullptr;
-    PG_TRY(dmalloc((void**)&partials, sizeof(double) * (size_t)nblk, s));
+    double *partials, *tiles;
+    PG_TRY(get_parts(nblk, &partials, &tiles));
     const SkView view = make_view(sk, est);
     const size_t shmem = sizeof(double) * ((size_t)sk->size + 1);
     {
@@ -1007,16 +1028,16 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
 #undef PG_TCP
       PG_LAUNCH_CHECK();
     }
-    PG_TRY(sum_chunks(partials, nblk, divisor, d_out, s));
-    return dfree(partials, s);
+    PG_TRY(sum_chunks(partials, nblk, divisor, d_out, s, tiles));
+    return put_parts(partials);
   }
   if (sk->kind == PG_MH_KHASH && (sk->size == 16 || sk->size == 32 || sk->size == 64) && g->n > 0) {
-    PG_TRY(graph_slabs(const_cast<pg_graph*>(g), s));
+    PG_TRY(plan());
     const SlabPlan& P = g->slabs;
     const int64_t nblk = std::max<int64_t>(slab_plan_blocks(P), 1);
     if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one triangle-count launch");
-    double* partials = nullptr;
-    PG_TRY(dmalloc((void**)&partials, sizeof(double) * (size_t)nblk, s));
+    double *partials, *tiles;
+    PG_TRY(get_parts(nblk, &partials, &tiles));
     const SkView view = make_view(sk, est);
     {
       ProfScope ps(s, "kh_tc");
@@ -1031,11 +1052,11 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
                            partials);
       PG_LAUNCH_CHECK();
     }
-    PG_TRY(sum_chunks(partials, nblk, divisor, d_out, s));
-    return dfree(partials, s);
+    PG_TRY(sum_chunks(partials, nblk, divisor, d_out, s, tiles));
+    return put_parts(partials);
   }
   if (sk->kind == PG_MH_1HASH && is_onehash_union(est) && g->n > 0) {
-    PG_TRY(graph_slabs(const_cast<pg_graph*>(g), s));
+    PG_TRY(plan());
     const SlabPlan& P = g->slabs;
     int64_t busiest = 0;
     for (int x = 0; x < kSlabs; ++x) busiest = std::max(busiest, oh_slab_blocks(P, x));
@@ -1043,8 +1064,8 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
     const int64_t nblk = std::max<int64_t>(grid_slabs + (P.n_whole + 3) / 4, 1);
     if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one launch");
     const int64_t nparts = nblk * (kBlock / kWave);
-    double* partials = nullptr;
-    PG_TRY(dmalloc((void**)&partials, sizeof(double) * (size_t)nparts, s));
+    double *partials, *tiles;
+    PG_TRY(get_parts(nparts, &partials, &tiles));
     const SkView view = make_view(sk, est);
     {
       ProfScope ps(s, "oh_tc");
@@ -1061,23 +1082,22 @@ int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s) {
         return PG_OK;
       }));
     }
-    PG_TRY(sum_chunks(partials, nparts, divisor, d_out, s));
-    return dfree(partials, s);
+    PG_TRY(sum_chunks(partials, nparts, divisor, d_out, s, tiles));
+    return put_parts(partials);
   }
   // general path: one lane per upper edge, fixed chunks
   const int64_t nchunks = std::max<int64_t>(chunk_count(g->m), 1);
-  double* chunks = nullptr;
-  PG_TRY(dmalloc((void**)&chunks, sizeof(double) * (size_t)nchunks, s));
+  double *chunks, *tiles;
+  PG_TRY(get_parts(nchunks, &chunks, &tiles));
   PG_TRY(fill_u64((uint64_t*)chunks, 0, nchunks, s));
   if (g->m > 0) PG_TRY(estimate_sum(sk, est, g->eu, g->ev, g->m, chunks, s));
-  PG_TRY(sum_chunks(chunks, nchunks, divisor, d_out, s));
-  return dfree(chunks, s);
+  PG_TRY(sum_chunks(chunks, nchunks, divisor, d_out, s, tiles));
+  return put_parts(chunks);
 }
 
 int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStream_t s) {
   PG_TRY(check_estimator(sk, est));
   if (sk->oriented) return fail(PG_E_UNSUPPORTED, kOrientedNeedsNv);
-  PG_TRY(ensure_table(const_cast<pg_sketches*>(sk), est, s));
   const pg_graph* g = sk->g;
   const SkView view = make_view(sk, est);
   ProfScope ps(s, "cc");

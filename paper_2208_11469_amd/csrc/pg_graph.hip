@@ -532,7 +532,11 @@ int fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s) {
   return PG_OK;
 }
 
-int sum_chunks(const double* chunks, int64_t nchunks, double divisor, double* out, hipStream_t s) {
+int64_t sum_chunks_tiles(int64_t nchunks) {
+  return (nchunks > 4 * kScanTile && nchunks > kWideMax) ? (nchunks + kScanTile - 1) / kScanTile : 0;
+}
+
+int sum_chunks(const double* chunks, int64_t nchunks, double divisor, double* out, hipStream_t s, double* tiles) {
   ProfScope ps(s, "sum_chunks");
   if (nchunks > 4 * kScanTile && nchunks <= kWideMax) {
     hipLaunchKernelGGL(k_sum_wide, dim3(1), dim3(kWideBlock), 0, s, chunks, nchunks, divisor, out);
@@ -541,15 +545,15 @@ int sum_chunks(const double* chunks, int64_t nchunks, double divisor, double* ou
   }
   if (nchunks > 4 * kScanTile) {
     // two levels: fixed tiles of kScanTile partials, then the tile sums
-    const int64_t nt = (nchunks + kScanTile - 1) / kScanTile;
-    double* tiles = nullptr;
-    PG_TRY(dmalloc((void**)&tiles, sizeof(double) * nt, s));
+    const int64_t nt = sum_chunks_tiles(nchunks);
+    const bool own = tiles == nullptr;
+    if (own) PG_TRY(dmalloc((void**)&tiles, sizeof(double) * nt, s));
     hipLaunchKernelGGL(k_array_chunks, dim3((unsigned)std::min<int64_t>(nt, 65536)), dim3(kBlock), 0, s, chunks,
                        nchunks, tiles);
     PG_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(kBlock), 0, s, (const double*)tiles, nt, divisor, out);
     PG_LAUNCH_CHECK();
-    return dfree(tiles, s);
+    return own ? dfree(tiles, s) : PG_OK;
   }
   hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(kBlock), 0, s, chunks, nchunks, divisor, out);
   PG_LAUNCH_CHECK();

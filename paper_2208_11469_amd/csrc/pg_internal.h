@@ -240,10 +240,9 @@ struct pg_sketches {
   uint32_t* sig = nullptr;    // [n*k]  MinHash rows
   uint64_t* ha = nullptr;     // device hash multipliers
   uint64_t* hc = nullptr;     // device hash increments
-  double* table = nullptr;    // [B+1]  estimator table (Bloom filters)
+  double* table = nullptr;    // [kBfTables * (B+1)] estimator tables (Bloom filters), one per estimator
   bool empty_rows_zero = false;  // Bloom filters: the rows of vertices without arcs are known to be zero
   uint64_t* scratch = nullptr;    // partial rows of heavy chunks (plan_all.n_chunks * W words)
-  int table_est = 0;          // estimator the table holds
 };
 
 namespace pg {
@@ -259,7 +258,12 @@ void free_plan(pg::VertexPlan* plan);
 void free_slabs(pg::SlabPlan* plan);
 int exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t count, hipStream_t s);
 int fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s);
-int sum_chunks(const double* chunks, int64_t nchunks, double divisor, double* out, hipStream_t s);
+// Fixed-order sum of nchunks partials, divided by `divisor`, into out[0].
+// Above kWideMax partials it needs sum_chunks_tiles(nchunks) doubles of
+// temporary memory: `tiles` if given, else allocated on the stream.
+int64_t sum_chunks_tiles(int64_t nchunks);
+int sum_chunks(const double* chunks, int64_t nchunks, double divisor, double* out, hipStream_t s,
+               double* tiles = nullptr);
 int sum_array(const double* x, int64_t count, double divisor, double* out, hipStream_t s);
 
 // ---- launchers (pg_build.hip) ------------------------------------------------
@@ -273,7 +277,13 @@ int bf_unpack(const pg_sketches* sk, void* rows, hipStream_t s);
 int bf_pack(pg_sketches* sk, const void* rows, const uint32_t* pc, hipStream_t s);
 
 // ---- launchers (pg_estimate.hip) ---------------------------------------------
-int ensure_table(pg_sketches* sk, int est, hipStream_t s);
+// Bloom-filter sets hold one table of B+1 entries per estimator
+// (PG_EST_BF_AND .. PG_EST_BF_PAPAPETROU), all filled when the set is made, so
+// calls on different streams never rewrite a table another call reads.
+constexpr int kBfTables = 4;
+int fill_tables(pg_sketches* sk, hipStream_t s);
+// The table of estimator `est` of a Bloom-filter set (NULL for MinHash sets).
+const double* bf_table(const pg_sketches* sk, int est);
 // Estimator table of a Bloom-filter size into a caller-owned [B+1] array.
 int fill_table(double* table, uint32_t B, uint32_t b, int est, hipStream_t s);
 // Per pair: est / raw / similarity (PG_SIM_* measure) outputs, each nullable.
@@ -289,7 +299,15 @@ int estimate_sum(const pg_sketches* sk, int est, const int32_t* u, const int32_t
                  double* chunks, hipStream_t s);
 int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStream_t s);
 // TC^ = (1/3) sum over the m edges of the estimate, into d_out[0] (device).
-int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s);
+// With a workspace the partial sums live there and the call allocates
+// nothing; it then needs the graph's triangle-count plan to exist already
+// (PG_E_UNSUPPORTED otherwise, or when the partials exceed the workspace).
+struct TcWorkspace {
+  double* ptr;      // device
+  int64_t doubles;  // capacity
+};
+int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s, const TcWorkspace* ws = nullptr);
+
 
 // ---- launchers (pg_exact.hip) ------------------------------------------------
 int exact_pairs(const pg_graph* g, int algo, const int32_t* u, const int32_t* v, int64_t npairs,

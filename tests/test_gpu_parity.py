@@ -474,3 +474,33 @@ def test_full_size_rmat20_khash_and_exact(ctx, g20):
     torch.cuda.synchronize()
     assert np.array_equal(np_(got).astype(np.uint32)[idx], oracle.exact_pairs(g, eu[idx], ev[idx]))
     dg.close()
+
+
+def test_estimators_on_two_streams_do_not_interfere(ctx):
+    """Every Bloom-filter estimator has its own table, filled when the set is
+    made: AND, OR, limit and the existing estimator interleaved on two streams
+    without waits give exactly what each gives alone."""
+    g = graph("rmat12")
+    say("two streams alternating Bloom-filter estimators, rmat12 bf320")
+    dg = pg.Graph(ctx, g.offsets, g.adj)
+    sk = dg.build_sketches("bf", 320, 1, seed=3)
+    ests = ["and", "or", "l", "pap"]
+    tc_alone = {e: sk.tc(e) for e in ests}
+    edge_alone = {e: sk.intersect(e, want_raw=False)[0].clone() for e in ests}
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    rounds = 6
+    tcs = torch.full((rounds * len(ests),), float("nan"), dtype=torch.float64, device="cuda")
+    edges = [torch.full((dg.m,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(rounds * len(ests))]
+    torch.cuda.synchronize()
+    for i in range(rounds * len(ests)):
+        e, st = ests[i % len(ests)], streams[i % 2]
+        sk.tc_async(e, tcs[i:i + 1], stream=st)
+        pg.pg_intersect_edges(ctx.h, sk.h, pg.ESTIMATORS[e], None, None, 0, edges[i], None, st)
+    torch.cuda.synchronize()
+    for i in range(rounds * len(ests)):
+        e = ests[i % len(ests)]
+        assert tcs[i].item() == tc_alone[e], (i, e)
+        assert torch.equal(edges[i], edge_alone[e]), (i, e)
+    sk.close()
+    dg.close()
