@@ -343,6 +343,7 @@ typedef struct pg_server_stats {
   uint64_t completed;        /* requests whose results were delivered */
   uint64_t batches;          /* launches */
   uint64_t pairs;            /* pairs answered */
+  uint64_t max_in_flight;    /* most batches launched and not yet retired at one time */
 } pg_server_stats;
 
 /* sketches: host array of nsketches handles built on `g`. params may be NULL. */

@@ -103,7 +103,7 @@ class _Request(ctypes.Structure):
 class _ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("rejected_busy", ctypes.c_uint64),
                 ("rejected_invalid", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
-                ("pairs", ctypes.c_uint64)]
+                ("pairs", ctypes.c_uint64), ("max_in_flight", ctypes.c_uint64)]
 
 
 PG_OP_CN = 1
@@ -533,6 +533,16 @@ class Graph:
             pg_graph_destroy(self.h)
             self.h = None
 
+    def csr_fingerprint(self) -> str:
+        """SHA-256 of the CSR arrays the graph was made from (offsets then adj, int32 little-endian)."""
+        import hashlib
+        off, ad = self._keep
+        h = hashlib.sha256()
+        for a in (off, ad):
+            a = a if isinstance(a, np.ndarray) else a.cpu().numpy()
+            h.update(np.ascontiguousarray(a, dtype="<i4").tobytes())
+        return h.hexdigest()
+
     def upper_edges(self, stream=None):
         torch = _torch()
         dev = torch.device("cuda", self.ctx.device)
@@ -611,7 +621,7 @@ class Graph:
                                                  rows if self.n else None, pc if self.n else None, stream))
 
     def load_sketches(self, path, stream=None) -> "Sketches":
-        """Resume a sketch set saved by Sketches.save (checks the graph's n and m)."""
+        """Resume a sketch set saved by Sketches.save (checks the graph's n, m and CSR fingerprint)."""
         import json
         torch = _torch()
         with np.load(path, allow_pickle=False) as f:
@@ -622,6 +632,8 @@ class Graph:
             raise ValueError(f"{path}: not a sketch file of this library's format and hash family")
         if header["n"] != self.n or header["m"] != self.m:
             raise ValueError(f"{path}: saved for a graph with n={header['n']} m={header['m']}, not n={self.n} m={self.m}")
+        if header.get("csr_sha256") != self.csr_fingerprint():
+            raise ValueError(f"{path}: saved for another graph of the same n and m (CSR fingerprints differ)")
         dev = self._dev()
         d_rows = torch.from_numpy(rows).to(dev)
         d_pc = torch.from_numpy(pc).to(dev) if pc is not None else None
@@ -737,7 +749,7 @@ class Sketches:
         _torch().cuda.synchronize(rows.device)
         header = {"format": SKETCH_FILE_FORMAT, "hash_family": HASH_FAMILY, "kind": self.kind,
                   "oriented": self.oriented, "size": self.size, "b": self.b, "seed": self.seed,
-                  "n": self.graph.n, "m": self.graph.m}
+                  "n": self.graph.n, "m": self.graph.m, "csr_sha256": self.graph.csr_fingerprint()}
         arrays = {"header": np.frombuffer(json.dumps(header).encode(), dtype=np.uint8),
                   "rows": rows.cpu().numpy()}
         if pc is not None:

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <string>
 
 #include "pg_device.h"
 #include "pg_internal.h"
@@ -508,6 +509,15 @@ __global__ void k_bf_popcounts(const uint64_t* __restrict__ dense, int64_t n, ui
   }
 }
 
+// Number of i with a[i] != b[i], added to *bad.
+__global__ void k_u32_mismatches(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, int64_t n,
+                                 unsigned long long* __restrict__ bad) {
+  uint32_t mine = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    mine += a[i] != b[i] ? 1u : 0u;
+  if (mine) atomicAdd(bad, (unsigned long long)mine);
+}
+
 }  // namespace
 
 int bf_pack(pg_sketches* sk, const void* rows, const uint32_t* pc, hipStream_t s) {
@@ -517,14 +527,32 @@ int bf_pack(pg_sketches* sk, const void* rows, const uint32_t* pc, hipStream_t s
   hipLaunchKernelGGL(k_bf_pack, dim3(grid_for(n * sk->W, kBlock, 65536)), dim3(kBlock), 0, s,
                      (const uint64_t*)rows, n, sk->W, sk->words);
   PG_LAUNCH_CHECK();
-  if (pc) {
-    PG_HIP(hipMemcpyAsync(sk->pc, pc, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
-  } else {
-    hipLaunchKernelGGL(k_bf_popcounts, dim3(grid_for(n, kBlock, 65536)), dim3(kBlock), 0, s,
-                       (const uint64_t*)rows, n, sk->W, sk->pc);
-    PG_LAUNCH_CHECK();
+  // the popcounts are always counted from the rows: the OR estimator indexes
+  // its table of B + 1 entries with pc_u + pc_v - c, so a count that is not
+  // the row's could read past it
+  hipLaunchKernelGGL(k_bf_popcounts, dim3(grid_for(n, kBlock, 65536)), dim3(kBlock), 0, s, (const uint64_t*)rows, n,
+                     sk->W, sk->pc);
+  PG_LAUNCH_CHECK();
+  if (!pc) return PG_OK;
+  // given popcounts must equal the counted ones
+  unsigned long long* d_bad = nullptr;
+  PG_TRY(dmalloc((void**)&d_bad, sizeof(unsigned long long), s));
+  int rc = fill_u64((uint64_t*)d_bad, 0, 1, s);
+  if (rc == PG_OK) {
+    hipLaunchKernelGGL(k_u32_mismatches, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, pc,
+                       (const uint32_t*)sk->pc, n, d_bad);
+    if (hipGetLastError() != hipSuccess) rc = fail(PG_E_DEVICE, "popcount check launch failed");
   }
-  return PG_OK;
+  unsigned long long bad = 0;
+  if (rc == PG_OK) {
+    hipError_t e = hipMemcpyAsync(&bad, d_bad, sizeof(bad), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(PG_E_DEVICE, std::string("popcount check: ") + hipGetErrorString(e));
+  }
+  dfree(d_bad, s);
+  if (rc == PG_OK && bad)
+    rc = fail(PG_E_INVALID, std::to_string(bad) + " given popcounts differ from the ones of their rows");
+  return rc;
 }
 
 int bf_unpack(const pg_sketches* sk, void* rows, hipStream_t s) {

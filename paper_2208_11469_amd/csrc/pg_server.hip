@@ -244,7 +244,9 @@ void engine_loop(pg_server* srv) {
       srv->stats.batches++;
       progressed = true;
     }
-    const bool inflight = std::any_of(srv->slots.begin(), srv->slots.end(), [](const Slot& s) { return s.busy; });
+    const uint64_t busy = (uint64_t)std::count_if(srv->slots.begin(), srv->slots.end(), [](const Slot& s) { return s.busy; });
+    srv->stats.max_in_flight = std::max(srv->stats.max_in_flight, busy);
+    const bool inflight = busy > 0;
     if (srv->stop && !inflight && srv->queue.empty()) break;
     if (!progressed) {
       if (inflight) {

@@ -162,3 +162,37 @@ def test_rebuilds_keep_rows_of_empty_sets_zero(ctx, oriented):
     sk2.close()
     sk.close()
     dg.close()
+
+
+def test_import_rejects_popcounts_that_differ_from_the_rows(ctx, graph):
+    """The OR estimator indexes its table with pc_u + pc_v - c: an import counts
+    the ones of the rows itself and refuses given popcounts that differ."""
+    g, dg = graph
+    say("import with a corrupted popcount")
+    sk = dg.build_sketches("bf", 320, 1, seed=5)
+    rows, pc = sk.export()
+    bad = pc.clone()
+    bad[7] += 1000
+    with pytest.raises(pg.PGError) as ei:
+        dg.import_sketches("bf", 320, 1, 5, rows, bad)
+    assert ei.value.code == pg.PG_E_INVALID
+    sk2 = dg.import_sketches("bf", 320, 1, 5, rows, pc)  # the true counts are accepted
+    assert sk2.tc("or") == sk.tc("or")
+    sk2.close()
+    sk.close()
+
+
+def test_load_refuses_a_graph_of_the_same_size(ctx, graph, tmp_path):
+    """Same n and m, other edges: the CSR fingerprint in the file differs."""
+    g, dg = graph
+    sk = dg.build_sketches("bf", 256, 1, seed=2)
+    sk.save(tmp_path / "bf.npz")
+    sk.close()
+    perm = np.random.default_rng(1).permutation(g.n).astype(np.int32)  # relabelled copy: same n and m
+    eu, ev = oracle.upper_edges(g)
+    other = pggen.from_pairs(g.n, perm[eu], perm[ev])
+    assert other.n == g.n and other.nnz == g.nnz and not np.array_equal(other.adj, g.adj)
+    dg2 = pg.Graph(ctx, other.offsets, other.adj)
+    with pytest.raises(ValueError, match="fingerprint"):
+        dg2.load_sketches(tmp_path / "bf.npz")
+    dg2.close()

@@ -136,3 +136,29 @@ def test_replay_open_and_closed_loop(env):
     srv.wait(t)
     assert out.tobytes() == reqs[3][1][2].tobytes()
     srv.close()
+
+
+def test_alone_equals_mixed_with_concurrent_batches(env):
+    """Every request of a mix replayed with three batch slots, small batches and
+    many requests outstanding (so batches overlap on the device) returns
+    bit for bit what it returns alone."""
+    g, ctx, dg, sks = env
+    reqs = _requests(g, 60, seed=5)
+    srv = pg.Server(dg, sks, max_batches_in_flight=1)
+    alone = []
+    for op, sk, est, u, v in reqs:
+        t, out = srv.submit(op, sk, est, u, v)
+        srv.wait(t)
+        alone.append(out.copy())
+    srv.close()
+    say("replaying the mix on three batch slots, batches of at most 4096 pairs")
+    srv = pg.Server(dg, sks, max_batches_in_flight=3, max_pairs_per_request=4096, max_batch_pairs=4096)
+    for rep in range(3):
+        mix = [srv.make_request(op, sk, est, u, v) for op, sk, est, u, v in reqs]
+        srv.replay(mix, max_outstanding=len(mix))
+        for i, (a, (_, keep)) in enumerate(zip(alone, mix)):
+            assert a.tobytes() == keep[2].tobytes(), (rep, i)
+    st = srv.stats()
+    assert st["completed"] == 3 * len(reqs)
+    assert st["max_in_flight"] > 1, st  # batches did run concurrently
+    srv.close()
