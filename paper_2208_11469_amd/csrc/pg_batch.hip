@@ -11,7 +11,16 @@
 // vertex. Persistent blocks take items from a counter reset at the start of
 // every run and leave when the list is exhausted. The estimate runs one
 // launch per row width W present (its items grouped by W), so W is a
-// compile-time constant of that launch.
+// compile-time constant of that launch; the launches are dealt to four
+// streams (longest first, each to the least-loaded stream) so that their
+// tails overlap, and a captured run keeps them as parallel graph branches.
+//
+// No block ever waits for another block: a block leaves as soon as the index
+// it draws from its queue counter is past the end of its list, every loop is
+// bounded by the list or the vertex's arcs, and every barrier sits where the
+// whole block takes the same branch (the drawn index and the item are read
+// from LDS after a barrier). So every launch ends whatever the number of
+// resident blocks.
 //
 // Each vertex is always reduced by the same lanes in the same order (its tier
 // is fixed by its degree), so results do not depend on the tile size, the grid
@@ -72,6 +81,7 @@ struct BatchView {
 };
 
 constexpr int kCounters = 2 + kMaxW;
+constexpr int kBranches = 4;  // concurrent estimate streams (the box's hardware queues per process)
 
 __global__ void k_batch_reset(uint32_t* counters) {
   if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
@@ -336,6 +346,15 @@ struct pg_batch {
   uint32_t* counters = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // the per-width estimate launches are dealt to kBranches streams: the
+  // caller's and these (default priority), forked after the build and joined
+  // before the triangle-count sums
+  hipStream_t side[pg::kBranches - 1] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[pg::kBranches - 1] = {};
+  int branch_of[pg::kMaxW + 1] = {};  // stream of each row width's launch (0 = the caller's)
+  int launch_order[pg::kMaxW] = {};   // row widths by descending work
+  int n_widths = 0;
 };
 
 namespace pg {
@@ -370,6 +389,23 @@ int build_items(pg_batch* bt) {
       if (bt->h_gd[it.graph].W == w) eitems.push_back(it);
   }
   bt->w_begin[kMaxW + 1] = (int64_t)eitems.size();
+  // work per row width (arcs times the row words each arc reads, plus one
+  // per vertex), dealt to the branches longest first, each to the branch with
+  // the least work so far
+  int64_t cost[kMaxW + 1] = {};
+  for (const auto& pr : list) cost[bt->h_gd[pr.second.graph].W] += pr.first * (int64_t)(bt->h_gd[pr.second.graph].W + 1);
+  std::vector<int> order;
+  for (int w = 1; w <= kMaxW; ++w)
+    if (bt->w_begin[w + 1] > bt->w_begin[w]) order.push_back(w);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  int64_t load[kBranches] = {};
+  bt->n_widths = (int)order.size();
+  for (size_t i = 0; i < order.size(); ++i) {
+    const int br = (int)(std::min_element(load, load + kBranches) - load);
+    load[br] += cost[order[i]];
+    bt->branch_of[order[i]] = br;
+    bt->launch_order[i] = order[i];
+  }
   if ((int64_t)items.size() > bt->items_cap) {
     pfree(bt->items);
     pfree(bt->eitems);
@@ -422,12 +458,17 @@ int enqueue_run(pg_batch* bt, int est, hipStream_t s) {
   PG_LAUNCH_CHECK();
   BatchView ev = bv;
   ev.items = bt->eitems;
-  for (int w = 1; w <= kMaxW; ++w) {
+  // the estimate launches on kBranches streams, ordered after the build and
+  // before the sums by events (these become graph edges under capture)
+  PG_HIP(hipEventRecord(bt->fork, s));
+  for (int i = 0; i < kBranches - 1; ++i) PG_HIP(hipStreamWaitEvent(bt->side[i], bt->fork, 0));
+  for (int i = 0; i < bt->n_widths; ++i) {
+    const int w = bt->launch_order[i];
     const int64_t b0 = bt->w_begin[w], b1 = bt->w_begin[w + 1];
-    if (b1 <= b0) continue;
+    const hipStream_t ws = bt->branch_of[w] == 0 ? s : bt->side[bt->branch_of[w] - 1];
     const unsigned grid = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>(b1 - b0, (int64_t)std::max(1, bt->ctx->num_cus) * bt->params.blocks_per_cu));
-#define PG_BE(WW) hipLaunchKernelGGL((k_batch_estimate<WW>), dim3(grid), dim3(kBlock), 0, s, ev, b0, b1)
+#define PG_BE(WW) hipLaunchKernelGGL((k_batch_estimate<WW>), dim3(grid), dim3(kBlock), 0, ws, ev, b0, b1)
     switch (w) {
       case 1: PG_BE(1); break;
       case 2: PG_BE(2); break;
@@ -449,6 +490,10 @@ int enqueue_run(pg_batch* bt, int est, hipStream_t s) {
 #undef PG_BE
     PG_LAUNCH_CHECK();
   }
+  for (int i = 0; i < kBranches - 1; ++i) {
+    PG_HIP(hipEventRecord(bt->join[i], bt->side[i]));
+    PG_HIP(hipStreamWaitEvent(s, bt->join[i], 0));
+  }
   hipLaunchKernelGGL(k_batch_tc, dim3((unsigned)bt->count), dim3(kBlock), 0, s, (const GraphDesc*)bt->gd,
                      (const double*)bt->Splus, bt->tc);
   PG_LAUNCH_CHECK();
@@ -464,6 +509,12 @@ void drop_graph(pg_batch* bt) {
 
 void free_batch(pg_batch* bt) {
   drop_graph(bt);
+  for (int i = 0; i < kBranches - 1; ++i) {
+    if (bt->side[i]) (void)hipStreamSynchronize(bt->side[i]);
+    if (bt->side[i]) (void)hipStreamDestroy(bt->side[i]);
+    if (bt->join[i]) (void)hipEventDestroy(bt->join[i]);
+  }
+  if (bt->fork) (void)hipEventDestroy(bt->fork);
   pfree(bt->gd);
   pfree(bt->items);
   pfree(bt->eitems);
@@ -578,6 +629,13 @@ int pg_batch_create(pg_ctx* ctx, int32_t count, const int32_t* const* offsets, c
     if (e == hipSuccess) e = hipMemcpy(bt->hc, hc, sizeof(uint64_t) * b, hipMemcpyHostToDevice);
     if (e != hipSuccess) rc = fail(PG_E_DEVICE, std::string("batch upload: ") + hipGetErrorString(e));
   }
+  for (int i = 0; i < kBranches - 1 && rc == PG_OK; ++i) {
+    if (hipStreamCreateWithFlags(&bt->side[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&bt->join[i], hipEventDisableTiming) != hipSuccess)
+      rc = fail(PG_E_DEVICE, "batch streams");
+  }
+  if (rc == PG_OK && hipEventCreateWithFlags(&bt->fork, hipEventDisableTiming) != hipSuccess)
+    rc = fail(PG_E_DEVICE, "batch events");
   if (rc == PG_OK) rc = build_items(bt);
   if (rc != PG_OK) {
     free_batch(bt);

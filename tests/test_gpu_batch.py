@@ -23,11 +23,14 @@ def say(msg):
 def batch_env():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    graphs, bits = pggen.graph_batch(count=24, seed0=11, log2_lo=6.0, log2_hi=11.0)
+    graphs, _ = pggen.graph_batch(count=24, seed0=11, log2_lo=6.0, log2_hi=11.0)
+    # every row width the batch path instantiates, W = 1..16 words (64..1024 bits)
+    bits = [64 * (1 + i % 16) for i in range(len(graphs))]
     extra = [pggen.disjoint_union(pggen.star(700), pggen.complete(12)), pggen.from_pairs(5, [], []),
              pggen.from_pairs(1, [], []), pggen.wheel(9)]
     graphs += extra
     bits += [128, 64, 64, 1024]
+    assert sorted({B // 64 for B in bits}) == list(range(1, 17))
     say(f"batch of {len(graphs)} graphs, n total {sum(g.n for g in graphs)}")
     ctx = pg.Context(0)
     bt = pg.Batch(ctx, graphs, bits, b=2, seed=5)
@@ -104,4 +107,34 @@ def test_batch_rejects_bad_graphs():
     with pytest.raises(pg.PGError) as ei:
         pg.Batch(ctx, [pggen.cycle(4)], [100])
     assert ei.value.code == pg.PG_E_INVALID
+    ctx.close()
+
+
+@pytest.mark.timeout(600)
+def test_full_batch_workload_matches_oracle():
+    """The batch the benchmark times (512 graphs, n log-uniform in [2^8, 2^16],
+    half G(n, p), half R-MAT; 128..1024-bit filters, so every row width 2..16):
+    every graph's triangle count and every vertex's clustering coefficient
+    against the oracle, after an eager run and after a HIP-graph replay."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("generating the 512-graph batch")
+    graphs, bits = pggen.graph_batch(count=512, seed0=1)
+    assert sorted({B // 64 for B in bits}) == list(range(2, 17))
+    ctx = pg.Context(0)
+    bt = pg.Batch(ctx, graphs, bits, b=1, seed=1)
+    say("eager run")
+    bt.run("and")
+    tc, cc = bt.results()
+    say("oracle over the 512 graphs")
+    want_tc, want_cc = _oracle(graphs, bits, 1, 1, "and")
+    assert np.allclose(tc, want_tc, rtol=1e-9, atol=1e-9)
+    assert np.allclose(cc, want_cc, rtol=1e-6 + 2.0**-23, atol=1e-30)
+    say("captured replay")
+    s = torch.cuda.Stream()
+    bt.capture("and", stream=s)
+    bt.replay(stream=s)
+    tc2, cc2 = bt.results(stream=s)
+    assert tc2.tobytes() == tc.tobytes() and cc2.tobytes() == cc.tobytes()
+    bt.close()
     ctx.close()
