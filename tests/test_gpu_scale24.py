@@ -3,13 +3,15 @@
 clustering coefficient and the exact merge baseline, in the launch
 configuration the library uses for every graph.
 
-At this size the oracle checks sampled outputs one by one: sketch rows of
-sampled vertices (bit-exact), integer counts and estimates of sampled edges,
-exact intersections of sampled edges, and the clustering coefficient of
-sampled vertices. Whole-graph results are checked through identities that hold
-at any size: the triangle-count estimate is one third of the sum of the
-per-edge estimates, and the exact triangle count is one third of the sum of
-the exact per-edge intersections."""
+The oracle builds the same sketches of every vertex on the host and checks:
+sketch rows of sampled vertices (bit-exact), integer counts and estimates of
+sampled edges, the whole-graph triangle-count estimate (the oracle's own sum
+over all m edges, in chunks), and the clustering coefficient of sampled
+vertices, the largest hubs among them. The exact baseline is checked on
+sampled edges and vertices (hubs up to 20,000 neighbours: the oracle's merge
+per arc is quadratic in the hub degree) and through the identity that the
+exact triangle count is one third of the sum of the exact per-edge
+intersections."""
 import sys
 
 import numpy as np
@@ -58,26 +60,44 @@ def big():
     ctx.close()
 
 
-def _pair_rows(g, su, sv, kind, size, b):
-    """Oracle rows of the endpoints of sampled pairs and the pairs re-indexed into them."""
-    ends = np.unique(np.concatenate([su, sv]))
-    ref = oracle.sketch_rows(g, ends, kind, size, b, SEED)
-    return ref, np.searchsorted(ends, su), np.searchsorted(ends, sv)
-
-
-def _cc_samples(g, rng, count=20, max_deg=500):
+def _cc_samples(g, rng, count=20, max_deg=500, hubs=0, hub_max=None):
+    """Random vertices of degree 2..max_deg, plus the `hubs` largest vertices
+    of degree at most hub_max (any degree if None)."""
     d = g.degrees()
     cand = np.flatnonzero((d >= 2) & (d <= max_deg))
-    return np.sort(rng.choice(cand, size=min(count, cand.shape[0]), replace=False))
+    out = rng.choice(cand, size=min(count, cand.shape[0]), replace=False)
+    if hubs:
+        order = np.argsort(-d, kind="stable")
+        if hub_max is not None:
+            order = order[d[order] <= hub_max]
+        out = np.concatenate([out, order[:hubs]])
+    return np.unique(out)
 
 
-def _oracle_cc(g, v, kind, size, b, est):
-    """Local clustering coefficient of v from oracle rows of v and N_v."""
+def _oracle_cc(g, ref, v, est):
+    """Local clustering coefficient of v from the oracle's rows of v and N_v."""
     nb = g.adj[g.offsets[v]:g.offsets[v + 1]].astype(np.int64)
-    ref = oracle.sketch_rows(g, np.concatenate([[v], nb]), kind, size, b, SEED)
     d = nb.shape[0]
-    vals = ref.estimate(np.zeros(d, np.int64), np.arange(1, d + 1), est)
+    vals = ref.estimate(np.full(d, v, np.int64), nb, est)
     return float(np.sum(vals)) / (d * (d - 1))
+
+
+def _oracle_tc_chunked(g, ref, est, target=1 << 25):
+    """The oracle's TC^ = (1/3) sum over all m upper edges, in chunks of about
+    `target` edges (progress printed per chunk)."""
+    off = g.offsets.astype(np.int64)
+    cuts = np.unique(np.concatenate([np.searchsorted(off, np.arange(0, g.nnz, 2 * target), side="right") - 1,
+                                     [g.n]]))
+    total, m = 0.0, 0
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        src = np.repeat(np.arange(a, b, dtype=np.int32), np.diff(off[a:b + 1]))
+        dst = g.adj[off[a]:off[b]]
+        keep = dst > src
+        u, v = src[keep], dst[keep]
+        total += float(np.sum(ref.estimate(u, v, est)))
+        m += u.shape[0]
+        say(f"oracle TC: {m} edges")
+    return total / 3.0, m
 
 
 def _close(got, want, rtol):
@@ -89,70 +109,78 @@ def _close(got, want, rtol):
 @pytest.mark.timeout(900)
 def test_scale24_bloom_1024(big):
     g, ctx, dg, idx, idx_t, su, sv, verts = big
-    say("bf 1024 build")
+    say("bf 1024 build (GPU, and the oracle on every vertex)")
     sk = dg.build_sketches("bf", 1024, 1, seed=SEED)
     rows, pc = sk.export()
     vt = torch.from_numpy(verts).to(rows.device)
     got_rows = rows[vt].cpu().numpy()
     got_pc = pc[vt].cpu().numpy().astype(np.uint32)
     del rows, pc
-    ref = oracle.sketch_rows(g, verts, oracle.KIND_BF, 1024, 1, SEED)
-    assert np.array_equal(got_rows, ref.words.view(np.uint8).reshape(len(verts), 128))
-    assert np.array_equal(got_pc, ref.pc)
+    ref = oracle.build_sketches(g, oracle.KIND_BF, 1024, 1, seed=SEED)
+    assert np.array_equal(got_rows, ref.words[verts].view(np.uint8).reshape(len(verts), 128))
+    assert np.array_equal(got_pc, ref.pc[verts])
 
     say("bf 1024 all-edge estimates, sampled against the oracle")
     est, raw = sk.intersect("and")
-    pref, iu, iv = _pair_rows(g, su, sv, oracle.KIND_BF, 1024, 1)
-    want_c = pref.counts(iu, iv)[0]
+    want_c = ref.counts(su, sv)[0]
     assert np.array_equal(raw[idx_t].cpu().numpy().astype(np.uint32), want_c)
-    _close(est[idx_t].cpu().numpy(), pref.estimate(iu, iv, "and"), RTOL)
+    _close(est[idx_t].cpu().numpy(), ref.estimate(su, sv, "and"), RTOL)
     total = float(est.sum().item())
     del est, raw
 
-    say("bf 1024 triangle count: one third of the edge sum")
-    _close([sk.tc("and")], [total / 3.0], 1e-9)
+    say("bf 1024 triangle count against the oracle's sum over all edges")
+    tc = sk.tc("and")
+    tc_o, m_o = _oracle_tc_chunked(g, ref, "and")
+    assert m_o == dg.m
+    _close([tc], [tc_o], 1e-9)
+    _close([tc], [total / 3.0], 1e-9)
 
-    say("bf 1024 clustering coefficient, sampled vertices")
+    say("bf 1024 clustering coefficient, sampled vertices and the largest hubs")
     cc = sk.cc("and")
     rng = np.random.default_rng(240)
-    for v in _cc_samples(g, rng):
-        want = _oracle_cc(g, v, oracle.KIND_BF, 1024, 1, "and")
+    for v in _cc_samples(g, rng, hubs=5):
+        want = _oracle_cc(g, ref, int(v), "and")
         got = float(cc[int(v)].item())
         assert abs(got - want) <= (RTOL + 2.0**-23) * abs(want) + 1e-30, (v, got, want)
+    del ref
     sk.close()
 
 
 @pytest.mark.timeout(900)
 def test_scale24_onehash_64(big):
     g, ctx, dg, idx, idx_t, su, sv, verts = big
-    say("1-hash k=64 build")
+    say("1-hash k=64 build (GPU, and the oracle on every vertex)")
     sk = dg.build_sketches("1h", 64, seed=SEED)
     rows, _ = sk.export()
     vt = torch.from_numpy(verts).to(rows.device)
     got_rows = rows[vt].cpu().numpy()
     del rows
-    ref = oracle.sketch_rows(g, verts, oracle.KIND_1H, 64, 1, SEED)
-    assert np.array_equal(got_rows, ref.sig.view(np.uint8).reshape(len(verts), 256))
+    ref = oracle.build_sketches(g, oracle.KIND_1H, 64, 1, seed=SEED)
+    assert np.array_equal(got_rows, ref.sig[verts].view(np.uint8).reshape(len(verts), 256))
 
     say("1-hash all-edge estimates, sampled against the oracle")
     est, raw = sk.intersect("1h")
-    pref, iu, iv = _pair_rows(g, su, sv, oracle.KIND_1H, 64, 1)
-    su_ref, _, _ = pref.counts(iu, iv)
+    su_ref, _, _ = ref.counts(su, sv)
     assert np.array_equal(raw[idx_t].cpu().numpy().astype(np.uint32), su_ref)
-    _close(est[idx_t].cpu().numpy(), pref.estimate(iu, iv, "1h"), RTOL)
+    _close(est[idx_t].cpu().numpy(), ref.estimate(su, sv, "1h"), RTOL)
     total = float(est.sum().item())
     del est, raw
 
-    say("1-hash triangle count: one third of the edge sum")
-    _close([sk.tc("1h")], [total / 3.0], 1e-9)
+    say("1-hash triangle count against the oracle's sum over all edges")
+    tc = sk.tc("1h")
+    tc_o, m_o = _oracle_tc_chunked(g, ref, "1h")
+    assert m_o == dg.m
+    _close([tc], [tc_o], 1e-9)
+    _close([tc], [total / 3.0], 1e-9)
 
-    say("1-hash clustering coefficient, sampled vertices")
+    say("1-hash clustering coefficient, sampled vertices and the largest hubs")
     cc = sk.cc("1h")
     rng = np.random.default_rng(241)
-    for v in _cc_samples(g, rng):
-        want = _oracle_cc(g, v, oracle.KIND_1H, 64, 1, "1h")
+    for v in _cc_samples(g, rng, hubs=5):
+        want = _oracle_cc(g, ref, int(v), "1h")
         got = float(cc[int(v)].item())
         assert abs(got - want) <= (RTOL + 2.0**-23) * abs(want) + 1e-30, (v, got, want)
+    del ref
     sk.close()
 
 
@@ -167,10 +195,10 @@ def test_scale24_exact_baseline(big):
     say("exact triangle count: one third of the edge sum")
     t = dg.exact_tc()
     assert 3 * t == total
-    say("exact clustering coefficient, sampled vertices")
+    say("exact clustering coefficient, sampled vertices and hubs of up to 20,000 neighbours")
     cc = dg.exact_cc()
     rng = np.random.default_rng(242)
-    for v in _cc_samples(g, rng):
+    for v in _cc_samples(g, rng, hubs=3, hub_max=20000):
         nb = g.adj[g.offsets[v]:g.offsets[v + 1]].astype(np.int64)
         d = nb.shape[0]
         want = float(np.sum(oracle.exact_pairs(g, np.full(d, v, np.int64), nb))) / (d * (d - 1))
