@@ -180,10 +180,27 @@ def measure_serving(args, pg, pggen, np, log):
             "requests": st["completed"]}
 
 
+def kernel_ms(pg, ctx, site, fn, reps, sync):
+    """Average device time of launch site `site` over reps calls of fn (HIP events)."""
+    sync()
+    pg.pg_profile_reset(ctx.h)
+    pg.pg_profile_select(ctx.h, site)
+    pg.pg_profile_enable(ctx.h, True)
+    for _ in range(reps):
+        fn()
+    sync()
+    pg.pg_profile_enable(ctx.h, False)
+    launches, total = pg.pg_profile_read(ctx.h).get(site, (0, 0.0))
+    pg.pg_profile_select(ctx.h, None)
+    pg.pg_profile_reset(ctx.h)
+    return total / launches if launches else float("nan")
+
+
 def measure_scale24(args, pg, pggen, torch, ctx, sync, log):
     """R-MAT scale 24, edge factor 32 (about 1e9 arcs): 1024-bit Bloom filters and
-    1-hash k = 64, triangle count and clustering coefficient, exact GPU baseline.
-    Opt-in (--scale24): generating the graph takes about a minute."""
+    1-hash k = 64, triangle count and clustering coefficient, exact GPU merge
+    baseline. The exact clustering coefficient (tens of seconds) and the bitmap
+    triangle count (minutes) run only with --scale24-slow."""
     t = time.perf_counter()
     g = pggen.rmat(24, 32, seed=args.seed)
     log(f"scale24: generated n={g.n} nnz={g.nnz} ({time.perf_counter() - t:.1f}s)")
@@ -195,30 +212,109 @@ def measure_scale24(args, pg, pggen, torch, ctx, sync, log):
     exact_ms = timed(lambda: dg.exact_tc(), 3, sync)
     out["exact"] = {"tc": exact_tc, "tc_ms": round(exact_ms, 3), "intersections_per_s": m / (exact_ms * 1e-3)}
     log(f"scale24 exact TC {exact_tc} in {exact_ms:.1f} ms")
-    # the slower exact variants run once each (tens of seconds at this size)
-    t0 = time.perf_counter()
-    dg.exact_cc()
-    sync()
-    out["exact"]["cc_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
-    log(f"scale24 exact CC in {out['exact']['cc_ms']:.1f} ms")
-    t0 = time.perf_counter()
-    assert dg.exact_tc(algo=pg.PG_EXACT_BITMAP) == exact_tc
-    out["exact"]["tc_bitmap_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
-    log(f"scale24 exact TC by bitmap in {out['exact']['tc_bitmap_ms']:.1f} ms")
-    for name, kind, size, est in (("bf1024", "bf", 1024, "and"), ("onehash64", "1h", 64, "1h")):
+    if args.scale24_slow:
+        t0 = time.perf_counter()
+        dg.exact_cc()
+        sync()
+        out["exact"]["cc_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        log(f"scale24 exact CC in {out['exact']['cc_ms']:.1f} ms")
+        t0 = time.perf_counter()
+        assert dg.exact_tc(algo=pg.PG_EXACT_BITMAP) == exact_tc
+        out["exact"]["tc_bitmap_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        log(f"scale24 exact TC by bitmap in {out['exact']['tc_bitmap_ms']:.1f} ms")
+    for name, kind, size, est, site, row_bytes in (("bf1024", "bf", 1024, "and", "bf_tc", 128),
+                                                   ("onehash64", "1h", 64, "1h", "oh_tc", 256)):
         sk = dg.build_sketches(kind, size, 1, seed=args.seed)
         tc = sk.tc(est)  # first call builds the triangle-count plan
         b_ms = timed(lambda: sk.rebuild(), 5, sync)
         t_ms = timed(lambda: sk.tc(est), 5, sync)
         c_ms = timed(lambda: sk.cc(est), 3, sync)
+        k_ms = kernel_ms(pg, ctx, site, lambda: sk.tc(est), 3, sync)
+        # per edge two rows and two IDs (plus two degrees for the MinHash estimate)
+        per_edge = 2 * row_bytes + 8 + (8 if kind == "1h" else 0)
+        gbs = m * per_edge / (k_ms * 1e-3) / 1e9
         out[name] = {"build_ms": round(b_ms, 3), "tc_ms": round(t_ms, 3), "cc_ms": round(c_ms, 3),
+                     "tc_kernel_ms": round(k_ms, 3),
+                     "tc_kernel_algorithmic": {"bytes_per_edge": per_edge, "gbs": round(gbs, 1),
+                                               "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4)},
                      "step_intersections_per_s": m / ((b_ms + t_ms) * 1e-3),
                      "estimate_intersections_per_s": m / (t_ms * 1e-3), "tc": tc,
                      "rel_err": abs(tc - exact_tc) / exact_tc, "speedup_vs_exact": exact_ms / (b_ms + t_ms)}
-        log(f"scale24 {name}: build {b_ms:.2f} ms, TC {t_ms:.2f} ms, CC {c_ms:.2f} ms, "
+        log(f"scale24 {name}: build {b_ms:.2f} ms, TC {t_ms:.2f} ms (kernel {k_ms:.2f}), CC {c_ms:.2f} ms, "
             f"rel err {abs(tc - exact_tc) / exact_tc:.3e}")
         sk.close()
     dg.close()
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def measure_cpu(args, g, B, m, tc_bf, exact_tc, exact_gpu_ms, log):
+    """The oracle on this host's cores: BF build + AND estimate of every edge +
+    TC sum (all cores, median of 3; and on one core), and the exact merge
+    triangle count of the node iterator (all cores, once)."""
+    import oracle
+    all_threads = oracle.threads()
+    times, tc_cpu = [], None
+    for _ in range(3):
+        t = time.perf_counter()
+        ref = oracle.build_sketches(g, oracle.KIND_BF, B, args.b, seed=args.seed)
+        tc_cpu = oracle.tc(ref, "and")
+        times.append(time.perf_counter() - t)
+        del ref
+    cpu_s = statistics.median(times)
+    oracle.set_threads(1)
+    t = time.perf_counter()
+    ref = oracle.build_sketches(g, oracle.KIND_BF, B, args.b, seed=args.seed)
+    tc_one = oracle.tc(ref, "and")
+    one_s = time.perf_counter() - t
+    del ref
+    oracle.set_threads(all_threads)
+    t = time.perf_counter()
+    ex = oracle.exact_tc_listing(g)
+    ex_s = time.perf_counter() - t
+    assert ex == exact_tc, (ex, exact_tc)
+    log(f"cpu oracle ({cpu_model()}): BF TC {cpu_s:.3f} s on {all_threads} threads, {one_s:.3f} s on 1; "
+        f"exact merge TC {ex_s:.3f} s")
+    return {"value": m / cpu_s, "unit": UNIT, "cores": all_threads, "kind": "oracle",
+            "sample": "full workload: oracle BF build (b=1, same B and seed) + AND counts and FP64 estimates "
+                      "for all m edges + TC sum; median of 3",
+            "seconds": round(cpu_s, 4), "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "tc_matches_gpu_rel": abs(tc_cpu - tc_bf) / abs(tc_cpu),
+            "single_core": {"seconds": round(one_s, 4), "value": m / one_s, "unit": UNIT, "cores": 1,
+                            "tc_equal": tc_one == tc_cpu},
+            "exact_merge_tc": {"seconds": round(ex_s, 4), "edge_intersections_per_s": m / ex_s,
+                               "cores": all_threads, "tc": ex,
+                               "algorithm": "degree-ordered node iterator, sorted merge per oriented edge",
+                               "gpu_exact_speedup": ex_s / (exact_gpu_ms * 1e-3)}}
+
+
+def measure_c0(args, pg, pggen, torch, ctx, sync, log):
+    """The small parity configuration: G(n, p), n = 4096, mean degree 16, seed 1;
+    256-bit Bloom filters, b = 1; AND and limit estimates of the triangle count
+    against the exact count (launch-latency bound, not a roofline case)."""
+    g = pggen.er(4096, 16, seed=args.seed)
+    dg = pg.Graph(ctx, g.offsets, g.adj)
+    sk = dg.build_sketches("bf", 256, 1, seed=args.seed)
+    exact = dg.exact_tc()
+    out = {"workload": f"G(n,p) n=4096 mean degree 16 seed {args.seed}; BF 256 bits b=1", "n": g.n, "m": dg.m,
+           "tc_exact": exact, "exact_ms": round(timed(lambda: dg.exact_tc(), 10, sync), 4)}
+    for est in ("and", "l"):
+        tc = sk.tc(est)
+        ms = timed(lambda: (sk.rebuild(), sk.tc(est)), 10, sync)
+        out[f"tc_{est}"] = {"tc": tc, "rel_err": abs(tc - exact) / exact if exact else None, "ms_per_call": round(ms, 4)}
+    sk.close()
+    dg.close()
+    log(f"C0: exact {exact}, AND {out['tc_and']['tc']:.1f}, limit {out['tc_l']['tc']:.1f}")
     return out
 
 
@@ -259,8 +355,11 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=10000)
     ap.add_argument("--skip-batch", action="store_true", help="leave out the batched-graphs measurement")
     ap.add_argument("--batch-graphs", type=int, default=512)
-    ap.add_argument("--scale24", action="store_true",
-                    help="also time the R-MAT s24 ef32 configuration (BF-1024, 1-hash-64, exact)")
+    ap.add_argument("--skip-scale24", action="store_true",
+                    help="leave out the R-MAT s24 ef32 configuration (BF-1024, 1-hash-64, exact merge)")
+    ap.add_argument("--scale24-slow", action="store_true",
+                    help="in the s24 configuration also time the exact CC and the bitmap exact TC (minutes)")
+    ap.add_argument("--skip-c0", action="store_true", help="leave out the small G(n,p) configuration")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -355,21 +454,35 @@ def main():
         launches, total = (prof if source is None else source).get(name, (0, 0.0))
         return total / launches if launches else float("nan")
 
-    # roofline of the dominant kernel: the vertex-centric edge-estimate sum.
-    # Algorithmic bytes: per upper edge the neighbour ID and its filter row;
-    # per vertex with upper edges its own row, ustart and two offsets.
+    # roofline of the dominant kernel, the vertex-centric edge-estimate sum.
+    # Algorithmic bytes by the per-intersection rule: two sketch rows and the
+    # two endpoint IDs per edge, 2S + 8. The kernel keeps the owner's row in
+    # registers across its upper edges, so it requests fewer bytes than that:
+    # per upper edge the neighbour ID and its row, per vertex with upper edges
+    # its own row, ustart and two offsets (the reuse-aware figure); and of those
+    # requests the caches serve part (the counter-measured HBM bytes).
     deg = np.diff(g.offsets).astype(np.int64)
     src = np.repeat(np.arange(n, dtype=np.int64), deg)
     n_active = int(np.count_nonzero(np.bincount(src[g.adj > src], minlength=n)))
-    alg_bytes = m * (S + 4) + n_active * (S + 12)
+    del src
+    alg_bytes = m * (2 * S + 8)
+    reuse_bytes = m * (S + 4) + n_active * (S + 12)
     k_ms = avg("bf_tc")
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     traffic = _read_traffic(B)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_bf_tc_slab (AND count + estimate over every upper edge, XCD-sliced vertex plan)",
-                "kernel_ms": round(k_ms, 5), "algorithmic_bytes": alg_bytes,
-                "bytes_rule": "m*(S+4) + n_active*(S+12), S = B/8"}
+                "kernel_ms": round(k_ms, 5), "algorithmic_bytes": alg_bytes, "bytes_rule": "m*(2S+8), S = B/8",
+                "frac_note": "above 1: the rows are re-read from the caches (the 44.7 MB filter array fits the "
+                             "256 MB Infinity Cache), so the per-intersection rule is an effective bandwidth",
+                "reuse_aware": {"bytes": reuse_bytes, "bytes_rule": "m*(S+4) + n_active*(S+12)",
+                                "gbs": round(reuse_bytes / (k_ms * 1e-3) / 1e9, 2),
+                                "frac": round(reuse_bytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                "hbm_measured": None if traffic is None else {
+                    "bytes": traffic, "gbs": round(traffic / (k_ms * 1e-3) / 1e9, 2),
+                    "frac": round(traffic / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "source": os.path.relpath(TRAFFIC_FILE, ROOT)}}
     build_ms = avg("bf_build", prof_phases)
     # build: offsets (two per vertex), every arc's ID, the row and popcount, the plan lists
     build_bytes = 8 * n + 4 * nnz + n * S + 4 * n + 4 * n
@@ -513,21 +626,7 @@ def main():
 
     cpu = None
     if not args.skip_cpu:
-        import oracle
-        sample = "full workload: oracle BF build (b=1, same B and seed) + AND counts and FP64 estimates " \
-                 "for all m edges + TC sum; median of 3"
-        times = []
-        tc_cpu = None
-        for _ in range(3):
-            t = time.perf_counter()
-            ref = oracle.build_sketches(g, oracle.KIND_BF, B, args.b, seed=args.seed)
-            tc_cpu = oracle.tc(ref, "and")
-            times.append(time.perf_counter() - t)
-        cpu_s = statistics.median(times)
-        cpu = {"value": m / cpu_s, "unit": UNIT, "cores": oracle.threads(), "kind": "oracle", "sample": sample,
-               "seconds": round(cpu_s, 4), "tc_matches_gpu_rel": abs(tc_cpu - tc_bf) / abs(tc_cpu)}
-        log(f"cpu oracle: {cpu_s:.3f} s -> {m / cpu_s:.4e} {UNIT} on {oracle.threads()} threads")
-
+        cpu = measure_cpu(args, g, B, m, tc_bf, exact_tc, exact_ms, log)
     batch = None
     if not args.skip_batch:
         batch = measure_batch(args, pg, pggen, np, torch, log)
@@ -536,7 +635,9 @@ def main():
     if not args.skip_serving:
         serving = measure_serving(args, pg, pggen, np, log)
 
-    scale24 = measure_scale24(args, pg, pggen, torch, ctx, sync, log) if args.scale24 else None
+    c0 = None if args.skip_c0 else measure_c0(args, pg, pggen, torch, ctx, sync, log)
+
+    scale24 = None if args.skip_scale24 else measure_scale24(args, pg, pggen, torch, ctx, sync, log)
 
     out = {
         "metric": METRIC,
@@ -572,6 +673,7 @@ def main():
         "rows": rows,
         "serving": serving,
         "batch": batch,
+        "c0": c0,
         "scale24": scale24,
     }
     print(json.dumps(out), flush=True)

@@ -54,6 +54,7 @@ def _load():
     u64, i32, i64, u32 = ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     sig = {
         "or_threads": (ctypes.c_int, []),
+        "or_set_threads": (None, [ctypes.c_int]),
         "or_splitmix64": (u64, [u64, u64]),
         "or_hash_consts": (None, [ctypes.c_int, u64, ctypes.c_int, u64p, u64p]),
         "or_bf_index": (u32, [u64, u64, u32, u32]),
@@ -92,6 +93,11 @@ def _i32(a):
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().or_threads())
+
+
+def set_threads(count: int) -> None:
+    """Threads of the oracle's later parallel loops (for timing on one core)."""
+    _load().or_set_threads(int(count))
 
 
 # ---------------------------------------------------------------- hashing

@@ -42,6 +42,11 @@
 /* Threads an OpenMP loop of this library uses (reported with CPU timings). */
 int or_threads(void) { return omp_get_max_threads(); }
 
+/* Set the threads of later parallel loops (timing on one core, or all). */
+void or_set_threads(int count) {
+  if (count > 0) omp_set_num_threads(count);
+}
+
 /* ---------------------------------------------------------------- hashing */
 
 static uint64_t or_mix(uint64_t z) {
