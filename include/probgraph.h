@@ -304,15 +304,20 @@ int pg_sketches_rebuild(pg_ctx* ctx, pg_sketches* sk, uint64_t seed, void* strea
 /* ---- serving: resident sketches, continuous batching ---------------------- */
 /* A server keeps a graph and its sketch sets resident and answers vertex-pair
  * queries (common-neighbour estimates or Jaccard similarities, Listing
- * "lst:sim") as they arrive. Admitted requests are packed into batches; up to
- * max_batches_in_flight batches run concurrently on separate streams, and
- * requests submitted while batches run join the next batch as soon as a batch
- * slot frees. A request is admitted only if its bytes (16 per pair: pair IDs
- * and result) fit in memory_budget_bytes together with all requests already
- * admitted and not yet collected; otherwise submit returns PG_E_BUSY.
- * Per-pair results do not depend on batching: a request's result is
- * bit-identical alone and in any mix. The graph and sketch sets must outlive
- * the server. One thread may submit while another waits. */
+ * "lst:sim") as they arrive. The memory budget is a staging arena of pinned
+ * host memory that the GPU reads and writes directly, 16 bytes per pair (the
+ * two IDs and the answer). A request is admitted if a contiguous range of the
+ * arena for its pairs is free; submit writes its pairs there (on the calling
+ * thread) and otherwise returns PG_E_BUSY. Up to max_batches_in_flight batches
+ * run concurrently on separate streams; requests submitted while batches run
+ * join the next batch as soon as a batch slot frees. A request's range (its
+ * bytes of the budget) is released when the request is collected: by
+ * pg_server_wait, or by the pg_server_poll that first finds it finished; both
+ * copy its answers into its output buffer on the calling thread. Per-pair
+ * results do not depend on batching: a request's result is bit-identical alone
+ * and in any mix. The graph and sketch sets must outlive the server. Several
+ * threads may submit, poll and wait at the same time (each ticket collected by
+ * one of them). */
 #define PG_OP_CN 1      /* estimate of |N_u cap N_v| (common neighbours), FP64 */
 #define PG_OP_JACCARD 2 /* estimated Jaccard similarity, FP32 (rounded once from FP64) */
 
@@ -351,19 +356,25 @@ int pg_server_create(pg_ctx* ctx, const pg_graph* g, pg_sketches* const* sketche
                      const pg_server_params* params, pg_server** out);
 /* Validates and admits a request (*ticket receives its id, host pointer).
  * PG_E_INVALID: malformed (op, sketch index, estimator/kind mismatch, npairs
- * out of range, a vertex ID outside [0, n)); PG_E_BUSY: not admitted now. */
+ * out of range or above the budget's 16-byte pair slots, a vertex ID outside
+ * [0, n)); PG_E_BUSY: not admitted now (no free range of the budget). */
 int pg_server_submit(pg_server* srv, const pg_request* req, uint64_t* ticket);
-/* *done = 1 once the request's results are in its out buffer. */
+/* *done = 1 once the request's results are in its out buffer: the first poll
+ * that finds the request finished copies them there and releases its bytes.
+ * The ticket stays valid until pg_server_wait. */
 int pg_server_poll(pg_server* srv, uint64_t ticket, int32_t* done);
-/* Blocks until the request is answered, then releases the ticket; latency_ms
- * (host, nullable) receives the time from submit to result delivery. */
+/* Blocks until the request is answered and its results are in its out buffer,
+ * then releases the ticket; latency_ms (host, nullable) receives the time from
+ * submit to that point. */
 int pg_server_wait(pg_server* srv, uint64_t ticket, double* latency_ms);
 int pg_server_get_stats(pg_server* srv, pg_server_stats* out);
-/* Load replay: submits reqs[0..nreq) in order -- at t0 + arrival_s[i] (open
- * loop) or, with arrival_s NULL, keeping max_outstanding requests unanswered
- * (closed loop) -- retrying while the server answers PG_E_BUSY, and writes each
- * request's latency from its arrival to its result (host array latency_ms).
- * *elapsed_s (nullable) receives the wall time of the whole replay. */
+/* Load replay: submits reqs[0..nreq) -- at t0 + arrival_s[i] (open loop) or,
+ * with arrival_s NULL, in order while at most max_outstanding requests are
+ * unanswered (closed loop) -- retrying while the server answers PG_E_BUSY, and
+ * writes each request's latency from its arrival to its collected result (host
+ * array latency_ms). Up to four threads submit and four collect (request i by
+ * thread i mod 4 of each). *elapsed_s (nullable) receives the wall time of the
+ * whole replay. */
 int pg_server_replay(pg_server* srv, int64_t nreq, const pg_request* reqs, const double* arrival_s,
                      int32_t max_outstanding, double* latency_ms, double* elapsed_s);
 /* Waits for every admitted request, stops the engine and frees the server. */

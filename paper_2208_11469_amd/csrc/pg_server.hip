@@ -1,15 +1,20 @@
 // Serving engine: resident sketches, vertex-pair queries, continuous batching.
 //
-// Submit validates a request on the host, copies its pairs and admits it if
-// the byte budget allows. An engine thread keeps up to K batches in flight,
-// one stream each (default priority). Whenever a batch slot is free and
-// requests wait, it packs as many of them as fit into one launch: pairs go to
-// the slot's pinned, coherent host buffers, a segment table tells each pair its
-// request's sketch set, estimator and operation, and one fused kernel reads the
-// pairs from host memory and writes every answer back there (no copy calls:
-// a batch is one launch and one event). When a batch's event completes, its
-// results are copied into the requests' host buffers and its slot and bytes are
-// released, so requests that arrived meanwhile start in the next launch.
+// The memory budget is a staging arena of pinned, coherent host memory, 16
+// bytes per pair slot (two IDs and the answer). Submit checks a request on the
+// calling thread, reserves a contiguous range of pair slots (first fit; no
+// range free = not admitted now) and writes the pairs there itself. An engine
+// thread keeps up to K batches in flight, one stream each (default priority):
+// whenever a batch slot is free and requests wait, it forms one launch from as
+// many of them as fit (a segment table tells each pair its request's sketch
+// set, estimator, operation and arena range) and one fused kernel reads the
+// pairs from the arena over the bus and writes every answer back into the
+// request's range. The engine neither packs nor copies pairs: per request it
+// only adds a segment, and it marks a batch's requests finished when the
+// batch's event completes, so requests that arrived meanwhile start in the next
+// launch. The thread that collects a request (wait, or the poll that first
+// sees it finished) copies its answers into the request's output buffer and
+// returns the range to the arena.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +23,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -34,11 +40,11 @@ namespace {
 
 constexpr int kMaxSegments = 1024;  // requests per batch
 constexpr int kEstSlots = 8;        // view slots per sketch set, indexed by estimator id
-
 constexpr int kArgSegments = 16;    // segment tables this small travel as kernel arguments
 
 struct SegDesc {
   int64_t begin;  // first pair of the segment in the batch
+  int64_t arena;  // first pair slot of its request in the arena
   int32_t view;   // index into the server's views (sketch * kEstSlots + estimator)
   int32_t op;     // PG_OP_CN or PG_OP_JACCARD
 };
@@ -48,12 +54,15 @@ struct SegArgs {
   SegDesc seg[kArgSegments];  // used when nseg <= kArgSegments
 };
 
-// One lane per pair; the segment is found by binary search over the batch's
-// segment starts held in LDS. `pu`, `pv` and `out` are pinned host memory.
+// One lane per pair of the batch; its segment is found by binary search over
+// the segment starts held in LDS. `au`, `av` and `out` are the arena (pinned
+// host memory). A common-neighbour answer is the FP64 estimate in the pair's
+// slot; a Jaccard answer is FP32, stored densely from the start of the
+// request's range (its output buffer is float[npairs]).
 __global__ __launch_bounds__(256) void k_serve_batch(const SkView* __restrict__ views, SegArgs a,
-                                                     const SegDesc* __restrict__ big, const int32_t* __restrict__ pu,
-                                                     const int32_t* __restrict__ pv, int64_t total,
-                                                     double* __restrict__ out) {
+                                                     const SegDesc* __restrict__ big, const int32_t* __restrict__ au,
+                                                     const int32_t* __restrict__ av, double* __restrict__ out,
+                                                     int64_t total) {
   __shared__ SegDesc table[kMaxSegments];
   const int32_t nseg = a.nseg;
   const SegDesc* segs = nseg <= kArgSegments ? a.seg : big;
@@ -70,32 +79,35 @@ __global__ __launch_bounds__(256) void k_serve_batch(const SkView* __restrict__ 
     }
     const SegDesc sd = table[lo];
     const SkView& s = views[sd.view];
-    const int32_t u = pu[e], v = pv[e];
+    const int64_t j = e - sd.begin;
+    const int64_t slot = sd.arena + j;
+    const int32_t u = au[slot], v = av[slot];
     uint32_t raw;
     const double est = eval_pair_any(s, u, v, raw);
-    out[e] = sd.op == PG_OP_CN ? est : jaccard_of(est, s.deg[u], s.deg[v]);
+    if (sd.op == PG_OP_CN)
+      out[slot] = est;
+    else
+      reinterpret_cast<float*>(out + sd.arena)[j] = (float)jaccard_of(est, s.deg[u], s.deg[v]);
   }
 }
 
 using Clock = std::chrono::steady_clock;
 
+enum State { kQueued = 0, kFinished = 1, kCollecting = 2, kCollected = 3 };
+
 struct Request {
   uint64_t ticket = 0;
   int32_t op = 0, view = 0;
   int64_t npairs = 0;
-  std::vector<int32_t> u, v;
+  int64_t arena = 0;  // first pair slot
   void* out = nullptr;
-  uint64_t bytes = 0;
-  Clock::time_point t_submit, t_done;
-  bool done = false;
+  Clock::time_point t_submit, t_collected;
+  int state = kQueued;
 };
 
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t event = nullptr;
-  int32_t* h_u = nullptr;  // pinned, coherent: the batch kernel reads the pairs here
-  int32_t* h_v = nullptr;
-  double* h_out = nullptr;  // and writes the answers here
   SegDesc* h_seg = nullptr;  // segment tables larger than kArgSegments, staged for d_seg
   SegDesc* d_seg = nullptr;
   std::vector<Request*> reqs;
@@ -110,12 +122,17 @@ struct pg_server {
   const pg_graph* g = nullptr;
   std::vector<pg_sketches*> sketches;
   pg::SkView* d_views = nullptr;
-  std::vector<double*> tables;  // server-owned estimator tables (Bloom filters)
   std::vector<bool> view_ok;
   pg_server_params p{};
+  // staging arena: cap pair slots of pinned, coherent host memory
+  int64_t cap = 0;
+  int32_t* a_u = nullptr;
+  int32_t* a_v = nullptr;
+  double* a_out = nullptr;
+  std::map<int64_t, int64_t> free_ranges;  // first slot -> length, disjoint and not adjacent
   std::mutex mu;
   std::condition_variable work_cv;  // engine: new requests or stop
-  std::condition_variable done_cv;  // waiters: results delivered
+  std::condition_variable done_cv;  // collectors: requests finished or collected
   std::deque<pg::Request*> queue;
   std::unordered_map<uint64_t, pg::Request*> live;
   std::vector<pg::Slot> slots;
@@ -131,13 +148,40 @@ struct pg_server {
 namespace pg {
 namespace {
 
-int slot_init(pg_server* srv, Slot& sl) {
-  const int64_t cap = srv->p.max_batch_pairs;
+constexpr uint64_t kBytesPerPair = 16;
+
+// First-fit range of `len` free slots; -1 if none. Caller holds srv->mu.
+int64_t arena_take(pg_server* srv, int64_t len) {
+  for (auto it = srv->free_ranges.begin(); it != srv->free_ranges.end(); ++it) {
+    if (it->second < len) continue;
+    const int64_t at = it->first, rest = it->second - len;
+    srv->free_ranges.erase(it);
+    if (rest > 0) srv->free_ranges.emplace(at + len, rest);
+    return at;
+  }
+  return -1;
+}
+
+// Return [at, at + len) to the arena, merging with free neighbours. Caller holds srv->mu.
+void arena_give(pg_server* srv, int64_t at, int64_t len) {
+  auto next = srv->free_ranges.lower_bound(at);
+  if (next != srv->free_ranges.end() && next->first == at + len) {
+    len += next->second;
+    next = srv->free_ranges.erase(next);
+  }
+  if (next != srv->free_ranges.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == at) {
+      prev->second += len;
+      return;
+    }
+  }
+  srv->free_ranges.emplace(at, len);
+}
+
+int slot_init(Slot& sl) {
   PG_HIP(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
   PG_HIP(hipEventCreateWithFlags(&sl.event, hipEventDisableTiming));
-  PG_HIP(hipHostMalloc((void**)&sl.h_u, sizeof(int32_t) * cap, hipHostMallocCoherent));
-  PG_HIP(hipHostMalloc((void**)&sl.h_v, sizeof(int32_t) * cap, hipHostMallocCoherent));
-  PG_HIP(hipHostMalloc((void**)&sl.h_out, sizeof(double) * cap, hipHostMallocCoherent));
   PG_HIP(hipHostMalloc((void**)&sl.h_seg, sizeof(SegDesc) * kMaxSegments, hipHostMallocDefault));
   PG_TRY(palloc((void**)&sl.d_seg, sizeof(SegDesc) * kMaxSegments));
   return PG_OK;
@@ -145,9 +189,6 @@ int slot_init(pg_server* srv, Slot& sl) {
 
 void slot_free(Slot& sl) {
   if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-  if (sl.h_u) (void)hipHostFree(sl.h_u);
-  if (sl.h_v) (void)hipHostFree(sl.h_v);
-  if (sl.h_out) (void)hipHostFree(sl.h_out);
   if (sl.h_seg) (void)hipHostFree(sl.h_seg);
   pfree(sl.d_seg);
   if (sl.event) (void)hipEventDestroy(sl.event);
@@ -155,19 +196,19 @@ void slot_free(Slot& sl) {
   sl = Slot();
 }
 
-// Pack requests into the slot's host buffers and enqueue the kernel and the
-// event (plus one small copy when the segment table is too big for arguments).
+// Enqueue the batch of the slot's requests: segment table (as kernel
+// arguments, or one small copy when it is larger), the kernel and the event.
 int launch_batch(pg_server* srv, Slot& sl) {
   int64_t total = 0;
   SegArgs a{};
   a.nseg = (int32_t)sl.reqs.size();
   int32_t i = 0;
   for (Request* r : sl.reqs) {
-    std::memcpy(sl.h_u + total, r->u.data(), sizeof(int32_t) * r->npairs);
-    std::memcpy(sl.h_v + total, r->v.data(), sizeof(int32_t) * r->npairs);
-    const SegDesc sd{total, r->view, r->op};
-    sl.h_seg[i] = sd;
-    if (i < kArgSegments) a.seg[i] = sd;
+    const SegDesc sd{total, r->arena, r->view, r->op};
+    if (a.nseg > kArgSegments)
+      sl.h_seg[i] = sd;
+    else
+      a.seg[i] = sd;
     ++i;
     total += r->npairs;
   }
@@ -175,24 +216,10 @@ int launch_batch(pg_server* srv, Slot& sl) {
     PG_HIP(hipMemcpyAsync(sl.d_seg, sl.h_seg, sizeof(SegDesc) * a.nseg, hipMemcpyHostToDevice, sl.stream));
   const unsigned grid = grid_for(total, 256, 16384);
   hipLaunchKernelGGL(k_serve_batch, dim3(grid), dim3(256), 0, sl.stream, (const SkView*)srv->d_views, a,
-                     (const SegDesc*)sl.d_seg, (const int32_t*)sl.h_u, (const int32_t*)sl.h_v, total, sl.h_out);
+                     (const SegDesc*)sl.d_seg, (const int32_t*)srv->a_u, (const int32_t*)srv->a_v, srv->a_out, total);
   PG_LAUNCH_CHECK();
   PG_HIP(hipEventRecord(sl.event, sl.stream));
   return PG_OK;
-}
-
-// Copy a finished batch's results to the requests' buffers.
-void deliver(Slot& sl) {
-  int64_t off = 0;
-  for (Request* r : sl.reqs) {
-    if (r->op == PG_OP_CN) {
-      std::memcpy(r->out, sl.h_out + off, sizeof(double) * r->npairs);
-    } else {
-      float* o = (float*)r->out;
-      for (int64_t i = 0; i < r->npairs; ++i) o[i] = (float)sl.h_out[off + i];
-    }
-    off += r->npairs;
-  }
 }
 
 void engine_loop(pg_server* srv) {
@@ -200,30 +227,22 @@ void engine_loop(pg_server* srv) {
   std::unique_lock<std::mutex> lk(srv->mu);
   for (;;) {
     bool progressed = false;
-    // retire finished batches
+    // retire finished batches: their answers are in the arena
     for (Slot& sl : srv->slots) {
       if (!sl.busy) continue;
       const hipError_t q = hipEventQuery(sl.event);
       if (q == hipErrorNotReady) continue;
-      if (q != hipSuccess) {
+      if (q != hipSuccess && srv->engine_error == PG_OK) {
         srv->engine_error = PG_E_DEVICE;
         srv->engine_msg = std::string("serving batch: ") + hipGetErrorString(q);
-      } else {
-        deliver(sl);
       }
-      const Clock::time_point now = Clock::now();
-      for (Request* r : sl.reqs) {
-        r->done = true;
-        r->t_done = now;
-        srv->stats.completed++;
-        srv->stats.pairs += (uint64_t)r->npairs;
-      }
+      for (Request* r : sl.reqs) r->state = kFinished;
       sl.reqs.clear();
       sl.busy = false;
       progressed = true;
       srv->done_cv.notify_all();
     }
-    // start batches on free slots
+    // start batches on free slots; the launch itself runs outside the lock
     for (Slot& sl : srv->slots) {
       if (sl.busy || srv->queue.empty()) continue;
       int64_t total = 0;
@@ -235,21 +254,24 @@ void engine_loop(pg_server* srv) {
         sl.reqs.push_back(r);
       }
       if (sl.reqs.empty()) continue;
-      const int rc = launch_batch(srv, sl);
-      if (rc != PG_OK) {
-        srv->engine_error = rc;
-        srv->engine_msg = pg_last_error();
-      }
       sl.busy = true;
       srv->stats.batches++;
       progressed = true;
+      lk.unlock();
+      const int rc = launch_batch(srv, sl);
+      const std::string msg = rc != PG_OK ? std::string(pg_last_error()) : std::string();
+      lk.lock();
+      if (rc != PG_OK && srv->engine_error == PG_OK) {
+        srv->engine_error = rc;
+        srv->engine_msg = msg;
+      }
     }
-    const uint64_t busy = (uint64_t)std::count_if(srv->slots.begin(), srv->slots.end(), [](const Slot& s) { return s.busy; });
+    const uint64_t busy =
+        (uint64_t)std::count_if(srv->slots.begin(), srv->slots.end(), [](const Slot& s) { return s.busy; });
     srv->stats.max_in_flight = std::max(srv->stats.max_in_flight, busy);
-    const bool inflight = busy > 0;
-    if (srv->stop && !inflight && srv->queue.empty()) break;
+    if (srv->stop && busy == 0 && srv->queue.empty()) break;
     if (!progressed) {
-      if (inflight) {
+      if (busy > 0) {
         // a batch is on the device: poll again shortly
         lk.unlock();
         std::this_thread::yield();
@@ -259,6 +281,25 @@ void engine_loop(pg_server* srv) {
       }
     }
   }
+}
+
+// Copy a finished request's answers from the arena into its output buffer and
+// return its range. The caller set r->state = kCollecting under the lock and
+// does not hold it now; the range belongs to r alone until it is returned.
+void collect(pg_server* srv, Request* r) {
+  if (r->op == PG_OP_CN)
+    std::memcpy(r->out, srv->a_out + r->arena, sizeof(double) * (size_t)r->npairs);
+  else
+    std::memcpy(r->out, srv->a_out + r->arena, sizeof(float) * (size_t)r->npairs);
+  const Clock::time_point now = Clock::now();
+  std::lock_guard<std::mutex> lk(srv->mu);
+  arena_give(srv, r->arena, r->npairs);
+  srv->bytes_admitted -= (uint64_t)r->npairs * kBytesPerPair;
+  srv->stats.completed++;
+  srv->stats.pairs += (uint64_t)r->npairs;
+  r->t_collected = now;
+  r->state = kCollected;
+  srv->done_cv.notify_all();
 }
 
 }  // namespace
@@ -279,12 +320,6 @@ int pg_server_create(pg_ctx* ctx, const pg_graph* g, pg_sketches* const* sketche
     if (sketches[i]->oriented)
       return fail(PG_E_UNSUPPORTED, "servers answer queries on N_v; an oriented sketch set sketches N+_v");
   }
-  PG_HIP(hipSetDevice(ctx->device));
-  pg_server* srv = new (std::nothrow) pg_server();
-  if (!srv) return fail(PG_E_NOMEM, "host allocation failed");
-  srv->ctx = ctx;
-  srv->g = g;
-  srv->sketches.assign(sketches, sketches + nsketches);
   pg_server_params p{};
   if (params) p = *params;
   if (p.max_batches_in_flight <= 0) p.max_batches_in_flight = 3;
@@ -293,42 +328,47 @@ int pg_server_create(pg_ctx* ctx, const pg_graph* g, pg_sketches* const* sketche
   if (p.memory_budget_bytes == 0) p.memory_budget_bytes = 256ull << 20;
   p.max_batches_in_flight = std::min(p.max_batches_in_flight, 16);
   p.max_batch_pairs = std::max<int64_t>(p.max_batch_pairs, p.max_pairs_per_request);
+  if (p.memory_budget_bytes < kBytesPerPair) return fail(PG_E_INVALID, "memory_budget_bytes below one pair (16 bytes)");
+  PG_HIP(hipSetDevice(ctx->device));
+  pg_server* srv = new (std::nothrow) pg_server();
+  if (!srv) return fail(PG_E_NOMEM, "host allocation failed");
+  srv->ctx = ctx;
+  srv->g = g;
+  srv->sketches.assign(sketches, sketches + nsketches);
   srv->p = p;
-  // one view per (sketch set, estimator); Bloom filters get server-owned tables
+  // one view per (sketch set, estimator); Bloom-filter views read the set's own tables
   std::vector<SkView> views((size_t)nsketches * kEstSlots);
   srv->view_ok.assign(views.size(), false);
-  int rc = PG_OK;
-  hipStream_t s = nullptr;
-  for (int i = 0; i < nsketches && rc == PG_OK; ++i) {
+  for (int i = 0; i < nsketches; ++i) {
     pg_sketches* sk = srv->sketches[i];
-    for (int est = 1; est < kEstSlots && rc == PG_OK; ++est) {
+    for (int est = 1; est < kEstSlots; ++est) {
       if (check_estimator(sk, est) != PG_OK) continue;
-      SkView v = make_view(sk, est);
-      if (sk->kind == PG_BF) {
-        double* t = nullptr;
-        rc = palloc((void**)&t, sizeof(double) * (sk->size + 1));
-        if (rc != PG_OK) break;
-        srv->tables.push_back(t);
-        rc = fill_table(t, sk->size, sk->b, est, s);
-        v.table = t;
-      }
-      views[(size_t)i * kEstSlots + est] = v;
+      views[(size_t)i * kEstSlots + est] = make_view(sk, est);
       srv->view_ok[(size_t)i * kEstSlots + est] = true;
     }
   }
   clear_error();
-  if (rc == PG_OK) rc = palloc((void**)&srv->d_views, sizeof(SkView) * views.size());
+  int rc = palloc((void**)&srv->d_views, sizeof(SkView) * views.size());
   if (rc == PG_OK) {
     hipError_t e = hipMemcpy(srv->d_views, views.data(), sizeof(SkView) * views.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) rc = fail(PG_E_DEVICE, std::string("server views: ") + hipGetErrorString(e));
   }
+  srv->cap = (int64_t)(p.memory_budget_bytes / kBytesPerPair);
+  if (rc == PG_OK) {
+    hipError_t e = hipHostMalloc((void**)&srv->a_u, sizeof(int32_t) * srv->cap, hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&srv->a_v, sizeof(int32_t) * srv->cap, hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&srv->a_out, sizeof(double) * srv->cap, hipHostMallocCoherent);
+    if (e != hipSuccess) rc = fail(PG_E_NOMEM, std::string("pinned staging arena: ") + hipGetErrorString(e));
+  }
+  srv->free_ranges.emplace(0, srv->cap);
   srv->slots.resize((size_t)p.max_batches_in_flight);
   for (Slot& sl : srv->slots)
-    if (rc == PG_OK) rc = slot_init(srv, sl);
+    if (rc == PG_OK) rc = slot_init(sl);
   if (rc != PG_OK) {
     for (Slot& sl : srv->slots) slot_free(sl);
-    for (double* t : srv->tables) pfree(t);
+    if (srv->a_u) (void)hipHostFree(srv->a_u);
+    if (srv->a_v) (void)hipHostFree(srv->a_v);
+    if (srv->a_out) (void)hipHostFree(srv->a_out);
     pfree(srv->d_views);
     delete srv;
     return rc;
@@ -352,35 +392,36 @@ int pg_server_submit(pg_server* srv, const pg_request* req, uint64_t* ticket) {
       !srv->view_ok[(size_t)req->sketch * kEstSlots + req->estimator])
     return invalid("estimator does not match the sketch kind");
   if (req->npairs < 1 || req->npairs > srv->p.max_pairs_per_request) return invalid("npairs out of range");
+  if (req->npairs > srv->cap) return invalid("request larger than the memory budget (16 bytes per pair)");
   if (!req->u || !req->v || !req->out) return invalid("NULL pair or output array");
-  const int32_t n = srv->g->n;
-  for (int64_t i = 0; i < req->npairs; ++i)
-    if ((uint32_t)req->u[i] >= (uint32_t)n || (uint32_t)req->v[i] >= (uint32_t)n)
-      return invalid("vertex ID out of range");
-  const uint64_t bytes = (uint64_t)req->npairs * 16;
+  const uint32_t n = (uint32_t)srv->g->n;
+  const int64_t L = req->npairs;
+  uint32_t bad = 0;
+  for (int64_t i = 0; i < L; ++i) bad |= (uint32_t)((uint32_t)req->u[i] >= n) | (uint32_t)((uint32_t)req->v[i] >= n);
+  if (bad) return invalid("vertex ID out of range");
+  Request* r = new (std::nothrow) Request();
+  if (!r) return fail(PG_E_NOMEM, "host allocation failed");
   {
     std::lock_guard<std::mutex> lk(srv->mu);
-    if (srv->engine_error != PG_OK) return fail(srv->engine_error, srv->engine_msg);
-    if (srv->stop) return fail(PG_E_INVALID, "server is stopping");
-    if (srv->bytes_admitted + bytes > srv->p.memory_budget_bytes) {
-      srv->stats.rejected_busy++;
-      return fail(PG_E_BUSY, "not admitted: memory budget in use");
+    if (srv->engine_error != PG_OK || srv->stop) {
+      delete r;
+      return srv->stop ? fail(PG_E_INVALID, "server is stopping") : fail(srv->engine_error, srv->engine_msg);
     }
-    srv->bytes_admitted += bytes;
+    r->arena = arena_take(srv, L);
+    if (r->arena < 0) {
+      srv->stats.rejected_busy++;
+      delete r;
+      return fail(PG_E_BUSY, "not admitted: no free range of the memory budget");
+    }
+    srv->bytes_admitted += (uint64_t)L * kBytesPerPair;
   }
-  Request* r = new (std::nothrow) Request();
-  if (!r) {
-    std::lock_guard<std::mutex> lk(srv->mu);
-    srv->bytes_admitted -= bytes;
-    return fail(PG_E_NOMEM, "host allocation failed");
-  }
+  // the range is this request's alone: write its pairs without the lock
+  std::memcpy(srv->a_u + r->arena, req->u, sizeof(int32_t) * (size_t)L);
+  std::memcpy(srv->a_v + r->arena, req->v, sizeof(int32_t) * (size_t)L);
   r->op = req->op;
   r->view = req->sketch * kEstSlots + req->estimator;
-  r->npairs = req->npairs;
-  r->u.assign(req->u, req->u + req->npairs);
-  r->v.assign(req->v, req->v + req->npairs);
+  r->npairs = L;
   r->out = req->out;
-  r->bytes = bytes;
   r->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -397,11 +438,21 @@ int pg_server_submit(pg_server* srv, const pg_request* req, uint64_t* ticket) {
 int pg_server_poll(pg_server* srv, uint64_t ticket, int32_t* done) {
   clear_error();
   if (!srv || !done) return fail(PG_E_INVALID, "NULL argument");
-  std::lock_guard<std::mutex> lk(srv->mu);
+  std::unique_lock<std::mutex> lk(srv->mu);
   auto it = srv->live.find(ticket);
   if (it == srv->live.end()) return fail(PG_E_INVALID, "unknown ticket");
-  *done = it->second->done ? 1 : 0;
-  return srv->engine_error;
+  Request* r = it->second;
+  if (r->state == kFinished) {  // this poll collects it
+    r->state = kCollecting;
+    lk.unlock();
+    collect(srv, r);
+    lk.lock();
+  } else if (r->state == kCollecting) {
+    srv->done_cv.wait(lk, [&] { return r->state == kCollected; });
+  }
+  *done = r->state == kCollected ? 1 : 0;
+  if (srv->engine_error != PG_OK) return fail(srv->engine_error, srv->engine_msg);
+  return PG_OK;
 }
 
 int pg_server_wait(pg_server* srv, uint64_t ticket, double* latency_ms) {
@@ -411,12 +462,20 @@ int pg_server_wait(pg_server* srv, uint64_t ticket, double* latency_ms) {
   auto it = srv->live.find(ticket);
   if (it == srv->live.end()) return fail(PG_E_INVALID, "unknown ticket");
   Request* r = it->second;
-  srv->done_cv.wait(lk, [&] { return r->done; });
-  if (latency_ms) latency_ms[0] = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
-  srv->live.erase(it);
-  srv->bytes_admitted -= r->bytes;
+  srv->live.erase(it);  // this call owns the ticket now
+  srv->done_cv.wait(lk, [&] { return r->state != kQueued; });
+  if (r->state == kFinished) {
+    r->state = kCollecting;
+    lk.unlock();
+    collect(srv, r);
+    lk.lock();
+  } else {
+    srv->done_cv.wait(lk, [&] { return r->state == kCollected; });
+  }
+  if (latency_ms) latency_ms[0] = std::chrono::duration<double, std::milli>(r->t_collected - r->t_submit).count();
   const int err = srv->engine_error;
   const std::string msg = srv->engine_msg;
+  lk.unlock();
   delete r;
   if (err != PG_OK) return fail(err, msg);
   return PG_OK;
@@ -436,61 +495,100 @@ int pg_server_replay(pg_server* srv, int64_t nreq, const pg_request* reqs, const
   if (!srv || (nreq > 0 && (!reqs || !latency_ms))) return fail(PG_E_INVALID, "NULL argument");
   if (nreq <= 0) return PG_OK;
   if (!arrival_s && max_outstanding < 1) return fail(PG_E_INVALID, "closed loop needs max_outstanding >= 1");
+  // a few submitting and a few collecting threads: request i is submitted by
+  // thread i mod S (in order of i within a thread) and collected by thread
+  // i mod C, so the per-pair copies at submit and collection run in parallel
+  const int S = (int)std::min<int64_t>(4, nreq), C = (int)std::min<int64_t>(4, nreq);
   std::vector<uint64_t> tickets((size_t)nreq, 0);
+  std::vector<char> ready((size_t)nreq, 0);
   std::vector<Clock::time_point> t_arr((size_t)nreq);
   std::mutex m;
   std::condition_variable cv;
-  int64_t submitted = 0, collected = 0;
+  int64_t outstanding = 0, next = 0;
   int err = PG_OK;
   std::string err_msg;
+  auto set_err = [&](int rc) {  // caller holds m
+    if (err == PG_OK) {
+      err = rc;
+      err_msg = pg_last_error();
+    }
+  };
   const Clock::time_point t0 = Clock::now();
-  // collector: waits for the requests in submission order
-  std::thread collector([&] {
-    for (int64_t i = 0; i < nreq; ++i) {
+  // open loop: per-thread index streams; closed loop: shared counter
+  auto open_submitter = [&](int t) {
+    for (int64_t i = t; i < nreq; i += S) {
+      {
+        std::lock_guard<std::mutex> lk(m);
+        if (err != PG_OK) return;
+      }
+      const Clock::time_point due =
+          t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
+      while (Clock::now() < due) std::this_thread::yield();
+      t_arr[(size_t)i] = due;
+      uint64_t tk = 0;
+      int rc;
+      while ((rc = pg_server_submit(srv, &reqs[i], &tk)) == PG_E_BUSY) std::this_thread::yield();
+      std::lock_guard<std::mutex> lk(m);
+      if (rc != PG_OK)
+        set_err(rc);
+      else {
+        tickets[(size_t)i] = tk;
+        ready[(size_t)i] = 1;
+      }
+      cv.notify_all();
+    }
+  };
+  auto closed_submitter = [&]() {
+    for (;;) {
+      int64_t i;
+      {
+        std::unique_lock<std::mutex> lk(m);
+        cv.wait(lk, [&] { return outstanding < max_outstanding || err != PG_OK || next >= nreq; });
+        if (err != PG_OK || next >= nreq) return;
+        i = next++;
+        ++outstanding;
+      }
+      t_arr[(size_t)i] = Clock::now();
+      uint64_t tk = 0;
+      int rc;
+      while ((rc = pg_server_submit(srv, &reqs[i], &tk)) == PG_E_BUSY) std::this_thread::yield();
+      std::lock_guard<std::mutex> lk(m);
+      if (rc != PG_OK)
+        set_err(rc);
+      else {
+        tickets[(size_t)i] = tk;
+        ready[(size_t)i] = 1;
+      }
+      cv.notify_all();
+    }
+  };
+  auto collector = [&](int c) {
+    for (int64_t i = c; i < nreq; i += C) {
       uint64_t tk;
       {
         std::unique_lock<std::mutex> lk(m);
-        cv.wait(lk, [&] { return submitted > i || err != PG_OK; });
-        if (submitted <= i) return;
+        cv.wait(lk, [&] { return ready[(size_t)i] || err != PG_OK; });
+        if (!ready[(size_t)i]) return;
         tk = tickets[(size_t)i];
       }
-      double lat = 0.0;
-      const int rc = pg_server_wait(srv, tk, &lat);
+      const int rc = pg_server_wait(srv, tk, nullptr);
+      const Clock::time_point now = Clock::now();
       std::lock_guard<std::mutex> lk(m);
-      if (rc != PG_OK && err == PG_OK) {
-        err = rc;
-        err_msg = pg_last_error();
-      }
-      latency_ms[i] = std::chrono::duration<double, std::milli>(Clock::now() - t_arr[(size_t)i]).count();
-      ++collected;
+      if (rc != PG_OK) set_err(rc);
+      latency_ms[i] = std::chrono::duration<double, std::milli>(now - t_arr[(size_t)i]).count();
+      --outstanding;
       cv.notify_all();
     }
-  });
-  for (int64_t i = 0; i < nreq && err == PG_OK; ++i) {
-    if (arrival_s) {
-      const Clock::time_point due = t0 + std::chrono::duration_cast<Clock::duration>(
-                                             std::chrono::duration<double>(arrival_s[i]));
-      while (Clock::now() < due) std::this_thread::yield();
-      t_arr[(size_t)i] = due;
-    } else {
-      std::unique_lock<std::mutex> lk(m);
-      cv.wait(lk, [&] { return submitted - collected < max_outstanding || err != PG_OK; });
-      t_arr[(size_t)i] = Clock::now();
-    }
-    uint64_t tk = 0;
-    int rc;
-    while ((rc = pg_server_submit(srv, &reqs[i], &tk)) == PG_E_BUSY) std::this_thread::yield();
-    std::lock_guard<std::mutex> lk(m);
-    if (rc != PG_OK) {
-      err = rc;
-      err_msg = pg_last_error();
-    } else {
-      tickets[(size_t)i] = tk;
-      ++submitted;
-    }
-    cv.notify_all();
+  };
+  std::vector<std::thread> threads;
+  for (int c = 0; c < C; ++c) threads.emplace_back(collector, c);
+  for (int t = 0; t < S; ++t) {
+    if (arrival_s)
+      threads.emplace_back(open_submitter, t);
+    else
+      threads.emplace_back(closed_submitter);
   }
-  collector.join();
+  for (std::thread& th : threads) th.join();
   if (elapsed_s) *elapsed_s = std::chrono::duration<double>(Clock::now() - t0).count();
   if (err != PG_OK) return fail(err, err_msg);
   return PG_OK;
@@ -508,7 +606,9 @@ int pg_server_destroy(pg_server* srv) {
   for (auto& kv : srv->live) delete kv.second;
   srv->live.clear();
   for (Slot& sl : srv->slots) slot_free(sl);
-  for (double* t : srv->tables) pfree(t);
+  if (srv->a_u) (void)hipHostFree(srv->a_u);
+  if (srv->a_v) (void)hipHostFree(srv->a_v);
+  if (srv->a_out) (void)hipHostFree(srv->a_out);
   pfree(srv->d_views);
   delete srv;
   return PG_OK;
