@@ -193,6 +193,21 @@ int pg_tc(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* tc, void* s
  * without waiting, so successive calls pipeline. */
 int pg_tc_async(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* d_tc, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the estimate
+ * of pg_tc_async, bit-identical to it, written to d_tc[0] (device FP64) and
+ * enqueued on `stream` without waiting. The call allocates and frees nothing:
+ * its partial sums go to a fixed device workspace of 16 MiB (2^21 FP64
+ * values) that the library holds on each GPU from the first pg_ctx_create on
+ * that GPU until the process ends. Every call on one GPU shares that workspace
+ * and leaves its last partials there; calls in order on one stream are safe,
+ * while calls that overlap on one GPU (other streams, other contexts of the
+ * same device) race and must be ordered by the caller. Errors: PG_E_INVALID as
+ * pg_tc_async; PG_E_UNSUPPORTED if the graph's triangle-count plan does not
+ * exist yet (the first pg_tc or pg_tc_async call on a sketch set of the graph
+ * builds it, and allocates) or if the partial sums exceed the workspace. */
+int pg_tc_noalloc(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* d_tc, void* stream);
+
 /* Estimated local clustering coefficient cc[n] (device, FP32 rounded once
  * from FP64): cc_v = sum_{u in N_v} I^(u,v) / (d_v (d_v - 1)), 0 if d_v < 2.
  * If transitivity (host) is not NULL it receives 3 TC^ / sum_v C(d_v, 2) and

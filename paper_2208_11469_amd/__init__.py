@@ -134,6 +134,7 @@ def _declare(lib):
         "pg_intersect_edges": (i, [_vp, _vp, i, _vp, _vp, i64, _vp, _vp, _vp]),
         "pg_tc": (i, [_vp, _vp, i, P(ctypes.c_double), _vp]),
         "pg_tc_async": (i, [_vp, _vp, i, _vp, _vp]),
+        "pg_tc_noalloc": (i, [_vp, _vp, i, _vp, _vp]),
         "pg_cc": (i, [_vp, _vp, i, _vp, P(ctypes.c_double), _vp]),
         "pg_jaccard": (i, [_vp, _vp, i, _vp, _vp, i64, _vp, _vp]),
         "pg_exact_intersect_edges": (i, [_vp, _vp, i, _vp, _vp, i64, _vp, _vp]),
@@ -316,6 +317,11 @@ def pg_tc(ctx, sk, estimator, stream=None) -> float:
 def pg_tc_async(ctx, sk, estimator, d_tc, stream=None):
     torch = _torch()
     _check(load().pg_tc_async(ctx, sk, estimator, _dptr(d_tc, torch.float64), _stream(stream)))
+
+
+def pg_tc_noalloc(ctx, sk, estimator, d_tc, stream=None):
+    torch = _torch()
+    _check(load().pg_tc_noalloc(ctx, sk, estimator, _dptr(d_tc, torch.float64), _stream(stream)))
 
 
 def pg_cc(ctx, sk, estimator, cc, want_transitivity=False, stream=None):

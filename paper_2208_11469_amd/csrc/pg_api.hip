@@ -170,6 +170,12 @@ int pg_ctx_create(int device, pg_ctx** out) {
     delete ctx;
     return fail(PG_E_NOMEM, "pinned host allocation failed");
   }
+  const int rc = noalloc_scratch(device, &ctx->scratch, &ctx->scratch_doubles);
+  if (rc != PG_OK) {
+    (void)hipHostFree(ctx->h_scalar);
+    delete ctx;
+    return rc;
+  }
   *out = ctx;
   return PG_OK;
 }
@@ -475,6 +481,15 @@ int pg_tc_async(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* d_tc,
   if (!ctx || !sk || !d_tc) return fail(PG_E_INVALID, "NULL argument");
   PG_TRY(use_device(ctx));
   return estimate_tc(sk, estimator, d_tc, (hipStream_t)stream);
+}
+
+int pg_tc_noalloc(pg_ctx* ctx, const pg_sketches* sk, int estimator, double* d_tc, void* stream) {
+  clear_error();
+  if (!ctx || !sk || !d_tc) return fail(PG_E_INVALID, "NULL argument");
+  if (!ctx->scratch) return fail(PG_E_DEVICE, "the context has no fixed workspace");
+  PG_TRY(use_device(ctx));
+  const TcWorkspace ws{ctx->scratch, ctx->scratch_doubles};
+  return estimate_tc(sk, estimator, d_tc, (hipStream_t)stream, &ws);
 }
 
 int pg_cc(pg_ctx* ctx, const pg_sketches* sk, int estimator, float* cc, double* transitivity, void* stream) {

@@ -20,6 +20,15 @@
 #include "pg_internal.h"
 #include "pg_pair.h"
 
+// ---- fixed workspace of pg_tc_noalloc -------------------------------------------
+// Partial sums of the triangle count for callers that cannot allocate device
+// memory. Every GPU the library runs on holds its own copy of this array until
+// the process ends. In host code the name stands for a host-side shadow, not a
+// device address: host code uses only the address hipGetSymbolAddress returns
+// on each device (noalloc_scratch below).
+constexpr int64_t kScratchDoubles = (int64_t)1 << 21;  // 16 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 namespace pg {
 namespace {
 
@@ -1222,6 +1231,25 @@ int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStre
 #undef PG_LAUNCH_CC_G
     PG_LAUNCH_CHECK();
   }
+  return PG_OK;
+}
+
+int noalloc_scratch(int device, double** ptr, int64_t* doubles) {
+  // device addresses of the array, one per device, each looked up once with
+  // that device current (the caller has made `device` current)
+  static std::mutex mu;
+  static double* addr[64] = {};
+  if (device < 0 || device >= 64) return fail(PG_E_INVALID, "device ordinal out of range for the fixed workspace");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PG_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    addr[device] = (double*)p;
+  }
+  *ptr = addr[device];
+  *doubles = kScratchDoubles;
   return PG_OK;
 }
 

@@ -194,6 +194,8 @@ struct pg_ctx {
   int device = 0;
   int num_cus = 0;
   double* h_scalar = nullptr;  // pinned host slot for scalar results
+  double* scratch = nullptr;   // the device's fixed workspace (pg_tc_noalloc), not owned
+  int64_t scratch_doubles = 0;
 };
 
 struct pg_graph {
@@ -307,7 +309,9 @@ struct TcWorkspace {
   int64_t doubles;  // capacity
 };
 int estimate_tc(const pg_sketches* sk, int est, double* d_out, hipStream_t s, const TcWorkspace* ws = nullptr);
-
+// The library's fixed workspace on `device` (see pg_tc_noalloc): its device
+// address, looked up once per device, and its size.
+int noalloc_scratch(int device, double** ptr, int64_t* doubles);
 
 // ---- launchers (pg_exact.hip) ------------------------------------------------
 int exact_pairs(const pg_graph* g, int algo, const int32_t* u, const int32_t* v, int64_t npairs,
