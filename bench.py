@@ -169,6 +169,7 @@ def measure_serving(args, pg, pggen, np, log):
     sat_pairs = reps * pairs / el
     sat_rate = reps * len(reqs) / el
     sat_hbm = reps * alg / el / 1e9
+    sat_bus = reps * bus / el / 1e9
     log(f"serving saturation: {sat_pairs:.3e} pairs/s, {sat_rate:.0f} requests/s, {sat_hbm:.1f} GB/s algorithmic, "
         f"p50 {np.percentile(lat, 50):.3f} ms")
     unit_gaps = np.diff(np.concatenate([[0.0], [r.arrival_s for r in trace]]))  # Poisson gaps at 1 request/s
@@ -191,7 +192,7 @@ def measure_serving(args, pg, pggen, np, log):
             "mean_pairs_per_request": mean_pairs, "saturation_pairs_per_s": sat_pairs,
             "saturation_requests_per_s": sat_rate,
             "saturation_algorithmic_gbs": round(sat_hbm, 2), "saturation_frac_hbm": round(sat_hbm / HBM_PEAK_GBS, 5),
-            "saturation_bus_gbs": round(reps * bus / el / 1e9, 2),
+            "saturation_bus_gbs": round(sat_bus, 2),
             "bytes_rule": "per pair 2 rows (BF-512: 64 B, k-hash-32: 128 B) + 8 (IDs) + answer (8 CN, 4 Jaccard) "
                           "+ 8 (degrees, Jaccard or MinHash); bus: 8 (IDs) + answer",
             "loads": loads, "batches": st["batches"], "max_batches_in_flight": st["max_in_flight"],
@@ -368,6 +369,7 @@ def main():
     ap.add_argument("--b", type=int, default=1)
     ap.add_argument("--skip-cpu", action="store_true", help="leave out the CPU oracle baseline")
     ap.add_argument("--skip-rows", action="store_true", help="leave out the extra rows")
+    ap.add_argument("--rows", default=None, help="comma-separated names of the extra rows to run (default: all)")
     ap.add_argument("--skip-serving", action="store_true", help="leave out the serving measurement")
     ap.add_argument("--serving-scale", type=int, default=22)
     ap.add_argument("--serving-requests", type=int, default=10000)
@@ -522,8 +524,13 @@ def main():
     del src, dst
 
     rows = {}
-    if not args.skip_rows:
-        reps = 10
+    sel = set(args.rows.split(",")) if args.rows else None
+
+    def want(*names):
+        return not args.skip_rows and (sel is None or any(k in sel for k in names))
+
+    reps = 10
+    if want("bf_b2_tc"):
         # b = 2 at the same budget
         sk2 = dg.build_sketches("bf", B, 2, seed=args.seed)
         ms = timed(lambda: (sk2.rebuild(), sk2.tc("and")), reps, sync)
@@ -531,6 +538,7 @@ def main():
         rows["bf_b2_tc"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3), "tc": tc2,
                             "rel_err": abs(tc2 - exact_tc) / exact_tc}
         sk2.close()
+    if want("khash32_tc", "khash32_jaccard_edges", "khash32_cc"):
         # k-hash, k = 32
         skk = dg.build_sketches("kh", 32, seed=args.seed)
         ms_b = timed(lambda: skk.rebuild(), reps, sync)
@@ -539,6 +547,12 @@ def main():
         rows["khash32_tc"] = {"build_ms": round(ms_b, 4), "tc_ms": round(ms_t, 4),
                               "intersections_per_s": m / ((ms_b + ms_t) * 1e-3), "tc": tck,
                               "rel_err": abs(tck - exact_tc) / exact_tc}
+        ms = timed(lambda: skk.jaccard("kh"), reps, sync)
+        rows["khash32_jaccard_edges"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
+        ms = timed(lambda: skk.cc("kh"), reps, sync)
+        rows["khash32_cc"] = {"ms": round(ms, 4), "arc_intersections_per_s": nnz / (ms * 1e-3)}
+        skk.close()
+    if want("bf_oriented_tc"):
         # sketches of the degree-oriented sets N+_v (node iterator form of the
         # triangle count): same sizes, smaller sets
         sko = dg.build_sketches("bf", B, 1, seed=args.seed, oriented=True)
@@ -547,6 +561,7 @@ def main():
         rows["bf_oriented_tc"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3), "tc": tco,
                                   "rel_err": abs(tco - exact_tc) / exact_tc}
         sko.close()
+    if want("khash32_oriented_tc"):
         sko = dg.build_sketches("kh", 32, seed=args.seed, oriented=True)
         ms_b = timed(lambda: sko.rebuild(), reps, sync)
         ms_t = timed(lambda: sko.tc("kh"), reps, sync)
@@ -555,8 +570,9 @@ def main():
                                        "intersections_per_s": m / ((ms_b + ms_t) * 1e-3), "tc": tco,
                                        "rel_err": abs(tco - exact_tc) / exact_tc}
         sko.close()
-        # KMV estimators on 1-hash rows, k = 32 (per-pair union walk), full and oriented sets
-        for key, oriented in (("kmv32_tc", False), ("kmv32_oriented_tc", True)):
+    # KMV estimators on 1-hash rows, k = 32, full and oriented sets
+    for key, oriented in (("kmv32_tc", False), ("kmv32_oriented_tc", True)):
+        if want(key):
             skm = dg.build_sketches("1h", 32, seed=args.seed, oriented=oriented)
             ms_b = timed(lambda: skm.rebuild(), reps, sync)
             ms_t = timed(lambda: skm.tc("kmv"), reps, sync)
@@ -566,6 +582,7 @@ def main():
                          "rel_err": abs(tcm - exact_tc) / exact_tc,
                          "tc_1hash_union": skm.tc("1h"), "tc_kmv_sketch_sizes": skm.tc("kmv_est")}
             skm.close()
+    if want("four_cliques"):
         # 4-cliques: exact, and with membership queries on the filters of N+_v
         sko = dg.build_sketches("bf", B, 1, seed=args.seed, oriented=True)
         ck_bf = sko.four_cliques()
@@ -582,21 +599,19 @@ def main():
                                 "rel_err_limit": (ck_l - ck_ex) / max(ck_ex, 1),
                                 "speedup_bf_and_vs_exact": ms_ex / ms_and}
         sko.close()
+    if want("bf_cc", "bf_jaccard_edges"):
         # clustering coefficient and Jaccard (BF AND, b = 1)
         ms = timed(lambda: sk.cc("and"), reps, sync)
         rows["bf_cc"] = {"ms": round(ms, 4), "arc_intersections_per_s": nnz / (ms * 1e-3)}
         ms = timed(lambda: sk.jaccard("and"), reps, sync)
         rows["bf_jaccard_edges"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
-        ms = timed(lambda: skk.jaccard("kh"), reps, sync)
-        rows["khash32_jaccard_edges"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
-        ms = timed(lambda: skk.cc("kh"), reps, sync)
-        rows["khash32_cc"] = {"ms": round(ms, 4), "arc_intersections_per_s": nnz / (ms * 1e-3)}
-        skk.close()
+    if want("exact_edges", "exact_cc"):
         # exact per-edge intersections (all m edges) and exact CC
         ms = timed(lambda: dg.exact_intersect(), 3, sync)
         rows["exact_edges"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
         ms = timed(lambda: dg.exact_cc(), 3, sync)
         rows["exact_cc"] = {"ms": round(ms, 4)}
+    if want("accuracy_bf_and"):
         # accuracy of the BF AND estimates on every edge and vertex: per-edge
         # relative error where I > 0, mean absolute error where I = 0, CC mean
         # absolute error, Jaccard absolute error quantiles
@@ -617,30 +632,33 @@ def main():
             "cc_mae": round(float((sk.cc("and").double() - dg.exact_cc().double()).abs().mean()), 6),
             "jaccard_abs_err": quantiles((sk.jaccard("and").double() - dg.exact_jaccard().double()).abs())}
         del i_ex, i_bf, pos
+    if want("exact_edges_bitmap", "exact_tc_bitmap"):
         # the bitmap variant of the exact baseline (all upper edges; triangle count)
         ms = timed(lambda: dg.exact_intersect(algo=pg.PG_EXACT_BITMAP), 3, sync)
         rows["exact_edges_bitmap"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
         assert dg.exact_tc(algo=pg.PG_EXACT_BITMAP) == exact_tc
         ms = timed(lambda: dg.exact_tc(algo=pg.PG_EXACT_BITMAP), 3, sync)
         rows["exact_tc_bitmap"] = {"ms": round(ms, 4), "intersections_per_s": m / (ms * 1e-3)}
+    for mname, tau in (("cn", 8.5), ("jaccard", 0.05), ("overlap", 0.5)):
+        if not want(f"jarvis_patrick_{mname}"):
+            continue
         # Jarvis-Patrick clustering over all m edges (similarity > tau) and its
         # clusters, from the filters and exactly (merge); accuracy as the
         # relative error of the counts
-        for mname, tau in (("cn", 8.5), ("jaccard", 0.05), ("overlap", 0.5)):
-            keep_b, kept_b = sk.jarvis_patrick("and", mname, tau)
-            ms_b = timed(lambda: sk.jarvis_patrick("and", mname, tau), reps, sync)
-            ncl_b = dg.clusters(keep_b)[1]
-            ms_c = timed(lambda: dg.clusters(keep_b), reps, sync)
-            keep_x, kept_x = dg.exact_jarvis_patrick(mname, tau)
-            ms_x = timed(lambda: dg.exact_jarvis_patrick(mname, tau), 3, sync)
-            ncl_x = dg.clusters(keep_x)[1]
-            rows[f"jarvis_patrick_{mname}"] = {
-                "tau": tau, "bf_ms": round(ms_b, 4), "bf_edges_per_s": m / (ms_b * 1e-3),
-                "clusters_ms": round(ms_c, 4), "exact_ms": round(ms_x, 4),
-                "speedup_bf_vs_exact": (ms_x + ms_c) / (ms_b + ms_c),
-                "kept_bf": kept_b, "kept_exact": kept_x, "clusters_bf": ncl_b, "clusters_exact": ncl_x,
-                "cluster_count_rel_err": abs(ncl_b - ncl_x) / max(ncl_x, 1)}
-            del keep_b, keep_x
+        keep_b, kept_b = sk.jarvis_patrick("and", mname, tau)
+        ms_b = timed(lambda: sk.jarvis_patrick("and", mname, tau), reps, sync)
+        ncl_b = dg.clusters(keep_b)[1]
+        ms_c = timed(lambda: dg.clusters(keep_b), reps, sync)
+        keep_x, kept_x = dg.exact_jarvis_patrick(mname, tau)
+        ms_x = timed(lambda: dg.exact_jarvis_patrick(mname, tau), 3, sync)
+        ncl_x = dg.clusters(keep_x)[1]
+        rows[f"jarvis_patrick_{mname}"] = {
+            "tau": tau, "bf_ms": round(ms_b, 4), "bf_edges_per_s": m / (ms_b * 1e-3),
+            "clusters_ms": round(ms_c, 4), "exact_ms": round(ms_x, 4),
+            "speedup_bf_vs_exact": (ms_x + ms_c) / (ms_b + ms_c),
+            "kept_bf": kept_b, "kept_exact": kept_x, "clusters_bf": ncl_b, "clusters_exact": ncl_x,
+            "cluster_count_rel_err": abs(ncl_b - ncl_x) / max(ncl_x, 1)}
+        del keep_b, keep_x
 
     cpu = None
     if not args.skip_cpu:

@@ -240,6 +240,9 @@ def pg_last_error() -> str:
 
 
 def pg_ctx_create(device: int = 0):
+    # torch's HIP runtime first: it does not find the GPUs if the library's
+    # runtime initialised them before it in this process
+    _torch().cuda.init()
     h = _vp()
     _check(load().pg_ctx_create(device, ctypes.byref(h)))
     return h

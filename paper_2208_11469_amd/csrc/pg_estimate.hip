@@ -513,6 +513,86 @@ __device__ __forceinline__ double oh_wave_estimate(const SkView& s, const uint64
   return minhash_estimate(uni >= s.size ? comk : com, kp, du, dv);
 }
 
+// Integer counts of the 1-hash ratio estimators for the pair (v, u), as in
+// oh_wave_estimate: sc = the matches the estimator counts and kk its
+// denominator (union reading: s and k' of the bottom-k' union; literal
+// reading: |M_u cap M_v| and k). The same in every lane (of the half).
+template <int E, bool HALF>
+__device__ __forceinline__ void oh_wave_ratio_counts(const SkView& s, const uint64_t* keys_v, uint32_t nv, int32_t du,
+                                                     const uint32_t (&x)[E], uint32_t& sc, uint32_t& kk) {
+  static_assert(!HALF || E == 1, "half waves hold at most 32 elements");
+  const uint32_t nu = du < 0 ? 0u : ((uint32_t)du < s.size ? (uint32_t)du : s.size);
+  const int l = lane_id();
+  const uint64_t hmask = HALF ? ((l & 32) ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull) : ~0ull;
+  const int base = HALF ? (l & 32) : 0;
+  const uint32_t le = (uint32_t)(l - base);
+  const uint64_t below = ((1ull << l) - 1ull) & hmask;
+  uint32_t com = 0, comk = 0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint32_t e = (uint32_t)(j * kWave) + le;
+    bool found = false;
+    uint32_t lo = 0;
+    if (e < nu) {
+      const uint64_t key = mh_key(s.a1, s.c1, x[j]);
+      uint32_t hi = nv;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (keys_v[mid] < key)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      found = lo < nv && keys_v[lo] == key;
+    }
+    const uint64_t fb = __ballot(found) & hmask;
+    const uint32_t before = com + (uint32_t)__popcll(fb & below);
+    const bool first_k = found && e + lo - before < s.size;
+    com += (uint32_t)__popcll(fb);
+    comk += (uint32_t)__popcll(__ballot(first_k) & hmask);
+  }
+  if (s.est == PG_EST_MH_1HASH_LITERAL) {
+    sc = com;
+    kk = s.size;
+    return;
+  }
+  const uint32_t uni = nu + nv - com;
+  kk = uni < s.size ? uni : s.size;
+  sc = uni >= s.size ? comk : com;
+}
+
+// The ratio estimate s/kk -> J/(1+J)(d_u + d_v) is FP64 work with divisions
+// that every lane of the wave would repeat for every pair. Instead the pairs a
+// wave evaluates are numbered in order; lane q mod 64 keeps the counts of
+// pair q, and after every 64 pairs all lanes map their counts at once. Each
+// estimate is the per-pair path's value; each lane adds its estimates in pair
+// order and the lanes' sums meet in a fixed butterfly, so the total does not
+// depend on scheduling.
+struct OhDeferred {
+  uint32_t s = 0, kk = 0;
+  int32_t du = 0, dv = 0;
+  bool has = false;
+  double acc = 0.0;
+  __device__ __forceinline__ void flush() {
+    if (has) acc += minhash_estimate(s, kk, du, dv);
+    has = false;
+  }
+  __device__ __forceinline__ void put(uint32_t q, uint32_t s_, uint32_t kk_, int32_t du_, int32_t dv_) {
+    if ((uint32_t)lane_id() == (q & 63u)) {
+      s = s_;
+      kk = kk_;
+      du = du_;
+      dv = dv_;
+      has = true;
+    }
+    if ((q & 63u) == 63u) flush();
+  }
+  __device__ __forceinline__ double total() {
+    flush();
+    return group_sum<kWave>(acc);
+  }
+};
+
 // Sum of the estimates of (v, adj[p]) over p in [beg, end), one wave. For
 // k <= 32 the two halves of the wave take neighbours p and p + 1 side by side;
 // the result is then the sum of the two halves' sums, the same in every lane.
@@ -526,7 +606,9 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int l = lane_id();
-  double acc = 0.0;
+  double acc = 0.0;     // KMV: the same in every lane (of the half)
+  OhDeferred df;        // ratio estimators: deferred estimates
+  uint32_t q = 0;       // pairs evaluated so far (the same in every lane)
   if constexpr (HALF) {  // k <= 32 (the launch checks it): a separate kernel, so the wave-per-pair loop keeps its registers
     static_assert(E == 1, "half waves hold at most 32 elements");
     {
@@ -545,11 +627,22 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
         }
 #pragma unroll
         for (int t = 0; t < kOhHalfAhead; ++t) {
-          const double est = oh_wave_estimate<1, true, KMV>(s, keys, nv, dv, du[t], x[t]);
-          if (du[t] >= 0) acc += est;
+          if constexpr (KMV) {
+            const double est = oh_wave_estimate<1, true, KMV>(s, keys, nv, dv, du[t], x[t]);
+            if (du[t] >= 0) acc += est;
+          } else {
+            uint32_t sc, kk;
+            oh_wave_ratio_counts<1, true>(s, keys, nv, du[t], x[t], sc, kk);
+            const int32_t du0 = __shfl(du[t], 0), du1 = __shfl(du[t], kWave / 2);
+            const uint32_t s0 = (uint32_t)__shfl((int)sc, 0), k0 = (uint32_t)__shfl((int)kk, 0);
+            const uint32_t s1 = (uint32_t)__shfl((int)sc, kWave / 2), k1 = (uint32_t)__shfl((int)kk, kWave / 2);
+            if (du0 >= 0) df.put(q++, s0, k0, du0, dv);
+            if (du1 >= 0) df.put(q++, s1, k1, du1, dv);
+          }
         }
       }
-      return __shfl(acc, 0) + __shfl(acc, kWave / 2);
+      if constexpr (KMV) return __shfl(acc, 0) + __shfl(acc, kWave / 2);
+      return df.total();
     }
   } else {
   // kOhAhead neighbours at a time: their degrees and rows are loaded before
@@ -570,10 +663,19 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
       }
     }
 #pragma unroll
-    for (int t = 0; t < kOhAhead; ++t)
-      if (du[t] >= 0) acc += oh_wave_estimate<E, false, KMV>(s, keys, nv, dv, du[t], x[t]);
+    for (int t = 0; t < kOhAhead; ++t) {
+      if (du[t] < 0) continue;
+      if constexpr (KMV) {
+        acc += oh_wave_estimate<E, false, KMV>(s, keys, nv, dv, du[t], x[t]);
+      } else {
+        uint32_t sc, kk;
+        oh_wave_ratio_counts<E, false>(s, keys, nv, du[t], x[t], sc, kk);
+        df.put(q++, sc, kk, du[t], dv);
+      }
+    }
   }
-  return acc;
+  if constexpr (KMV) return acc;
+  return df.total();
   }
 }
 

@@ -134,6 +134,7 @@ struct pg_server {
   std::condition_variable work_cv;  // engine: new requests or stop
   std::condition_variable done_cv;  // collectors: requests finished or collected
   std::deque<pg::Request*> queue;
+  std::atomic<int64_t> queued{0};  // queue.size(), readable without the lock
   std::unordered_map<uint64_t, pg::Request*> live;
   std::vector<pg::Slot> slots;
   std::thread engine;
@@ -224,60 +225,79 @@ int launch_batch(pg_server* srv, Slot& sl) {
 
 void engine_loop(pg_server* srv) {
   (void)hipSetDevice(srv->ctx->device);
-  std::unique_lock<std::mutex> lk(srv->mu);
+  const int nslots = (int)srv->slots.size();
+  std::vector<Slot*> done, start;
+  std::vector<hipError_t> done_status;
   for (;;) {
-    bool progressed = false;
-    // retire finished batches: their answers are in the arena
+    // poll the batches on the device without the lock: only this thread
+    // touches the slots while they are busy
+    done.clear();
+    done_status.clear();
+    int busy = 0;
     for (Slot& sl : srv->slots) {
       if (!sl.busy) continue;
       const hipError_t q = hipEventQuery(sl.event);
-      if (q == hipErrorNotReady) continue;
-      if (q != hipSuccess && srv->engine_error == PG_OK) {
-        srv->engine_error = PG_E_DEVICE;
-        srv->engine_msg = std::string("serving batch: ") + hipGetErrorString(q);
+      if (q == hipErrorNotReady) {
+        ++busy;
+        continue;
       }
-      for (Request* r : sl.reqs) r->state = kFinished;
-      sl.reqs.clear();
-      sl.busy = false;
-      progressed = true;
-      srv->done_cv.notify_all();
+      done.push_back(&sl);
+      done_status.push_back(q);
     }
-    // start batches on free slots; the launch itself runs outside the lock
-    for (Slot& sl : srv->slots) {
-      if (sl.busy || srv->queue.empty()) continue;
-      int64_t total = 0;
-      while (!srv->queue.empty() && (int)sl.reqs.size() < kMaxSegments &&
-             total + srv->queue.front()->npairs <= srv->p.max_batch_pairs) {
-        Request* r = srv->queue.front();
-        srv->queue.pop_front();
-        total += r->npairs;
-        sl.reqs.push_back(r);
-      }
-      if (sl.reqs.empty()) continue;
-      sl.busy = true;
-      srv->stats.batches++;
-      progressed = true;
-      lk.unlock();
-      const int rc = launch_batch(srv, sl);
-      const std::string msg = rc != PG_OK ? std::string(pg_last_error()) : std::string();
-      lk.lock();
-      if (rc != PG_OK && srv->engine_error == PG_OK) {
-        srv->engine_error = rc;
-        srv->engine_msg = msg;
-      }
-    }
-    const uint64_t busy =
-        (uint64_t)std::count_if(srv->slots.begin(), srv->slots.end(), [](const Slot& s) { return s.busy; });
-    srv->stats.max_in_flight = std::max(srv->stats.max_in_flight, busy);
-    if (srv->stop && busy == 0 && srv->queue.empty()) break;
-    if (!progressed) {
-      if (busy > 0) {
-        // a batch is on the device: poll again shortly
-        lk.unlock();
+    if (done.empty() && (busy == nslots || srv->queued.load(std::memory_order_acquire) == 0)) {
+      if (busy > 0) {  // a batch is on the device: poll again shortly
         std::this_thread::yield();
-        lk.lock();
-      } else {
-        srv->work_cv.wait(lk, [&] { return srv->stop || !srv->queue.empty(); });
+        continue;
+      }
+      std::unique_lock<std::mutex> lk(srv->mu);
+      if (srv->stop && srv->queue.empty()) break;
+      srv->work_cv.wait(lk, [&] { return srv->stop || !srv->queue.empty(); });
+      continue;
+    }
+    start.clear();
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      // retire finished batches: their answers are in the arena
+      for (size_t i = 0; i < done.size(); ++i) {
+        if (done_status[i] != hipSuccess && srv->engine_error == PG_OK) {
+          srv->engine_error = PG_E_DEVICE;
+          srv->engine_msg = std::string("serving batch: ") + hipGetErrorString(done_status[i]);
+        }
+        for (Request* r : done[i]->reqs) r->state = kFinished;
+        done[i]->reqs.clear();
+        done[i]->busy = false;
+      }
+      if (!done.empty()) srv->done_cv.notify_all();
+      // fill free slots from the queue
+      for (Slot& sl : srv->slots) {
+        if (sl.busy || srv->queue.empty()) continue;
+        int64_t total = 0;
+        while (!srv->queue.empty() && (int)sl.reqs.size() < kMaxSegments &&
+               total + srv->queue.front()->npairs <= srv->p.max_batch_pairs) {
+          Request* r = srv->queue.front();
+          srv->queue.pop_front();
+          total += r->npairs;
+          sl.reqs.push_back(r);
+        }
+        if (sl.reqs.empty()) continue;
+        sl.busy = true;
+        srv->stats.batches++;
+        start.push_back(&sl);
+      }
+      srv->queued.store((int64_t)srv->queue.size(), std::memory_order_release);
+      const uint64_t inflight =
+          (uint64_t)std::count_if(srv->slots.begin(), srv->slots.end(), [](const Slot& s) { return s.busy; });
+      srv->stats.max_in_flight = std::max(srv->stats.max_in_flight, inflight);
+    }
+    // launches run outside the lock
+    for (Slot* sl : start) {
+      const int rc = launch_batch(srv, *sl);
+      if (rc != PG_OK) {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->engine_error == PG_OK) {
+          srv->engine_error = rc;
+          srv->engine_msg = pg_last_error();
+        }
       }
     }
   }
@@ -428,6 +448,7 @@ int pg_server_submit(pg_server* srv, const pg_request* req, uint64_t* ticket) {
     r->ticket = srv->next_ticket++;
     srv->live[r->ticket] = r;
     srv->queue.push_back(r);
+    srv->queued.store((int64_t)srv->queue.size(), std::memory_order_release);
     srv->stats.submitted++;
     *ticket = r->ticket;
   }
