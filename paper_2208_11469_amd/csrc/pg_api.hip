@@ -341,6 +341,10 @@ int make_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, uint
     if (rc == PG_OK && build && g->n > 0) rc = build_bf(sk, s);
   } else {
     if (rc == PG_OK) rc = palloc((void**)&sk->sig, sizeof(uint32_t) * size * n);
+    if (rc == PG_OK && kind == PG_MH_KHASH) {  // chunk partials of heavy vertices: k keys and k elements per chunk
+      const size_t slots = (size_t)size * (size_t)std::max<int64_t>(rows->plan_all.n_chunks, 1);
+      rc = palloc((void**)&sk->scratch, sizeof(uint64_t) * (slots + (slots + 1) / 2));
+    }
     if (rc == PG_OK && build && g->n > 0) rc = kind == PG_MH_KHASH ? build_khash(sk, s) : build_onehash(sk, s);
   }
   if (rc != PG_OK) {

@@ -219,19 +219,25 @@ __device__ __forceinline__ void min_pair_group(uint64_t& key, uint32_t& id) {
   }
 }
 
+// Vertices of one degree bin, G lanes each; vertices with more than max_deg
+// arcs are left to the chunked kernels below.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_kh_build(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
                                                      const int32_t* __restrict__ verts, int64_t nverts, uint32_t k,
                                                      const uint64_t* __restrict__ ha, const uint64_t* __restrict__ hc,
-                                                     uint32_t* __restrict__ sig) {
+                                                     uint32_t* __restrict__ sig, int64_t max_deg) {
   __shared__ uint64_t lkey[(G > kWave) ? (kBlock / kWave) * kKhBatch : 1];
   __shared__ uint32_t lid[(G > kWave) ? (kBlock / kWave) * kKhBatch : 1];
   const int64_t grp = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / G;
   const int lane = threadIdx.x % G;
-  const bool active = grp < nverts;
+  bool active = grp < nverts;
   const int32_t v = active ? verts[grp] : 0;
   const int64_t beg = active ? off[v] : 0;
-  const int64_t end = active ? off[v + 1] : 0;
+  int64_t end = active ? off[v + 1] : 0;
+  if (end - beg > max_deg) {  // chunked instead (the whole group skips it)
+    active = false;
+    end = beg;
+  }
   for (uint32_t i0 = 0; i0 < k; i0 += kKhBatch) {
     uint64_t best[kKhBatch];
     uint32_t bid[kKhBatch];
@@ -292,6 +298,92 @@ __global__ __launch_bounds__(kBlock) void k_kh_build(const int32_t* __restrict__
         if (i0 + j < k && (j % G) == lane) row[i0 + j] = bid[j];
     }
   }
+}
+
+// Heavy vertices (more than kMediumMax arcs), split into the work plan's
+// chunks of kHeavyChunk arcs, one block per chunk: the chunk's argmin of every
+// hash function, (key, element) per hash into the partials. One block per
+// vertex let the largest hub set the length of the whole build.
+__global__ __launch_bounds__(kBlock) void k_kh_build_chunks(PlanView P, const int32_t* __restrict__ adj, uint32_t k,
+                                                            const uint64_t* __restrict__ ha,
+                                                            const uint64_t* __restrict__ hc,
+                                                            uint64_t* __restrict__ part_key,
+                                                            uint32_t* __restrict__ part_id) {
+  __shared__ uint64_t lkey[(kBlock / kWave) * kKhBatch];
+  __shared__ uint32_t lid[(kBlock / kWave) * kKhBatch];
+  const int64_t c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t beg = P.chunk_begin[c], end = P.chunk_end[c];
+  for (uint32_t i0 = 0; i0 < k; i0 += kKhBatch) {
+    uint64_t best[kKhBatch];
+    uint32_t bid[kKhBatch];
+#pragma unroll
+    for (int j = 0; j < kKhBatch; ++j) {
+      best[j] = ~0ull;
+      bid[j] = kBottom;
+    }
+    for (int64_t p = beg + tid; p < end; p += kBlock) {
+      const uint32_t x = (uint32_t)adj[p];
+#pragma unroll
+      for (int j = 0; j < kKhBatch; ++j) {
+        if (i0 + j < k) {
+          const uint64_t key = mh_key(ha[i0 + j], hc[i0 + j], x);
+          if (key < best[j] || (key == best[j] && x < bid[j])) {
+            best[j] = key;
+            bid[j] = x;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kKhBatch; ++j) min_pair_group<kWave>(best[j], bid[j]);
+    const int wv = tid / kWave;
+    if (lane_id() == 0) {
+#pragma unroll
+      for (int j = 0; j < kKhBatch; ++j) {
+        lkey[wv * kKhBatch + j] = best[j];
+        lid[wv * kKhBatch + j] = bid[j];
+      }
+    }
+    __syncthreads();
+    if (tid < kKhBatch && i0 + tid < k) {
+      uint64_t bk = lkey[tid];
+      uint32_t bi = lid[tid];
+      for (int w = 1; w < kBlock / kWave; ++w) {
+        const uint64_t ok = lkey[w * kKhBatch + tid];
+        const uint32_t oi = lid[w * kKhBatch + tid];
+        if (ok < bk || (ok == bk && oi < bi)) {
+          bk = ok;
+          bi = oi;
+        }
+      }
+      part_key[c * (int64_t)k + i0 + tid] = bk;
+      part_id[c * (int64_t)k + i0 + tid] = bi;
+    }
+    __syncthreads();
+  }
+}
+
+// Slot i of heavy vertex h: the least (key, element) over its chunks. The
+// minimum does not depend on the order of the chunks.
+__global__ void k_kh_combine(PlanView P, int64_t n_heavy, uint32_t k, const uint64_t* __restrict__ part_key,
+                             const uint32_t* __restrict__ part_id, uint32_t* __restrict__ sig) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n_heavy * (int64_t)k) return;
+  const int64_t h = t / k;
+  const uint32_t i = (uint32_t)(t % k);
+  const int32_t c0 = P.heavy_first[h], c1 = P.heavy_first[h + 1];
+  uint64_t best = ~0ull;
+  uint32_t bid = kBottom;
+  for (int32_t c = c0; c < c1; ++c) {
+    const uint64_t key = part_key[(int64_t)c * k + i];
+    const uint32_t id = part_id[(int64_t)c * k + i];
+    if (key < best || (key == best && id < bid)) {
+      best = key;
+      bid = id;
+    }
+  }
+  sig[(size_t)P.chunk_vertex[c0] * k + i] = bid;
 }
 
 // ---------------------------------------------------------------- 1-hash
@@ -619,24 +711,37 @@ int build_bf(pg_sketches* sk, hipStream_t s) {
 int build_khash(pg_sketches* sk, hipStream_t s) {
   const pg_graph* g = sk->rows;  // the lists the rows sketch (N_v or N+_v)
   ProfScope ps(s, "kh_build");
+  const VertexPlan& P = g->plan_all;
+  // vertices up to kMediumMax arcs by degree bin; the heavier ones in chunks
   for (int bin = 0; bin < kNumBins; ++bin) {
     const int64_t cnt = g->bin_start[bin + 1] - g->bin_start[bin];
     if (cnt <= 0) continue;
+    if (bin > 0 && kBinMaxDeg[bin - 1] >= kMediumMax) continue;  // every vertex of the bin is heavy
     const int32_t* verts = g->bin_verts + g->bin_start[bin];
-    const int G = kBinGroup[bin];
+    const int G = std::min(kBinGroup[bin], kWave);
     const unsigned grid = (unsigned)((cnt * G + kBlock - 1) / kBlock);
+    const int64_t max_deg = kMediumMax;
     if (G == 4)
       hipLaunchKernelGGL(k_kh_build<4>, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, verts, cnt, sk->size, sk->ha,
-                         sk->hc, sk->sig);
+                         sk->hc, sk->sig, max_deg);
     else if (G == 16)
       hipLaunchKernelGGL(k_kh_build<16>, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, verts, cnt, sk->size, sk->ha,
-                         sk->hc, sk->sig);
-    else if (G == 64)
-      hipLaunchKernelGGL(k_kh_build<64>, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, verts, cnt, sk->size, sk->ha,
-                         sk->hc, sk->sig);
+                         sk->hc, sk->sig, max_deg);
     else
-      hipLaunchKernelGGL(k_kh_build<256>, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, verts, cnt, sk->size,
-                         sk->ha, sk->hc, sk->sig);
+      hipLaunchKernelGGL(k_kh_build<64>, dim3(grid), dim3(kBlock), 0, s, g->off, g->adj, verts, cnt, sk->size, sk->ha,
+                         sk->hc, sk->sig, max_deg);
+    PG_LAUNCH_CHECK();
+  }
+  if (P.n_chunks > 0) {
+    const PlanView pv = plan_view(P);
+    uint64_t* part_key = sk->scratch;
+    uint32_t* part_id = reinterpret_cast<uint32_t*>(sk->scratch + P.n_chunks * (int64_t)sk->size);
+    hipLaunchKernelGGL(k_kh_build_chunks, dim3((unsigned)P.n_chunks), dim3(kBlock), 0, s, pv, g->adj, sk->size, sk->ha,
+                       sk->hc, part_key, part_id);
+    PG_LAUNCH_CHECK();
+    const int64_t t = P.n_heavy * (int64_t)sk->size;
+    hipLaunchKernelGGL(k_kh_combine, dim3((unsigned)((t + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pv, P.n_heavy,
+                       sk->size, (const uint64_t*)part_key, (const uint32_t*)part_id, sk->sig);
     PG_LAUNCH_CHECK();
   }
   return PG_OK;

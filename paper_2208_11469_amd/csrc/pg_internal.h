@@ -244,7 +244,8 @@ struct pg_sketches {
   uint64_t* hc = nullptr;     // device hash increments
   double* table = nullptr;    // [kBfTables * (B+1)] estimator tables (Bloom filters), one per estimator
   bool empty_rows_zero = false;  // Bloom filters: the rows of vertices without arcs are known to be zero
-  uint64_t* scratch = nullptr;    // partial rows of heavy chunks (plan_all.n_chunks * W words)
+  uint64_t* scratch = nullptr;    // heavy-chunk partials: Bloom-filter rows (n_chunks * W words) or
+                                  // k-hash (key, element) pairs (n_chunks * k keys, then n_chunks * k uint32)
 };
 
 namespace pg {
