@@ -41,6 +41,13 @@ namespace {
 constexpr int kMaxSegments = 1024;  // requests per batch
 constexpr int kEstSlots = 8;        // view slots per sketch set, indexed by estimator id
 constexpr int kArgSegments = 16;    // segment tables this small travel as kernel arguments
+// While a batch is on the device, the next one starts only once the queue
+// holds this many pairs (at most half a batch) or its oldest request has
+// waited this long: each launch costs the engine thread a few microseconds,
+// so under load requests gather into fewer, larger batches, and with the GPU
+// idle a request starts at once.
+constexpr int64_t kBusyBatchPairs = 1 << 18;
+constexpr int64_t kMaxQueueWaitNs = 50000;
 
 struct SegDesc {
   int64_t begin;  // first pair of the segment in the batch
@@ -92,6 +99,9 @@ __global__ __launch_bounds__(256) void k_serve_batch(const SkView* __restrict__ 
 }
 
 using Clock = std::chrono::steady_clock;
+inline int64_t to_ns(Clock::time_point t) {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(t.time_since_epoch()).count();
+}
 
 enum State { kQueued = 0, kFinished = 1, kCollecting = 2, kCollected = 3 };
 
@@ -134,7 +144,9 @@ struct pg_server {
   std::condition_variable work_cv;  // engine: new requests or stop
   std::condition_variable done_cv;  // collectors: requests finished or collected
   std::deque<pg::Request*> queue;
-  std::atomic<int64_t> queued{0};  // queue.size(), readable without the lock
+  std::atomic<int64_t> queued{0};        // queue.size(), readable without the lock
+  std::atomic<int64_t> queued_pairs{0};  // pairs of the queued requests
+  std::atomic<int64_t> front_ns{0};      // submit time of the oldest queued request (steady clock, ns)
   std::unordered_map<uint64_t, pg::Request*> live;
   std::vector<pg::Slot> slots;
   std::thread engine;
@@ -244,7 +256,14 @@ void engine_loop(pg_server* srv) {
       done.push_back(&sl);
       done_status.push_back(q);
     }
-    if (done.empty() && (busy == nslots || srv->queued.load(std::memory_order_acquire) == 0)) {
+    const int64_t min_pairs = std::min<int64_t>(kBusyBatchPairs, srv->p.max_batch_pairs / 2);
+    auto ready_to_launch = [&](int inflight) {
+      if (srv->queued.load(std::memory_order_acquire) == 0) return false;
+      if (inflight == 0 || srv->queued_pairs.load(std::memory_order_acquire) >= min_pairs) return true;
+      const int64_t now = std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now().time_since_epoch()).count();
+      return now - srv->front_ns.load(std::memory_order_acquire) >= kMaxQueueWaitNs;
+    };
+    if (done.empty() && (busy == nslots || !ready_to_launch(busy))) {
       if (busy > 0) {  // a batch is on the device: poll again shortly
         std::this_thread::yield();
         continue;
@@ -268,9 +287,13 @@ void engine_loop(pg_server* srv) {
         done[i]->busy = false;
       }
       if (!done.empty()) srv->done_cv.notify_all();
-      // fill free slots from the queue
+      // fill free slots from the queue (while batches run, only a queue that
+      // is large or old enough starts another)
+      int inflight = 0;
+      for (const Slot& sl : srv->slots) inflight += sl.busy ? 1 : 0;
       for (Slot& sl : srv->slots) {
         if (sl.busy || srv->queue.empty()) continue;
+        if (!ready_to_launch(inflight)) break;
         int64_t total = 0;
         while (!srv->queue.empty() && (int)sl.reqs.size() < kMaxSegments &&
                total + srv->queue.front()->npairs <= srv->p.max_batch_pairs) {
@@ -281,13 +304,14 @@ void engine_loop(pg_server* srv) {
         }
         if (sl.reqs.empty()) continue;
         sl.busy = true;
+        ++inflight;
         srv->stats.batches++;
+        srv->queued_pairs.fetch_sub(total, std::memory_order_acq_rel);
+        srv->queued.store((int64_t)srv->queue.size(), std::memory_order_release);
+        if (!srv->queue.empty()) srv->front_ns.store(to_ns(srv->queue.front()->t_submit), std::memory_order_release);
         start.push_back(&sl);
       }
-      srv->queued.store((int64_t)srv->queue.size(), std::memory_order_release);
-      const uint64_t inflight =
-          (uint64_t)std::count_if(srv->slots.begin(), srv->slots.end(), [](const Slot& s) { return s.busy; });
-      srv->stats.max_in_flight = std::max(srv->stats.max_in_flight, inflight);
+      srv->stats.max_in_flight = std::max(srv->stats.max_in_flight, (uint64_t)inflight);
     }
     // launches run outside the lock
     for (Slot* sl : start) {
@@ -448,6 +472,8 @@ int pg_server_submit(pg_server* srv, const pg_request* req, uint64_t* ticket) {
     r->ticket = srv->next_ticket++;
     srv->live[r->ticket] = r;
     srv->queue.push_back(r);
+    if (srv->queue.size() == 1) srv->front_ns.store(to_ns(r->t_submit), std::memory_order_release);
+    srv->queued_pairs.fetch_add(r->npairs, std::memory_order_acq_rel);
     srv->queued.store((int64_t)srv->queue.size(), std::memory_order_release);
     srv->stats.submitted++;
     *ticket = r->ticket;
