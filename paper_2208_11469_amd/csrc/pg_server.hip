@@ -15,6 +15,12 @@
 // launch. The thread that collects a request (wait, or the poll that first
 // sees it finished) copies its answers into the request's output buffer and
 // returns the range to the arena.
+//
+// Synchronisation is split so that client threads rarely meet: submitted
+// requests reach the engine through a lock-free stack that it empties in one
+// exchange (the engine's queue is its own); the arena, the ticket table
+// (sharded), the finished/collected states and the engine's sleep each have
+// their own lock.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -112,7 +118,8 @@ struct Request {
   int64_t arena = 0;  // first pair slot
   void* out = nullptr;
   Clock::time_point t_submit, t_collected;
-  int state = kQueued;
+  std::atomic<int> state{kQueued};
+  Request* next = nullptr;  // link in the submission stack
 };
 
 struct Slot {
@@ -122,6 +129,12 @@ struct Slot {
   SegDesc* d_seg = nullptr;
   std::vector<Request*> reqs;
   bool busy = false;
+};
+
+constexpr int kShards = 16;  // ticket table shards
+struct TicketShard {
+  std::mutex mu;
+  std::unordered_map<uint64_t, Request*> map;
 };
 
 }  // namespace
@@ -139,23 +152,26 @@ struct pg_server {
   int32_t* a_u = nullptr;
   int32_t* a_v = nullptr;
   double* a_out = nullptr;
+  std::mutex arena_mu;                     // guards free_ranges and bytes_admitted
   std::map<int64_t, int64_t> free_ranges;  // first slot -> length, disjoint and not adjacent
-  std::mutex mu;
-  std::condition_variable work_cv;  // engine: new requests or stop
-  std::condition_variable done_cv;  // collectors: requests finished or collected
-  std::deque<pg::Request*> queue;
-  std::atomic<int64_t> queued{0};        // queue.size(), readable without the lock
-  std::atomic<int64_t> queued_pairs{0};  // pairs of the queued requests
-  std::atomic<int64_t> front_ns{0};      // submit time of the oldest queued request (steady clock, ns)
-  std::unordered_map<uint64_t, pg::Request*> live;
+  uint64_t bytes_admitted = 0;
+  std::atomic<pg::Request*> inbox{nullptr};  // submitted requests the engine has not taken yet (a stack)
+  std::mutex work_mu;                        // the engine's sleep
+  std::condition_variable work_cv;
+  std::atomic<bool> engine_sleeping{false};
+  std::mutex done_mu;                 // state changes waiters wait for
+  std::condition_variable done_cv;    // a request finished (its answers are in the arena)
+  std::condition_variable taken_cv;   // a request was collected
+  pg::TicketShard tickets[pg::kShards];
+  std::atomic<uint64_t> next_ticket{1};
   std::vector<pg::Slot> slots;
   std::thread engine;
-  bool stop = false;
-  int engine_error = PG_OK;
+  std::atomic<bool> stop{false};
+  std::atomic<int> engine_error{PG_OK};
+  std::mutex err_mu;
   std::string engine_msg;
-  uint64_t next_ticket = 1;
-  uint64_t bytes_admitted = 0;
-  pg_server_stats stats{};
+  std::atomic<uint64_t> st_submitted{0}, st_rejected_busy{0}, st_rejected_invalid{0}, st_completed{0},
+      st_batches{0}, st_pairs{0}, st_max_in_flight{0};
 };
 
 namespace pg {
@@ -163,7 +179,7 @@ namespace {
 
 constexpr uint64_t kBytesPerPair = 16;
 
-// First-fit range of `len` free slots; -1 if none. Caller holds srv->mu.
+// First-fit range of `len` free slots; -1 if none. Caller holds srv->arena_mu.
 int64_t arena_take(pg_server* srv, int64_t len) {
   for (auto it = srv->free_ranges.begin(); it != srv->free_ranges.end(); ++it) {
     if (it->second < len) continue;
@@ -175,7 +191,7 @@ int64_t arena_take(pg_server* srv, int64_t len) {
   return -1;
 }
 
-// Return [at, at + len) to the arena, merging with free neighbours. Caller holds srv->mu.
+// Return [at, at + len) to the arena, merging with free neighbours. Caller holds srv->arena_mu.
 void arena_give(pg_server* srv, int64_t at, int64_t len) {
   auto next = srv->free_ranges.lower_bound(at);
   if (next != srv->free_ranges.end() && next->first == at + len) {
@@ -190,6 +206,21 @@ void arena_give(pg_server* srv, int64_t at, int64_t len) {
     }
   }
   srv->free_ranges.emplace(at, len);
+}
+
+TicketShard& shard_of(pg_server* srv, uint64_t ticket) { return srv->tickets[ticket % kShards]; }
+
+void set_engine_error(pg_server* srv, int code, const std::string& msg) {
+  std::lock_guard<std::mutex> lk(srv->err_mu);
+  if (srv->engine_error.load() == PG_OK) {
+    srv->engine_msg = msg;
+    srv->engine_error.store(code);
+  }
+}
+
+int engine_failure(pg_server* srv) {
+  std::lock_guard<std::mutex> lk(srv->err_mu);
+  return fail(srv->engine_error.load(), srv->engine_msg);
 }
 
 int slot_init(Slot& sl) {
@@ -237,113 +268,129 @@ int launch_batch(pg_server* srv, Slot& sl) {
 
 void engine_loop(pg_server* srv) {
   (void)hipSetDevice(srv->ctx->device);
-  const int nslots = (int)srv->slots.size();
-  std::vector<Slot*> done, start;
+  std::deque<Request*> queue;  // the engine's own: submission order
+  int64_t queued_pairs = 0;
+  std::vector<Request*> taken;
+  std::vector<Slot*> done;
   std::vector<hipError_t> done_status;
+  const int64_t min_pairs = std::min<int64_t>(kBusyBatchPairs, srv->p.max_batch_pairs / 2);
   for (;;) {
-    // poll the batches on the device without the lock: only this thread
-    // touches the slots while they are busy
+    // new submissions: the stack holds them newest first
+    if (Request* list = srv->inbox.exchange(nullptr, std::memory_order_acq_rel)) {
+      taken.clear();
+      for (Request* r = list; r; r = r->next) taken.push_back(r);
+      for (auto it = taken.rbegin(); it != taken.rend(); ++it) {
+        queue.push_back(*it);
+        queued_pairs += (*it)->npairs;
+      }
+    }
+    // batches on the device
     done.clear();
     done_status.clear();
-    int busy = 0;
+    int inflight = 0;
     for (Slot& sl : srv->slots) {
       if (!sl.busy) continue;
       const hipError_t q = hipEventQuery(sl.event);
       if (q == hipErrorNotReady) {
-        ++busy;
+        ++inflight;
         continue;
       }
       done.push_back(&sl);
       done_status.push_back(q);
     }
-    const int64_t min_pairs = std::min<int64_t>(kBusyBatchPairs, srv->p.max_batch_pairs / 2);
-    auto ready_to_launch = [&](int inflight) {
-      if (srv->queued.load(std::memory_order_acquire) == 0) return false;
-      if (inflight == 0 || srv->queued_pairs.load(std::memory_order_acquire) >= min_pairs) return true;
-      const int64_t now = std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now().time_since_epoch()).count();
-      return now - srv->front_ns.load(std::memory_order_acquire) >= kMaxQueueWaitNs;
-    };
-    if (done.empty() && (busy == nslots || !ready_to_launch(busy))) {
-      if (busy > 0) {  // a batch is on the device: poll again shortly
-        std::this_thread::yield();
-        continue;
+    if (!done.empty()) {  // retire: their answers are in the arena
+      {
+        std::lock_guard<std::mutex> lk(srv->done_mu);
+        for (size_t i = 0; i < done.size(); ++i) {
+          if (done_status[i] != hipSuccess)
+            set_engine_error(srv, PG_E_DEVICE, std::string("serving batch: ") + hipGetErrorString(done_status[i]));
+          for (Request* r : done[i]->reqs) r->state.store(kFinished, std::memory_order_release);
+          done[i]->reqs.clear();
+          done[i]->busy = false;
+        }
       }
-      std::unique_lock<std::mutex> lk(srv->mu);
-      if (srv->stop && srv->queue.empty()) break;
-      srv->work_cv.wait(lk, [&] { return srv->stop || !srv->queue.empty(); });
+      srv->done_cv.notify_all();
+    }
+    // start batches on free slots: at once when the GPU is idle; while batches
+    // run, once the queue is large or old enough
+    bool launched = false;
+    for (Slot& sl : srv->slots) {
+      if (sl.busy || queue.empty()) continue;
+      const bool ready = inflight == 0 || queued_pairs >= min_pairs ||
+                         to_ns(Clock::now()) - to_ns(queue.front()->t_submit) >= kMaxQueueWaitNs;
+      if (!ready) break;
+      int64_t total = 0;
+      while (!queue.empty() && (int)sl.reqs.size() < kMaxSegments &&
+             total + queue.front()->npairs <= srv->p.max_batch_pairs) {
+        Request* r = queue.front();
+        queue.pop_front();
+        total += r->npairs;
+        sl.reqs.push_back(r);
+      }
+      queued_pairs -= total;
+      sl.busy = true;
+      ++inflight;
+      launched = true;
+      srv->st_batches.fetch_add(1, std::memory_order_relaxed);
+      const int rc = launch_batch(srv, sl);
+      if (rc != PG_OK) set_engine_error(srv, rc, pg_last_error());
+    }
+    uint64_t seen = srv->st_max_in_flight.load(std::memory_order_relaxed);
+    while ((uint64_t)inflight > seen &&
+           !srv->st_max_in_flight.compare_exchange_weak(seen, (uint64_t)inflight, std::memory_order_relaxed)) {
+    }
+    if (!done.empty() || launched) continue;
+    if (inflight > 0 || !queue.empty()) {  // a batch is on the device, or the queue waits to grow
+      std::this_thread::yield();
       continue;
     }
-    start.clear();
-    {
-      std::lock_guard<std::mutex> lk(srv->mu);
-      // retire finished batches: their answers are in the arena
-      for (size_t i = 0; i < done.size(); ++i) {
-        if (done_status[i] != hipSuccess && srv->engine_error == PG_OK) {
-          srv->engine_error = PG_E_DEVICE;
-          srv->engine_msg = std::string("serving batch: ") + hipGetErrorString(done_status[i]);
-        }
-        for (Request* r : done[i]->reqs) r->state = kFinished;
-        done[i]->reqs.clear();
-        done[i]->busy = false;
-      }
-      if (!done.empty()) srv->done_cv.notify_all();
-      // fill free slots from the queue (while batches run, only a queue that
-      // is large or old enough starts another)
-      int inflight = 0;
-      for (const Slot& sl : srv->slots) inflight += sl.busy ? 1 : 0;
-      for (Slot& sl : srv->slots) {
-        if (sl.busy || srv->queue.empty()) continue;
-        if (!ready_to_launch(inflight)) break;
-        int64_t total = 0;
-        while (!srv->queue.empty() && (int)sl.reqs.size() < kMaxSegments &&
-               total + srv->queue.front()->npairs <= srv->p.max_batch_pairs) {
-          Request* r = srv->queue.front();
-          srv->queue.pop_front();
-          total += r->npairs;
-          sl.reqs.push_back(r);
-        }
-        if (sl.reqs.empty()) continue;
-        sl.busy = true;
-        ++inflight;
-        srv->stats.batches++;
-        srv->queued_pairs.fetch_sub(total, std::memory_order_acq_rel);
-        srv->queued.store((int64_t)srv->queue.size(), std::memory_order_release);
-        if (!srv->queue.empty()) srv->front_ns.store(to_ns(srv->queue.front()->t_submit), std::memory_order_release);
-        start.push_back(&sl);
-      }
-      srv->stats.max_in_flight = std::max(srv->stats.max_in_flight, (uint64_t)inflight);
-    }
-    // launches run outside the lock
-    for (Slot* sl : start) {
-      const int rc = launch_batch(srv, *sl);
-      if (rc != PG_OK) {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        if (srv->engine_error == PG_OK) {
-          srv->engine_error = rc;
-          srv->engine_msg = pg_last_error();
-        }
-      }
-    }
+    // idle: sleep until a submission or the stop
+    std::unique_lock<std::mutex> lk(srv->work_mu);
+    if (srv->stop.load() && srv->inbox.load() == nullptr) break;
+    srv->engine_sleeping.store(true);
+    srv->work_cv.wait(lk, [&] { return srv->stop.load() || srv->inbox.load() != nullptr; });
+    srv->engine_sleeping.store(false);
   }
 }
 
 // Copy a finished request's answers from the arena into its output buffer and
-// return its range. The caller set r->state = kCollecting under the lock and
-// does not hold it now; the range belongs to r alone until it is returned.
+// return its range. The caller moved r from kFinished to kCollecting; the
+// range belongs to r alone until it is returned.
 void collect(pg_server* srv, Request* r) {
   if (r->op == PG_OP_CN)
     std::memcpy(r->out, srv->a_out + r->arena, sizeof(double) * (size_t)r->npairs);
   else
     std::memcpy(r->out, srv->a_out + r->arena, sizeof(float) * (size_t)r->npairs);
-  const Clock::time_point now = Clock::now();
-  std::lock_guard<std::mutex> lk(srv->mu);
-  arena_give(srv, r->arena, r->npairs);
-  srv->bytes_admitted -= (uint64_t)r->npairs * kBytesPerPair;
-  srv->stats.completed++;
-  srv->stats.pairs += (uint64_t)r->npairs;
-  r->t_collected = now;
-  r->state = kCollected;
-  srv->done_cv.notify_all();
+  {
+    std::lock_guard<std::mutex> lk(srv->arena_mu);
+    arena_give(srv, r->arena, r->npairs);
+    srv->bytes_admitted -= (uint64_t)r->npairs * kBytesPerPair;
+  }
+  srv->st_completed.fetch_add(1, std::memory_order_relaxed);
+  srv->st_pairs.fetch_add((uint64_t)r->npairs, std::memory_order_relaxed);
+  {
+    std::lock_guard<std::mutex> lk(srv->done_mu);
+    r->t_collected = Clock::now();
+    r->state.store(kCollected, std::memory_order_release);
+  }
+  srv->taken_cv.notify_all();
+}
+
+// Collect r if it is finished and no other thread does, else wait until
+// whoever collects it is done (state kCollected). `wait_finish`: also wait
+// for the batch to finish first.
+void collect_or_wait(pg_server* srv, Request* r, bool wait_finish) {
+  if (wait_finish && r->state.load(std::memory_order_acquire) == kQueued) {
+    std::unique_lock<std::mutex> lk(srv->done_mu);
+    srv->done_cv.wait(lk, [&] { return r->state.load(std::memory_order_acquire) != kQueued; });
+  }
+  int expected = kFinished;
+  if (r->state.compare_exchange_strong(expected, kCollecting, std::memory_order_acq_rel)) {
+    collect(srv, r);
+  } else if (expected == kCollecting) {
+    std::unique_lock<std::mutex> lk(srv->done_mu);
+    srv->taken_cv.wait(lk, [&] { return r->state.load(std::memory_order_acquire) == kCollected; });
+  }
 }
 
 }  // namespace
@@ -426,8 +473,7 @@ int pg_server_submit(pg_server* srv, const pg_request* req, uint64_t* ticket) {
   clear_error();
   if (!srv || !req || !ticket) return fail(PG_E_INVALID, "NULL argument");
   auto invalid = [&](const char* why) {
-    std::lock_guard<std::mutex> lk(srv->mu);
-    srv->stats.rejected_invalid++;
+    srv->st_rejected_invalid.fetch_add(1, std::memory_order_relaxed);
     return fail(PG_E_INVALID, why);
   };
   if (req->op != PG_OP_CN && req->op != PG_OP_JACCARD) return invalid("unknown op");
@@ -443,23 +489,21 @@ int pg_server_submit(pg_server* srv, const pg_request* req, uint64_t* ticket) {
   uint32_t bad = 0;
   for (int64_t i = 0; i < L; ++i) bad |= (uint32_t)((uint32_t)req->u[i] >= n) | (uint32_t)((uint32_t)req->v[i] >= n);
   if (bad) return invalid("vertex ID out of range");
+  if (srv->stop.load()) return fail(PG_E_INVALID, "server is stopping");
+  if (srv->engine_error.load() != PG_OK) return engine_failure(srv);
   Request* r = new (std::nothrow) Request();
   if (!r) return fail(PG_E_NOMEM, "host allocation failed");
   {
-    std::lock_guard<std::mutex> lk(srv->mu);
-    if (srv->engine_error != PG_OK || srv->stop) {
-      delete r;
-      return srv->stop ? fail(PG_E_INVALID, "server is stopping") : fail(srv->engine_error, srv->engine_msg);
-    }
+    std::lock_guard<std::mutex> lk(srv->arena_mu);
     r->arena = arena_take(srv, L);
-    if (r->arena < 0) {
-      srv->stats.rejected_busy++;
-      delete r;
-      return fail(PG_E_BUSY, "not admitted: no free range of the memory budget");
-    }
-    srv->bytes_admitted += (uint64_t)L * kBytesPerPair;
+    if (r->arena >= 0) srv->bytes_admitted += (uint64_t)L * kBytesPerPair;
   }
-  // the range is this request's alone: write its pairs without the lock
+  if (r->arena < 0) {
+    srv->st_rejected_busy.fetch_add(1, std::memory_order_relaxed);
+    delete r;
+    return fail(PG_E_BUSY, "not admitted: no free range of the memory budget");
+  }
+  // the range is this request's alone: write its pairs without a lock
   std::memcpy(srv->a_u + r->arena, req->u, sizeof(int32_t) * (size_t)L);
   std::memcpy(srv->a_v + r->arena, req->v, sizeof(int32_t) * (size_t)L);
   r->op = req->op;
@@ -467,72 +511,69 @@ int pg_server_submit(pg_server* srv, const pg_request* req, uint64_t* ticket) {
   r->npairs = L;
   r->out = req->out;
   r->t_submit = Clock::now();
+  r->ticket = srv->next_ticket.fetch_add(1, std::memory_order_relaxed);
   {
-    std::lock_guard<std::mutex> lk(srv->mu);
-    r->ticket = srv->next_ticket++;
-    srv->live[r->ticket] = r;
-    srv->queue.push_back(r);
-    if (srv->queue.size() == 1) srv->front_ns.store(to_ns(r->t_submit), std::memory_order_release);
-    srv->queued_pairs.fetch_add(r->npairs, std::memory_order_acq_rel);
-    srv->queued.store((int64_t)srv->queue.size(), std::memory_order_release);
-    srv->stats.submitted++;
-    *ticket = r->ticket;
+    TicketShard& sh = shard_of(srv, r->ticket);
+    std::lock_guard<std::mutex> lk(sh.mu);
+    sh.map[r->ticket] = r;
   }
-  srv->work_cv.notify_one();
+  *ticket = r->ticket;
+  srv->st_submitted.fetch_add(1, std::memory_order_relaxed);
+  // hand it to the engine, waking it if it sleeps
+  Request* head = srv->inbox.load(std::memory_order_relaxed);
+  do {
+    r->next = head;
+  } while (!srv->inbox.compare_exchange_weak(head, r, std::memory_order_seq_cst));
+  if (srv->engine_sleeping.load()) {
+    std::lock_guard<std::mutex> lk(srv->work_mu);
+    srv->work_cv.notify_one();
+  }
   return PG_OK;
 }
 
 int pg_server_poll(pg_server* srv, uint64_t ticket, int32_t* done) {
   clear_error();
   if (!srv || !done) return fail(PG_E_INVALID, "NULL argument");
-  std::unique_lock<std::mutex> lk(srv->mu);
-  auto it = srv->live.find(ticket);
-  if (it == srv->live.end()) return fail(PG_E_INVALID, "unknown ticket");
+  TicketShard& sh = shard_of(srv, ticket);
+  std::lock_guard<std::mutex> lk(sh.mu);  // held so that a wait on the same ticket cannot free it meanwhile
+  auto it = sh.map.find(ticket);
+  if (it == sh.map.end()) return fail(PG_E_INVALID, "unknown ticket");
   Request* r = it->second;
-  if (r->state == kFinished) {  // this poll collects it
-    r->state = kCollecting;
-    lk.unlock();
-    collect(srv, r);
-    lk.lock();
-  } else if (r->state == kCollecting) {
-    srv->done_cv.wait(lk, [&] { return r->state == kCollected; });
-  }
-  *done = r->state == kCollected ? 1 : 0;
-  if (srv->engine_error != PG_OK) return fail(srv->engine_error, srv->engine_msg);
+  if (r->state.load(std::memory_order_acquire) != kQueued) collect_or_wait(srv, r, false);
+  *done = r->state.load(std::memory_order_acquire) == kCollected ? 1 : 0;
+  if (srv->engine_error.load() != PG_OK) return engine_failure(srv);
   return PG_OK;
 }
 
 int pg_server_wait(pg_server* srv, uint64_t ticket, double* latency_ms) {
   clear_error();
   if (!srv) return fail(PG_E_INVALID, "NULL argument");
-  std::unique_lock<std::mutex> lk(srv->mu);
-  auto it = srv->live.find(ticket);
-  if (it == srv->live.end()) return fail(PG_E_INVALID, "unknown ticket");
-  Request* r = it->second;
-  srv->live.erase(it);  // this call owns the ticket now
-  srv->done_cv.wait(lk, [&] { return r->state != kQueued; });
-  if (r->state == kFinished) {
-    r->state = kCollecting;
-    lk.unlock();
-    collect(srv, r);
-    lk.lock();
-  } else {
-    srv->done_cv.wait(lk, [&] { return r->state == kCollected; });
+  Request* r = nullptr;
+  {
+    TicketShard& sh = shard_of(srv, ticket);
+    std::lock_guard<std::mutex> lk(sh.mu);
+    auto it = sh.map.find(ticket);
+    if (it == sh.map.end()) return fail(PG_E_INVALID, "unknown ticket");
+    r = it->second;
+    sh.map.erase(it);  // this call owns the ticket now
   }
+  collect_or_wait(srv, r, true);
   if (latency_ms) latency_ms[0] = std::chrono::duration<double, std::milli>(r->t_collected - r->t_submit).count();
-  const int err = srv->engine_error;
-  const std::string msg = srv->engine_msg;
-  lk.unlock();
   delete r;
-  if (err != PG_OK) return fail(err, msg);
+  if (srv->engine_error.load() != PG_OK) return engine_failure(srv);
   return PG_OK;
 }
 
 int pg_server_get_stats(pg_server* srv, pg_server_stats* out) {
   clear_error();
   if (!srv || !out) return fail(PG_E_INVALID, "NULL argument");
-  std::lock_guard<std::mutex> lk(srv->mu);
-  *out = srv->stats;
+  out->submitted = srv->st_submitted.load();
+  out->rejected_busy = srv->st_rejected_busy.load();
+  out->rejected_invalid = srv->st_rejected_invalid.load();
+  out->completed = srv->st_completed.load();
+  out->batches = srv->st_batches.load();
+  out->pairs = srv->st_pairs.load();
+  out->max_in_flight = srv->st_max_in_flight.load();
   return PG_OK;
 }
 
@@ -543,88 +584,68 @@ int pg_server_replay(pg_server* srv, int64_t nreq, const pg_request* reqs, const
   if (nreq <= 0) return PG_OK;
   if (!arrival_s && max_outstanding < 1) return fail(PG_E_INVALID, "closed loop needs max_outstanding >= 1");
   // a few submitting and a few collecting threads: request i is submitted by
-  // thread i mod S (in order of i within a thread) and collected by thread
-  // i mod C, so the per-pair copies at submit and collection run in parallel
+  // thread i mod S (in order of i within a thread; closed loop: the next
+  // request of a shared counter) and collected by thread i mod C. The threads
+  // meet only through atomics (they spin, yielding, while they wait).
   const int S = (int)std::min<int64_t>(4, nreq), C = (int)std::min<int64_t>(4, nreq);
-  std::vector<uint64_t> tickets((size_t)nreq, 0);
-  std::vector<char> ready((size_t)nreq, 0);
+  std::vector<std::atomic<uint64_t>> tickets((size_t)nreq);
+  for (auto& t : tickets) t.store(0, std::memory_order_relaxed);
   std::vector<Clock::time_point> t_arr((size_t)nreq);
-  std::mutex m;
-  std::condition_variable cv;
-  int64_t outstanding = 0, next = 0;
-  int err = PG_OK;
+  std::atomic<int64_t> outstanding{0}, next{0};
+  std::atomic<int> err{PG_OK};
+  std::mutex err_m;
   std::string err_msg;
-  auto set_err = [&](int rc) {  // caller holds m
-    if (err == PG_OK) {
-      err = rc;
+  auto set_err = [&](int rc) {
+    std::lock_guard<std::mutex> lk(err_m);
+    if (err.load() == PG_OK) {
       err_msg = pg_last_error();
+      err.store(rc);
     }
   };
   const Clock::time_point t0 = Clock::now();
-  // open loop: per-thread index streams; closed loop: shared counter
+  auto submit_one = [&](int64_t i) {
+    uint64_t tk = 0;
+    int rc;
+    while ((rc = pg_server_submit(srv, &reqs[i], &tk)) == PG_E_BUSY) std::this_thread::yield();
+    if (rc != PG_OK) {
+      set_err(rc);
+      return false;
+    }
+    tickets[(size_t)i].store(tk, std::memory_order_release);
+    return true;
+  };
   auto open_submitter = [&](int t) {
-    for (int64_t i = t; i < nreq; i += S) {
-      {
-        std::lock_guard<std::mutex> lk(m);
-        if (err != PG_OK) return;
-      }
+    for (int64_t i = t; i < nreq && err.load() == PG_OK; i += S) {
       const Clock::time_point due =
           t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
       while (Clock::now() < due) std::this_thread::yield();
       t_arr[(size_t)i] = due;
-      uint64_t tk = 0;
-      int rc;
-      while ((rc = pg_server_submit(srv, &reqs[i], &tk)) == PG_E_BUSY) std::this_thread::yield();
-      std::lock_guard<std::mutex> lk(m);
-      if (rc != PG_OK)
-        set_err(rc);
-      else {
-        tickets[(size_t)i] = tk;
-        ready[(size_t)i] = 1;
-      }
-      cv.notify_all();
+      if (!submit_one(i)) return;
     }
   };
   auto closed_submitter = [&]() {
     for (;;) {
-      int64_t i;
-      {
-        std::unique_lock<std::mutex> lk(m);
-        cv.wait(lk, [&] { return outstanding < max_outstanding || err != PG_OK || next >= nreq; });
-        if (err != PG_OK || next >= nreq) return;
-        i = next++;
-        ++outstanding;
-      }
+      while (outstanding.load(std::memory_order_acquire) >= max_outstanding && err.load() == PG_OK)
+        std::this_thread::yield();
+      if (err.load() != PG_OK) return;
+      const int64_t i = next.fetch_add(1);
+      if (i >= nreq) return;
+      outstanding.fetch_add(1);
       t_arr[(size_t)i] = Clock::now();
-      uint64_t tk = 0;
-      int rc;
-      while ((rc = pg_server_submit(srv, &reqs[i], &tk)) == PG_E_BUSY) std::this_thread::yield();
-      std::lock_guard<std::mutex> lk(m);
-      if (rc != PG_OK)
-        set_err(rc);
-      else {
-        tickets[(size_t)i] = tk;
-        ready[(size_t)i] = 1;
-      }
-      cv.notify_all();
+      if (!submit_one(i)) return;
     }
   };
   auto collector = [&](int c) {
     for (int64_t i = c; i < nreq; i += C) {
       uint64_t tk;
-      {
-        std::unique_lock<std::mutex> lk(m);
-        cv.wait(lk, [&] { return ready[(size_t)i] || err != PG_OK; });
-        if (!ready[(size_t)i]) return;
-        tk = tickets[(size_t)i];
+      while ((tk = tickets[(size_t)i].load(std::memory_order_acquire)) == 0) {
+        if (err.load() != PG_OK) return;
+        std::this_thread::yield();
       }
       const int rc = pg_server_wait(srv, tk, nullptr);
-      const Clock::time_point now = Clock::now();
-      std::lock_guard<std::mutex> lk(m);
+      latency_ms[i] = std::chrono::duration<double, std::milli>(Clock::now() - t_arr[(size_t)i]).count();
       if (rc != PG_OK) set_err(rc);
-      latency_ms[i] = std::chrono::duration<double, std::milli>(now - t_arr[(size_t)i]).count();
-      --outstanding;
-      cv.notify_all();
+      outstanding.fetch_sub(1);
     }
   };
   std::vector<std::thread> threads;
@@ -637,7 +658,7 @@ int pg_server_replay(pg_server* srv, int64_t nreq, const pg_request* reqs, const
   }
   for (std::thread& th : threads) th.join();
   if (elapsed_s) *elapsed_s = std::chrono::duration<double>(Clock::now() - t0).count();
-  if (err != PG_OK) return fail(err, err_msg);
+  if (err.load() != PG_OK) return fail(err.load(), err_msg);
   return PG_OK;
 }
 
@@ -645,13 +666,15 @@ int pg_server_destroy(pg_server* srv) {
   clear_error();
   if (!srv) return fail(PG_E_INVALID, "server is NULL");
   {
-    std::lock_guard<std::mutex> lk(srv->mu);
-    srv->stop = true;
+    std::lock_guard<std::mutex> lk(srv->work_mu);
+    srv->stop.store(true);
   }
   srv->work_cv.notify_all();
   if (srv->engine.joinable()) srv->engine.join();
-  for (auto& kv : srv->live) delete kv.second;
-  srv->live.clear();
+  for (TicketShard& sh : srv->tickets) {
+    for (auto& kv : sh.map) delete kv.second;
+    sh.map.clear();
+  }
   for (Slot& sl : srv->slots) slot_free(sl);
   if (srv->a_u) (void)hipHostFree(srv->a_u);
   if (srv->a_v) (void)hipHostFree(srv->a_v);
