@@ -303,12 +303,28 @@ __global__ __launch_bounds__(kBlock) void k_batch_estimate(BatchView bv, int64_t
 }
 
 // One block per graph: TC_g = (1/3) sum of the upper sums, fixed order.
+// Thread t adds entries t, t + 256, ... in rounds of kTcLoads independent
+// loads into kTcLoads accumulators (the largest graphs have 2^16 vertices:
+// one load in flight per thread took 0.1 ms), then a fixed tree.
+constexpr int kTcLoads = 8;
 __global__ __launch_bounds__(kBlock) void k_batch_tc(const GraphDesc* __restrict__ gd,
                                                      const double* __restrict__ Splus, double* __restrict__ tc) {
   __shared__ double red[kBlock / kWave];
   const GraphDesc d = gd[blockIdx.x];
-  double acc = 0.0;
-  for (int32_t v = threadIdx.x; v < d.n; v += kBlock) acc += Splus[d.vbase + v];
+  double a[kTcLoads];
+#pragma unroll
+  for (int j = 0; j < kTcLoads; ++j) a[j] = 0.0;
+  for (int32_t v0 = threadIdx.x; v0 < d.n; v0 += kBlock * kTcLoads) {
+    double x[kTcLoads];
+#pragma unroll
+    for (int j = 0; j < kTcLoads; ++j) {
+      const int32_t v = v0 + j * kBlock;
+      x[j] = v < d.n ? Splus[d.vbase + v] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kTcLoads; ++j) a[j] += x[j];
+  }
+  const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   const double r = block_sum_256(acc, red);
   if (threadIdx.x == 0) tc[blockIdx.x] = r / 3.0;
 }

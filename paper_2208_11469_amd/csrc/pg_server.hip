@@ -614,11 +614,26 @@ int pg_server_replay(pg_server* srv, int64_t nreq, const pg_request* reqs, const
     tickets[(size_t)i].store(tk, std::memory_order_release);
     return true;
   };
+  // waiting for a time point: sleep while it is far, spin (yielding) over the
+  // last stretch, so that idle load-generator threads leave the cores to the
+  // threads that work
+  auto wait_until = [&](Clock::time_point due) {
+    for (;;) {
+      const Clock::time_point now = Clock::now();
+      if (now >= due) return;
+      if (due - now > std::chrono::microseconds(200))
+        std::this_thread::sleep_for(due - now - std::chrono::microseconds(100));
+      else
+        std::this_thread::yield();
+    }
+  };
+  auto due_of = [&](int64_t i) {
+    return t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
+  };
   auto open_submitter = [&](int t) {
     for (int64_t i = t; i < nreq && err.load() == PG_OK; i += S) {
-      const Clock::time_point due =
-          t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
-      while (Clock::now() < due) std::this_thread::yield();
+      const Clock::time_point due = due_of(i);
+      wait_until(due);
       t_arr[(size_t)i] = due;
       if (!submit_one(i)) return;
     }
@@ -637,6 +652,7 @@ int pg_server_replay(pg_server* srv, int64_t nreq, const pg_request* reqs, const
   };
   auto collector = [&](int c) {
     for (int64_t i = c; i < nreq; i += C) {
+      if (arrival_s) wait_until(due_of(i));  // open loop: not submitted before its arrival
       uint64_t tk;
       while ((tk = tickets[(size_t)i].load(std::memory_order_acquire)) == 0) {
         if (err.load() != PG_OK) return;

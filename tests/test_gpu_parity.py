@@ -504,3 +504,17 @@ def test_estimators_on_two_streams_do_not_interfere(ctx):
         assert torch.equal(edges[i], edge_alone[e]), (i, e)
     sk.close()
     dg.close()
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096, 16 * 1023, 16 * (256 * 4 * 3 + 77), 1 << 24])
+def test_reference_copy_kernel(ctx, nbytes):
+    """pg_copy (the stream-copy reference for bandwidth and byte counters) copies
+    every byte: whole tiles and the ragged tail."""
+    say(f"pg_copy {nbytes} bytes")
+    g = torch.Generator().manual_seed(nbytes)
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, generator=g).cuda()
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
+    pg.pg_copy(ctx.h, dst[:nbytes], src, nbytes)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src)
+    assert int(dst[nbytes:].sum()) == 0  # nothing written past the end
