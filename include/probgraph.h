@@ -323,7 +323,9 @@ int pg_sketches_rebuild(pg_ctx* ctx, pg_sketches* sk, uint64_t seed, void* strea
  * host memory that the GPU reads and writes directly, 16 bytes per pair (the
  * two IDs and the answer). A request is admitted if a contiguous range of the
  * arena for its pairs is free; submit writes its pairs there (on the calling
- * thread) and otherwise returns PG_E_BUSY. Up to max_batches_in_flight batches
+ * thread) and otherwise returns PG_E_BUSY. (The arena is split into up to 16
+ * equal parts of at least four largest requests each; a range lies within
+ * one part.) Up to max_batches_in_flight batches
  * run concurrently on separate streams; requests submitted while batches run
  * join the next batch as soon as a batch slot frees. A request's range (its
  * bytes of the budget) is released when the request is collected: by
@@ -341,7 +343,7 @@ typedef struct pg_server pg_server;
 typedef struct pg_server_params {
   int32_t max_batches_in_flight; /* concurrent batches (streams); 0 = 3 */
   int32_t max_pairs_per_request; /* 0 = 65536 */
-  int64_t max_batch_pairs;       /* pairs packed into one launch; 0 = 1 << 20 */
+  int64_t max_batch_pairs;       /* pairs packed into one launch; 0 = 1 << 20; at most 1 << 30 */
   uint64_t memory_budget_bytes;  /* admission budget; 0 = 256 MiB */
 } pg_server_params;
 
@@ -364,6 +366,7 @@ typedef struct pg_server_stats {
   uint64_t batches;          /* launches */
   uint64_t pairs;            /* pairs answered */
   uint64_t max_in_flight;    /* most batches launched and not yet retired at one time */
+  uint64_t max_batch_requests; /* most requests packed into one launch */
 } pg_server_stats;
 
 /* sketches: host array of nsketches handles built on `g`. params may be NULL. */

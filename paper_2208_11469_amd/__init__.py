@@ -103,7 +103,8 @@ class _Request(ctypes.Structure):
 class _ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("rejected_busy", ctypes.c_uint64),
                 ("rejected_invalid", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
-                ("pairs", ctypes.c_uint64), ("max_in_flight", ctypes.c_uint64)]
+                ("pairs", ctypes.c_uint64), ("max_in_flight", ctypes.c_uint64),
+                ("max_batch_requests", ctypes.c_uint64)]
 
 
 PG_OP_CN = 1
@@ -803,7 +804,10 @@ class Server:
     def make_request(self, op, sketch, estimator, u, v):
         u = np.ascontiguousarray(u, dtype=np.int32)
         v = np.ascontiguousarray(v, dtype=np.int32)
-        out = np.empty(u.shape[0], dtype=np.float64 if op == PG_OP_CN else np.float32)
+        # written once here, so that its pages are mapped before the server
+        # first copies answers into it
+        out = np.zeros(u.shape[0], dtype=np.float64 if op == PG_OP_CN else np.float32)
+        out.fill(0)
         req = _Request(op, sketch, ESTIMATORS.get(estimator, estimator), 0, u.shape[0], u.ctypes.data,
                        v.ctypes.data, out.ctypes.data)
         return req, (u, v, out)

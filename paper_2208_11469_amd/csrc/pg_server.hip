@@ -2,8 +2,9 @@
 //
 // The memory budget is a staging arena of pinned, coherent host memory, 16
 // bytes per pair slot (two IDs and the answer). Submit checks a request on the
-// calling thread, reserves a contiguous range of pair slots (first fit; no
-// range free = not admitted now) and writes the pairs there itself. An engine
+// calling thread, reserves a contiguous range of pair slots (best fit within
+// one part of the arena; no range free = not admitted now) and writes the
+// pairs there itself. An engine
 // thread keeps up to K batches in flight, one stream each (default priority):
 // whenever a batch slot is free and requests wait, it forms one launch from as
 // many of them as fit (a segment table tells each pair its request's sketch
@@ -18,9 +19,9 @@
 //
 // Synchronisation is split so that client threads rarely meet: submitted
 // requests reach the engine through a lock-free stack that it empties in one
-// exchange (the engine's queue is its own); the arena, the ticket table
-// (sharded), the finished/collected states and the engine's sleep each have
-// their own lock.
+// exchange (the engine's queue is its own); the arena (split into parts,
+// each under a spinning lock), the ticket table (sharded), the
+// finished/collected states and the engine's sleep each have their own lock.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,8 +31,10 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -46,7 +49,9 @@ namespace {
 
 constexpr int kMaxSegments = 1024;  // requests per batch
 constexpr int kEstSlots = 8;        // view slots per sketch set, indexed by estimator id
-constexpr int kArgSegments = 16;    // segment tables this small travel as kernel arguments
+// Segment tables this small travel as kernel arguments (16 bytes each, 2 KiB):
+// larger ones need a copy in front of the kernel on the slot's stream.
+constexpr int kArgSegments = 128;
 // While a batch is on the device, the next one starts only once the queue
 // holds this many pairs (at most half a batch) or its oldest request has
 // waited this long: each launch costs the engine thread a few microseconds,
@@ -55,12 +60,42 @@ constexpr int kArgSegments = 16;    // segment tables this small travel as kerne
 constexpr int64_t kBusyBatchPairs = 1 << 18;
 constexpr int64_t kMaxQueueWaitNs = 50000;
 
-struct SegDesc {
-  int64_t begin;  // first pair of the segment in the batch
-  int64_t arena;  // first pair slot of its request in the arena
-  int32_t view;   // index into the server's views (sketch * kEstSlots + estimator)
-  int32_t op;     // PG_OP_CN or PG_OP_JACCARD
+// Test-and-test-and-set lock for the arena's short critical sections (a few
+// ordered-map operations). Under contention a blocking mutex hands over
+// through sleeping threads, several microseconds per hand-over, and the
+// submitting and collecting threads formed a convoy on it.
+class SpinLock {
+ public:
+  void lock() {
+    for (;;) {
+      if (!f_.exchange(true, std::memory_order_acquire)) return;
+      while (f_.load(std::memory_order_relaxed)) __builtin_ia32_pause();
+    }
+  }
+  void unlock() { f_.store(false, std::memory_order_release); }
+
+ private:
+  std::atomic<bool> f_{false};
 };
+
+// One part of the staging arena: its free ranges, indexed by first slot (to
+// merge neighbours) and by length (best fit), under its own lock.
+struct alignas(64) ArenaPart {
+  SpinLock mu;
+  std::map<int64_t, int64_t> by_start;           // first slot -> length, disjoint and not adjacent
+  std::set<std::pair<int64_t, int64_t>> by_len;  // (length, first slot) of the same ranges
+};
+// The arena has at most this many parts, each of at least four requests of
+// the largest size.
+constexpr int64_t kArenaParts = 16;
+
+struct SegDesc {
+  int64_t arena;  // first pair slot of its request in the arena
+  int32_t begin;  // first pair of the segment in the batch (batches hold at most 2^30 pairs)
+  int16_t view;   // index into the server's views (sketch * kEstSlots + estimator, below 512)
+  int16_t op;     // PG_OP_CN or PG_OP_JACCARD
+};
+static_assert(sizeof(SegDesc) == 16, "segment descriptors are 16 bytes");
 
 struct SegArgs {
   int32_t nseg;
@@ -152,9 +187,13 @@ struct pg_server {
   int32_t* a_u = nullptr;
   int32_t* a_v = nullptr;
   double* a_out = nullptr;
-  std::mutex arena_mu;                     // guards free_ranges and bytes_admitted
-  std::map<int64_t, int64_t> free_ranges;  // first slot -> length, disjoint and not adjacent
-  uint64_t bytes_admitted = 0;
+  // Its free ranges are split into parts, each under its own lock: a
+  // submitting thread takes from its home part first and a range returns to
+  // the part that holds it, so threads seldom meet on a lock. One allocator
+  // for all threads spent 1-2 us per operation in cache misses on its tree
+  // nodes and 4-9 us waiting for its lock.
+  std::vector<std::unique_ptr<pg::ArenaPart>> parts;
+  int64_t part_len = 0;  // slots per part; the last part also holds the remainder
   std::atomic<pg::Request*> inbox{nullptr};  // submitted requests the engine has not taken yet (a stack)
   std::mutex work_mu;                        // the engine's sleep
   std::condition_variable work_cv;
@@ -171,7 +210,8 @@ struct pg_server {
   std::mutex err_mu;
   std::string engine_msg;
   std::atomic<uint64_t> st_submitted{0}, st_rejected_busy{0}, st_rejected_invalid{0}, st_completed{0},
-      st_batches{0}, st_pairs{0}, st_max_in_flight{0};
+      st_batches{0}, st_pairs{0}, st_max_in_flight{0},
+      st_max_batch_requests{0};
 };
 
 namespace pg {
@@ -179,33 +219,66 @@ namespace {
 
 constexpr uint64_t kBytesPerPair = 16;
 
-// First-fit range of `len` free slots; -1 if none. Caller holds srv->arena_mu.
+void add_free(ArenaPart& a, int64_t at, int64_t len) {
+  a.by_start.emplace(at, len);
+  a.by_len.emplace(len, at);
+}
+
+// Best-fit range of `len` free slots in part `a` (the shortest free range
+// that holds them, lowest first slot among equals), O(log ranges); -1 if
+// none. (A linear first-fit scan grew slow once small holes gathered at the
+// front.) Caller holds a.mu.
+int64_t part_take(ArenaPart& a, int64_t len) {
+  auto it = a.by_len.lower_bound({len, INT64_MIN});
+  if (it == a.by_len.end()) return -1;
+  const int64_t have = it->first, at = it->second;
+  a.by_len.erase(it);
+  a.by_start.erase(at);
+  if (have > len) add_free(a, at + len, have - len);
+  return at;
+}
+
+// Return [at, at + len) to part `a`, merging with free neighbours. Caller holds a.mu.
+void part_give(ArenaPart& a, int64_t at, int64_t len) {
+  auto next = a.by_start.lower_bound(at);
+  if (next != a.by_start.end() && next->first == at + len) {
+    len += next->second;
+    a.by_len.erase({next->second, next->first});
+    next = a.by_start.erase(next);
+  }
+  if (next != a.by_start.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == at) {
+      at = prev->first;
+      len += prev->second;
+      a.by_len.erase({prev->second, prev->first});
+      a.by_start.erase(prev);
+    }
+  }
+  add_free(a, at, len);
+}
+
+std::atomic<uint32_t> g_next_home{0};
+
+// A range of `len` slots: from the calling thread's home part, else from the
+// next part that has one; -1 if no part has a free range that long.
 int64_t arena_take(pg_server* srv, int64_t len) {
-  for (auto it = srv->free_ranges.begin(); it != srv->free_ranges.end(); ++it) {
-    if (it->second < len) continue;
-    const int64_t at = it->first, rest = it->second - len;
-    srv->free_ranges.erase(it);
-    if (rest > 0) srv->free_ranges.emplace(at + len, rest);
-    return at;
+  thread_local uint32_t home = g_next_home.fetch_add(1, std::memory_order_relaxed);
+  const size_t P = srv->parts.size();
+  for (size_t k = 0; k < P; ++k) {
+    ArenaPart& a = *srv->parts[(home + k) % P];
+    std::lock_guard<SpinLock> lk(a.mu);
+    const int64_t at = part_take(a, len);
+    if (at >= 0) return at;
   }
   return -1;
 }
 
-// Return [at, at + len) to the arena, merging with free neighbours. Caller holds srv->arena_mu.
 void arena_give(pg_server* srv, int64_t at, int64_t len) {
-  auto next = srv->free_ranges.lower_bound(at);
-  if (next != srv->free_ranges.end() && next->first == at + len) {
-    len += next->second;
-    next = srv->free_ranges.erase(next);
-  }
-  if (next != srv->free_ranges.begin()) {
-    auto prev = std::prev(next);
-    if (prev->first + prev->second == at) {
-      prev->second += len;
-      return;
-    }
-  }
-  srv->free_ranges.emplace(at, len);
+  const int64_t p = std::min<int64_t>(at / srv->part_len, (int64_t)srv->parts.size() - 1);
+  ArenaPart& a = *srv->parts[(size_t)p];
+  std::lock_guard<SpinLock> lk(a.mu);
+  part_give(a, at, len);
 }
 
 TicketShard& shard_of(pg_server* srv, uint64_t ticket) { return srv->tickets[ticket % kShards]; }
@@ -248,7 +321,7 @@ int launch_batch(pg_server* srv, Slot& sl) {
   a.nseg = (int32_t)sl.reqs.size();
   int32_t i = 0;
   for (Request* r : sl.reqs) {
-    const SegDesc sd{total, r->arena, r->view, r->op};
+    const SegDesc sd{r->arena, (int32_t)total, (int16_t)r->view, (int16_t)r->op};
     if (a.nseg > kArgSegments)
       sl.h_seg[i] = sd;
     else
@@ -328,6 +401,8 @@ void engine_loop(pg_server* srv) {
         sl.reqs.push_back(r);
       }
       queued_pairs -= total;
+      if (sl.reqs.size() > srv->st_max_batch_requests.load(std::memory_order_relaxed))
+        srv->st_max_batch_requests.store(sl.reqs.size(), std::memory_order_relaxed);  // only this thread writes it
       sl.busy = true;
       ++inflight;
       launched = true;
@@ -361,11 +436,7 @@ void collect(pg_server* srv, Request* r) {
     std::memcpy(r->out, srv->a_out + r->arena, sizeof(double) * (size_t)r->npairs);
   else
     std::memcpy(r->out, srv->a_out + r->arena, sizeof(float) * (size_t)r->npairs);
-  {
-    std::lock_guard<std::mutex> lk(srv->arena_mu);
-    arena_give(srv, r->arena, r->npairs);
-    srv->bytes_admitted -= (uint64_t)r->npairs * kBytesPerPair;
-  }
+  arena_give(srv, r->arena, r->npairs);
   srv->st_completed.fetch_add(1, std::memory_order_relaxed);
   srv->st_pairs.fetch_add((uint64_t)r->npairs, std::memory_order_relaxed);
   {
@@ -418,7 +489,7 @@ int pg_server_create(pg_ctx* ctx, const pg_graph* g, pg_sketches* const* sketche
   if (p.max_batch_pairs <= 0) p.max_batch_pairs = 1 << 20;
   if (p.memory_budget_bytes == 0) p.memory_budget_bytes = 256ull << 20;
   p.max_batches_in_flight = std::min(p.max_batches_in_flight, 16);
-  p.max_batch_pairs = std::max<int64_t>(p.max_batch_pairs, p.max_pairs_per_request);
+  p.max_batch_pairs = std::min<int64_t>(std::max<int64_t>(p.max_batch_pairs, p.max_pairs_per_request), 1 << 30);
   if (p.memory_budget_bytes < kBytesPerPair) return fail(PG_E_INVALID, "memory_budget_bytes below one pair (16 bytes)");
   PG_HIP(hipSetDevice(ctx->device));
   pg_server* srv = new (std::nothrow) pg_server();
@@ -451,7 +522,28 @@ int pg_server_create(pg_ctx* ctx, const pg_graph* g, pg_sketches* const* sketche
     if (e == hipSuccess) e = hipHostMalloc((void**)&srv->a_out, sizeof(double) * srv->cap, hipHostMallocCoherent);
     if (e != hipSuccess) rc = fail(PG_E_NOMEM, std::string("pinned staging arena: ") + hipGetErrorString(e));
   }
-  srv->free_ranges.emplace(0, srv->cap);
+  if (rc == PG_OK) {
+    // touch every page once now: the first CPU access to a page of this
+    // mapping faults it in (about 10 us per 48 KB request range otherwise)
+    std::memset(srv->a_u, 0, sizeof(int32_t) * srv->cap);
+    std::memset(srv->a_v, 0, sizeof(int32_t) * srv->cap);
+    std::memset(srv->a_out, 0, sizeof(double) * srv->cap);
+  }
+  {
+    const int64_t P = std::max<int64_t>(
+        1, std::min<int64_t>(kArenaParts, srv->cap / (4 * (int64_t)p.max_pairs_per_request)));
+    srv->part_len = srv->cap / P;
+    for (int64_t i = 0; i < P && rc == PG_OK; ++i) {
+      ArenaPart* part = new (std::nothrow) ArenaPart();
+      if (!part) {
+        rc = fail(PG_E_NOMEM, "host allocation failed");
+        break;
+      }
+      srv->parts.emplace_back(part);
+      const int64_t b = i * srv->part_len, e = i == P - 1 ? srv->cap : b + srv->part_len;
+      add_free(*part, b, e - b);
+    }
+  }
   srv->slots.resize((size_t)p.max_batches_in_flight);
   for (Slot& sl : srv->slots)
     if (rc == PG_OK) rc = slot_init(sl);
@@ -493,11 +585,7 @@ int pg_server_submit(pg_server* srv, const pg_request* req, uint64_t* ticket) {
   if (srv->engine_error.load() != PG_OK) return engine_failure(srv);
   Request* r = new (std::nothrow) Request();
   if (!r) return fail(PG_E_NOMEM, "host allocation failed");
-  {
-    std::lock_guard<std::mutex> lk(srv->arena_mu);
-    r->arena = arena_take(srv, L);
-    if (r->arena >= 0) srv->bytes_admitted += (uint64_t)L * kBytesPerPair;
-  }
+  r->arena = arena_take(srv, L);
   if (r->arena < 0) {
     srv->st_rejected_busy.fetch_add(1, std::memory_order_relaxed);
     delete r;
@@ -574,6 +662,7 @@ int pg_server_get_stats(pg_server* srv, pg_server_stats* out) {
   out->batches = srv->st_batches.load();
   out->pairs = srv->st_pairs.load();
   out->max_in_flight = srv->st_max_in_flight.load();
+  out->max_batch_requests = srv->st_max_batch_requests.load();
   return PG_OK;
 }
 

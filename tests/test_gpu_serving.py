@@ -104,6 +104,41 @@ def test_admission_by_memory_budget(env):
     srv.close()
 
 
+def test_budget_ranges_split_and_merge(env):
+    """The budget is handed out as contiguous ranges of 16-byte pair slots:
+    freed neighbours merge, and a request needs one range that holds it."""
+    g, ctx, dg, sks = env
+    srv = pg.Server(dg, sks, memory_budget_bytes=16 * 1000)
+    u = (np.arange(100, dtype=np.int32) * 7) % g.n
+    held = [srv.submit(pg.PG_OP_CN, 0, "and", u, u[::-1].copy()) for _ in range(10)]  # the whole budget
+    for i in (2, 5):  # two separate holes of 100 pairs
+        srv.wait(held[i][0])
+    big = np.zeros(150, np.int32)
+    with pytest.raises(pg.PGError) as ei:
+        srv.submit(pg.PG_OP_CN, 0, "and", big, big)
+    assert ei.value.code == pg.PG_E_BUSY
+    srv.wait(held[3][0])  # merges with the hole before it: 200 pairs in one range
+    t, out = srv.submit(pg.PG_OP_CN, 0, "and", big, big)
+    t2, out2 = srv.submit(pg.PG_OP_CN, 0, "and", u[:100], u[:100])  # the other hole, exactly
+    # 50 pairs are left, at the end of the merged range
+    with pytest.raises(pg.PGError) as ei:
+        srv.submit(pg.PG_OP_CN, 0, "and", u[:60], u[:60])
+    assert ei.value.code == pg.PG_E_BUSY
+    for i in (0, 1, 4, 6, 7, 8, 9):
+        srv.wait(held[i][0])
+    srv.wait(t)
+    srv.wait(t2)
+    t3, _ = srv.submit(pg.PG_OP_CN, 0, "and", np.zeros(1000, np.int32), np.zeros(1000, np.int32))  # all merged
+    srv.wait(t3)
+    ref = pg.Server(dg, sks)
+    tr, want = ref.submit(pg.PG_OP_CN, 0, "and", u, u[::-1].copy())
+    ref.wait(tr)
+    for _, o in held:
+        assert o.tobytes() == want.tobytes()
+    ref.close()
+    srv.close()
+
+
 def test_malformed_requests_rejected_before_enqueue(env):
     g, ctx, dg, sks = env
     srv = pg.Server(dg, sks, max_pairs_per_request=100)
@@ -161,4 +196,39 @@ def test_alone_equals_mixed_with_concurrent_batches(env):
     st = srv.stats()
     assert st["completed"] == 3 * len(reqs)
     assert st["max_in_flight"] > 1, st  # batches did run concurrently
+    srv.close()
+
+
+def test_many_small_requests_in_one_batch(env):
+    """Thousands of tiny requests queue behind a running batch, so batches hold
+    more requests than travel as kernel arguments (their segment table is
+    copied in front of the kernel) and up to the 1024 a batch holds; every
+    answer equals the direct call's bit for bit."""
+    g, ctx, dg, sks = env
+    rng = np.random.default_rng(11)
+    say("3000 requests of 1..4 pairs, one batch slot")
+    srv = pg.Server(dg, sks, max_batches_in_flight=1)
+    kinds = [(0, "and"), (1, "kh"), (2, "1h")]
+    spec = []
+    for i in range(3000):
+        L = int(rng.integers(1, 5))
+        u = rng.integers(0, g.n, L).astype(np.int32)
+        v = rng.integers(0, g.n, L).astype(np.int32)
+        sk, est = kinds[i % 3]
+        op = pg.PG_OP_CN if i % 2 == 0 else pg.PG_OP_JACCARD
+        spec.append((op, sk, est, u, v))
+    dev = torch.device("cuda", 0)
+    for rep in range(3):
+        mix = [srv.make_request(*s) for s in spec]
+        srv.replay(mix, max_outstanding=len(mix))
+        if srv.stats()["max_batch_requests"] > 128:
+            break
+    st = srv.stats()
+    assert st["max_batch_requests"] > 128, st
+    assert st["max_batch_requests"] <= 1024, st
+    for (op, sk, est, u, v), (_, keep) in zip(spec, mix):
+        tu, tv = torch.from_numpy(u).to(dev), torch.from_numpy(v).to(dev)
+        direct = sks[sk].intersect(est, tu, tv)[0] if op == pg.PG_OP_CN else sks[sk].jaccard(est, tu, tv)
+        torch.cuda.synchronize()
+        assert direct.cpu().numpy().tobytes() == keep[2].tobytes()
     srv.close()
