@@ -111,7 +111,9 @@ __global__ void k_degree_bin_keys(const int32_t* __restrict__ deg, int32_t n, ui
 }
 
 // Plan tier of a count of arcs: 1 light, 2 medium, 3 heavy.
-__device__ __forceinline__ uint8_t plan_tier(int64_t d) { return d <= kLightMax ? 1 : (d <= kMediumMax ? 2 : 3); }
+__device__ __forceinline__ uint8_t plan_tier(int64_t d, int64_t light_max = kLightMax) {
+  return d <= light_max ? 1 : (d <= kMediumMax ? 2 : 3);
+}
 
 // Vertices without arcs, added into *count (one atomic per wave).
 __global__ void k_count_empty(const int32_t* __restrict__ off, int32_t n, unsigned long long* __restrict__ count) {
@@ -140,7 +142,7 @@ __global__ void k_slab_keys(const int32_t* __restrict__ off, const int32_t* __re
     return;
   }
   const int64_t d = slab_end(off, split, (size_t)n, x, v) - slab_begin(ustart, split, (size_t)n, x, v);
-  key[i] = (dup <= kSliceMin || d == 0) ? 0 : plan_tier(d);
+  key[i] = (dup <= kSliceMin || d == 0) ? 0 : plan_tier(d, kSlabLightMax);
 }
 
 // Stable partition of the vertices by a small key (< kNumBins): per-block

@@ -64,16 +64,19 @@ constexpr int kBinGroup[kNumBins] = {4, 16, 64, 256};
 //   medium (kLightMax < d_v <= kMediumMax): one wave per vertex
 //   light  (d_v <= kLightMax): kLightGroup lanes per vertex in the filter
 //          build (the clustering kernels pick their own group size)
+// (Measured on R-MAT s20, BF-320: light limits of 32 / 64 / 128 / 256 / 512
+// vertices gave the build 72 / 54 / 52 / 46 / 46 us, 43 us with 8 loads per
+// lane and pass; the triangle count's slab items do best at 256.)
 // Isolated vertices stay in the light tier (their sketch rows still have to
 // be written; they end the light list). The light list is sorted by
 // descending passes of the filter build, ceil(d_v / (kLightGroup *
 // kLightUnroll)), in ID order within a pass count: the groups of a wave take
 // equally many passes and neighbouring groups keep nearby IDs.
-constexpr int32_t kLightMax = 64;
+constexpr int32_t kLightMax = 512;
 constexpr int32_t kMediumMax = 2048;
 constexpr int64_t kHeavyChunk = 2048;
 constexpr int kLightGroup = 4;
-constexpr int kLightUnroll = 4;  // arcs each lane of a light group loads per pass of the filter build
+constexpr int kLightUnroll = 8;  // arcs each lane of a light group loads per pass of the filter build
 
 struct VertexPlan {
   int64_t n_light = 0;
@@ -136,8 +139,9 @@ inline int64_t plan_blocks(const VertexPlan& p) {
 //
 // Only vertices with more than kSliceMin upper neighbours are sliced: item
 // (x, v) is v's upper neighbours inside slab x, tiered by their number like a
-// VertexPlan (light items get kSlabLightGroup lanes, medium ones a wave, heavy
-// ones chunks of kHeavyChunk arcs). The slabs hold about equal numbers of
+// VertexPlan but with its own light limit, kSlabLightMax (light items get
+// kSlabLightGroup lanes, medium ones a wave, heavy ones chunks of kHeavyChunk
+// arcs). The slabs hold about equal numbers of
 // these arcs. The remaining vertices ("whole" vertices, 1..kSliceMin upper
 // neighbours) are not worth a slab each: their blocks follow the slab blocks,
 // kWholeGroup lanes per vertex over all upper neighbours. Light lists are
@@ -145,6 +149,7 @@ inline int64_t plan_blocks(const VertexPlan& p) {
 // many arcs and few load instructions run with idle lanes.
 constexpr int kSlabs = 8;
 constexpr int32_t kSliceMin = 64;
+constexpr int32_t kSlabLightMax = 256;  // light slab items: at most this many arcs (then a wave, then chunks)
 constexpr int kSlabLightGroup = 8;
 constexpr int kWholeGroup = 8;      // lanes per light vertex of the clustering-coefficient plan
 constexpr int kSlabWholeGroup = 4;  // lanes per whole (unsliced) vertex of the triangle-count slab plan
