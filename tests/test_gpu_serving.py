@@ -200,25 +200,27 @@ def test_alone_equals_mixed_with_concurrent_batches(env):
 
 
 def test_many_small_requests_in_one_batch(env):
-    """Thousands of tiny requests queue behind a running batch, so batches hold
-    more requests than travel as kernel arguments (their segment table is
-    copied in front of the kernel) and up to the 1024 a batch holds; every
-    answer equals the direct call's bit for bit."""
+    """Thousands of tiny requests queue behind long batches (three requests
+    of 65,536 pairs in every 300), so batches hold more requests than travel as
+    kernel arguments (their segment table is copied in front of the kernel)
+    and up to the 1024 a batch holds; every answer equals the direct call's
+    bit for bit."""
     g, ctx, dg, sks = env
     rng = np.random.default_rng(11)
-    say("3000 requests of 1..4 pairs, one batch slot")
+    say("3000 requests of 1..4 pairs, three in every 300 of 65536 pairs, one batch slot")
     srv = pg.Server(dg, sks, max_batches_in_flight=1)
     kinds = [(0, "and"), (1, "kh"), (2, "1h")]
     spec = []
     for i in range(3000):
-        L = int(rng.integers(1, 5))
+        long = i % 300 < 3  # three long 1-hash requests in a row
+        L = 65536 if long else int(rng.integers(1, 5))
         u = rng.integers(0, g.n, L).astype(np.int32)
         v = rng.integers(0, g.n, L).astype(np.int32)
-        sk, est = kinds[i % 3]
+        sk, est = kinds[2] if long else kinds[i % 3]
         op = pg.PG_OP_CN if i % 2 == 0 else pg.PG_OP_JACCARD
         spec.append((op, sk, est, u, v))
     dev = torch.device("cuda", 0)
-    for rep in range(3):
+    for rep in range(5):
         mix = [srv.make_request(*s) for s in spec]
         srv.replay(mix, max_outstanding=len(mix))
         if srv.stats()["max_batch_requests"] > 128:
