@@ -801,61 +801,100 @@ int oh_dispatch_e(uint32_t k, F&& launch) {
   return launch(std::integral_constant<int, 16>(), std::false_type());
 }
 
-// ---- clustering coefficient over the full-neighbourhood plan (Bloom filters) --
+// ---- clustering coefficient over XCD slabs of all of N_v (Bloom filters) ----
 //
-// The triangle count's vertex-centric item (B_v in registers, two-lane row
-// reads, estimator table in LDS) over all of N_v: light vertices (natural
-// order) get kWholeGroup lanes, medium ones a wave, heavy ones chunks whose
-// block sums are combined per vertex afterwards.
+// The triangle count's slab plan built over all arcs: block i < slab_grid
+// works on slab i mod kSlabs, so each XCD gathers the rows of an eighth of
+// the vertices. A vertex with at most kSliceMin arcs ("whole") is summed by
+// one group of kSlabWholeGroup lanes, which writes its coefficient. A sliced
+// vertex's items write their sums to part[x * n_sliced + rank[v]] (zero where
+// it has no arcs in slab x) and its heavy chunks to chunk_part; then
+// k_cc_slab_combine adds them in slab order, then chunk order.
 template <int W, bool OR>
-__global__ __launch_bounds__(kBlock) void k_bf_cc_plan(PlanView P, SkView s, const int32_t* __restrict__ off,
+__global__ __launch_bounds__(kBlock) void k_bf_cc_slab(SlabPlan P, SkView s, const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ adj, float* __restrict__ cc,
-                                                       double* __restrict__ vsum, double* __restrict__ part) {
+                                                       double* __restrict__ vsum, double* __restrict__ part,
+                                                       double* __restrict__ chunk_part) {
+  const bool whole = (int64_t)blockIdx.x >= P.slab_grid;
+  const int x = (int)(blockIdx.x % kSlabs);
+  const int64_t blk = whole ? (int64_t)blockIdx.x - P.slab_grid : (int64_t)(blockIdx.x / kSlabs);
+  const int64_t n_chunks = whole ? 0 : P.n_chunks[x];
+  const int64_t n_medium_blocks = whole ? 0 : (P.n_medium[x] + 3) / 4;
+  if (!whole && blk >= slab_blocks(P, x)) return;
   extern __shared__ double tab[];
   __shared__ double red[kBlock / kWave];
   for (uint32_t i = threadIdx.x; i <= s.size; i += kBlock) tab[i] = s.table[i];
   __syncthreads();
   constexpr int U = RowUnroll<W>::value;
-  const int64_t blk = blockIdx.x;
+  const size_t n = (size_t)s.n;
   const int tid = threadIdx.x;
-  if (blk < P.n_chunks) {
-    const double acc = bf_item<W, U, kBlock, OR>(s, P.chunk_vertex[blk], adj, P.chunk_begin[blk], P.chunk_end[blk],
-                                                 tid, tab);
+  if (whole) {
+    const int64_t idx = (blk * kBlock + tid) / kSlabWholeGroup;
+    int32_t v = -1;
+    double acc = 0.0;
+    if (idx < P.n_whole) {
+      v = P.verts[P.whole_at + idx];
+      acc = bf_item<W, U, kSlabWholeGroup, OR>(s, v, adj, off[v], off[v + 1], tid % kSlabWholeGroup, tab);
+    }
+    const double tot = group_sum<kSlabWholeGroup>(acc);
+    if (v >= 0 && tid % kSlabWholeGroup == 0) {
+      const int32_t d = s.deg[v];
+      cc[v] = (float)(d >= 2 ? tot / ((double)d * ((double)d - 1.0)) : 0.0);
+      if (vsum) vsum[v] = tot;
+    }
+  } else if (blk < n_chunks) {  // heavy chunk: the whole block
+    const int64_t c = P.chunk_at[x] + blk;
+    const double acc =
+        bf_item<W, U, kBlock, OR>(s, P.chunk_vertex[c], adj, P.chunk_begin[c], P.chunk_end[c], tid, tab);
     const double r = block_sum_256(acc, red);
-    if (tid == 0) part[blk] = r;
+    if (tid == 0) chunk_part[c] = r;
+  } else if (blk - n_chunks < n_medium_blocks) {  // medium: one wave per item
+    const int64_t idx = (blk - n_chunks) * (kBlock / kWave) + tid / kWave;
+    int32_t v = -1;
+    double acc = 0.0;
+    if (idx < P.n_medium[x]) {
+      v = P.verts[P.medium_at[x] + idx];
+      acc = bf_item<W, U, kWave, OR>(s, v, adj, slab_begin(off, P.split, n, x, v), slab_end(off, P.split, n, x, v),
+                                     lane_id(), tab);
+    }
+    const double tot = group_sum<kWave>(acc);
+    if (v >= 0 && lane_id() == 0) part[(size_t)x * (size_t)P.n_sliced + (size_t)P.rank[v]] = tot;
+  } else {  // light: kSlabLightGroup lanes per item
+    const int64_t idx = ((blk - n_chunks - n_medium_blocks) * kBlock + tid) / kSlabLightGroup;
+    int32_t v = -1;
+    double acc = 0.0;
+    if (idx < P.n_light[x]) {
+      v = P.verts[P.light_at[x] + idx];
+      acc = bf_item<W, U, kSlabLightGroup, OR>(s, v, adj, slab_begin(off, P.split, n, x, v),
+                                                slab_end(off, P.split, n, x, v), tid % kSlabLightGroup, tab);
+    }
+    const double tot = group_sum<kSlabLightGroup>(acc);
+    if (v >= 0 && tid % kSlabLightGroup == 0) part[(size_t)x * (size_t)P.n_sliced + (size_t)P.rank[v]] = tot;
+  }
+}
+
+// Coefficients of the sliced vertices from their item and chunk sums, and of
+// the vertices without arcs (0); whole vertices were written by k_bf_cc_slab.
+__global__ void k_cc_slab_combine(SlabPlan P, int32_t n, const int32_t* __restrict__ deg,
+                                  const double* __restrict__ part, const double* __restrict__ chunk_part,
+                                  float* __restrict__ cc, double* __restrict__ vsum) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t r = P.rank[v];
+  const int32_t d = deg[v];
+  if (r < 0) {
+    if (d == 0) {
+      cc[v] = 0.0f;
+      if (vsum) vsum[v] = 0.0;
+    }
     return;
   }
-  const int64_t mb = blk - P.n_chunks;
-  int32_t v = -1;
   double tot = 0.0;
-  bool lead = false;
-  if (mb < P.n_medium_blocks) {  // one wave per vertex
-    const int64_t idx = mb * (kBlock / kWave) + tid / kWave;
-    double acc = 0.0;
-    if (idx < P.n_medium) {
-      v = P.medium[idx];
-      acc = bf_item<W, U, kWave, OR>(s, v, adj, off[v], off[v + 1], lane_id(), tab);
-    }
-    tot = group_sum<kWave>(acc);
-    lead = lane_id() == 0;
-  } else {  // light: kWholeGroup lanes per vertex, natural order
-    const int64_t idx = ((mb - P.n_medium_blocks) * kBlock + tid) / kWholeGroup;
-    double acc = 0.0;
-    if (idx < P.n_light) {
-      const int32_t u = P.light ? P.light[idx] : (int32_t)idx;
-      if (off[u + 1] - off[u] <= kLightMax) {
-        v = u;
-        acc = bf_item<W, U, kWholeGroup, OR>(s, v, adj, off[v], off[v + 1], tid % kWholeGroup, tab);
-      }
-    }
-    tot = group_sum<kWholeGroup>(acc);
-    lead = tid % kWholeGroup == 0;
-  }
-  if (v >= 0 && lead) {
-    const int32_t d = s.deg[v];
-    cc[v] = (float)(d >= 2 ? tot / ((double)d * ((double)d - 1.0)) : 0.0);
-    if (vsum) vsum[v] = tot;
-  }
+#pragma unroll
+  for (int x = 0; x < kSlabs; ++x) tot += part[(size_t)x * (size_t)P.n_sliced + (size_t)r];
+  for (int32_t i = P.chunk_ptr[r]; i < P.chunk_ptr[r + 1]; ++i) tot += chunk_part[P.chunk_list[i]];
+  cc[v] = (float)(d >= 2 ? tot / ((double)d * ((double)d - 1.0)) : 0.0);
+  if (vsum) vsum[v] = tot;
 }
 
 // k-hash clustering coefficient over the same plan: the triangle count's
@@ -1265,46 +1304,52 @@ int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStre
     return dfree(part, s);
   }
   if (sk->kind == PG_BF && sk->W <= 16) {
-    const VertexPlan& P = g->plan_all;
-    const PlanView pv = plan_view(P);
-    const int64_t nblk = P.n_chunks + pv.n_medium_blocks + (P.n_light * kWholeGroup + kBlock - 1) / kBlock;
-    if (nblk <= 0) return PG_OK;
+    PG_TRY(graph_slabs_all(const_cast<pg_graph*>(g), s));
+    const SlabPlan& P = g->slabs_all;
+    const int64_t nblk = slab_plan_blocks(P);
     if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one launch");
+    int64_t n_chunks = 0;
+    for (int x = 0; x < kSlabs; ++x) n_chunks += P.n_chunks[x];
+    const int64_t n_part = (int64_t)kSlabs * P.n_sliced;
     double* part = nullptr;
-    PG_TRY(dmalloc((void**)&part, sizeof(double) * (size_t)std::max<int64_t>(P.n_chunks, 1), s));
+    PG_TRY(dmalloc((void**)&part, sizeof(double) * (size_t)std::max<int64_t>(n_part + n_chunks, 1), s));
+    double* chunk_part = part + n_part;
+    if (n_part > 0) PG_TRY(fill_u64(reinterpret_cast<uint64_t*>(part), 0, n_part, s));  // 0.0 where v has no item
     const size_t shmem = sizeof(double) * ((size_t)sk->size + 1);
-#define PG_CCP(WW)                                                                                                 \
-  do {                                                                                                             \
-    if (est == PG_EST_BF_OR)                                                                                       \
-      hipLaunchKernelGGL((k_bf_cc_plan<WW, true>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, pv, view, g->off, \
-                         g->adj, cc, vsum, part);                                                                  \
-    else                                                                                                           \
-      hipLaunchKernelGGL((k_bf_cc_plan<WW, false>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, pv, view,        \
-                         g->off, g->adj, cc, vsum, part);                                                          \
+    if (nblk > 0) {
+#define PG_CCS(WW)                                                                                                   \
+  do {                                                                                                               \
+    if (est == PG_EST_BF_OR)                                                                                         \
+      hipLaunchKernelGGL((k_bf_cc_slab<WW, true>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, P, view, g->off,    \
+                         g->adj, cc, vsum, part, chunk_part);                                                        \
+    else                                                                                                             \
+      hipLaunchKernelGGL((k_bf_cc_slab<WW, false>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, P, view, g->off,   \
+                         g->adj, cc, vsum, part, chunk_part);                                                        \
   } while (0)
-    switch (sk->W) {
-      case 1: PG_CCP(1); break;
-      case 2: PG_CCP(2); break;
-      case 3: PG_CCP(3); break;
-      case 4: PG_CCP(4); break;
-      case 5: PG_CCP(5); break;
-      case 6: PG_CCP(6); break;
-      case 7: PG_CCP(7); break;
-      case 8: PG_CCP(8); break;
-      case 9: PG_CCP(9); break;
-      case 10: PG_CCP(10); break;
-      case 11: PG_CCP(11); break;
-      case 12: PG_CCP(12); break;
-      case 13: PG_CCP(13); break;
-      case 14: PG_CCP(14); break;
-      case 15: PG_CCP(15); break;
-      default: PG_CCP(16); break;
+      switch (sk->W) {
+        case 1: PG_CCS(1); break;
+        case 2: PG_CCS(2); break;
+        case 3: PG_CCS(3); break;
+        case 4: PG_CCS(4); break;
+        case 5: PG_CCS(5); break;
+        case 6: PG_CCS(6); break;
+        case 7: PG_CCS(7); break;
+        case 8: PG_CCS(8); break;
+        case 9: PG_CCS(9); break;
+        case 10: PG_CCS(10); break;
+        case 11: PG_CCS(11); break;
+        case 12: PG_CCS(12); break;
+        case 13: PG_CCS(13); break;
+        case 14: PG_CCS(14); break;
+        case 15: PG_CCS(15); break;
+        default: PG_CCS(16); break;
+      }
+#undef PG_CCS
+      PG_LAUNCH_CHECK();
     }
-#undef PG_CCP
-    PG_LAUNCH_CHECK();
-    if (P.n_heavy > 0) {
-      hipLaunchKernelGGL(k_cc_combine, dim3((unsigned)((P.n_heavy + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pv,
-                         (const double*)part, P.n_heavy, g->deg, cc, vsum);
+    if (g->n > 0) {
+      hipLaunchKernelGGL(k_cc_slab_combine, dim3((unsigned)((g->n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, P,
+                         g->n, (const int32_t*)g->deg, (const double*)part, (const double*)chunk_part, cc, vsum);
       PG_LAUNCH_CHECK();
     }
     return dfree(part, s);

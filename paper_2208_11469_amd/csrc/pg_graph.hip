@@ -407,7 +407,7 @@ __global__ void k_slab_split(const int32_t* __restrict__ off, const int32_t* __r
 
 // Sort key of listed items: ceil(arcs / bucket), the arcs of (x, v) for slab
 // x >= 0, else off[v+1] - ustart[v] (upper neighbours, or all of N_v when
-// ustart = off). At most 255 arcs.
+// ustart = off), at most 255 (longer items share the first place).
 __global__ void k_item_keys(const int32_t* __restrict__ verts, int64_t count, int x, int bucket,
                             const int32_t* __restrict__ off,
                             const int32_t* __restrict__ ustart, const int32_t* __restrict__ split, int32_t n,
@@ -417,7 +417,21 @@ __global__ void k_item_keys(const int32_t* __restrict__ verts, int64_t count, in
   const int32_t v = verts[i];
   const int64_t d = x < 0 ? off[v + 1] - ustart[v]
                           : slab_end(off, split, (size_t)n, x, v) - slab_begin(ustart, split, (size_t)n, x, v);
-  key[i] = (uint8_t)((d + bucket - 1) / bucket);  // ceil(d / bucket): 0 only without arcs
+  key[i] = (uint8_t)std::min<int64_t>((d + bucket - 1) / bucket, 255);  // ceil(d / bucket): 0 only without arcs
+}
+
+// Sliced vertices (more than kSliceMin arcs in [begin[v], off[v+1])) as 0/1.
+__global__ void k_sliced_flags(const int32_t* __restrict__ off, const int32_t* __restrict__ begin, int32_t n,
+                               int64_t* __restrict__ flag) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v < n) flag[v] = off[v + 1] - begin[v] > kSliceMin ? 1 : 0;
+}
+
+// Rank of each sliced vertex among them (its exclusive prefix), -1 otherwise.
+__global__ void k_sliced_rank(const int64_t* __restrict__ flag, const int64_t* __restrict__ pre, int32_t n,
+                              int32_t* __restrict__ rank) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v < n) rank[v] = flag[v] ? (int32_t)pre[v] : -1;
 }
 
 // Complemented 2-bit digit `pass` of a key: partitioning by it, least
@@ -693,8 +707,8 @@ int sort_light_list(int32_t* verts, int64_t count, int x, int bucket, pg_graph* 
 // Heavy-tier chunks: the arc ranges of `nh` listed vertices (read back from
 // the device) cut into pieces of at most kHeavyChunk arcs, appended to the
 // host vectors. `slot` numbers the vertices from slot0.
-int heavy_chunks(const int32_t* d_verts, int64_t nh, pg_graph* g, const int32_t* split, int x, int32_t slot0,
-                 std::vector<int32_t>& cv,
+int heavy_chunks(const int32_t* d_verts, int64_t nh, pg_graph* g, const int32_t* begin, const int32_t* split, int x,
+                 int32_t slot0, std::vector<int32_t>& cv,
                  std::vector<int64_t>& cb, std::vector<int64_t>& ce, std::vector<int32_t>& cslot,
                  std::vector<int32_t>& first, hipStream_t s) {
   if (nh <= 0) return PG_OK;
@@ -703,7 +717,7 @@ int heavy_chunks(const int32_t* d_verts, int64_t nh, pg_graph* g, const int32_t*
   int64_t* d_ranges = nullptr;
   PG_TRY(dmalloc((void**)&d_ranges, sizeof(int64_t) * 2 * nh, s));
   hipLaunchKernelGGL(k_heavy_ranges, dim3((unsigned)((nh + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d_verts, nh,
-                     g->off, g->ustart, split, g->n, x, d_ranges);
+                     g->off, begin, split, g->n, x, d_ranges);
   PG_LAUNCH_CHECK();
   PG_HIP(hipMemcpyAsync(ranges.data(), d_ranges, sizeof(int64_t) * 2 * nh, hipMemcpyDeviceToHost, s));
   PG_HIP(hipMemcpyAsync(hv.data(), d_verts, sizeof(int32_t) * nh, hipMemcpyDeviceToHost, s));
@@ -768,7 +782,7 @@ int build_plan(pg_graph* g, VertexPlan* P, hipStream_t s) {
   P->n_heavy = starts[4] - starts[3];
   std::vector<int32_t> cv, cslot, first;
   std::vector<int64_t> cb, ce;
-  PG_TRY(heavy_chunks(P->sorted + starts[3], P->n_heavy, g, nullptr, -1, 0, cv, cb, ce, cslot, first, s));
+  PG_TRY(heavy_chunks(P->sorted + starts[3], P->n_heavy, g, g->off, nullptr, -1, 0, cv, cb, ce, cslot, first, s));
   first.push_back((int32_t)cv.size());
   P->n_chunks = (int64_t)cv.size();
   PG_TRY(upload(&P->chunk_vertex, cv, s));
@@ -957,13 +971,19 @@ void free_slabs(SlabPlan* p) {
   pfree(p->chunk_vertex);
   pfree(p->chunk_begin);
   pfree(p->chunk_end);
+  pfree(p->rank);
+  pfree(p->chunk_ptr);
+  pfree(p->chunk_list);
   *p = SlabPlan();
 }
 
-int graph_slabs(pg_graph* g, hipStream_t s) {
-  SlabPlan& P = g->slabs;
-  if (P.split || g->n == 0) return PG_OK;
-  ProfScope ps(s, "slabs");
+namespace {
+
+// A slab plan over the arcs [begin[v], off[v+1]) of every vertex: the upper
+// neighbours (begin = ustart, the triangle count) or all of N_v (begin = off,
+// the clustering coefficient, which also gets the sliced vertices' ranks and
+// chunk lists).
+int build_slabs(pg_graph* g, const int32_t* begin, bool all, SlabPlan* out, hipStream_t s) {
   const int32_t n = g->n;
   SlabPlan Q;  // filled here, moved into the graph once complete
   int rc = [&]() -> int {
@@ -973,13 +993,13 @@ int graph_slabs(pg_graph* g, hipStream_t s) {
     int64_t* pre = cnt + n;
     int32_t* lo = (int32_t*)(pre + n);
     PG_TRY(fill_u64((uint64_t*)cnt, 0, n, s));
-    PG_FOR_BINS(k_in_sliced, g, s, g->off, g->ustart, g->adj, verts_, cnt_, (unsigned long long*)cnt);
+    PG_FOR_BINS(k_in_sliced, g, s, g->off, begin, g->adj, verts_, cnt_, (unsigned long long*)cnt);
     PG_TRY(exclusive_scan_i64(cnt, pre, n, s));
     hipLaunchKernelGGL(k_slab_bounds, dim3(1), dim3(64), 0, s, (const int64_t*)pre, (const int64_t*)cnt, n, lo);
     PG_LAUNCH_CHECK();
     PG_TRY(palloc((void**)&Q.split, sizeof(int32_t) * (size_t)(kSlabs - 1) * (size_t)n));
-    hipLaunchKernelGGL(k_slab_split, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, g->off, g->ustart, g->adj,
-                       n, (const int32_t*)lo, Q.split);
+    hipLaunchKernelGGL(k_slab_split, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, g->off, begin, g->adj, n,
+                       (const int32_t*)lo, Q.split);
     PG_LAUNCH_CHECK();
     PG_TRY(dfree(cnt, s));
     // 3. item tiers slab by slab, then the whole vertices
@@ -988,8 +1008,8 @@ int graph_slabs(pg_graph* g, hipStream_t s) {
     int32_t* sorted = nullptr;
     PG_TRY(dmalloc((void**)&keys, (size_t)nk, s));
     PG_TRY(dmalloc((void**)&sorted, sizeof(int32_t) * (size_t)nk, s));
-    hipLaunchKernelGGL(k_slab_keys, dim3((unsigned)((nk + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g->off,
-                       g->ustart, (const int32_t*)Q.split, n, keys);
+    hipLaunchKernelGGL(k_slab_keys, dim3((unsigned)((nk + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g->off, begin,
+                       (const int32_t*)Q.split, n, keys);
     PG_LAUNCH_CHECK();
     int64_t st[kSlabs + 1][kNumBins + 1];
     int64_t lists = 0;
@@ -1017,16 +1037,16 @@ int graph_slabs(pg_graph* g, hipStream_t s) {
       at += cnt_x;
     }
     for (int x = 0; x < kSlabs; ++x)
-      PG_TRY(sort_light_list(Q.verts + Q.light_at[x], Q.n_light[x], x, kSlabLightBucket, g, g->off, g->ustart,
-                             Q.split, s));
-    PG_TRY(sort_light_list(Q.verts + Q.whole_at, Q.n_whole, -1, kSlabWholeBucket, g, g->off, g->ustart, Q.split, s));
+      PG_TRY(sort_light_list(Q.verts + Q.light_at[x], Q.n_light[x], x, kSlabLightBucket, g, g->off, begin, Q.split,
+                             s));
+    PG_TRY(sort_light_list(Q.verts + Q.whole_at, Q.n_whole, -1, kSlabWholeBucket, g, g->off, begin, Q.split, s));
     // 5. heavy items in chunks
     std::vector<int32_t> cv, cslot, first;
     std::vector<int64_t> cb, ce;
     for (int x = 0; x < kSlabs; ++x) {
       Q.chunk_at[x] = (int64_t)cv.size();
-      PG_TRY(heavy_chunks(sorted + (size_t)x * n + st[x][3], st[x][4] - st[x][3], g, Q.split, x, 0, cv, cb, ce, cslot,
-                          first, s));
+      PG_TRY(heavy_chunks(sorted + (size_t)x * n + st[x][3], st[x][4] - st[x][3], g, begin, Q.split, x, 0, cv, cb, ce,
+                          cslot, first, s));
       Q.n_chunks[x] = (int64_t)cv.size() - Q.chunk_at[x];
     }
     int64_t busiest = 0;
@@ -1035,6 +1055,41 @@ int graph_slabs(pg_graph* g, hipStream_t s) {
     PG_TRY(upload(&Q.chunk_vertex, cv, s));
     PG_TRY(upload(&Q.chunk_begin, cb, s));
     PG_TRY(upload(&Q.chunk_end, ce, s));
+    std::vector<int32_t> cptr, clist;
+    if (all) {
+      // 6. ranks of the sliced vertices, and each one's chunks (whatever slab they are in)
+      int64_t* flag = nullptr;
+      PG_TRY(dmalloc((void**)&flag, sizeof(int64_t) * 2 * (size_t)n, s));
+      int64_t* pre = flag + n;
+      hipLaunchKernelGGL(k_sliced_flags, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g->off, begin,
+                         n, flag);
+      PG_LAUNCH_CHECK();
+      PG_TRY(exclusive_scan_i64(flag, pre, n, s));
+      PG_TRY(palloc((void**)&Q.rank, sizeof(int32_t) * (size_t)n));
+      hipLaunchKernelGGL(k_sliced_rank, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                         (const int64_t*)flag, (const int64_t*)pre, n, Q.rank);
+      PG_LAUNCH_CHECK();
+      std::vector<int32_t> rank_h((size_t)n);
+      int64_t last[2] = {0, 0};
+      PG_HIP(hipMemcpyAsync(rank_h.data(), Q.rank, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+      PG_HIP(hipMemcpyAsync(&last[0], flag + (n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      PG_HIP(hipMemcpyAsync(&last[1], pre + (n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      PG_HIP(hipStreamSynchronize(s));
+      PG_TRY(dfree(flag, s));
+      Q.n_sliced = last[0] + last[1];
+      cptr.assign((size_t)Q.n_sliced + 1, 0);
+      for (int32_t v : cv) {
+        const int32_t r = rank_h[(size_t)v];
+        if (r < 0) return fail(PG_E_DEVICE, "slab plan: a chunk of a vertex that is not sliced");
+        ++cptr[(size_t)r + 1];
+      }
+      for (int64_t r = 0; r < Q.n_sliced; ++r) cptr[(size_t)r + 1] += cptr[(size_t)r];
+      clist.assign(cv.size(), 0);
+      std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
+      for (size_t c = 0; c < cv.size(); ++c) clist[(size_t)fill[(size_t)rank_h[(size_t)cv[c]]]++] = (int32_t)c;
+      PG_TRY(upload(&Q.chunk_ptr, cptr, s));
+      PG_TRY(upload(&Q.chunk_list, clist, s));
+    }
     PG_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     PG_TRY(dfree(sorted, s));
     return dfree(keys, s);
@@ -1043,8 +1098,22 @@ int graph_slabs(pg_graph* g, hipStream_t s) {
     free_slabs(&Q);
     return rc;
   }
-  P = Q;
+  *out = Q;
   return PG_OK;
+}
+
+}  // namespace
+
+int graph_slabs(pg_graph* g, hipStream_t s) {
+  if (g->slabs.split || g->n == 0) return PG_OK;
+  ProfScope ps(s, "slabs");
+  return build_slabs(g, g->ustart, false, &g->slabs, s);
+}
+
+int graph_slabs_all(pg_graph* g, hipStream_t s) {
+  if (g->slabs_all.split || g->n == 0) return PG_OK;
+  ProfScope ps(s, "slabs");
+  return build_slabs(g, g->off, true, &g->slabs_all, s);
 }
 
 }  // namespace pg

@@ -173,6 +173,12 @@ struct SlabPlan {
   int32_t* chunk_vertex = nullptr;
   int64_t* chunk_begin = nullptr;
   int64_t* chunk_end = nullptr;
+  // clustering-coefficient plans (over all of N_v) only: where each sliced
+  // vertex's item sums go
+  int64_t n_sliced = 0;           // vertices with more than kSliceMin arcs
+  int32_t* rank = nullptr;        // [n] index among the sliced vertices, -1 for the others
+  int32_t* chunk_ptr = nullptr;   // [n_sliced + 1] a sliced vertex's chunks in chunk_list
+  int32_t* chunk_list = nullptr;  // chunk indices by sliced vertex, in chunk order
 };
 
 // Blocks of slab x (block i of the slab part serves slab i mod kSlabs).
@@ -218,6 +224,7 @@ struct pg_graph {
   int64_t* upoff = nullptr;    // [n+1] first upper-edge index of v (edges in CSR order)
   pg::VertexPlan plan_all;     // work over N_v (sketch builds, clustering coefficient)
   pg::SlabPlan slabs;          // triangle-count plan over XCD slabs (built on first use)
+  pg::SlabPlan slabs_all;      // clustering-coefficient plan over XCD slabs, all of N_v (built on first use)
   int32_t* eu = nullptr;       // [m] smaller endpoint of each undirected edge
   int32_t* ev = nullptr;       // [m] larger endpoint
   int32_t* arc_src = nullptr;  // [nnz] source vertex of each arc
@@ -261,6 +268,7 @@ int graph_arc_sources(pg_graph* g, hipStream_t s);
 int graph_orient(pg_graph* g, hipStream_t s);
 int graph_oriented(pg_graph* g, hipStream_t s);  // g->oriented (and the oriented CSR) on first use
 int graph_slabs(pg_graph* g, hipStream_t s);
+int graph_slabs_all(pg_graph* g, hipStream_t s);
 int build_plan(pg_graph* g, pg::VertexPlan* plan, hipStream_t s);
 void free_plan(pg::VertexPlan* plan);
 void free_slabs(pg::SlabPlan* plan);

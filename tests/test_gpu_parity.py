@@ -518,3 +518,26 @@ def test_reference_copy_kernel(ctx, nbytes):
     torch.cuda.synchronize()
     assert torch.equal(dst[:nbytes], src)
     assert int(dst[nbytes:].sum()) == 0  # nothing written past the end
+
+
+def test_cc_over_slabs_every_vertex(ctx):
+    """The clustering coefficient over XCD slabs of all of N_v: a 40,000-leaf
+    star (its items in every slab exceed the 2,048-arc chunk, so they run as
+    heavy chunks), an R-MAT graph (light and medium items, whole vertices) and
+    isolated vertices; every vertex against the oracle, for a ratio estimator
+    (AND) and one that reads the popcounts (OR), and the transitivity."""
+    g = pggen.disjoint_union(pggen.star(40000), pggen.rmat(12, 16, seed=5), pggen.er(50, 0, seed=1))
+    say(f"cc over slabs: n={g.n}")
+    dg = pg.Graph(ctx, g.offsets, g.adj, validate=True)
+    sk = dg.build_sketches("bf", 512, 1, seed=2)
+    ref = oracle.build_sketches(g, oracle.KIND_BF, 512, 1, seed=2)
+    for est in ("and", "or"):
+        cc, trans = sk.cc(est, transitivity=True)
+        torch.cuda.synchronize()
+        _close32(np_(cc), oracle.cc(ref, est))
+        wedges = float(np.sum(g.degrees() * (g.degrees() - 1) // 2))
+        _close([trans], [3 * oracle.tc(ref, est) / wedges], rtol=1e-9)
+        again = sk.cc(est)
+        assert torch.equal(cc, again)  # the same bits on a second call
+    sk.close()
+    dg.close()
