@@ -238,6 +238,127 @@ __device__ __forceinline__ double bf_row_sum(const SkView& s, const uint64_t (&r
   return acc;
 }
 
+// Per-edge outputs of one group's upper neighbours adj[beg, end) of v (the
+// pair kernel's values, bit for bit): edge e = ebase + p of position p gets
+// the estimate, the raw count (the AND count, or for OR the ones of the OR)
+// and the similarity `measure` (each output only if its pointer is set).
+template <int W, int U, int G, bool OR>
+__device__ __forceinline__ void bf_row_emit(const SkView& s, const uint64_t (&ru)[TcTeam<W, G>::words], int32_t du,
+                                            uint32_t pcu, const int32_t* __restrict__ adj, int64_t beg,
+                                            int64_t end, int lane, const double* __restrict__ tab, int64_t ebase,
+                                            double* __restrict__ est_out, uint32_t* __restrict__ raw_out,
+                                            float* __restrict__ sim_out, int measure) {
+  constexpr int T = TcTeam<W, G>::value;
+  constexpr int Q = TcTeam<W, G>::words;
+  constexpr int NT = G / T;
+  const int k = lane % T;
+  const bool reads = k * Q < W;
+  for (int64_t p0 = beg + lane / T; p0 < end; p0 += (int64_t)NT * U) {
+    int32_t x[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int64_t p = p0 + (int64_t)j * NT;
+      x[j] = p < end ? adj[p] : -1;
+    }
+    uint64_t rv[U][Q];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (x[j] >= 0 && reads) {
+        const uint64_t* r = s.words + bf_row_offset(x[j], W) + k * Q;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) rv[j][i] = r[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) rv[j][i] = 0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) c += (uint32_t)__popcll(ru[i] & rv[j][i]);
+      c = team_sum<T>(c);
+      if (k == 0 && x[j] >= 0) {
+        const int64_t e = ebase + p0 + (int64_t)j * NT;
+        uint32_t raw = c;
+        double est;
+        if constexpr (OR) {
+          raw = pcu + s.pc[x[j]] - c;
+          est = ((double)du + (double)s.deg[x[j]]) + tab[raw];
+        } else {
+          est = tab[c];
+        }
+        if (est_out) est_out[e] = est;
+        if (raw_out) raw_out[e] = raw;
+        if (sim_out) sim_out[e] = (float)similarity_of(measure, est, du, s.deg[x[j]]);
+      }
+    }
+  }
+}
+
+template <int W, int U, int G, bool OR>
+__device__ __forceinline__ void bf_item_emit(const SkView& s, int32_t v, const int32_t* __restrict__ adj,
+                                             int64_t beg, int64_t end, int lane, const double* __restrict__ tab,
+                                             int64_t ebase, double* __restrict__ est_out,
+                                             uint32_t* __restrict__ raw_out, float* __restrict__ sim_out,
+                                             int measure) {
+  uint64_t ru[TcTeam<W, G>::words];
+  load_team_row<W, G>(s.words, v, lane % TcTeam<W, G>::value, ru);
+  bf_row_emit<W, U, G, OR>(s, ru, s.deg[v], OR ? s.pc[v] : 0u, adj, beg, end, lane, tab, ebase, est_out, raw_out,
+                           sim_out, measure);
+}
+
+// All upper edges over the triangle count's slab plan, with per-edge outputs
+// at the edges' CSR order (edge upoff[v] + p - ustart[v] at position p).
+template <int W, bool OR>
+__global__ __launch_bounds__(kBlock) void k_bf_edges_slab(SlabPlan P, SkView s, const int32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ ustart,
+                                                          const int32_t* __restrict__ adj,
+                                                          const int64_t* __restrict__ upoff,
+                                                          double* __restrict__ est_out, uint32_t* __restrict__ raw_out,
+                                                          float* __restrict__ sim_out, int measure) {
+  const bool whole = (int64_t)blockIdx.x >= P.slab_grid;
+  const int x = (int)(blockIdx.x % kSlabs);
+  const int64_t blk = whole ? (int64_t)blockIdx.x - P.slab_grid : (int64_t)(blockIdx.x / kSlabs);
+  const int64_t n_chunks = whole ? 0 : P.n_chunks[x];
+  const int64_t n_medium_blocks = whole ? 0 : (P.n_medium[x] + 3) / 4;
+  if (!whole && blk >= slab_blocks(P, x)) return;
+  extern __shared__ double tab[];
+  for (uint32_t i = threadIdx.x; i <= s.size; i += kBlock) tab[i] = s.table[i];
+  __syncthreads();
+  constexpr int U = RowUnroll<W>::value;
+  const size_t n = (size_t)s.n;
+  const int tid = threadIdx.x;
+  if (whole) {
+    const int64_t idx = (blk * kBlock + tid) / kSlabWholeGroup;
+    if (idx < P.n_whole) {
+      const int32_t v = P.verts[P.whole_at + idx];
+      bf_item_emit<W, U, kSlabWholeGroup, OR>(s, v, adj, ustart[v], off[v + 1], tid % kSlabWholeGroup, tab,
+                                              upoff[v] - ustart[v], est_out, raw_out, sim_out, measure);
+    }
+  } else if (blk < n_chunks) {
+    const int64_t c = P.chunk_at[x] + blk;
+    const int32_t v = P.chunk_vertex[c];
+    bf_item_emit<W, U, kBlock, OR>(s, v, adj, P.chunk_begin[c], P.chunk_end[c], tid, tab, upoff[v] - ustart[v],
+                                   est_out, raw_out, sim_out, measure);
+  } else if (blk - n_chunks < n_medium_blocks) {
+    const int64_t idx = (blk - n_chunks) * (kBlock / kWave) + tid / kWave;
+    if (idx < P.n_medium[x]) {
+      const int32_t v = P.verts[P.medium_at[x] + idx];
+      bf_item_emit<W, U, kWave, OR>(s, v, adj, slab_begin(ustart, P.split, n, x, v), slab_end(off, P.split, n, x, v),
+                                    lane_id(), tab, upoff[v] - ustart[v], est_out, raw_out, sim_out, measure);
+    }
+  } else {
+    const int64_t idx = ((blk - n_chunks - n_medium_blocks) * kBlock + tid) / kSlabLightGroup;
+    if (idx < P.n_light[x]) {
+      const int32_t v = P.verts[P.light_at[x] + idx];
+      bf_item_emit<W, U, kSlabLightGroup, OR>(s, v, adj, slab_begin(ustart, P.split, n, x, v),
+                                              slab_end(off, P.split, n, x, v), tid % kSlabLightGroup, tab,
+                                              upoff[v] - ustart[v], est_out, raw_out, sim_out, measure);
+    }
+  }
+}
+
 // Block i < slab_grid serves slab x = i mod kSlabs (the XCD it runs on) and
 // works on the (i / kSlabs)-th block of that slab's plan; the slab part is
 // sized for the busiest slab and surplus blocks of the other slabs write a
@@ -1061,6 +1182,49 @@ int estimate_pairs(const pg_sketches* sk, int est, const int32_t* u, const int32
     return fail(PG_E_INVALID, "unknown similarity measure");
   if (npairs <= 0) return PG_OK;
   const SkView view = make_view(sk, est);
+  const pg_graph* g = sk->g;
+  if (sk->kind == PG_BF && sk->W <= 16 && u == g->eu && v == g->ev && npairs == g->m) {
+    // all upper edges (the caller passed none): walk the triangle count's
+    // XCD slab plan and write each edge's values at its CSR position
+    PG_TRY(graph_slabs(const_cast<pg_graph*>(g), s));
+    const SlabPlan& P = g->slabs;
+    const int64_t nblk = slab_plan_blocks(P);
+    if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one launch");
+    const size_t shmem = sizeof(double) * ((size_t)sk->size + 1);
+    ProfScope ps(s, "edges");
+#define PG_EDS(WW)                                                                                                     \
+  do {                                                                                                                 \
+    if (est == PG_EST_BF_OR)                                                                                           \
+      hipLaunchKernelGGL((k_bf_edges_slab<WW, true>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, P, view, g->off,   \
+                         g->ustart, g->adj, (const int64_t*)g->upoff, est_out, raw_out, sim_out, measure);             \
+    else                                                                                                               \
+      hipLaunchKernelGGL((k_bf_edges_slab<WW, false>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, P, view, g->off,  \
+                         g->ustart, g->adj, (const int64_t*)g->upoff, est_out, raw_out, sim_out, measure);             \
+  } while (0)
+    if (nblk > 0) {
+      switch (sk->W) {
+        case 1: PG_EDS(1); break;
+        case 2: PG_EDS(2); break;
+        case 3: PG_EDS(3); break;
+        case 4: PG_EDS(4); break;
+        case 5: PG_EDS(5); break;
+        case 6: PG_EDS(6); break;
+        case 7: PG_EDS(7); break;
+        case 8: PG_EDS(8); break;
+        case 9: PG_EDS(9); break;
+        case 10: PG_EDS(10); break;
+        case 11: PG_EDS(11); break;
+        case 12: PG_EDS(12); break;
+        case 13: PG_EDS(13); break;
+        case 14: PG_EDS(14); break;
+        case 15: PG_EDS(15); break;
+        default: PG_EDS(16); break;
+      }
+      PG_LAUNCH_CHECK();
+    }
+#undef PG_EDS
+    return PG_OK;
+  }
   const unsigned grid = grid_for(npairs, kBlock, 65536);
   ProfScope ps(s, "pairs");
 #define PG_LAUNCH_PAIRS(KIND, WT)                                                                                   \
