@@ -574,6 +574,65 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
   for (int64_t t = taken + lane; t < (int64_t)k; t += kWave) row[t] = kBottom;
 }
 
+// Vertices of at most D arcs (and k >= D): every element is kept, so the row
+// is N_v in ascending key order, then kBottom. G lanes per vertex hash its
+// elements into the group's LDS slice, rank them (keys are distinct) and
+// write the row in 16-byte pieces when k is a multiple of 4. A wave per such
+// small vertex spent most of its time starting and finishing (R-MAT s24,
+// k = 64: 21.6 -> 17.5 ms for the whole build; a second tier of 16 lanes for
+// 17..64 arcs changed nothing, the radix selection of the larger vertices
+// takes the rest).
+constexpr int kOhSmall = 16;  // degree bin 0: 4 lanes per vertex
+
+template <int G, int D>
+__global__ __launch_bounds__(kBlock) void k_oh_build_small(const int32_t* __restrict__ off,
+                                                           const int32_t* __restrict__ adj,
+                                                           const int32_t* __restrict__ verts, int64_t nverts,
+                                                           uint32_t k, uint64_t a, uint64_t c,
+                                                           uint32_t* __restrict__ sig) {
+  static_assert(kWave % G == 0, "groups lie inside one wave");
+  __shared__ uint64_t skey[kBlock / G][D];
+  __shared__ uint32_t sid[kBlock / G][D];
+  __shared__ uint32_t sorted[kBlock / G][D];
+  const int grp = threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  const int64_t gi = blockIdx.x * (int64_t)(kBlock / G) + grp;
+  const int32_t v = gi < nverts ? verts[gi] : 0;
+  const int64_t beg = gi < nverts ? off[v] : 0;
+  const int64_t dv = gi < nverts ? off[v + 1] - beg : 0;
+  const bool active = gi < nverts && dv <= D;
+  const int d = active ? (int)dv : 0;
+  for (int t = lane; t < d; t += G) {
+    const uint32_t x = (uint32_t)adj[beg + t];
+    skey[grp][t] = mh_key(a, c, x);
+    sid[grp][t] = x;
+  }
+  wave_sync();
+  for (int t = lane; t < d; t += G) {
+    const uint64_t key = skey[grp][t];
+    int r = 0;
+    for (int q = 0; q < d; ++q) r += skey[grp][q] < key ? 1 : 0;
+    sorted[grp][r] = sid[grp][t];
+  }
+  wave_sync();
+  if (!active) return;
+  uint32_t* row = sig + (size_t)v * k;
+  if (k % 4 == 0) {
+    uint4* row4 = reinterpret_cast<uint4*>(row);
+    for (uint32_t q = (uint32_t)lane; q < k / 4; q += G) {
+      uint32_t e[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t i = 4 * q + (uint32_t)j;
+        e[j] = i < (uint32_t)d ? sorted[grp][i] : kBottom;
+      }
+      row4[q] = make_uint4(e[0], e[1], e[2], e[3]);
+    }
+  } else {
+    for (uint32_t i = (uint32_t)lane; i < k; i += G) row[i] = i < (uint32_t)d ? sorted[grp][i] : kBottom;
+  }
+}
+
 // Dense copy of the rows (row v at v * W words) for export.
 __global__ void k_bf_unpack(const uint64_t* __restrict__ words, int64_t n, uint32_t W, uint64_t* __restrict__ out) {
   const int64_t total = n * (int64_t)W;
@@ -755,10 +814,21 @@ int build_onehash(pg_sketches* sk, hipStream_t s) {
   uint64_t a = 0, c = 0;
   hash_constants(PG_MH_1HASH, sk->seed, 1, &a, &c);
   ProfScope ps(s, "oh_build");
-  // all vertices, in bin order (degree-sorted blocks balance better)
-  hipLaunchKernelGGL(k_oh_build, dim3((unsigned)((nv + kOhWaves - 1) / kOhWaves)), dim3(kBlock), shmem, s, g->off,
-                     g->adj, g->bin_verts, nv, sk->size, a, c, sk->sig);
-  PG_LAUNCH_CHECK();
+  // vertices of at most kOhSmall arcs (degree bin 0) four lanes each, the
+  // others a wave each, in bin order (degree-sorted blocks balance better)
+  static_assert(kBinMaxDeg[0] == kOhSmall, "bin 0 holds the small vertices");
+  const int64_t n0 = sk->size >= (uint32_t)kOhSmall ? g->bin_start[1] - g->bin_start[0] : 0;
+  if (n0 > 0) {
+    constexpr int G = 4;
+    hipLaunchKernelGGL((k_oh_build_small<G, kOhSmall>), dim3((unsigned)((n0 * G + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, g->off, g->adj, g->bin_verts, n0, sk->size, a, c, sk->sig);
+    PG_LAUNCH_CHECK();
+  }
+  if (nv - n0 > 0) {
+    hipLaunchKernelGGL(k_oh_build, dim3((unsigned)((nv - n0 + kOhWaves - 1) / kOhWaves)), dim3(kBlock), shmem, s,
+                       g->off, g->adj, g->bin_verts + n0, nv - n0, sk->size, a, c, sk->sig);
+    PG_LAUNCH_CHECK();
+  }
   return PG_OK;
 }
 
