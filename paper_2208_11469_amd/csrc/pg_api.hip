@@ -359,6 +359,11 @@ int make_sketches(pg_ctx* ctx, const pg_graph* gc, int kind, uint32_t size, uint
       const size_t slots = (size_t)size * (size_t)std::max<int64_t>(rows->plan_all.n_chunks, 1);
       rc = palloc((void**)&sk->scratch, sizeof(uint64_t) * (slots + (slots + 1) / 2));
     }
+    if (rc == PG_OK && kind == PG_MH_1HASH && size <= (uint32_t)kHeavyChunk && rows->plan_all.n_chunks > 0) {
+      // heavy vertices' chunk candidates: k elements per chunk
+      const size_t slots = (size_t)size * (size_t)rows->plan_all.n_chunks;
+      rc = palloc((void**)&sk->scratch, sizeof(uint64_t) * ((slots + 1) / 2));
+    }
     if (rc == PG_OK && build && g->n > 0) rc = kind == PG_MH_KHASH ? build_khash(sk, s) : build_onehash(sk, s);
   }
   if (rc != PG_OK) {

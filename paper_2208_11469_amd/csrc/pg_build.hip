@@ -410,30 +410,24 @@ __host__ __device__ constexpr size_t oh_wave_bytes(uint32_t k) {
 // collects the bin in LDS, where the remaining smallest keys are found by
 // rank counting. Every key is hashed twice when the first bin fits (d up to
 // about 100,000), once more per further pass.
-__global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
-                                                     const int32_t* __restrict__ verts, int64_t nverts, uint32_t k,
-                                                     uint64_t a, uint64_t c, uint32_t* __restrict__ sig) {
-  extern __shared__ unsigned char smem[];
-  const int wv = threadIdx.x / kWave;
+// The min(k, end - beg) elements of list[beg, end) with the smallest keys,
+// in ascending key order, to row[0 ..), then kBottom up to row[k - 1]; run
+// by one whole wave on its LDS slice.
+__device__ void oh_select(const uint32_t* __restrict__ list, int64_t beg, int64_t end, uint32_t k, uint64_t a,
+                          uint64_t c, uint32_t* __restrict__ row, unsigned char* __restrict__ slice) {
   const int lane = lane_id();
-  const size_t per_wave = oh_wave_bytes(k);
   // wave slice: [skey: k][ckey: cap] (8 bytes each), [sid: k][cid: cap][hist: 256] (4 bytes each)
   const uint32_t cap = oh_cand(k);
-  uint64_t* skey = (uint64_t*)(smem + wv * per_wave);
+  uint64_t* skey = (uint64_t*)slice;
   uint64_t* ckey = skey + k;
   uint32_t* sid = (uint32_t*)(ckey + cap);
   uint32_t* cid = sid + k;
   uint32_t* hist = cid + cap;
-  const int64_t grp = blockIdx.x * (int64_t)kOhWaves + wv;
-  if (grp >= nverts) return;
-  const int32_t v = verts[grp];
-  const int64_t beg = off[v], end = off[v + 1];
   const int64_t d = end - beg;
-  uint32_t* row = sig + (size_t)v * k;
   int64_t taken = 0;  // elements staged in skey/sid
   if (d <= (int64_t)k) {
     for (int64_t t = lane; t < d; t += kWave) {
-      const uint32_t x = (uint32_t)adj[beg + t];
+      const uint32_t x = list[beg + t];
       skey[t] = mh_key(a, c, x);
       sid[t] = x;
     }
@@ -448,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       for (int64_t t = beg + lane; t < end; t += kWave) {
-        const uint64_t key = mh_key(a, c, (uint32_t)adj[t]);
+        const uint64_t key = mh_key(a, c, list[t]);
         if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -500,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
           uint64_t key = 0;
           uint32_t x = 0;
           if (t < end) {
-            x = (uint32_t)adj[t];
+            x = list[t];
             key = mh_key(a, c, x);
           }
           const bool lo = t < end && key < P;
@@ -546,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
       uint32_t x = 0;
       bool keep = false;
       if (t < end) {
-        x = (uint32_t)adj[t];
+        x = list[t];
         key = mh_key(a, c, x);
         keep = key <= prefix;
       }
@@ -572,6 +566,50 @@ __global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__
     row[r] = sid[t];
   }
   for (int64_t t = taken + lane; t < (int64_t)k; t += kWave) row[t] = kBottom;
+}
+
+__device__ __forceinline__ unsigned char* oh_slice(uint32_t k) {
+  extern __shared__ unsigned char smem[];
+  return smem + (threadIdx.x / kWave) * oh_wave_bytes(k);
+}
+
+// One wave per listed vertex; vertices of more than max_deg arcs are left to
+// the chunk kernels.
+__global__ __launch_bounds__(kBlock) void k_oh_build(const int32_t* __restrict__ off, const int32_t* __restrict__ adj,
+                                                     const int32_t* __restrict__ verts, int64_t nverts, uint32_t k,
+                                                     uint64_t a, uint64_t c, uint32_t* __restrict__ sig,
+                                                     int64_t max_deg) {
+  const int64_t grp = blockIdx.x * (int64_t)kOhWaves + threadIdx.x / kWave;
+  if (grp >= nverts) return;
+  const int32_t v = verts[grp];
+  const int64_t beg = off[v], end = off[v + 1];
+  if (end - beg > max_deg) return;
+  oh_select(reinterpret_cast<const uint32_t*>(adj), beg, end, k, a, c, sig + (size_t)v * k, oh_slice(k));
+}
+
+// Heavy vertices: one wave per work-plan chunk writes the chunk's smallest
+// min(k, arcs) elements to cand[chunk * k ..]; then one wave per heavy vertex
+// selects the k smallest among its chunks' candidates, which hold them (the
+// k smallest of a union are among the k smallest of each part). Every chunk
+// but a vertex's last has kHeavyChunk >= k arcs, so a vertex's candidates are
+// contiguous.
+__global__ __launch_bounds__(kBlock) void k_oh_build_chunks(PlanView P, const int32_t* __restrict__ adj, uint32_t k,
+                                                            uint64_t a, uint64_t c, uint32_t* __restrict__ cand) {
+  const int64_t ch = blockIdx.x * (int64_t)kOhWaves + threadIdx.x / kWave;
+  if (ch >= P.n_chunks) return;
+  oh_select(reinterpret_cast<const uint32_t*>(adj), P.chunk_begin[ch], P.chunk_end[ch], k, a, c, cand + (size_t)ch * k,
+            oh_slice(k));
+}
+
+__global__ __launch_bounds__(kBlock) void k_oh_build_combine(PlanView P, int64_t n_heavy,
+                                                             const uint32_t* __restrict__ cand, uint32_t k, uint64_t a,
+                                                             uint64_t c, uint32_t* __restrict__ sig) {
+  const int64_t h = blockIdx.x * (int64_t)kOhWaves + threadIdx.x / kWave;
+  if (h >= n_heavy) return;
+  const int32_t c0 = P.heavy_first[h], c1 = P.heavy_first[h + 1];
+  const int64_t last = P.chunk_end[c1 - 1] - P.chunk_begin[c1 - 1];
+  const int64_t end = (int64_t)(c1 - 1) * k + (last < (int64_t)k ? last : (int64_t)k);
+  oh_select(cand, (int64_t)c0 * k, end, k, a, c, sig + (size_t)P.chunk_vertex[c0] * k, oh_slice(k));
 }
 
 // Vertices of at most D arcs (and k >= D): every element is kept, so the row
@@ -824,9 +862,24 @@ int build_onehash(pg_sketches* sk, hipStream_t s) {
                        dim3(kBlock), 0, s, g->off, g->adj, g->bin_verts, n0, sk->size, a, c, sk->sig);
     PG_LAUNCH_CHECK();
   }
+  // heavy vertices in the work plan's chunks when k fits a chunk (the scratch
+  // then holds k candidates per chunk)
+  const VertexPlan& P = g->plan_all;
+  const bool chunked = P.n_chunks > 0 && sk->size <= (uint32_t)kHeavyChunk && sk->scratch;
   if (nv - n0 > 0) {
     hipLaunchKernelGGL(k_oh_build, dim3((unsigned)((nv - n0 + kOhWaves - 1) / kOhWaves)), dim3(kBlock), shmem, s,
-                       g->off, g->adj, g->bin_verts + n0, nv - n0, sk->size, a, c, sk->sig);
+                       g->off, g->adj, g->bin_verts + n0, nv - n0, sk->size, a, c, sk->sig,
+                       chunked ? (int64_t)kMediumMax : INT64_MAX);
+    PG_LAUNCH_CHECK();
+  }
+  if (chunked) {
+    const PlanView pv = plan_view(P);
+    uint32_t* cand = reinterpret_cast<uint32_t*>(sk->scratch);
+    hipLaunchKernelGGL(k_oh_build_chunks, dim3((unsigned)((P.n_chunks + kOhWaves - 1) / kOhWaves)), dim3(kBlock),
+                       shmem, s, pv, g->adj, sk->size, a, c, cand);
+    PG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_oh_build_combine, dim3((unsigned)((P.n_heavy + kOhWaves - 1) / kOhWaves)), dim3(kBlock),
+                       shmem, s, pv, P.n_heavy, (const uint32_t*)cand, sk->size, a, c, sk->sig);
     PG_LAUNCH_CHECK();
   }
   return PG_OK;

@@ -258,6 +258,7 @@ struct pg_sketches {
   bool empty_rows_zero = false;  // Bloom filters: the rows of vertices without arcs are known to be zero
   uint64_t* scratch = nullptr;    // heavy-chunk partials: Bloom-filter rows (n_chunks * W words) or
                                   // k-hash (key, element) pairs (n_chunks * k keys, then n_chunks * k uint32)
+                                  // or 1-hash candidates (n_chunks * k uint32, when k <= kHeavyChunk)
 };
 
 namespace pg {
