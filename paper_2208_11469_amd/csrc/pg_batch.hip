@@ -56,6 +56,12 @@ struct GraphDesc {
   int32_t pad;
 };
 
+// The estimate items of one row width, split by XCD: XCD x takes
+// eitems[at[x] .. at[x + 1]).
+struct XQueues {
+  int64_t at[kSlabs + 1];
+};
+
 struct Item {
   int32_t graph;
   int32_t heavy;  // 1: the single vertex v0 with a whole block
@@ -77,14 +83,16 @@ struct BatchView {
   double* S;
   double* Splus;
   float* cc;
-  uint32_t* counters;  // [0] build queue, [1 + W] estimate queue of row width W
+  uint32_t* counters;  // [0] build queue, [1 + W * kSlabs + x] estimate queue of row width W on XCD x
 };
 
-constexpr int kCounters = 2 + kMaxW;
+// [0] the build queue, then per row width W one estimate queue per XCD
+// (slab): counter 1 + W * kSlabs + x
+constexpr int kCounters = 1 + (kMaxW + 1) * kSlabs;
 constexpr int kBranches = 4;  // concurrent estimate streams (the box's hardware queues per process)
 
 __global__ void k_batch_reset(uint32_t* counters) {
-  if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kCounters; i += blockDim.x) counters[i] = 0;
 }
 
 // One block per graph: T_g[c] for c = 0..B_g (same formulas as the single-graph tables).
@@ -260,13 +268,14 @@ __device__ __forceinline__ void vertex_sums(const BatchView& bv, const GraphDesc
 
 // Estimate items [begin, end) of one row width W (graphs with B = 64 W).
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_batch_estimate(BatchView bv, int64_t begin, int64_t end) {
+__global__ __launch_bounds__(kBlock) void k_batch_estimate(BatchView bv, XQueues q) {
   __shared__ double red[kBlock / kWave];
   __shared__ int64_t slot;
   const int tid = threadIdx.x;
+  const int x = (int)(blockIdx.x % kSlabs);  // the XCD the block runs on: it takes that XCD's graphs
   for (;;) {
-    const int64_t it = begin + next_item(&bv.counters[1 + W], &slot);
-    if (it >= end) return;
+    const int64_t it = q.at[x] + next_item(&bv.counters[1 + W * kSlabs + x], &slot);
+    if (it >= q.at[x + 1]) return;
     const Item item = bv.items[it];
     const GraphDesc gd = bv.gd[item.graph];
     if (item.heavy) {
@@ -348,6 +357,7 @@ struct pg_batch {
   int64_t nitems = 0;
   pg::Item* eitems = nullptr;  // estimate work list: by row width W, heaviest first inside
   int64_t w_begin[pg::kMaxW + 2] = {};  // items of width W: eitems[w_begin[W] .. w_begin[W + 1])
+  pg::XQueues xq[pg::kMaxW + 1] = {};   // of those, XCD x's: eitems[xq[W].at[x] .. xq[W].at[x + 1])
   int64_t* off = nullptr;
   int32_t* adj = nullptr;
   uint64_t* words = nullptr;
@@ -398,11 +408,30 @@ int build_items(pg_batch* bt) {
   std::vector<Item> items(list.size()), eitems;
   for (size_t i = 0; i < list.size(); ++i) items[i] = list[i].second;
   eitems.reserve(items.size());
+  // graphs of each row width dealt to the XCDs longest first, each to the
+  // XCD with the least work so far, so that a graph's rows stay in one L2
+  std::vector<int64_t> gcost((size_t)bt->count, 0);
+  for (const auto& pr : list) gcost[(size_t)pr.second.graph] += pr.first;
+  std::vector<int32_t> gorder((size_t)bt->count);
+  for (int32_t g = 0; g < bt->count; ++g) gorder[(size_t)g] = g;
+  std::stable_sort(gorder.begin(), gorder.end(), [&](int32_t a, int32_t b) { return gcost[(size_t)a] > gcost[(size_t)b]; });
+  std::vector<int8_t> gxcd((size_t)bt->count, 0);
+  int64_t xload[kMaxW + 1][kSlabs] = {};
+  for (int32_t g : gorder) {
+    int64_t* ld = xload[bt->h_gd[g].W];
+    const int x = (int)(std::min_element(ld, ld + kSlabs) - ld);
+    ld[x] += gcost[(size_t)g];
+    gxcd[(size_t)g] = (int8_t)x;
+  }
   for (int w = 0; w <= kMaxW + 1; ++w) bt->w_begin[w] = 0;
-  for (uint32_t w = 1; w <= (uint32_t)kMaxW; ++w) {  // stable: heaviest first inside a width
+  for (uint32_t w = 1; w <= (uint32_t)kMaxW; ++w) {  // stable: heaviest first inside a queue
     bt->w_begin[w] = (int64_t)eitems.size();
-    for (const Item& it : items)
-      if (bt->h_gd[it.graph].W == w) eitems.push_back(it);
+    for (int x = 0; x < kSlabs; ++x) {
+      bt->xq[w].at[x] = (int64_t)eitems.size();
+      for (const Item& it : items)
+        if (bt->h_gd[it.graph].W == w && gxcd[(size_t)it.graph] == x) eitems.push_back(it);
+    }
+    bt->xq[w].at[kSlabs] = (int64_t)eitems.size();
   }
   bt->w_begin[kMaxW + 1] = (int64_t)eitems.size();
   // work per row width (arcs times the row words each arc reads, plus one
@@ -465,7 +494,7 @@ int enqueue_run(pg_batch* bt, int est, hipStream_t s) {
   const BatchView bv = view_of(bt);
   const unsigned persistent = (unsigned)std::max<int64_t>(
       1, std::min<int64_t>(bt->nitems, (int64_t)std::max(1, bt->ctx->num_cus) * bt->params.blocks_per_cu));
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, bt->counters);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(kBlock), 0, s, bt->counters);
   PG_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_batch_tables, dim3((unsigned)bt->count), dim3(kBlock), 0, s, (const GraphDesc*)bt->gd, bt->b,
                      est, bt->tables);
@@ -482,9 +511,11 @@ int enqueue_run(pg_batch* bt, int est, hipStream_t s) {
     const int w = bt->launch_order[i];
     const int64_t b0 = bt->w_begin[w], b1 = bt->w_begin[w + 1];
     const hipStream_t ws = bt->branch_of[w] == 0 ? s : bt->side[bt->branch_of[w] - 1];
-    const unsigned grid = (unsigned)std::max<int64_t>(
-        1, std::min<int64_t>(b1 - b0, (int64_t)std::max(1, bt->ctx->num_cus) * bt->params.blocks_per_cu));
-#define PG_BE(WW) hipLaunchKernelGGL((k_batch_estimate<WW>), dim3(grid), dim3(kBlock), 0, ws, ev, b0, b1)
+    // a multiple of kSlabs blocks, so that every XCD's queue has blocks
+    const int64_t want = std::min<int64_t>(b1 - b0, (int64_t)std::max(1, bt->ctx->num_cus) * bt->params.blocks_per_cu);
+    const unsigned grid = (unsigned)(std::max<int64_t>(1, (want + kSlabs - 1) / kSlabs) * kSlabs);
+    const XQueues q = bt->xq[w];
+#define PG_BE(WW) hipLaunchKernelGGL((k_batch_estimate<WW>), dim3(grid), dim3(kBlock), 0, ws, ev, q)
     switch (w) {
       case 1: PG_BE(1); break;
       case 2: PG_BE(2); break;
