@@ -14,6 +14,9 @@
 // compile-time constant of that launch; the launches are dealt to four
 // streams (longest first, each to the least-loaded stream) so that their
 // tails overlap, and a captured run keeps them as parallel graph branches.
+// Within a width, each graph belongs to one XCD (dealt longest first to the
+// least-loaded one): block i runs on XCD i mod 8 and takes items only from
+// that XCD's queue, so a graph's rows are gathered through one L2.
 //
 // No block ever waits for another block: a block leaves as soon as the index
 // it draws from its queue counter is past the end of its list, every loop is
