@@ -922,7 +922,7 @@ int oh_dispatch_e(uint32_t k, F&& launch) {
   return launch(std::integral_constant<int, 16>(), std::false_type());
 }
 
-// ---- clustering coefficient over XCD slabs of all of N_v (Bloom filters) ----
+// ---- clustering coefficient over XCD slabs of all of N_v ---------------------
 //
 // The triangle count's slab plan built over all arcs: block i < slab_grid
 // works on slab i mod kSlabs, so each XCD gathers the rows of an eighth of
@@ -930,12 +930,33 @@ int oh_dispatch_e(uint32_t k, F&& launch) {
 // one group of kSlabWholeGroup lanes, which writes its coefficient. A sliced
 // vertex's items write their sums to part[x * n_sliced + rank[v]] (zero where
 // it has no arcs in slab x) and its heavy chunks to chunk_part; then
-// k_cc_slab_combine adds them in slab order, then chunk order.
+// k_cc_slab_combine adds them in slab order, then chunk order. F is the
+// sketch kind's per-item sum (the triangle count's item over all of N_v).
 template <int W, bool OR>
-__global__ __launch_bounds__(kBlock) void k_bf_cc_slab(SlabPlan P, SkView s, const int32_t* __restrict__ off,
-                                                       const int32_t* __restrict__ adj, float* __restrict__ cc,
-                                                       double* __restrict__ vsum, double* __restrict__ part,
-                                                       double* __restrict__ chunk_part) {
+struct BfCcItem {
+  static constexpr bool kTable = true;  // the estimator table staged in LDS
+  template <int G>
+  __device__ static double sum(const SkView& s, int32_t v, const int32_t* __restrict__ adj, int64_t beg, int64_t end,
+                               int lane, const double* __restrict__ tab) {
+    return bf_item<W, RowUnroll<W>::value, G, OR>(s, v, adj, beg, end, lane, tab);
+  }
+};
+
+template <int K>
+struct KhCcItem {
+  static constexpr bool kTable = false;
+  template <int G>
+  __device__ static double sum(const SkView& s, int32_t v, const int32_t* __restrict__ adj, int64_t beg, int64_t end,
+                               int lane, const double* __restrict__) {
+    return kh_item<K, (K <= 32 ? 4 : 2), G>(s, v, adj, beg, end, lane);
+  }
+};
+
+template <class F>
+__global__ __launch_bounds__(kBlock) void k_cc_slab(SlabPlan P, SkView s, const int32_t* __restrict__ off,
+                                                    const int32_t* __restrict__ adj, float* __restrict__ cc,
+                                                    double* __restrict__ vsum, double* __restrict__ part,
+                                                    double* __restrict__ chunk_part) {
   const bool whole = (int64_t)blockIdx.x >= P.slab_grid;
   const int x = (int)(blockIdx.x % kSlabs);
   const int64_t blk = whole ? (int64_t)blockIdx.x - P.slab_grid : (int64_t)(blockIdx.x / kSlabs);
@@ -944,9 +965,10 @@ __global__ __launch_bounds__(kBlock) void k_bf_cc_slab(SlabPlan P, SkView s, con
   if (!whole && blk >= slab_blocks(P, x)) return;
   extern __shared__ double tab[];
   __shared__ double red[kBlock / kWave];
-  for (uint32_t i = threadIdx.x; i <= s.size; i += kBlock) tab[i] = s.table[i];
-  __syncthreads();
-  constexpr int U = RowUnroll<W>::value;
+  if constexpr (F::kTable) {
+    for (uint32_t i = threadIdx.x; i <= s.size; i += kBlock) tab[i] = s.table[i];
+    __syncthreads();
+  }
   const size_t n = (size_t)s.n;
   const int tid = threadIdx.x;
   if (whole) {
@@ -955,7 +977,7 @@ __global__ __launch_bounds__(kBlock) void k_bf_cc_slab(SlabPlan P, SkView s, con
     double acc = 0.0;
     if (idx < P.n_whole) {
       v = P.verts[P.whole_at + idx];
-      acc = bf_item<W, U, kSlabWholeGroup, OR>(s, v, adj, off[v], off[v + 1], tid % kSlabWholeGroup, tab);
+      acc = F::template sum<kSlabWholeGroup>(s, v, adj, off[v], off[v + 1], tid % kSlabWholeGroup, tab);
     }
     const double tot = group_sum<kSlabWholeGroup>(acc);
     if (v >= 0 && tid % kSlabWholeGroup == 0) {
@@ -966,7 +988,7 @@ __global__ __launch_bounds__(kBlock) void k_bf_cc_slab(SlabPlan P, SkView s, con
   } else if (blk < n_chunks) {  // heavy chunk: the whole block
     const int64_t c = P.chunk_at[x] + blk;
     const double acc =
-        bf_item<W, U, kBlock, OR>(s, P.chunk_vertex[c], adj, P.chunk_begin[c], P.chunk_end[c], tid, tab);
+        F::template sum<kBlock>(s, P.chunk_vertex[c], adj, P.chunk_begin[c], P.chunk_end[c], tid, tab);
     const double r = block_sum_256(acc, red);
     if (tid == 0) chunk_part[c] = r;
   } else if (blk - n_chunks < n_medium_blocks) {  // medium: one wave per item
@@ -975,8 +997,8 @@ __global__ __launch_bounds__(kBlock) void k_bf_cc_slab(SlabPlan P, SkView s, con
     double acc = 0.0;
     if (idx < P.n_medium[x]) {
       v = P.verts[P.medium_at[x] + idx];
-      acc = bf_item<W, U, kWave, OR>(s, v, adj, slab_begin(off, P.split, n, x, v), slab_end(off, P.split, n, x, v),
-                                     lane_id(), tab);
+      acc = F::template sum<kWave>(s, v, adj, slab_begin(off, P.split, n, x, v), slab_end(off, P.split, n, x, v),
+                                   lane_id(), tab);
     }
     const double tot = group_sum<kWave>(acc);
     if (v >= 0 && lane_id() == 0) part[(size_t)x * (size_t)P.n_sliced + (size_t)P.rank[v]] = tot;
@@ -986,8 +1008,8 @@ __global__ __launch_bounds__(kBlock) void k_bf_cc_slab(SlabPlan P, SkView s, con
     double acc = 0.0;
     if (idx < P.n_light[x]) {
       v = P.verts[P.light_at[x] + idx];
-      acc = bf_item<W, U, kSlabLightGroup, OR>(s, v, adj, slab_begin(off, P.split, n, x, v),
-                                                slab_end(off, P.split, n, x, v), tid % kSlabLightGroup, tab);
+      acc = F::template sum<kSlabLightGroup>(s, v, adj, slab_begin(off, P.split, n, x, v),
+                                             slab_end(off, P.split, n, x, v), tid % kSlabLightGroup, tab);
     }
     const double tot = group_sum<kSlabLightGroup>(acc);
     if (v >= 0 && tid % kSlabLightGroup == 0) part[(size_t)x * (size_t)P.n_sliced + (size_t)P.rank[v]] = tot;
@@ -995,7 +1017,7 @@ __global__ __launch_bounds__(kBlock) void k_bf_cc_slab(SlabPlan P, SkView s, con
 }
 
 // Coefficients of the sliced vertices from their item and chunk sums, and of
-// the vertices without arcs (0); whole vertices were written by k_bf_cc_slab.
+// the vertices without arcs (0); whole vertices were written by k_cc_slab.
 __global__ void k_cc_slab_combine(SlabPlan P, int32_t n, const int32_t* __restrict__ deg,
                                   const double* __restrict__ part, const double* __restrict__ chunk_part,
                                   float* __restrict__ cc, double* __restrict__ vsum) {
@@ -1018,56 +1040,6 @@ __global__ void k_cc_slab_combine(SlabPlan P, int32_t n, const int32_t* __restri
   if (vsum) vsum[v] = tot;
 }
 
-// k-hash clustering coefficient over the same plan: the triangle count's
-// k-hash item (sig_v in registers, teams of kKhTeam lanes per neighbour
-// signature) over all of N_v; heavy chunks write block sums combined by
-// k_cc_combine.
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_kh_cc_plan(PlanView P, SkView s, const int32_t* __restrict__ off,
-                                                       const int32_t* __restrict__ adj, float* __restrict__ cc,
-                                                       double* __restrict__ vsum, double* __restrict__ part) {
-  __shared__ double red[kBlock / kWave];
-  constexpr int U = K <= 32 ? 4 : 2;
-  const int64_t blk = blockIdx.x;
-  const int tid = threadIdx.x;
-  if (blk < P.n_chunks) {
-    const double acc = kh_item<K, U, kBlock>(s, P.chunk_vertex[blk], adj, P.chunk_begin[blk], P.chunk_end[blk], tid);
-    const double r = block_sum_256(acc, red);
-    if (tid == 0) part[blk] = r;
-    return;
-  }
-  const int64_t mb = blk - P.n_chunks;
-  int32_t v = -1;
-  double tot = 0.0;
-  bool lead = false;
-  if (mb < P.n_medium_blocks) {  // one wave per vertex
-    const int64_t idx = mb * (kBlock / kWave) + tid / kWave;
-    double acc = 0.0;
-    if (idx < P.n_medium) {
-      v = P.medium[idx];
-      acc = kh_item<K, U, kWave>(s, v, adj, off[v], off[v + 1], lane_id());
-    }
-    tot = group_sum<kWave>(acc);
-    lead = lane_id() == 0;
-  } else {  // light: kWholeGroup lanes per vertex
-    const int64_t idx = ((mb - P.n_medium_blocks) * kBlock + tid) / kWholeGroup;
-    double acc = 0.0;
-    if (idx < P.n_light) {
-      const int32_t u = P.light ? P.light[idx] : (int32_t)idx;
-      if (off[u + 1] - off[u] <= kLightMax) {
-        v = u;
-        acc = kh_item<K, U, kWholeGroup>(s, v, adj, off[v], off[v + 1], tid % kWholeGroup);
-      }
-    }
-    tot = group_sum<kWholeGroup>(acc);
-    lead = tid % kWholeGroup == 0;
-  }
-  if (v >= 0 && lead) {
-    const int32_t d = s.deg[v];
-    cc[v] = (float)(d >= 2 ? tot / ((double)d * ((double)d - 1.0)) : 0.0);
-    if (vsum) vsum[v] = tot;
-  }
-}
 
 __global__ void k_make_table(double* __restrict__ t, uint32_t B, uint32_t b, int est) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1442,32 +1414,9 @@ int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStre
     }
     return dfree(part, s);
   }
-  if (sk->kind == PG_MH_KHASH && (sk->size == 16 || sk->size == 32 || sk->size == 64)) {
-    const VertexPlan& P = g->plan_all;
-    const PlanView pv = plan_view(P);
-    const int64_t nblk = P.n_chunks + pv.n_medium_blocks + (P.n_light * kWholeGroup + kBlock - 1) / kBlock;
-    if (nblk <= 0) return PG_OK;
-    if (nblk > (int64_t)(UINT32_MAX / kBlock)) return fail(PG_E_UNSUPPORTED, "graph too large for one launch");
-    double* part = nullptr;
-    PG_TRY(dmalloc((void**)&part, sizeof(double) * (size_t)std::max<int64_t>(P.n_chunks, 1), s));
-    if (sk->size == 16)
-      hipLaunchKernelGGL(k_kh_cc_plan<16>, dim3((unsigned)nblk), dim3(kBlock), 0, s, pv, view, g->off, g->adj, cc, vsum,
-                         part);
-    else if (sk->size == 32)
-      hipLaunchKernelGGL(k_kh_cc_plan<32>, dim3((unsigned)nblk), dim3(kBlock), 0, s, pv, view, g->off, g->adj, cc, vsum,
-                         part);
-    else
-      hipLaunchKernelGGL(k_kh_cc_plan<64>, dim3((unsigned)nblk), dim3(kBlock), 0, s, pv, view, g->off, g->adj, cc, vsum,
-                         part);
-    PG_LAUNCH_CHECK();
-    if (P.n_heavy > 0) {
-      hipLaunchKernelGGL(k_cc_combine, dim3((unsigned)((P.n_heavy + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pv,
-                         (const double*)part, P.n_heavy, g->deg, cc, vsum);
-      PG_LAUNCH_CHECK();
-    }
-    return dfree(part, s);
-  }
-  if (sk->kind == PG_BF && sk->W <= 16) {
+  // the slab plan over all of N_v: part (8 sums per sliced vertex, zero where
+  // it has no item) and chunk sums, the launch, then the per-vertex combine
+  auto slab_cc = [&](size_t shmem, auto launch) -> int {
     PG_TRY(graph_slabs_all(const_cast<pg_graph*>(g), s));
     const SlabPlan& P = g->slabs_all;
     const int64_t nblk = slab_plan_blocks(P);
@@ -1479,36 +1428,8 @@ int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStre
     PG_TRY(dmalloc((void**)&part, sizeof(double) * (size_t)std::max<int64_t>(n_part + n_chunks, 1), s));
     double* chunk_part = part + n_part;
     if (n_part > 0) PG_TRY(fill_u64(reinterpret_cast<uint64_t*>(part), 0, n_part, s));  // 0.0 where v has no item
-    const size_t shmem = sizeof(double) * ((size_t)sk->size + 1);
     if (nblk > 0) {
-#define PG_CCS(WW)                                                                                                   \
-  do {                                                                                                               \
-    if (est == PG_EST_BF_OR)                                                                                         \
-      hipLaunchKernelGGL((k_bf_cc_slab<WW, true>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, P, view, g->off,    \
-                         g->adj, cc, vsum, part, chunk_part);                                                        \
-    else                                                                                                             \
-      hipLaunchKernelGGL((k_bf_cc_slab<WW, false>), dim3((unsigned)nblk), dim3(kBlock), shmem, s, P, view, g->off,   \
-                         g->adj, cc, vsum, part, chunk_part);                                                        \
-  } while (0)
-      switch (sk->W) {
-        case 1: PG_CCS(1); break;
-        case 2: PG_CCS(2); break;
-        case 3: PG_CCS(3); break;
-        case 4: PG_CCS(4); break;
-        case 5: PG_CCS(5); break;
-        case 6: PG_CCS(6); break;
-        case 7: PG_CCS(7); break;
-        case 8: PG_CCS(8); break;
-        case 9: PG_CCS(9); break;
-        case 10: PG_CCS(10); break;
-        case 11: PG_CCS(11); break;
-        case 12: PG_CCS(12); break;
-        case 13: PG_CCS(13); break;
-        case 14: PG_CCS(14); break;
-        case 15: PG_CCS(15); break;
-        default: PG_CCS(16); break;
-      }
-#undef PG_CCS
+      launch(P, dim3((unsigned)nblk), shmem, part, chunk_part);
       PG_LAUNCH_CHECK();
     }
     if (g->n > 0) {
@@ -1517,6 +1438,52 @@ int estimate_cc(const pg_sketches* sk, int est, float* cc, double* vsum, hipStre
       PG_LAUNCH_CHECK();
     }
     return dfree(part, s);
+  };
+  if (sk->kind == PG_MH_KHASH && (sk->size == 16 || sk->size == 32 || sk->size == 64)) {
+    return slab_cc(0, [&](const SlabPlan& P, dim3 grid, size_t shmem, double* part, double* chunk_part) {
+      if (sk->size == 16)
+        hipLaunchKernelGGL(k_cc_slab<KhCcItem<16>>, grid, dim3(kBlock), shmem, s, P, view, g->off, g->adj, cc, vsum,
+                           part, chunk_part);
+      else if (sk->size == 32)
+        hipLaunchKernelGGL(k_cc_slab<KhCcItem<32>>, grid, dim3(kBlock), shmem, s, P, view, g->off, g->adj, cc, vsum,
+                           part, chunk_part);
+      else
+        hipLaunchKernelGGL(k_cc_slab<KhCcItem<64>>, grid, dim3(kBlock), shmem, s, P, view, g->off, g->adj, cc, vsum,
+                           part, chunk_part);
+    });
+  }
+  if (sk->kind == PG_BF && sk->W <= 16) {
+    return slab_cc(sizeof(double) * ((size_t)sk->size + 1),
+                   [&](const SlabPlan& P, dim3 grid, size_t shmem, double* part, double* chunk_part) {
+#define PG_CCS(WW)                                                                                                 \
+  do {                                                                                                             \
+    if (est == PG_EST_BF_OR)                                                                                       \
+      hipLaunchKernelGGL((k_cc_slab<BfCcItem<WW, true>>), grid, dim3(kBlock), shmem, s, P, view, g->off, g->adj,    \
+                         cc, vsum, part, chunk_part);                                                              \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_cc_slab<BfCcItem<WW, false>>), grid, dim3(kBlock), shmem, s, P, view, g->off, g->adj,   \
+                         cc, vsum, part, chunk_part);                                                              \
+  } while (0)
+                     switch (sk->W) {
+                       case 1: PG_CCS(1); break;
+                       case 2: PG_CCS(2); break;
+                       case 3: PG_CCS(3); break;
+                       case 4: PG_CCS(4); break;
+                       case 5: PG_CCS(5); break;
+                       case 6: PG_CCS(6); break;
+                       case 7: PG_CCS(7); break;
+                       case 8: PG_CCS(8); break;
+                       case 9: PG_CCS(9); break;
+                       case 10: PG_CCS(10); break;
+                       case 11: PG_CCS(11); break;
+                       case 12: PG_CCS(12); break;
+                       case 13: PG_CCS(13); break;
+                       case 14: PG_CCS(14); break;
+                       case 15: PG_CCS(15); break;
+                       default: PG_CCS(16); break;
+                     }
+#undef PG_CCS
+                   });
   }
   for (int bin = 0; bin < kNumBins; ++bin) {
     const int64_t cnt = g->bin_start[bin + 1] - g->bin_start[bin];

@@ -524,8 +524,9 @@ def test_cc_over_slabs_every_vertex(ctx):
     """The clustering coefficient over XCD slabs of all of N_v: a 40,000-leaf
     star (its items in every slab exceed the 2,048-arc chunk, so they run as
     heavy chunks), an R-MAT graph (light and medium items, whole vertices) and
-    isolated vertices; every vertex against the oracle, for a ratio estimator
-    (AND) and one that reads the popcounts (OR), and the transitivity."""
+    isolated vertices; every vertex against the oracle, for Bloom filters with
+    a ratio estimator (AND) and one that reads the popcounts (OR), and for
+    k-hash signatures, and the transitivity."""
     g = pggen.disjoint_union(pggen.star(40000), pggen.rmat(12, 16, seed=5), pggen.er(50, 0, seed=1))
     say(f"cc over slabs: n={g.n}")
     dg = pg.Graph(ctx, g.offsets, g.adj, validate=True)
@@ -540,6 +541,15 @@ def test_cc_over_slabs_every_vertex(ctx):
         again = sk.cc(est)
         assert torch.equal(cc, again)  # the same bits on a second call
     sk.close()
+    for k in (16, 32, 64):  # k-hash over the same plan
+        say(f"cc over slabs: k-hash k={k}")
+        sk = dg.build_sketches("kh", k, seed=4)
+        ref = oracle.build_sketches(g, oracle.KIND_KH, k, seed=4)
+        cc, trans = sk.cc("kh", transitivity=True)
+        torch.cuda.synchronize()
+        _close32(np_(cc), oracle.cc(ref, "kh"))
+        _close([trans], [3 * oracle.tc(ref, "kh") / wedges], rtol=1e-9)
+        sk.close()
     dg.close()
 
 
