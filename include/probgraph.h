@@ -24,6 +24,11 @@
  *     the stream before returning.
  *   - A pg_ctx and the handles made from it may be used by one host thread at
  *     a time; separate contexts are independent.
+ *   - Work plans of a graph (the XCD slab plans of the triangle count and of
+ *     the clustering coefficient) are built and allocated by the first call
+ *     that needs them and kept with the graph; per-call temporaries come from
+ *     the device's stream-ordered pool (pg_ctx_create lets it keep up to
+ *     1 GiB of freed memory for reuse).
  *   - Vertex IDs are int32 in [0, n). Graphs are undirected CSR: offsets[n+1]
  *     and adj[nnz], each N_v = adj[offsets[v] .. offsets[v+1]) sorted
  *     ascending, symmetric, with no duplicates and no self-loops (Section 2.1).
