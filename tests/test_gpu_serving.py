@@ -139,6 +139,32 @@ def test_budget_ranges_split_and_merge(env):
     srv.close()
 
 
+def test_budget_split_into_parts(env):
+    """With a budget of many largest requests the arena is split into 16 parts:
+    one thread's requests fill its home part and then the others, the whole
+    budget is admitted, one more pair is not, and collecting returns every
+    range (the same fill succeeds again)."""
+    g, ctx, dg, sks = env
+    srv = pg.Server(dg, sks, max_pairs_per_request=64, memory_budget_bytes=16 * 4096)  # 16 parts of 256 pairs
+    rng = np.random.default_rng(21)
+    u = rng.integers(0, g.n, 64).astype(np.int32)
+    v = rng.integers(0, g.n, 64).astype(np.int32)
+    ref = pg.Server(dg, sks)
+    tr, want = ref.submit(pg.PG_OP_CN, 0, "and", u, v)
+    ref.wait(tr)
+    ref.close()
+    for rep in range(2):
+        held = [srv.submit(pg.PG_OP_CN, 0, "and", u, v) for _ in range(64)]  # 64 x 64 = the whole budget
+        with pytest.raises(pg.PGError) as ei:
+            srv.submit(pg.PG_OP_CN, 0, "and", u[:1], v[:1])
+        assert ei.value.code == pg.PG_E_BUSY
+        for t, out in held:
+            srv.wait(t)
+            assert out.tobytes() == want.tobytes()
+    assert srv.stats()["completed"] == 128 and srv.stats()["rejected_busy"] == 2
+    srv.close()
+
+
 def test_malformed_requests_rejected_before_enqueue(env):
     g, ctx, dg, sks = env
     srv = pg.Server(dg, sks, max_pairs_per_request=100)
