@@ -545,7 +545,8 @@ __global__ __launch_bounds__(kBlock) void k_kh_tc_slab(SlabPlan P, SkView s, con
 // estimators the k-th smallest union key is either the key of the element of
 // M_u at position k - 1, or, when there is none, the element of M_v after
 // k - a + c - 1 others, a being the elements of M_u before position k - 1 and
-// c the common ones among them.
+// c the common ones among them. The ratio estimators at k <= 64 replace the
+// key search by a lookup of M_u's IDs in a hash table of M_v's (below).
 
 constexpr int kOhAhead = 4;      // neighbour rows in flight per wave, a wave per pair
 constexpr int kOhHalfAhead = 2;  // neighbour rows in flight per half wave (k <= 32)
@@ -559,6 +560,79 @@ __device__ __forceinline__ void oh_keys_to_lds(const SkView& s, int32_t v, uint3
     const uint32_t e = (uint32_t)(j * kWave + l);
     if (e < nv) keys[e] = mh_key(s.a1, s.c1, row[e]);
   }
+}
+
+// The ratio estimators need, for each element of M_u, only whether it is in
+// M_v and, if so, its index there: equal IDs are equal keys, and the common
+// elements keep their relative order in both rows, so the union position of
+// a common element e of M_u is e plus its index in M_v minus the common
+// elements before it. For k <= 64 the wave therefore puts M_v's IDs in a
+// bucketed hash table in LDS and looks each element of M_u up by ID: the
+// neighbour rows are never hashed to keys nor searched by key, and the counts
+// are the key walk's exactly. The table has kOhBuckets buckets of four ID
+// slots (at most 64 IDs, so half a slot per bucket on average) and a byte per
+// slot with the element's index in M_v. An ID goes to the first bucket, from
+// its hash bucket on, that has a free slot, so a lookup reads one bucket (one
+// 16-byte LDS read) and moves on only past a full bucket without the ID.
+constexpr int kOhBuckets = 128;
+constexpr int kOhSlots = 4 * kOhBuckets;
+constexpr uint32_t kOhFree = 0xFFFFFFFFu;  // no vertex has this ID
+
+__device__ __forceinline__ uint32_t oh_bucket_of(uint32_t id) {
+  return (id * 0x9E3779B1u) >> 25;  // Fibonacci hashing to 7 bits
+}
+
+// 32-bit words of a wave's table: the ID slots, then the index bytes.
+constexpr int kOhTableWords = kOhSlots + kOhSlots / 4;
+
+// Clear the wave's table, then insert M_v's nv <= 64 IDs, element e in lane e.
+__device__ __forceinline__ void oh_table_to_lds(const SkView& s, int32_t v, uint32_t nv, uint32_t* tab) {
+  const int l = lane_id();
+  uint4* ids4 = reinterpret_cast<uint4*>(tab);
+#pragma unroll
+  for (int j = 0; j < kOhBuckets / kWave; ++j) ids4[j * kWave + l] = make_uint4(kOhFree, kOhFree, kOhFree, kOhFree);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if ((uint32_t)l < nv) {
+    const uint32_t id = s.sig[(size_t)v * s.size + l];
+    uint32_t b = oh_bucket_of(id);
+    // at most 64 of the slots are ever taken, so a free one is always found
+    for (;;) {
+      int j = 0;
+      while (j < 4 && atomicCAS(tab + 4 * b + j, kOhFree, id) != kOhFree) ++j;
+      if (j < 4) {
+        reinterpret_cast<uint8_t*>(tab + kOhSlots)[4 * b + j] = (uint8_t)l;
+        break;
+      }
+      b = (b + 1) & (kOhBuckets - 1);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lookups: the slots of a bucket holding the ID, and whether a bucket has a
+// free slot (which ends a search: at most 16 of the kOhBuckets buckets are
+// full).
+__device__ __forceinline__ uint32_t oh_hits(const uint4& q, uint32_t id) {
+  return (uint32_t)(q.x == id) | ((uint32_t)(q.y == id) << 1) | ((uint32_t)(q.z == id) << 2) |
+         ((uint32_t)(q.w == id) << 3);
+}
+__device__ __forceinline__ bool oh_open(const uint4& q) {
+  return max(max(q.x, q.y), max(q.z, q.w)) == kOhFree;  // the free mark is the largest word
+}
+// The ID table serves the ratio estimators for k <= 64; the KMV estimators
+// need the keys themselves and larger k keep the key search.
+template <int E, bool KMV>
+__host__ __device__ constexpr bool oh_by_table() {
+  return !KMV && E == 1;
+}
+// 64-bit LDS words a wave of the 1-hash kernels holds.
+template <int E, bool KMV>
+__host__ __device__ constexpr int oh_lds_words() {
+  return oh_by_table<E, KMV>() ? kOhTableWords / 2 : kWave * E;
 }
 
 // Estimate for the pair (v, u) given M_v's nv keys in LDS and this lane's
@@ -682,6 +756,57 @@ __device__ __forceinline__ void oh_wave_ratio_counts(const SkView& s, const uint
   sc = uni >= s.size ? comk : com;
 }
 
+// oh_wave_ratio_counts for k <= 64 (E = 1) over the ID table of M_v, for A
+// neighbours at once (du[t] < 0: none): their bucket reads are issued
+// together, then resolved.
+template <bool HALF, int A>
+__device__ __forceinline__ void oh_table_ratio_counts(const SkView& s, const uint32_t* tab, uint32_t nv,
+                                                      const int32_t (&du)[A], const uint32_t (&x)[A],
+                                                      uint32_t (&sc)[A], uint32_t (&kk)[A]) {
+  const int l = lane_id();
+  const uint64_t hmask = HALF ? ((l & 32) ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull) : ~0ull;
+  const uint32_t le = (uint32_t)(l - (HALF ? (l & 32) : 0));
+  const uint64_t below = ((1ull << l) - 1ull) & hmask;
+  const uint4* ids4 = reinterpret_cast<const uint4*>(tab);
+  const uint8_t* index = reinterpret_cast<const uint8_t*>(tab + kOhSlots);
+  uint32_t nu[A], b[A], hit[A];
+  uint4 q[A];
+#pragma unroll
+  for (int t = 0; t < A; ++t) {
+    nu[t] = du[t] < 0 ? 0u : ((uint32_t)du[t] < s.size ? (uint32_t)du[t] : s.size);
+    b[t] = oh_bucket_of(x[t]);
+    q[t] = ids4[b[t]];
+  }
+#pragma unroll
+  for (int t = 0; t < A; ++t) {
+    hit[t] = le < nu[t] ? oh_hits(q[t], x[t]) : 0u;
+    if (le < nu[t] && hit[t] == 0u && !oh_open(q[t])) {  // a full bucket without the ID: rare
+      do {
+        b[t] = (b[t] + 1) & (kOhBuckets - 1);
+        q[t] = ids4[b[t]];
+        hit[t] = oh_hits(q[t], x[t]);
+      } while (hit[t] == 0u && !oh_open(q[t]));
+    }
+  }
+  uint32_t iv[A];
+#pragma unroll
+  for (int t = 0; t < A; ++t) iv[t] = hit[t] ? index[4 * b[t] + (uint32_t)__builtin_ctz(hit[t])] : 0u;
+#pragma unroll
+  for (int t = 0; t < A; ++t) {
+    const bool found = hit[t] != 0u;
+    const uint64_t fb = __ballot(found) & hmask;
+    const uint32_t before = (uint32_t)__popcll(fb & below);  // common elements ahead of this one
+    const bool first_k = found && le + iv[t] - before < s.size;
+    const uint32_t com = (uint32_t)__popcll(fb);
+    const uint32_t comk = (uint32_t)__popcll(__ballot(first_k) & hmask);
+    // literal reading: |M_u cap M_v| of k; union reading: s of k'
+    const bool lit = s.est == PG_EST_MH_1HASH_LITERAL;
+    const uint32_t uni = nu[t] + nv - com;
+    kk[t] = lit ? s.size : (uni < s.size ? uni : s.size);
+    sc[t] = (lit || uni < s.size) ? com : comk;
+  }
+}
+
 // The ratio estimate s/kk -> J/(1+J)(d_u + d_v) is FP64 work with divisions
 // that every lane of the wave would repeat for every pair. Instead the pairs a
 // wave evaluates are numbered in order; lane q mod 64 keeps the counts of
@@ -720,12 +845,17 @@ struct OhDeferred {
 template <int E, bool HALF, bool KMV>
 __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const int32_t* __restrict__ adj,
                                                int64_t beg, int64_t end, uint64_t* keys) {
+  constexpr bool TAB = oh_by_table<E, KMV>();
   const int32_t dv = s.deg[v];
   const uint32_t nv = (uint32_t)dv < s.size ? (uint32_t)dv : s.size;
-  oh_keys_to_lds<E>(s, v, nv, keys);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if constexpr (TAB) {
+    oh_table_to_lds(s, v, nv, reinterpret_cast<uint32_t*>(keys));
+  } else {
+    oh_keys_to_lds<E>(s, v, nv, keys);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
   const int l = lane_id();
   double acc = 0.0;     // KMV: the same in every lane (of the half)
   OhDeferred df;        // ratio estimators: deferred estimates
@@ -746,17 +876,22 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
           const uint32_t nu = u < 0 ? 0u : ((uint32_t)du[t] < s.size ? (uint32_t)du[t] : s.size);
           x[t][0] = le < nu ? s.sig[(size_t)u * s.size + le] : 0u;
         }
+        if constexpr (KMV) {
 #pragma unroll
-        for (int t = 0; t < kOhHalfAhead; ++t) {
-          if constexpr (KMV) {
+          for (int t = 0; t < kOhHalfAhead; ++t) {
             const double est = oh_wave_estimate<1, true, KMV>(s, keys, nv, dv, du[t], x[t]);
             if (du[t] >= 0) acc += est;
-          } else {
-            uint32_t sc, kk;
-            oh_wave_ratio_counts<1, true>(s, keys, nv, du[t], x[t], sc, kk);
+          }
+        } else {
+          uint32_t xs[kOhHalfAhead], sc[kOhHalfAhead], kk[kOhHalfAhead];
+#pragma unroll
+          for (int t = 0; t < kOhHalfAhead; ++t) xs[t] = x[t][0];
+          oh_table_ratio_counts<true, kOhHalfAhead>(s, reinterpret_cast<const uint32_t*>(keys), nv, du, xs, sc, kk);
+#pragma unroll
+          for (int t = 0; t < kOhHalfAhead; ++t) {
             const int32_t du0 = __shfl(du[t], 0), du1 = __shfl(du[t], kWave / 2);
-            const uint32_t s0 = (uint32_t)__shfl((int)sc, 0), k0 = (uint32_t)__shfl((int)kk, 0);
-            const uint32_t s1 = (uint32_t)__shfl((int)sc, kWave / 2), k1 = (uint32_t)__shfl((int)kk, kWave / 2);
+            const uint32_t s0 = (uint32_t)__shfl((int)sc[t], 0), k0 = (uint32_t)__shfl((int)kk[t], 0);
+            const uint32_t s1 = (uint32_t)__shfl((int)sc[t], kWave / 2), k1 = (uint32_t)__shfl((int)kk[t], kWave / 2);
             if (du0 >= 0) df.put(q++, s0, k0, du0, dv);
             if (du1 >= 0) df.put(q++, s1, k1, du1, dv);
           }
@@ -783,15 +918,25 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
         x[t][j] = e < nu ? row[e] : 0u;
       }
     }
+    if constexpr (TAB) {
+      uint32_t xs[kOhAhead], sc[kOhAhead], kk[kOhAhead];
 #pragma unroll
-    for (int t = 0; t < kOhAhead; ++t) {
-      if (du[t] < 0) continue;
-      if constexpr (KMV) {
-        acc += oh_wave_estimate<E, false, KMV>(s, keys, nv, dv, du[t], x[t]);
-      } else {
-        uint32_t sc, kk;
-        oh_wave_ratio_counts<E, false>(s, keys, nv, du[t], x[t], sc, kk);
-        df.put(q++, sc, kk, du[t], dv);
+      for (int t = 0; t < kOhAhead; ++t) xs[t] = x[t][0];
+      oh_table_ratio_counts<false, kOhAhead>(s, reinterpret_cast<const uint32_t*>(keys), nv, du, xs, sc, kk);
+#pragma unroll
+      for (int t = 0; t < kOhAhead; ++t)
+        if (du[t] >= 0) df.put(q++, sc[t], kk[t], du[t], dv);
+    } else {
+#pragma unroll
+      for (int t = 0; t < kOhAhead; ++t) {
+        if (du[t] < 0) continue;
+        if constexpr (KMV) {
+          acc += oh_wave_estimate<E, false, KMV>(s, keys, nv, dv, du[t], x[t]);
+        } else {
+          uint32_t sc, kk;
+          oh_wave_ratio_counts<E, false>(s, keys, nv, du[t], x[t], sc, kk);
+          df.put(q++, sc, kk, du[t], dv);
+        }
       }
     }
   }
@@ -813,7 +958,7 @@ __global__ __launch_bounds__(kBlock) void k_oh_tc_slab(SlabPlan P, SkView s, con
                                                        const int32_t* __restrict__ ustart,
                                                        const int32_t* __restrict__ adj, int64_t grid_slabs,
                                                        double* __restrict__ partials) {
-  __shared__ uint64_t keys[kBlock / kWave][kWave * E];
+  __shared__ __align__(16) uint64_t keys[kBlock / kWave][oh_lds_words<E, KMV>()];
   const int w = threadIdx.x / kWave;
   const size_t n = (size_t)s.n;
   double acc = 0.0;
@@ -860,7 +1005,7 @@ template <int E, bool HALF, bool KMV>
 __global__ __launch_bounds__(kBlock) void k_oh_cc_plan(PlanView P, SkView s, const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ adj, float* __restrict__ cc,
                                                        double* __restrict__ vsum, double* __restrict__ part) {
-  __shared__ uint64_t keys[kBlock / kWave][kWave * E];
+  __shared__ __align__(16) uint64_t keys[kBlock / kWave][oh_lds_words<E, KMV>()];
   __shared__ double red[kBlock / kWave];
   const int w = threadIdx.x / kWave;
   const int64_t blk = blockIdx.x;
