@@ -901,6 +901,41 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
       return df.total();
     }
   } else {
+  if constexpr (TAB) {
+    // kOhAhead neighbours at a time, the next group's degrees and rows loaded
+    // while this group is looked up; a row is loaded whole (k slots) without
+    // waiting for the degree, which masks the lanes afterwards
+    const uint32_t* tab = reinterpret_cast<const uint32_t*>(keys);
+    const bool in_row = (uint32_t)l < s.size;
+    auto load = [&](int64_t p0, int32_t (&du)[kOhAhead], uint32_t (&x)[kOhAhead]) {
+#pragma unroll
+      for (int t = 0; t < kOhAhead; ++t) {
+        const int32_t u = p0 + t < end ? adj[p0 + t] : -1;
+        du[t] = u >= 0 ? s.deg[u] : -1;
+        x[t] = (u >= 0 && in_row) ? s.sig[(size_t)u * s.size + l] : 0u;
+      }
+    };
+    int32_t du[kOhAhead], du_next[kOhAhead];
+    uint32_t x[kOhAhead], x_next[kOhAhead];
+    if (beg < end) load(beg, du, x);
+    for (int64_t p0 = beg; p0 < end; p0 += kOhAhead) {
+      const bool more = p0 + kOhAhead < end;
+      if (more) load(p0 + kOhAhead, du_next, x_next);
+      uint32_t sc[kOhAhead], kk[kOhAhead];
+      oh_table_ratio_counts<false, kOhAhead>(s, tab, nv, du, x, sc, kk);
+#pragma unroll
+      for (int t = 0; t < kOhAhead; ++t)
+        if (du[t] >= 0) df.put(q++, sc[t], kk[t], du[t], dv);
+      if (more) {
+#pragma unroll
+        for (int t = 0; t < kOhAhead; ++t) {
+          du[t] = du_next[t];
+          x[t] = x_next[t];
+        }
+      }
+    }
+    return df.total();
+  } else {
   // kOhAhead neighbours at a time: their degrees and rows are loaded before
   // any of them is evaluated
   for (int64_t p0 = beg; p0 < end; p0 += kOhAhead) {
@@ -918,30 +953,21 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
         x[t][j] = e < nu ? row[e] : 0u;
       }
     }
-    if constexpr (TAB) {
-      uint32_t xs[kOhAhead], sc[kOhAhead], kk[kOhAhead];
 #pragma unroll
-      for (int t = 0; t < kOhAhead; ++t) xs[t] = x[t][0];
-      oh_table_ratio_counts<false, kOhAhead>(s, reinterpret_cast<const uint32_t*>(keys), nv, du, xs, sc, kk);
-#pragma unroll
-      for (int t = 0; t < kOhAhead; ++t)
-        if (du[t] >= 0) df.put(q++, sc[t], kk[t], du[t], dv);
-    } else {
-#pragma unroll
-      for (int t = 0; t < kOhAhead; ++t) {
-        if (du[t] < 0) continue;
-        if constexpr (KMV) {
-          acc += oh_wave_estimate<E, false, KMV>(s, keys, nv, dv, du[t], x[t]);
-        } else {
-          uint32_t sc, kk;
-          oh_wave_ratio_counts<E, false>(s, keys, nv, du[t], x[t], sc, kk);
-          df.put(q++, sc, kk, du[t], dv);
-        }
+    for (int t = 0; t < kOhAhead; ++t) {
+      if (du[t] < 0) continue;
+      if constexpr (KMV) {
+        acc += oh_wave_estimate<E, false, KMV>(s, keys, nv, dv, du[t], x[t]);
+      } else {
+        uint32_t sc, kk;
+        oh_wave_ratio_counts<E, false>(s, keys, nv, du[t], x[t], sc, kk);
+        df.put(q++, sc, kk, du[t], dv);
       }
     }
   }
   if constexpr (KMV) return acc;
   return df.total();
+  }
   }
 }
 

@@ -526,7 +526,10 @@ def test_cc_over_slabs_every_vertex(ctx):
     heavy chunks), an R-MAT graph (light and medium items, whole vertices) and
     isolated vertices; every vertex against the oracle, for Bloom filters with
     a ratio estimator (AND) and one that reads the popcounts (OR), and for
-    k-hash signatures, and the transitivity."""
+    k-hash signatures, and the transitivity. The same graph also checks every
+    vertex's 1-hash coefficient (the vertex plan with heavy chunks; half waves
+    at k = 16, the ID table at k = 64, the key search at k = 100, and a KMV
+    estimator)."""
     g = pggen.disjoint_union(pggen.star(40000), pggen.rmat(12, 16, seed=5), pggen.er(50, 0, seed=1))
     say(f"cc over slabs: n={g.n}")
     dg = pg.Graph(ctx, g.offsets, g.adj, validate=True)
@@ -549,6 +552,16 @@ def test_cc_over_slabs_every_vertex(ctx):
         torch.cuda.synchronize()
         _close32(np_(cc), oracle.cc(ref, "kh"))
         _close([trans], [3 * oracle.tc(ref, "kh") / wedges], rtol=1e-9)
+        sk.close()
+    for k, ests in ((16, ("1h", "1h_lit")), (64, ("1h", "1h_lit", "kmv")), (100, ("1h",))):
+        say(f"cc over slabs: 1-hash k={k}")
+        sk = dg.build_sketches("1h", k, seed=6)
+        ref = oracle.build_sketches(g, oracle.KIND_1H, k, seed=6)
+        for est in ests:
+            cc, trans = sk.cc(est, transitivity=True)
+            torch.cuda.synchronize()
+            _close32(np_(cc), oracle.cc(ref, est))
+            _close([trans], [3 * oracle.tc(ref, est) / wedges], rtol=1e-9)
         sk.close()
     dg.close()
 
