@@ -550,6 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_kh_tc_slab(SlabPlan P, SkView s, con
 
 constexpr int kOhAhead = 4;      // neighbour rows in flight per wave, a wave per pair
 constexpr int kOhHalfAhead = 2;  // neighbour rows in flight per half wave (k <= 32)
+constexpr int kOhTabAhead = 4;   // neighbour rows per group, the ID-table path (two groups in flight)
 
 template <int E>
 __device__ __forceinline__ void oh_keys_to_lds(const SkView& s, int32_t v, uint32_t nv, uint64_t* keys) {
@@ -862,9 +863,48 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
   uint32_t q = 0;       // pairs evaluated so far (the same in every lane)
   if constexpr (HALF) {  // k <= 32 (the launch checks it): a separate kernel, so the wave-per-pair loop keeps its registers
     static_assert(E == 1, "half waves hold at most 32 elements");
-    {
-      const int h = l >> 5;
-      const uint32_t le = (uint32_t)(l & 31);
+    const int h = l >> 5;
+    const uint32_t le = (uint32_t)(l & 31);
+    if constexpr (!KMV) {
+      // the ID-table path: as for whole waves, the next group's rows are
+      // loaded (whole, without waiting for the degrees) during the lookups
+      const uint32_t* tab = reinterpret_cast<const uint32_t*>(keys);
+      const bool in_row = le < s.size;
+      auto load = [&](int64_t p0, int32_t (&du)[kOhHalfAhead], uint32_t (&x)[kOhHalfAhead]) {
+#pragma unroll
+        for (int t = 0; t < kOhHalfAhead; ++t) {
+          const int64_t p = p0 + 2 * t + h;
+          const int32_t u = p < end ? adj[p] : -1;
+          du[t] = u >= 0 ? s.deg[u] : -1;
+          x[t] = (u >= 0 && in_row) ? s.sig[(size_t)u * s.size + le] : 0u;
+        }
+      };
+      int32_t du[kOhHalfAhead], du_next[kOhHalfAhead];
+      uint32_t x[kOhHalfAhead], x_next[kOhHalfAhead];
+      if (beg < end) load(beg, du, x);
+      for (int64_t p0 = beg; p0 < end; p0 += 2 * kOhHalfAhead) {
+        const bool more = p0 + 2 * kOhHalfAhead < end;
+        if (more) load(p0 + 2 * kOhHalfAhead, du_next, x_next);
+        uint32_t sc[kOhHalfAhead], kk[kOhHalfAhead];
+        oh_table_ratio_counts<true, kOhHalfAhead>(s, tab, nv, du, x, sc, kk);
+#pragma unroll
+        for (int t = 0; t < kOhHalfAhead; ++t) {
+          const int32_t du0 = __shfl(du[t], 0), du1 = __shfl(du[t], kWave / 2);
+          const uint32_t s0 = (uint32_t)__shfl((int)sc[t], 0), k0 = (uint32_t)__shfl((int)kk[t], 0);
+          const uint32_t s1 = (uint32_t)__shfl((int)sc[t], kWave / 2), k1 = (uint32_t)__shfl((int)kk[t], kWave / 2);
+          if (du0 >= 0) df.put(q++, s0, k0, du0, dv);
+          if (du1 >= 0) df.put(q++, s1, k1, du1, dv);
+        }
+        if (more) {
+#pragma unroll
+          for (int t = 0; t < kOhHalfAhead; ++t) {
+            du[t] = du_next[t];
+            x[t] = x_next[t];
+          }
+        }
+      }
+      return df.total();
+    } else {
       for (int64_t p0 = beg; p0 < end; p0 += 2 * kOhHalfAhead) {
         int32_t du[kOhHalfAhead];
         uint32_t x[kOhHalfAhead][1];
@@ -876,59 +916,43 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
           const uint32_t nu = u < 0 ? 0u : ((uint32_t)du[t] < s.size ? (uint32_t)du[t] : s.size);
           x[t][0] = le < nu ? s.sig[(size_t)u * s.size + le] : 0u;
         }
-        if constexpr (KMV) {
 #pragma unroll
-          for (int t = 0; t < kOhHalfAhead; ++t) {
-            const double est = oh_wave_estimate<1, true, KMV>(s, keys, nv, dv, du[t], x[t]);
-            if (du[t] >= 0) acc += est;
-          }
-        } else {
-          uint32_t xs[kOhHalfAhead], sc[kOhHalfAhead], kk[kOhHalfAhead];
-#pragma unroll
-          for (int t = 0; t < kOhHalfAhead; ++t) xs[t] = x[t][0];
-          oh_table_ratio_counts<true, kOhHalfAhead>(s, reinterpret_cast<const uint32_t*>(keys), nv, du, xs, sc, kk);
-#pragma unroll
-          for (int t = 0; t < kOhHalfAhead; ++t) {
-            const int32_t du0 = __shfl(du[t], 0), du1 = __shfl(du[t], kWave / 2);
-            const uint32_t s0 = (uint32_t)__shfl((int)sc[t], 0), k0 = (uint32_t)__shfl((int)kk[t], 0);
-            const uint32_t s1 = (uint32_t)__shfl((int)sc[t], kWave / 2), k1 = (uint32_t)__shfl((int)kk[t], kWave / 2);
-            if (du0 >= 0) df.put(q++, s0, k0, du0, dv);
-            if (du1 >= 0) df.put(q++, s1, k1, du1, dv);
-          }
+        for (int t = 0; t < kOhHalfAhead; ++t) {
+          const double est = oh_wave_estimate<1, true, KMV>(s, keys, nv, dv, du[t], x[t]);
+          if (du[t] >= 0) acc += est;
         }
       }
-      if constexpr (KMV) return __shfl(acc, 0) + __shfl(acc, kWave / 2);
-      return df.total();
+      return __shfl(acc, 0) + __shfl(acc, kWave / 2);
     }
   } else {
   if constexpr (TAB) {
-    // kOhAhead neighbours at a time, the next group's degrees and rows loaded
+    // kOhTabAhead neighbours at a time, the next group's degrees and rows loaded
     // while this group is looked up; a row is loaded whole (k slots) without
     // waiting for the degree, which masks the lanes afterwards
     const uint32_t* tab = reinterpret_cast<const uint32_t*>(keys);
     const bool in_row = (uint32_t)l < s.size;
-    auto load = [&](int64_t p0, int32_t (&du)[kOhAhead], uint32_t (&x)[kOhAhead]) {
+    auto load = [&](int64_t p0, int32_t (&du)[kOhTabAhead], uint32_t (&x)[kOhTabAhead]) {
 #pragma unroll
-      for (int t = 0; t < kOhAhead; ++t) {
+      for (int t = 0; t < kOhTabAhead; ++t) {
         const int32_t u = p0 + t < end ? adj[p0 + t] : -1;
         du[t] = u >= 0 ? s.deg[u] : -1;
         x[t] = (u >= 0 && in_row) ? s.sig[(size_t)u * s.size + l] : 0u;
       }
     };
-    int32_t du[kOhAhead], du_next[kOhAhead];
-    uint32_t x[kOhAhead], x_next[kOhAhead];
+    int32_t du[kOhTabAhead], du_next[kOhTabAhead];
+    uint32_t x[kOhTabAhead], x_next[kOhTabAhead];
     if (beg < end) load(beg, du, x);
-    for (int64_t p0 = beg; p0 < end; p0 += kOhAhead) {
-      const bool more = p0 + kOhAhead < end;
-      if (more) load(p0 + kOhAhead, du_next, x_next);
-      uint32_t sc[kOhAhead], kk[kOhAhead];
-      oh_table_ratio_counts<false, kOhAhead>(s, tab, nv, du, x, sc, kk);
+    for (int64_t p0 = beg; p0 < end; p0 += kOhTabAhead) {
+      const bool more = p0 + kOhTabAhead < end;
+      if (more) load(p0 + kOhTabAhead, du_next, x_next);
+      uint32_t sc[kOhTabAhead], kk[kOhTabAhead];
+      oh_table_ratio_counts<false, kOhTabAhead>(s, tab, nv, du, x, sc, kk);
 #pragma unroll
-      for (int t = 0; t < kOhAhead; ++t)
+      for (int t = 0; t < kOhTabAhead; ++t)
         if (du[t] >= 0) df.put(q++, sc[t], kk[t], du[t], dv);
       if (more) {
 #pragma unroll
-        for (int t = 0; t < kOhAhead; ++t) {
+        for (int t = 0; t < kOhTabAhead; ++t) {
           du[t] = du_next[t];
           x[t] = x_next[t];
         }
