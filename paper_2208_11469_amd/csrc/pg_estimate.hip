@@ -550,7 +550,8 @@ __global__ __launch_bounds__(kBlock) void k_kh_tc_slab(SlabPlan P, SkView s, con
 
 constexpr int kOhAhead = 4;      // neighbour rows in flight per wave, a wave per pair
 constexpr int kOhHalfAhead = 2;  // neighbour rows in flight per half wave (k <= 32)
-constexpr int kOhTabAhead = 4;   // neighbour rows per group, the ID-table path (two groups in flight)
+constexpr int kOhTabAhead = 2;      // neighbour rows per group, ID-table path, whole waves (two groups in flight)
+constexpr int kOhTabHalfAhead = 1;  // the same per half wave (k <= 32)
 
 template <int E>
 __device__ __forceinline__ void oh_keys_to_lds(const SkView& s, int32_t v, uint32_t nv, uint64_t* keys) {
@@ -870,25 +871,25 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
       // loaded (whole, without waiting for the degrees) during the lookups
       const uint32_t* tab = reinterpret_cast<const uint32_t*>(keys);
       const bool in_row = le < s.size;
-      auto load = [&](int64_t p0, int32_t (&du)[kOhHalfAhead], uint32_t (&x)[kOhHalfAhead]) {
+      auto load = [&](int64_t p0, int32_t (&du)[kOhTabHalfAhead], uint32_t (&x)[kOhTabHalfAhead]) {
 #pragma unroll
-        for (int t = 0; t < kOhHalfAhead; ++t) {
+        for (int t = 0; t < kOhTabHalfAhead; ++t) {
           const int64_t p = p0 + 2 * t + h;
           const int32_t u = p < end ? adj[p] : -1;
           du[t] = u >= 0 ? s.deg[u] : -1;
           x[t] = (u >= 0 && in_row) ? s.sig[(size_t)u * s.size + le] : 0u;
         }
       };
-      int32_t du[kOhHalfAhead], du_next[kOhHalfAhead];
-      uint32_t x[kOhHalfAhead], x_next[kOhHalfAhead];
+      int32_t du[kOhTabHalfAhead], du_next[kOhTabHalfAhead];
+      uint32_t x[kOhTabHalfAhead], x_next[kOhTabHalfAhead];
       if (beg < end) load(beg, du, x);
-      for (int64_t p0 = beg; p0 < end; p0 += 2 * kOhHalfAhead) {
-        const bool more = p0 + 2 * kOhHalfAhead < end;
-        if (more) load(p0 + 2 * kOhHalfAhead, du_next, x_next);
-        uint32_t sc[kOhHalfAhead], kk[kOhHalfAhead];
-        oh_table_ratio_counts<true, kOhHalfAhead>(s, tab, nv, du, x, sc, kk);
+      for (int64_t p0 = beg; p0 < end; p0 += 2 * kOhTabHalfAhead) {
+        const bool more = p0 + 2 * kOhTabHalfAhead < end;
+        if (more) load(p0 + 2 * kOhTabHalfAhead, du_next, x_next);
+        uint32_t sc[kOhTabHalfAhead], kk[kOhTabHalfAhead];
+        oh_table_ratio_counts<true, kOhTabHalfAhead>(s, tab, nv, du, x, sc, kk);
 #pragma unroll
-        for (int t = 0; t < kOhHalfAhead; ++t) {
+        for (int t = 0; t < kOhTabHalfAhead; ++t) {
           const int32_t du0 = __shfl(du[t], 0), du1 = __shfl(du[t], kWave / 2);
           const uint32_t s0 = (uint32_t)__shfl((int)sc[t], 0), k0 = (uint32_t)__shfl((int)kk[t], 0);
           const uint32_t s1 = (uint32_t)__shfl((int)sc[t], kWave / 2), k1 = (uint32_t)__shfl((int)kk[t], kWave / 2);
@@ -897,7 +898,7 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
         }
         if (more) {
 #pragma unroll
-          for (int t = 0; t < kOhHalfAhead; ++t) {
+          for (int t = 0; t < kOhTabHalfAhead; ++t) {
             du[t] = du_next[t];
             x[t] = x_next[t];
           }
