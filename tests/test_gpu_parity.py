@@ -566,6 +566,49 @@ def test_cc_over_slabs_every_vertex(ctx):
     dg.close()
 
 
+def _id_bucket(x):
+    """Bucket of vertex ID x in the ID table the 1-hash ratio kernels (k <= 64)
+    build in LDS: the top 7 bits of x * 0x9E3779B1 mod 2^32."""
+    return ((x * 0x9E3779B1) & 0xFFFFFFFF) >> 25
+
+
+def test_onehash_id_table_full_buckets(ctx):
+    """1-hash triangle count and clustering coefficient where an owner's IDs
+    all fall in one bucket of the kernels' ID table: hub 0 has 96 neighbours
+    from bucket 0 (its 64 or 32 kept IDs fill 16 or 8 buckets in a row, so
+    lookups walk past full buckets), hub 2 has 80 from bucket 127 (the chain
+    wraps to bucket 0); the hubs' neighbours form paths and share hub 1, and
+    random edges join the rest. TC and every vertex's CC against the oracle,
+    whole waves (k = 64) and half waves (k = 32), both ratio readings."""
+    n = 30000
+    b0 = [x for x in range(3, n) if _id_bucket(x) == 0][:96]
+    b127 = [x for x in range(3, n) if _id_bucket(x) == 127][:80]
+    assert len(b0) == 96 and len(b127) == 80
+    src, dst = [0], [1]
+    for hub, ids in ((0, b0), (2, b127)):
+        src += [hub] * len(ids) + ids[:-1] + [1] * len(ids)
+        dst += ids + ids[1:] + ids
+    rng = np.random.default_rng(5)
+    src = np.concatenate([np.array(src), rng.integers(0, n, 20000)])
+    dst = np.concatenate([np.array(dst), rng.integers(0, n, 20000)])
+    g = pggen.from_pairs(n, src, dst)
+    say(f"ID-table buckets: n={g.n} nnz={g.nnz}")
+    dg = pg.Graph(ctx, g.offsets, g.adj, validate=True)
+    wedges = float(np.sum(g.degrees() * (g.degrees() - 1) // 2))
+    for k in (64, 32):
+        sk = dg.build_sketches("1h", k, seed=7)
+        ref = oracle.build_sketches(g, oracle.KIND_1H, k, seed=7)
+        for est in ("1h", "1h_lit"):
+            say(f"  k={k} {est}")
+            _close([sk.tc(est)], [oracle.tc(ref, est)], rtol=1e-9)
+            cc, trans = sk.cc(est, transitivity=True)
+            torch.cuda.synchronize()
+            _close32(np_(cc), oracle.cc(ref, est))
+            _close([trans], [3 * oracle.tc(ref, est) / wedges], rtol=1e-9)
+        sk.close()
+    dg.close()
+
+
 @pytest.mark.parametrize("bits", [64, 320, 1024])
 def test_all_edges_over_slabs_equal_explicit_pairs(ctx, bits):
     """The all-edges calls (no pairs given) walk the triangle count's slab
