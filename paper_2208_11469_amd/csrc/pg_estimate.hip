@@ -812,28 +812,28 @@ __device__ __forceinline__ void oh_table_ratio_counts(const SkView& s, const uin
 // The ratio estimate s/kk -> J/(1+J)(d_u + d_v) is FP64 work with divisions
 // that every lane of the wave would repeat for every pair. Instead the pairs a
 // wave evaluates are numbered in order; lane q mod 64 keeps the counts of
-// pair q, and after every 64 pairs all lanes map their counts at once. Each
-// estimate is the per-pair path's value; each lane adds its estimates in pair
-// order and the lanes' sums meet in a fixed butterfly, so the total does not
-// depend on scheduling.
+// pair q (written into that lane alone, s and kk packed in one word), and
+// after every 64 pairs all lanes map their counts at once. Each estimate is
+// the per-pair path's value; each lane adds its estimates in pair order and
+// the lanes' sums meet in a fixed butterfly, so the total does not depend on
+// scheduling. d_v is the item owner's, the same for all its pairs.
 struct OhDeferred {
-  uint32_t s = 0, kk = 0;
-  int32_t du = 0, dv = 0;
-  bool has = false;
+  int32_t dv;
+  uint32_t counts = 0;  // lane q: s << 16 | kk of pair q (s, kk <= k <= 1024)
+  int32_t du = 0;       // lane q: d_u of pair q
+  uint32_t n = 0;       // pairs held, the same in every lane
   double acc = 0.0;
+  __device__ explicit OhDeferred(int32_t dv_) : dv(dv_) {}
   __device__ __forceinline__ void flush() {
-    if (has) acc += minhash_estimate(s, kk, du, dv);
-    has = false;
+    if ((uint32_t)lane_id() < n) acc += minhash_estimate(counts >> 16, counts & 0xFFFFu, du, dv);
+    n = 0;
   }
-  __device__ __forceinline__ void put(uint32_t q, uint32_t s_, uint32_t kk_, int32_t du_, int32_t dv_) {
-    if ((uint32_t)lane_id() == (q & 63u)) {
-      s = s_;
-      kk = kk_;
-      du = du_;
-      dv = dv_;
-      has = true;
-    }
-    if ((q & 63u) == 63u) flush();
+  // s_, kk_ and du_ are the same in every lane
+  __device__ __forceinline__ void put(uint32_t s_, uint32_t kk_, int32_t du_) {
+    const bool mine = (uint32_t)lane_id() == n;
+    counts = mine ? ((s_ << 16) | kk_) : counts;
+    du = mine ? du_ : du;
+    if (++n == (uint32_t)kWave) flush();
   }
   __device__ __forceinline__ double total() {
     flush();
@@ -860,8 +860,7 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
   }
   const int l = lane_id();
   double acc = 0.0;     // KMV: the same in every lane (of the half)
-  OhDeferred df;        // ratio estimators: deferred estimates
-  uint32_t q = 0;       // pairs evaluated so far (the same in every lane)
+  OhDeferred df(dv);    // ratio estimators: deferred estimates
   if constexpr (HALF) {  // k <= 32 (the launch checks it): a separate kernel, so the wave-per-pair loop keeps its registers
     static_assert(E == 1, "half waves hold at most 32 elements");
     const int h = l >> 5;
@@ -893,8 +892,8 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
           const int32_t du0 = __shfl(du[t], 0), du1 = __shfl(du[t], kWave / 2);
           const uint32_t s0 = (uint32_t)__shfl((int)sc[t], 0), k0 = (uint32_t)__shfl((int)kk[t], 0);
           const uint32_t s1 = (uint32_t)__shfl((int)sc[t], kWave / 2), k1 = (uint32_t)__shfl((int)kk[t], kWave / 2);
-          if (du0 >= 0) df.put(q++, s0, k0, du0, dv);
-          if (du1 >= 0) df.put(q++, s1, k1, du1, dv);
+          if (du0 >= 0) df.put(s0, k0, du0);
+          if (du1 >= 0) df.put(s1, k1, du1);
         }
         if (more) {
 #pragma unroll
@@ -950,7 +949,7 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
       oh_table_ratio_counts<false, kOhTabAhead>(s, tab, nv, du, x, sc, kk);
 #pragma unroll
       for (int t = 0; t < kOhTabAhead; ++t)
-        if (du[t] >= 0) df.put(q++, sc[t], kk[t], du[t], dv);
+        if (du[t] >= 0) df.put(sc[t], kk[t], du[t]);
       if (more) {
 #pragma unroll
         for (int t = 0; t < kOhTabAhead; ++t) {
@@ -986,7 +985,7 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
       } else {
         uint32_t sc, kk;
         oh_wave_ratio_counts<E, false>(s, keys, nv, du[t], x[t], sc, kk);
-        df.put(q++, sc, kk, du[t], dv);
+        df.put(sc, kk, du[t]);
       }
     }
   }
