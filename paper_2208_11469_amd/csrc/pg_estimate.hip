@@ -770,14 +770,15 @@ __device__ __forceinline__ void oh_table_ratio_counts(const SkView& s, const uin
   const uint32_t le = (uint32_t)(l - (HALF ? (l & 32) : 0));
   const uint64_t below = ((1ull << l) - 1ull) & hmask;
   const uint4* ids4 = reinterpret_cast<const uint4*>(tab);
-  const uint8_t* index = reinterpret_cast<const uint8_t*>(tab + kOhSlots);
-  uint32_t nu[A], b[A], hit[A];
+  const uint32_t* index4 = tab + kOhSlots;  // a bucket's four index bytes as one word
+  uint32_t nu[A], b[A], hit[A], w[A];
   uint4 q[A];
 #pragma unroll
   for (int t = 0; t < A; ++t) {
     nu[t] = du[t] < 0 ? 0u : ((uint32_t)du[t] < s.size ? (uint32_t)du[t] : s.size);
     b[t] = oh_bucket_of(x[t]);
     q[t] = ids4[b[t]];
+    w[t] = index4[b[t]];
   }
 #pragma unroll
   for (int t = 0; t < A; ++t) {
@@ -786,13 +787,14 @@ __device__ __forceinline__ void oh_table_ratio_counts(const SkView& s, const uin
       do {
         b[t] = (b[t] + 1) & (kOhBuckets - 1);
         q[t] = ids4[b[t]];
+        w[t] = index4[b[t]];
         hit[t] = oh_hits(q[t], x[t]);
       } while (hit[t] == 0u && !oh_open(q[t]));
     }
   }
   uint32_t iv[A];
 #pragma unroll
-  for (int t = 0; t < A; ++t) iv[t] = hit[t] ? index[4 * b[t] + (uint32_t)__builtin_ctz(hit[t])] : 0u;
+  for (int t = 0; t < A; ++t) iv[t] = hit[t] ? (w[t] >> (8u * (uint32_t)__builtin_ctz(hit[t]))) & 0xFFu : 0u;
 #pragma unroll
   for (int t = 0; t < A; ++t) {
     const bool found = hit[t] != 0u;
