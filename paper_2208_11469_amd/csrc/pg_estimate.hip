@@ -545,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_kh_tc_slab(SlabPlan P, SkView s, con
 // estimators the k-th smallest union key is either the key of the element of
 // M_u at position k - 1, or, when there is none, the element of M_v after
 // k - a + c - 1 others, a being the elements of M_u before position k - 1 and
-// c the common ones among them. The ratio estimators at k <= 64 replace the
+// c the common ones among them. The ratio estimators at k <= 128 replace the
 // key search by a lookup of M_u's IDs in a hash table of M_v's (below).
 
 constexpr int kOhAhead = 4;      // neighbour rows in flight per wave, a wave per pair
@@ -568,46 +568,58 @@ __device__ __forceinline__ void oh_keys_to_lds(const SkView& s, int32_t v, uint3
 // M_v and, if so, its index there: equal IDs are equal keys, and the common
 // elements keep their relative order in both rows, so the union position of
 // a common element e of M_u is e plus its index in M_v minus the common
-// elements before it. For k <= 64 the wave therefore puts M_v's IDs in a
+// elements before it. For k <= 128 the wave therefore puts M_v's IDs in a
 // bucketed hash table in LDS and looks each element of M_u up by ID: the
 // neighbour rows are never hashed to keys nor searched by key, and the counts
-// are the key walk's exactly. The table has kOhBuckets buckets of four ID
-// slots (at most 64 IDs, so half a slot per bucket on average) and a byte per
-// slot with the element's index in M_v. An ID goes to the first bucket, from
-// its hash bucket on, that has a free slot, so a lookup reads one bucket (one
-// 16-byte LDS read) and moves on only past a full bucket without the ID.
-constexpr int kOhBuckets = 128;
-constexpr int kOhSlots = 4 * kOhBuckets;
+// are the key walk's exactly. With E elements per lane (E = 1 for k <= 64,
+// 2 for k <= 128) the table has 128 E buckets of four ID slots (half a slot
+// per bucket on average when full) and a byte per slot with the element's
+// index in M_v. An ID goes to the first bucket, from its hash bucket on, that
+// has a free slot, so a lookup reads one bucket (one 16-byte LDS read, and
+// the bucket's four index bytes as one word) and moves on only past a full
+// bucket without the ID; at most 16 E buckets are full.
+template <int E>
+struct OhTable {
+  static constexpr int kBuckets = 128 * E;
+  static constexpr int kSlots = 4 * kBuckets;
+  static constexpr int kWords = kSlots + kBuckets;  // 32-bit words: the ID slots, then the index bytes
+  static constexpr int kShift = E == 1 ? 25 : 24;   // Fibonacci hashing to log2(kBuckets) bits
+};
 constexpr uint32_t kOhFree = 0xFFFFFFFFu;  // no vertex has this ID
 
+template <int E>
 __device__ __forceinline__ uint32_t oh_bucket_of(uint32_t id) {
-  return (id * 0x9E3779B1u) >> 25;  // Fibonacci hashing to 7 bits
+  return (id * 0x9E3779B1u) >> OhTable<E>::kShift;
 }
 
-// 32-bit words of a wave's table: the ID slots, then the index bytes.
-constexpr int kOhTableWords = kOhSlots + kOhSlots / 4;
-
-// Clear the wave's table, then insert M_v's nv <= 64 IDs, element e in lane e.
+// Clear the wave's table, then insert M_v's nv <= 64 E IDs, element j * 64 + l
+// in lane l.
+template <int E>
 __device__ __forceinline__ void oh_table_to_lds(const SkView& s, int32_t v, uint32_t nv, uint32_t* tab) {
+  using T = OhTable<E>;
   const int l = lane_id();
   uint4* ids4 = reinterpret_cast<uint4*>(tab);
 #pragma unroll
-  for (int j = 0; j < kOhBuckets / kWave; ++j) ids4[j * kWave + l] = make_uint4(kOhFree, kOhFree, kOhFree, kOhFree);
+  for (int j = 0; j < T::kBuckets / kWave; ++j) ids4[j * kWave + l] = make_uint4(kOhFree, kOhFree, kOhFree, kOhFree);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if ((uint32_t)l < nv) {
-    const uint32_t id = s.sig[(size_t)v * s.size + l];
-    uint32_t b = oh_bucket_of(id);
-    // at most 64 of the slots are ever taken, so a free one is always found
-    for (;;) {
-      int j = 0;
-      while (j < 4 && atomicCAS(tab + 4 * b + j, kOhFree, id) != kOhFree) ++j;
-      if (j < 4) {
-        reinterpret_cast<uint8_t*>(tab + kOhSlots)[4 * b + j] = (uint8_t)l;
-        break;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint32_t e = (uint32_t)(j * kWave + l);
+    if (e < nv) {
+      const uint32_t id = s.sig[(size_t)v * s.size + e];
+      uint32_t b = oh_bucket_of<E>(id);
+      // at most 64 E of the slots are ever taken, so a free one is always found
+      for (;;) {
+        int q = 0;
+        while (q < 4 && atomicCAS(tab + 4 * b + q, kOhFree, id) != kOhFree) ++q;
+        if (q < 4) {
+          reinterpret_cast<uint8_t*>(tab + T::kSlots)[4 * b + q] = (uint8_t)e;
+          break;
+        }
+        b = (b + 1) & (T::kBuckets - 1);
       }
-      b = (b + 1) & (kOhBuckets - 1);
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -616,8 +628,7 @@ __device__ __forceinline__ void oh_table_to_lds(const SkView& s, int32_t v, uint
 }
 
 // Lookups: the slots of a bucket holding the ID, and whether a bucket has a
-// free slot (which ends a search: at most 16 of the kOhBuckets buckets are
-// full).
+// free slot (which ends a search).
 __device__ __forceinline__ uint32_t oh_hits(const uint4& q, uint32_t id) {
   return (uint32_t)(q.x == id) | ((uint32_t)(q.y == id) << 1) | ((uint32_t)(q.z == id) << 2) |
          ((uint32_t)(q.w == id) << 3);
@@ -625,16 +636,16 @@ __device__ __forceinline__ uint32_t oh_hits(const uint4& q, uint32_t id) {
 __device__ __forceinline__ bool oh_open(const uint4& q) {
   return max(max(q.x, q.y), max(q.z, q.w)) == kOhFree;  // the free mark is the largest word
 }
-// The ID table serves the ratio estimators for k <= 64; the KMV estimators
+// The ID table serves the ratio estimators for k <= 128; the KMV estimators
 // need the keys themselves and larger k keep the key search.
 template <int E, bool KMV>
 __host__ __device__ constexpr bool oh_by_table() {
-  return !KMV && E == 1;
+  return !KMV && E <= 2;
 }
 // 64-bit LDS words a wave of the 1-hash kernels holds.
 template <int E, bool KMV>
 __host__ __device__ constexpr int oh_lds_words() {
-  return oh_by_table<E, KMV>() ? kOhTableWords / 2 : kWave * E;
+  return oh_by_table<E, KMV>() ? OhTable<E>::kWords / 2 : kWave * E;
 }
 
 // Estimate for the pair (v, u) given M_v's nv keys in LDS and this lane's
@@ -758,51 +769,68 @@ __device__ __forceinline__ void oh_wave_ratio_counts(const SkView& s, const uint
   sc = uni >= s.size ? comk : com;
 }
 
-// oh_wave_ratio_counts for k <= 64 (E = 1) over the ID table of M_v, for A
+// oh_wave_ratio_counts for k <= 128 over the ID table of M_v, for A
 // neighbours at once (du[t] < 0: none): their bucket reads are issued
-// together, then resolved.
-template <bool HALF, int A>
+// together, then resolved. HALF needs E = 1.
+template <bool HALF, int A, int E>
 __device__ __forceinline__ void oh_table_ratio_counts(const SkView& s, const uint32_t* tab, uint32_t nv,
-                                                      const int32_t (&du)[A], const uint32_t (&x)[A],
+                                                      const int32_t (&du)[A], const uint32_t (&x)[A][E],
                                                       uint32_t (&sc)[A], uint32_t (&kk)[A]) {
+  static_assert(!HALF || E == 1, "half waves hold at most 32 elements");
+  using T = OhTable<E>;
   const int l = lane_id();
   const uint64_t hmask = HALF ? ((l & 32) ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull) : ~0ull;
   const uint32_t le = (uint32_t)(l - (HALF ? (l & 32) : 0));
   const uint64_t below = ((1ull << l) - 1ull) & hmask;
   const uint4* ids4 = reinterpret_cast<const uint4*>(tab);
-  const uint32_t* index4 = tab + kOhSlots;  // a bucket's four index bytes as one word
-  uint32_t nu[A], b[A], hit[A], w[A];
-  uint4 q[A];
+  const uint32_t* index4 = tab + T::kSlots;  // a bucket's four index bytes as one word
+  uint32_t nu[A], b[A][E], hit[A][E], w[A][E];
+  uint4 q[A][E];
 #pragma unroll
   for (int t = 0; t < A; ++t) {
     nu[t] = du[t] < 0 ? 0u : ((uint32_t)du[t] < s.size ? (uint32_t)du[t] : s.size);
-    b[t] = oh_bucket_of(x[t]);
-    q[t] = ids4[b[t]];
-    w[t] = index4[b[t]];
-  }
 #pragma unroll
-  for (int t = 0; t < A; ++t) {
-    hit[t] = le < nu[t] ? oh_hits(q[t], x[t]) : 0u;
-    if (le < nu[t] && hit[t] == 0u && !oh_open(q[t])) {  // a full bucket without the ID: rare
-      do {
-        b[t] = (b[t] + 1) & (kOhBuckets - 1);
-        q[t] = ids4[b[t]];
-        w[t] = index4[b[t]];
-        hit[t] = oh_hits(q[t], x[t]);
-      } while (hit[t] == 0u && !oh_open(q[t]));
+    for (int j = 0; j < E; ++j) {
+      b[t][j] = oh_bucket_of<E>(x[t][j]);
+      q[t][j] = ids4[b[t][j]];
+      w[t][j] = index4[b[t][j]];
     }
   }
-  uint32_t iv[A];
-#pragma unroll
-  for (int t = 0; t < A; ++t) iv[t] = hit[t] ? (w[t] >> (8u * (uint32_t)__builtin_ctz(hit[t]))) & 0xFFu : 0u;
 #pragma unroll
   for (int t = 0; t < A; ++t) {
-    const bool found = hit[t] != 0u;
-    const uint64_t fb = __ballot(found) & hmask;
-    const uint32_t before = (uint32_t)__popcll(fb & below);  // common elements ahead of this one
-    const bool first_k = found && le + iv[t] - before < s.size;
-    const uint32_t com = (uint32_t)__popcll(fb);
-    const uint32_t comk = (uint32_t)__popcll(__ballot(first_k) & hmask);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const bool mine = (uint32_t)(j * kWave) + le < nu[t];
+      hit[t][j] = mine ? oh_hits(q[t][j], x[t][j]) : 0u;
+      if (mine && hit[t][j] == 0u && !oh_open(q[t][j])) {  // a full bucket without the ID: rare
+        do {
+          b[t][j] = (b[t][j] + 1) & (T::kBuckets - 1);
+          q[t][j] = ids4[b[t][j]];
+          w[t][j] = index4[b[t][j]];
+          hit[t][j] = oh_hits(q[t][j], x[t][j]);
+        } while (hit[t][j] == 0u && !oh_open(q[t][j]));
+      }
+    }
+  }
+  uint32_t iv[A][E];
+#pragma unroll
+  for (int t = 0; t < A; ++t)
+#pragma unroll
+    for (int j = 0; j < E; ++j)
+      iv[t][j] = hit[t][j] ? (w[t][j] >> (8u * (uint32_t)__builtin_ctz(hit[t][j]))) & 0xFFu : 0u;
+#pragma unroll
+  for (int t = 0; t < A; ++t) {
+    uint32_t com = 0, comk = 0;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const uint32_t e = (uint32_t)(j * kWave) + le;
+      const bool found = hit[t][j] != 0u;
+      const uint64_t fb = __ballot(found) & hmask;
+      const uint32_t before = com + (uint32_t)__popcll(fb & below);  // common elements ahead of this one
+      const bool first_k = found && e + iv[t][j] - before < s.size;
+      com += (uint32_t)__popcll(fb);
+      comk += (uint32_t)__popcll(__ballot(first_k) & hmask);
+    }
     // literal reading: |M_u cap M_v| of k; union reading: s of k'
     const bool lit = s.est == PG_EST_MH_1HASH_LITERAL;
     const uint32_t uni = nu[t] + nv - com;
@@ -853,7 +881,7 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
   const int32_t dv = s.deg[v];
   const uint32_t nv = (uint32_t)dv < s.size ? (uint32_t)dv : s.size;
   if constexpr (TAB) {
-    oh_table_to_lds(s, v, nv, reinterpret_cast<uint32_t*>(keys));
+    oh_table_to_lds<E>(s, v, nv, reinterpret_cast<uint32_t*>(keys));
   } else {
     oh_keys_to_lds<E>(s, v, nv, keys);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -872,23 +900,23 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
       // loaded (whole, without waiting for the degrees) during the lookups
       const uint32_t* tab = reinterpret_cast<const uint32_t*>(keys);
       const bool in_row = le < s.size;
-      auto load = [&](int64_t p0, int32_t (&du)[kOhTabHalfAhead], uint32_t (&x)[kOhTabHalfAhead]) {
+      auto load = [&](int64_t p0, int32_t (&du)[kOhTabHalfAhead], uint32_t (&x)[kOhTabHalfAhead][1]) {
 #pragma unroll
         for (int t = 0; t < kOhTabHalfAhead; ++t) {
           const int64_t p = p0 + 2 * t + h;
           const int32_t u = p < end ? adj[p] : -1;
           du[t] = u >= 0 ? s.deg[u] : -1;
-          x[t] = (u >= 0 && in_row) ? s.sig[(size_t)u * s.size + le] : 0u;
+          x[t][0] = (u >= 0 && in_row) ? s.sig[(size_t)u * s.size + le] : 0u;
         }
       };
       int32_t du[kOhTabHalfAhead], du_next[kOhTabHalfAhead];
-      uint32_t x[kOhTabHalfAhead], x_next[kOhTabHalfAhead];
+      uint32_t x[kOhTabHalfAhead][1], x_next[kOhTabHalfAhead][1];
       if (beg < end) load(beg, du, x);
       for (int64_t p0 = beg; p0 < end; p0 += 2 * kOhTabHalfAhead) {
         const bool more = p0 + 2 * kOhTabHalfAhead < end;
         if (more) load(p0 + 2 * kOhTabHalfAhead, du_next, x_next);
         uint32_t sc[kOhTabHalfAhead], kk[kOhTabHalfAhead];
-        oh_table_ratio_counts<true, kOhTabHalfAhead>(s, tab, nv, du, x, sc, kk);
+        oh_table_ratio_counts<true, kOhTabHalfAhead, 1>(s, tab, nv, du, x, sc, kk);
 #pragma unroll
         for (int t = 0; t < kOhTabHalfAhead; ++t) {
           const int32_t du0 = __shfl(du[t], 0), du1 = __shfl(du[t], kWave / 2);
@@ -901,7 +929,7 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
 #pragma unroll
           for (int t = 0; t < kOhTabHalfAhead; ++t) {
             du[t] = du_next[t];
-            x[t] = x_next[t];
+            x[t][0] = x_next[t][0];
           }
         }
       }
@@ -932,23 +960,27 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
     // while this group is looked up; a row is loaded whole (k slots) without
     // waiting for the degree, which masks the lanes afterwards
     const uint32_t* tab = reinterpret_cast<const uint32_t*>(keys);
-    const bool in_row = (uint32_t)l < s.size;
-    auto load = [&](int64_t p0, int32_t (&du)[kOhTabAhead], uint32_t (&x)[kOhTabAhead]) {
+    bool in_row[E];  // element j * 64 + l is a slot of the rows
+#pragma unroll
+    for (int j = 0; j < E; ++j) in_row[j] = (uint32_t)(j * kWave + l) < s.size;
+    auto load = [&](int64_t p0, int32_t (&du)[kOhTabAhead], uint32_t (&x)[kOhTabAhead][E]) {
 #pragma unroll
       for (int t = 0; t < kOhTabAhead; ++t) {
         const int32_t u = p0 + t < end ? adj[p0 + t] : -1;
         du[t] = u >= 0 ? s.deg[u] : -1;
-        x[t] = (u >= 0 && in_row) ? s.sig[(size_t)u * s.size + l] : 0u;
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+          x[t][j] = (u >= 0 && in_row[j]) ? s.sig[(size_t)u * s.size + j * kWave + l] : 0u;
       }
     };
     int32_t du[kOhTabAhead], du_next[kOhTabAhead];
-    uint32_t x[kOhTabAhead], x_next[kOhTabAhead];
+    uint32_t x[kOhTabAhead][E], x_next[kOhTabAhead][E];
     if (beg < end) load(beg, du, x);
     for (int64_t p0 = beg; p0 < end; p0 += kOhTabAhead) {
       const bool more = p0 + kOhTabAhead < end;
       if (more) load(p0 + kOhTabAhead, du_next, x_next);
       uint32_t sc[kOhTabAhead], kk[kOhTabAhead];
-      oh_table_ratio_counts<false, kOhTabAhead>(s, tab, nv, du, x, sc, kk);
+      oh_table_ratio_counts<false, kOhTabAhead, E>(s, tab, nv, du, x, sc, kk);
 #pragma unroll
       for (int t = 0; t < kOhTabAhead; ++t)
         if (du[t] >= 0) df.put(sc[t], kk[t], du[t]);
@@ -956,7 +988,8 @@ __device__ __forceinline__ double oh_wave_item(const SkView& s, int32_t v, const
 #pragma unroll
         for (int t = 0; t < kOhTabAhead; ++t) {
           du[t] = du_next[t];
-          x[t] = x_next[t];
+#pragma unroll
+          for (int j = 0; j < E; ++j) x[t][j] = x_next[t][j];
         }
       }
     }

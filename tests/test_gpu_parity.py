@@ -222,6 +222,7 @@ EST_CASES = [
     ("rmat12", "1h", 32, 1, ("1h", "1h_lit")),
     ("er4096", "1h", 64, 1, ("1h", "1h_lit")),
     ("hub", "1h", 16, 1, ("1h", "1h_lit")),
+    ("rmat12", "1h", 128, 1, ("1h", "1h_lit")),
 ]
 KIND_OF = {"bf": oracle.KIND_BF, "kh": oracle.KIND_KH, "1h": oracle.KIND_1H}
 
@@ -566,26 +567,28 @@ def test_cc_over_slabs_every_vertex(ctx):
     dg.close()
 
 
-def _id_bucket(x):
-    """Bucket of vertex ID x in the ID table the 1-hash ratio kernels (k <= 64)
-    build in LDS: the top 7 bits of x * 0x9E3779B1 mod 2^32."""
-    return ((x * 0x9E3779B1) & 0xFFFFFFFF) >> 25
+def _id_bucket8(x):
+    """Top 8 bits of x * 0x9E3779B1 mod 2^32: the bucket of vertex ID x in the
+    ID table the 1-hash ratio kernels build in LDS for 64 < k <= 128 (256
+    buckets); its top 7 bits are the bucket for k <= 64 (128 buckets)."""
+    return ((x * 0x9E3779B1) & 0xFFFFFFFF) >> 24
 
 
 def test_onehash_id_table_full_buckets(ctx):
     """1-hash triangle count and clustering coefficient where an owner's IDs
-    all fall in one bucket of the kernels' ID table: hub 0 has 96 neighbours
-    from bucket 0 (its 64 or 32 kept IDs fill 16 or 8 buckets in a row, so
-    lookups walk past full buckets), hub 2 has 80 from bucket 127 (the chain
-    wraps to bucket 0); the hubs' neighbours form paths and share hub 1, and
-    random edges join the rest. TC and every vertex's CC against the oracle,
-    whole waves (k = 64) and half waves (k = 32), both ratio readings."""
-    n = 30000
-    b0 = [x for x in range(3, n) if _id_bucket(x) == 0][:96]
-    b127 = [x for x in range(3, n) if _id_bucket(x) == 127][:80]
-    assert len(b0) == 96 and len(b127) == 80
+    all fall in one bucket of the kernels' ID table: hub 0 has 160 neighbours
+    from the first bucket (its kept IDs fill a run of buckets, so lookups walk
+    past full buckets), hub 2 has 150 from the last bucket (the chain wraps to
+    the first); the hubs' neighbours form paths and share hub 1, and random
+    edges join the rest. TC and every vertex's CC against the oracle, two
+    elements per lane (k = 128), whole waves (k = 64) and half waves (k = 32),
+    both ratio readings."""
+    n = 60000
+    b0 = [x for x in range(3, n) if _id_bucket8(x) == 0][:160]
+    blast = [x for x in range(3, n) if _id_bucket8(x) == 255][:150]
+    assert len(b0) == 160 and len(blast) == 150
     src, dst = [0], [1]
-    for hub, ids in ((0, b0), (2, b127)):
+    for hub, ids in ((0, b0), (2, blast)):
         src += [hub] * len(ids) + ids[:-1] + [1] * len(ids)
         dst += ids + ids[1:] + ids
     rng = np.random.default_rng(5)
@@ -595,7 +598,7 @@ def test_onehash_id_table_full_buckets(ctx):
     say(f"ID-table buckets: n={g.n} nnz={g.nnz}")
     dg = pg.Graph(ctx, g.offsets, g.adj, validate=True)
     wedges = float(np.sum(g.degrees() * (g.degrees() - 1) // 2))
-    for k in (64, 32):
+    for k in (128, 64, 32):
         sk = dg.build_sketches("1h", k, seed=7)
         ref = oracle.build_sketches(g, oracle.KIND_1H, k, seed=7)
         for est in ("1h", "1h_lit"):
