@@ -223,6 +223,8 @@ EST_CASES = [
     ("er4096", "1h", 64, 1, ("1h", "1h_lit")),
     ("hub", "1h", 16, 1, ("1h", "1h_lit")),
     ("rmat12", "1h", 128, 1, ("1h", "1h_lit")),
+    ("rmat12", "1h", 48, 1, ("1h", "1h_lit")),  # lanes 48..63 hold no slot of the rows
+    ("hub", "1h", 7, 1, ("1h", "1h_lit")),      # half waves, rows of 7 slots
 ]
 KIND_OF = {"bf": oracle.KIND_BF, "kh": oracle.KIND_KH, "1h": oracle.KIND_1H}
 
